@@ -1,0 +1,579 @@
+"""Plain FP64 CPU oracle of one timestep of the remeshing-free graph-based FEM.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call this
+module: only the tests, the smoke check and the CPU-baseline leg of the
+benchmark use it.  It shares no code with the HIP library; the only common
+input is the seeded mesh generator, which holds none of the method's
+arithmetic.
+
+What is computed, and where it comes from (Mandal, Chaudhuri & Chaudhuri,
+"Remeshing-Free Graph-Based Finite Element Method for Ductile and Brittle
+Fracture"):
+
+* Linear tetrahedra; consistent element mass (Sec. 3.1, Eq. 5); forces and
+  tangent stiffness of the per-element energy (Eq. 7, 9, 10, 11).
+* The element energy is the stable neo-Hookean density (Sec. 5.1, Eq. 35),
+  evaluated from the six squared edge lengths of the tet (Sec. 3.5,
+  Theorem 3.1, Eq. 27-31): the Gram matrix of the edge vectors is linear in
+  the squared lengths, so I_C = tr(G G0^-1) and J^2 = det G / det G0.  Nodal
+  forces are sums along the tet's edges (Sec. 3.2, Eq. 12).
+* Per-edge binary damage, irreversible (Sec. 3.3, Eq. 20-21, local kernel
+  R_d = 0), evaluated as a Green normal-strain threshold along the edge.
+* Per-tet energy fraction chi (Sec. 3.4, Eq. 22-25), zero when the tet's
+  unbroken edges no longer connect its four nodes.
+* The fractured system f* = chi f, K* = sum chi k (Sec. 3.6, Eq. 32-34),
+  mass unchanged, damping b* = alpha M + beta K*.
+* One linearised backward-Euler step per timestep solved by conjugate
+  gradients (Sec. 4.3 and Algorithm 1), here with a 3x3 block-Jacobi
+  preconditioner; positions advance by dt * v.
+
+Readings where the paper is silent or garbled are the ones listed in the
+design notes (squared (J - alpha) term in Eq. 35, Smith's reparametrisation of
+the Lame constants, rest-frame edge directions in Eq. 28, tensor projection
+of the 2nd Piola-Kirchhoff stress for Eq. 16, (1 - zeta) for Eq. 22, a strain
+threshold for Eq. 21, coefficient-clamped edge Hessian, additive Green-strain
+plasticity for the ductile case).
+
+Parity unpinned: the chi 0/0 fallback, the plasticity model and the load and
+notch geometry are readings with no closed form in the paper to pin them to;
+they are graded against the GPU path only.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+# Local edge order of a tet: (0,1),(0,2),(0,3),(1,2),(1,3),(2,3) -- the
+# 12,13,14,23,24,34 order of Eq. 15.
+LOCAL_EDGES = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
+EDGE_A = np.array([a for a, _ in LOCAL_EDGES])
+EDGE_B = np.array([b for _, b in LOCAL_EDGES])
+
+
+# --------------------------------------------------------------------------
+# Constants of the reference simplex
+# --------------------------------------------------------------------------
+
+def reference_edges() -> np.ndarray:
+    """e_hat_k: edge k of the reference simplex, node 0 at the origin and
+    node i at the i-th unit vector.  s_k = e_hat_k^T G e_hat_k."""
+    e = np.zeros((6, 3))
+    for k, (a, b) in enumerate(LOCAL_EDGES):
+        if b > 0:
+            e[k, b - 1] += 1.0
+        if a > 0:
+            e[k, a - 1] -= 1.0
+    return e
+
+
+def polarisation_basis() -> np.ndarray:
+    """E_k = dG/ds_k, where G = Ds^T Ds is the Gram matrix of the edge vectors
+    from node 0: G_ii = s_0i and G_ij = (s_0i + s_0j - s_ij)/2."""
+    E = np.zeros((6, 3, 3))
+    for k, (a, b) in enumerate(LOCAL_EDGES):
+        if a == 0:
+            i = b - 1
+            E[k, i, i] = 1.0
+            for j in range(3):
+                if j != i:
+                    E[k, i, j] += 0.5
+                    E[k, j, i] += 0.5
+        else:
+            i, j = a - 1, b - 1
+            E[k, i, j] -= 0.5
+            E[k, j, i] -= 0.5
+    return E
+
+
+EHAT = reference_edges()
+EK = polarisation_basis()
+
+
+def disconnected_masks() -> np.ndarray:
+    """LUT over the 64 broken-edge masks of a tet: True when the unbroken
+    edges leave the four nodes in more than one connected piece (the
+    'disjoint fragments' case of Sec. 3.4).  Brute-force graph search."""
+    lut = np.zeros(64, dtype=bool)
+    for mask in range(64):
+        adj = {n: set() for n in range(4)}
+        for k, (a, b) in enumerate(LOCAL_EDGES):
+            if not (mask >> k) & 1:
+                adj[a].add(b)
+                adj[b].add(a)
+        seen, stack = {0}, [0]
+        while stack:
+            n = stack.pop()
+            for m in adj[n]:
+                if m not in seen:
+                    seen.add(m)
+                    stack.append(m)
+        lut[mask] = len(seen) < 4
+    return lut
+
+
+DISCONNECTED = disconnected_masks()
+
+
+def material(youngs: float, poisson: float):
+    """Lame constants of (E, nu), then the stable neo-Hookean reparametrisation
+    mu' = 4 mu / 3, lambda' = lambda + 5 mu / 6 (so that the small-strain
+    response of Eq. 35 has the given E and nu), and alpha of Eq. 35."""
+    mu = youngs / (2.0 * (1.0 + poisson))
+    lam = youngs * poisson / ((1.0 + poisson) * (1.0 - 2.0 * poisson))
+    mu_s = 4.0 * mu / 3.0
+    lam_s = lam + 5.0 * mu / 6.0
+    alpha = 1.0 + mu_s / lam_s - mu_s / (4.0 * lam_s)
+    return mu_s, lam_s, alpha
+
+
+# --------------------------------------------------------------------------
+# Mesh set-up
+# --------------------------------------------------------------------------
+
+@dataclass
+class Mesh:
+    X: np.ndarray            # (n,3) rest positions
+    tets: np.ndarray         # (m,4) positively oriented
+    edges: np.ndarray        # (ne,2) i<j, lexicographic
+    tet_edge: np.ndarray     # (m,6) edge id of each local edge
+    Dm: np.ndarray           # (m,3,3) rest edge vectors from node 0 (columns)
+    Dm_inv: np.ndarray
+    G0: np.ndarray
+    G0_inv: np.ndarray
+    detG0: np.ndarray
+    V: np.ndarray            # (m,) rest volume
+    S: np.ndarray            # (m,6) rest squared lengths per local edge
+    c: np.ndarray            # (m,6) c_k = tr(E_k G0^-1) = dI_C/ds_k
+    S_edge: np.ndarray       # (ne,) rest squared length per global edge
+    M: sp.csr_matrix         # (3n,3n) consistent mass
+    params: dict
+    mu: float = 0.0
+    lam: float = 0.0
+    alpha: float = 0.0
+
+
+def setup(X: np.ndarray, tets: np.ndarray, params: dict) -> Mesh:
+    X = np.asarray(X, dtype=np.float64)
+    tets = np.asarray(tets, dtype=np.int64).copy()
+    Dm = np.stack([X[tets[:, i]] - X[tets[:, 0]] for i in (1, 2, 3)], axis=2)
+    neg = np.linalg.det(Dm) < 0
+    tets[neg, 2], tets[neg, 3] = tets[neg, 3].copy(), tets[neg, 2].copy()
+    Dm = np.stack([X[tets[:, i]] - X[tets[:, 0]] for i in (1, 2, 3)], axis=2)
+    detDm = np.linalg.det(Dm)
+    if np.any(detDm <= 0):
+        raise ValueError("degenerate tetrahedron")
+    V = detDm / 6.0
+    G0 = np.einsum("tji,tjk->tik", Dm, Dm)
+    G0_inv = np.linalg.inv(G0)
+    pairs = np.stack([np.sort(tets[:, [a, b]], axis=1) for a, b in LOCAL_EDGES], axis=1)
+    edges, inv = np.unique(pairs.reshape(-1, 2), axis=0, return_inverse=True)
+    tet_edge = inv.reshape(-1, 6)
+    S = np.stack([np.sum((X[tets[:, b]] - X[tets[:, a]]) ** 2, axis=1) for a, b in LOCAL_EDGES], 1)
+    S_edge = np.sum((X[edges[:, 1]] - X[edges[:, 0]]) ** 2, axis=1)
+    c = np.einsum("kij,tji->tk", EK, G0_inv)
+    M = consistent_mass(X.shape[0], tets, V, params["density"])
+    mu, lam, alpha = material(params["youngs"], params["poisson"])
+    return Mesh(X, tets, edges, tet_edge, Dm, np.linalg.inv(Dm), G0, G0_inv,
+                np.linalg.det(G0), V, S, c, S_edge, M, params, mu, lam, alpha)
+
+
+def consistent_mass(n: int, tets: np.ndarray, V: np.ndarray, rho: float) -> sp.csr_matrix:
+    """Eq. 5 for linear shape functions: m_ab = rho V (1 + delta_ab) / 20 I_3."""
+    rows, cols, vals = [], [], []
+    for a in range(4):
+        for b in range(4):
+            m = rho * V * (2.0 if a == b else 1.0) / 20.0
+            for d in range(3):
+                rows.append(3 * tets[:, a] + d)
+                cols.append(3 * tets[:, b] + d)
+                vals.append(m)
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(3 * n, 3 * n)).tocsr()
+
+
+# --------------------------------------------------------------------------
+# State
+# --------------------------------------------------------------------------
+
+@dataclass
+class State:
+    x: np.ndarray                    # (n,3) positions
+    v: np.ndarray                    # (n,3) velocities
+    zeta: np.ndarray                 # (ne,) bool, True = broken
+    Ep: np.ndarray                   # (m,3,3) plastic Green strain (material frame)
+    step: int = 0
+
+
+def initial_state(mesh: Mesh) -> State:
+    n, m = mesh.X.shape[0], mesh.tets.shape[0]
+    return State(mesh.X.copy(), np.zeros((n, 3)), np.zeros(mesh.edges.shape[0], bool),
+                 np.zeros((m, 3, 3)))
+
+
+def break_pairs(mesh: Mesh, state: State, pairs: np.ndarray) -> None:
+    """OR the given node pairs (i<j) into the damage labels."""
+    if len(pairs) == 0:
+        return
+    n = mesh.X.shape[0] + 1
+    key = mesh.edges[:, 0] * n + mesh.edges[:, 1]
+    pk = np.sort(np.asarray(pairs, dtype=np.int64), axis=1)
+    state.zeta |= np.isin(key, pk[:, 0] * n + pk[:, 1])
+
+
+# --------------------------------------------------------------------------
+# Damage (Eq. 20-21, local support)
+# --------------------------------------------------------------------------
+
+def edge_strain(mesh: Mesh, x: np.ndarray) -> np.ndarray:
+    """Green normal strain along each edge: (s - S) / (2 S) = (lambda^2 - 1)/2
+    with lambda the stretch of Eq. 27; by Eq. 28 it equals q^T E q."""
+    s = np.sum((x[mesh.edges[:, 1]] - x[mesh.edges[:, 0]]) ** 2, axis=1)
+    return (s - mesh.S_edge) / (2.0 * mesh.S_edge)
+
+
+def damage_update(mesh: Mesh, x: np.ndarray, zeta: np.ndarray, near_tol: float = 1e-6,
+                  override: dict | None = None):
+    """zeta <- zeta OR (strain >= threshold); labels never revert (Sec. 3.3).
+    Returns (new zeta, indices of edges within near_tol of the threshold).
+    `override` maps edge id -> label for near-threshold edges only."""
+    eps = edge_strain(mesh, x)
+    thr = mesh.params["damage_strain"]
+    hit = eps >= thr
+    near = np.nonzero(np.abs(eps - thr) < near_tol)[0]
+    if override:
+        near_set = set(near.tolist())
+        for e, lab in override.items():
+            if e in near_set:
+                hit[e] = bool(lab)
+    return zeta | hit, near
+
+
+# --------------------------------------------------------------------------
+# Plasticity (ductile case): additive Green-strain flow with instant return
+# --------------------------------------------------------------------------
+
+def deformation_gradient(mesh: Mesh, x: np.ndarray) -> np.ndarray:
+    t = mesh.tets
+    Ds = np.stack([x[t[:, i]] - x[t[:, 0]] for i in (1, 2, 3)], axis=2)
+    return Ds @ mesh.Dm_inv
+
+
+def plastic_update(mesh: Mesh, x: np.ndarray, Ep: np.ndarray) -> np.ndarray:
+    """E_e = E - E_p; if |dev E_e|_F > yield, move the excess into E_p."""
+    ey = mesh.params.get("yield_strain", 0.0)
+    if ey <= 0:
+        return Ep
+    F = deformation_gradient(mesh, x)
+    C = np.einsum("tji,tjk->tik", F, F)
+    Ee = 0.5 * (C - np.eye(3)) - Ep
+    dev = Ee - np.trace(Ee, axis1=1, axis2=2)[:, None, None] / 3.0 * np.eye(3)
+    nrm = np.sqrt(np.sum(dev * dev, axis=(1, 2)))
+    fac = np.where(nrm > ey, 1.0 - ey / np.where(nrm > 0, nrm, 1.0), 0.0)
+    return Ep + fac[:, None, None] * dev
+
+
+def gram_offset(mesh: Mesh, Ep: np.ndarray) -> np.ndarray:
+    """Plastic strain expressed on the Gram matrix: P = 2 Dm^T Ep Dm, so the
+    elastic Gram matrix is G - P."""
+    return 2.0 * np.einsum("tji,tjk,tkl->til", mesh.Dm, Ep, mesh.Dm)
+
+
+# --------------------------------------------------------------------------
+# Edge-length element (Theorem 3.1 + Eq. 12 + Eq. 35)
+# --------------------------------------------------------------------------
+
+@dataclass
+class Element:
+    s: np.ndarray        # (m,6) current squared edge lengths
+    d: np.ndarray        # (m,6,3) current edge vectors x_b - x_a
+    IC: np.ndarray
+    J: np.ndarray
+    G: np.ndarray
+    Ginv: np.ndarray
+    g: np.ndarray        # (m,6) dPsi/ds_k
+    v: np.ndarray        # (m,6) tr(G^-1 E_k)
+    Mkl: np.ndarray      # (m,6,6)
+    coef: np.ndarray     # (m,3) unclamped Hessian coefficients
+    psi: np.ndarray
+    collapsed: np.ndarray
+
+
+def element(mesh: Mesh, x: np.ndarray, Ep: np.ndarray | None = None) -> Element:
+    t = mesh.tets
+    d = np.stack([x[t[:, b]] - x[t[:, a]] for a, b in LOCAL_EDGES], axis=1)
+    s = np.sum(d * d, axis=2)
+    G = np.einsum("tk,kij->tij", s, EK)
+    if Ep is not None:
+        G = G - gram_offset(mesh, Ep)
+    mu, lam, al = mesh.mu, mesh.lam, mesh.alpha
+    # A collapsed tet (det G = 0) has no finite edge-space derivatives; it is
+    # evaluated at its rest Gram matrix instead and must carry chi = 0.
+    collapsed = np.linalg.det(G) <= 1e-12 * mesh.detG0
+    G = np.where(collapsed[:, None, None], mesh.G0, G)
+    IC = np.einsum("tij,tji->t", G, mesh.G0_inv)
+    Ds = np.stack([x[t[:, i]] - x[t[:, 0]] for i in (1, 2, 3)], axis=2)
+    sign = np.where(np.linalg.det(Ds) < 0, -1.0, 1.0)
+    J = sign * np.sqrt(np.maximum(np.linalg.det(G) / mesh.detG0, 0.0))
+    Ginv = np.linalg.inv(G)
+    W = np.einsum("tij,kjl->tkil", Ginv, EK)           # G^-1 E_k
+    v = np.einsum("tkii->tk", W)
+    Mkl = np.einsum("tkij,tlji->tkl", W, W)
+    g = 0.5 * mu * (1.0 - 1.0 / (IC + 1.0))[:, None] * mesh.c \
+        + 0.5 * lam * ((J - al) * J)[:, None] * v
+    coef = np.stack([0.5 * mu / (IC + 1.0) ** 2,
+                     0.25 * lam * (2.0 * J - al) * J,
+                     -0.5 * lam * (J - al) * J], axis=1)
+    psi = 0.5 * mu * (IC - 3.0) + 0.5 * lam * (J - al) ** 2 - 0.5 * mu * np.log(IC + 1.0)
+    return Element(s, d, IC, J, G, Ginv, g, v, Mkl, coef, psi, collapsed)
+
+
+def edge_hessian(mesh: Mesh, el: Element, clamp: bool = True) -> np.ndarray:
+    """d^2 Psi / ds_k ds_l = a1 c c^T + a2 v v^T + a3 M; clamped: each a_i >= 0
+    (c c^T, v v^T and the Gram matrix M are PSD, so the result is PSD)."""
+    a = np.maximum(el.coef, 0.0) if clamp else el.coef
+    c, v = mesh.c, el.v
+    return (a[:, 0, None, None] * c[:, :, None] * c[:, None, :]
+            + a[:, 1, None, None] * v[:, :, None] * v[:, None, :]
+            + a[:, 2, None, None] * el.Mkl)
+
+
+def edge_jacobian(el: Element) -> np.ndarray:
+    """Js (m,6,12): ds_k/dx, edge k=(a,b) gives +2 d_k at b and -2 d_k at a."""
+    m = el.d.shape[0]
+    Js = np.zeros((m, 6, 12))
+    for k, (a, b) in enumerate(LOCAL_EDGES):
+        Js[:, k, 3 * b:3 * b + 3] = 2.0 * el.d[:, k]
+        Js[:, k, 3 * a:3 * a + 3] = -2.0 * el.d[:, k]
+    return Js
+
+
+LAPLACE = np.zeros((6, 12, 12))
+for _k, (_a, _b) in enumerate(LOCAL_EDGES):
+    _u = np.zeros(4)
+    _u[_a], _u[_b] = 1.0, -1.0
+    LAPLACE[_k] = np.kron(np.outer(_u, _u), np.eye(3))
+
+
+def element_forces(mesh: Mesh, el: Element, chi: np.ndarray) -> np.ndarray:
+    """Restoring nodal forces (m,4,3): f_a = 2 V chi sum_{k ∋ a} g_k (x_b - x_a)
+    (Eq. 12 with the unit vector pointing from a to the other node, times the
+    energy fraction of Eq. 32)."""
+    f = np.zeros((el.d.shape[0], 4, 3))
+    w = 2.0 * (mesh.V * chi)[:, None] * el.g
+    for k, (a, b) in enumerate(LOCAL_EDGES):
+        f[:, a] += w[:, k, None] * el.d[:, k]
+        f[:, b] -= w[:, k, None] * el.d[:, k]
+    return f
+
+
+def element_stiffness(mesh: Mesh, el: Element, chi: np.ndarray, clamp: bool = True) -> np.ndarray:
+    """k*_e = chi V [Js^T H Js + sum_k 2 g_k L_k]  (Eq. 10, 33), with the clamped
+    H and g_k -> max(g_k, 0) for a PSD tangent."""
+    H = edge_hessian(mesh, el, clamp)
+    Js = edge_jacobian(el)
+    gg = np.maximum(el.g, 0.0) if clamp else el.g
+    K = np.einsum("tki,tkl,tlj->tij", Js, H, Js) + 2.0 * np.einsum("tk,kij->tij", gg, LAPLACE)
+    return (mesh.V * chi)[:, None, None] * K
+
+
+# --------------------------------------------------------------------------
+# Energy fraction chi (Eq. 22-25)
+# --------------------------------------------------------------------------
+
+def edge_normal_stress(mesh: Mesh, x: np.ndarray, Ep: np.ndarray | None = None) -> np.ndarray:
+    """sigma_k = q_k^T S q_k: the 2nd Piola-Kirchhoff stress S = 2 dPsi/dC of
+    Eq. 35 projected on the rest unit direction q_k of each edge (Eq. 16-19,
+    as a tensor projection)."""
+    F = deformation_gradient(mesh, x)
+    C = np.einsum("tji,tjk->tik", F, F)
+    if Ep is not None:
+        C = C - 2.0 * Ep
+    mu, lam, al = mesh.mu, mesh.lam, mesh.alpha
+    IC = np.trace(C, axis1=1, axis2=2)
+    J = np.sign(np.linalg.det(F)) * np.sqrt(np.maximum(np.linalg.det(C), 0.0))
+    Cinv = np.linalg.inv(C)
+    Sst = (mu * (1.0 - 1.0 / (IC + 1.0)))[:, None, None] * np.eye(3) \
+        + (lam * (J - al) * J)[:, None, None] * Cinv
+    t = mesh.tets
+    q = np.stack([mesh.X[t[:, b]] - mesh.X[t[:, a]] for a, b in LOCAL_EDGES], axis=1)
+    q /= np.linalg.norm(q, axis=2, keepdims=True)
+    return np.einsum("tki,tij,tkj->tk", q, Sst, q)
+
+
+def energy_fraction(mesh: Mesh, x: np.ndarray, zeta: np.ndarray, Ep: np.ndarray | None = None):
+    """chi of Eq. 25 with sigma' = (1 - zeta) sigma; 0 for disconnected tets;
+    n_unbroken/6 when the stress is (numerically) zero.  Returns (chi, mask)."""
+    zt = zeta[mesh.tet_edge]
+    mask = np.sum(zt.astype(np.int64) << np.arange(6), axis=1)
+    chi = np.ones(mesh.tets.shape[0])
+    dmg = mask != 0
+    if np.any(dmg):
+        sig = np.abs(edge_normal_stress(mesh, x, Ep))
+        den = sig.sum(axis=1)
+        num = np.where(zt, 0.0, sig).sum(axis=1)
+        small = den <= 1e-12 * (mesh.mu + mesh.lam)
+        ratio = np.where(small, (6 - zt.sum(axis=1)) / 6.0, num / np.where(small, 1.0, den))
+        chi = np.where(dmg, ratio, 1.0)
+    chi = np.where(DISCONNECTED[mask], 0.0, chi)
+    return chi, mask
+
+
+# --------------------------------------------------------------------------
+# Global system, solve and step
+# --------------------------------------------------------------------------
+
+def scatter_forces(n: int, tets: np.ndarray, fe: np.ndarray) -> np.ndarray:
+    f = np.zeros((n, 3))
+    for a in range(4):
+        np.add.at(f, tets[:, a], fe[:, a])
+    return f
+
+
+def assemble_stiffness(n: int, tets: np.ndarray, Ke: np.ndarray) -> sp.csr_matrix:
+    dof = (3 * tets[:, :, None] + np.arange(3)).reshape(-1, 12)
+    rows = np.repeat(dof, 12, axis=1).ravel()
+    cols = np.tile(dof, (1, 12)).ravel()
+    return sp.coo_matrix((Ke.ravel(), (rows, cols)), shape=(3 * n, 3 * n)).tocsr()
+
+
+def restoring_forces(mesh: Mesh, state: State) -> np.ndarray:
+    """f* = sum_e chi_e f_e at the state's positions and labels (n,3)."""
+    chi, _ = energy_fraction(mesh, state.x, state.zeta, state.Ep)
+    el = element(mesh, state.x, state.Ep)
+    return scatter_forces(mesh.X.shape[0], mesh.tets, element_forces(mesh, el, chi))
+
+
+def total_energy(mesh: Mesh, x: np.ndarray, chi: np.ndarray, Ep=None) -> float:
+    el = element(mesh, x, Ep)
+    return float(np.sum(mesh.V * chi * el.psi))
+
+
+@dataclass
+class System:
+    A: sp.csr_matrix
+    b: np.ndarray          # (3n,)
+    dv_c: np.ndarray       # (k,3) prescribed velocity increments
+    chi: np.ndarray
+    stats: dict = field(default_factory=dict)
+
+
+def build_system(mesh: Mesh, state: State, dir_nodes, dir_vel, zeta: np.ndarray, Ep) -> System:
+    """A = M + dt (aM + bK*) + dt^2 K*;
+    b = dt (f_ext + f* - (aM + bK*) v) - dt^2 K* v; then Dirichlet elimination."""
+    p = mesh.params
+    n = mesh.X.shape[0]
+    dt = p["dt"]
+    chi, mask = energy_fraction(mesh, state.x, zeta, Ep)
+    el = element(mesh, state.x, Ep)
+    f = scatter_forces(n, mesh.tets, element_forces(mesh, el, chi)).ravel()
+    K = assemble_stiffness(n, mesh.tets, element_stiffness(mesh, el, chi))
+    M = mesh.M
+    ra, rb = p.get("rayleigh_alpha", 0.0), p.get("rayleigh_beta", 0.0)
+    D = ra * M + rb * K
+    v = state.v.ravel()
+    fext = M @ np.tile(np.asarray(p.get("gravity", (0, 0, 0)), float), n)
+    A = (M + dt * D + dt * dt * K).tocsr()
+    b = dt * (fext + f - D @ v) - dt * dt * (K @ v)
+    dir_nodes = np.asarray(dir_nodes, dtype=np.int64)
+    dv_c = np.asarray(dir_vel, float) - state.v[dir_nodes]
+    if dir_nodes.size:
+        cdof = (3 * dir_nodes[:, None] + np.arange(3)).ravel()
+        xc = np.zeros(3 * n)
+        xc[cdof] = dv_c.ravel()
+        b = b - A @ xc
+        keep = np.ones(3 * n)
+        keep[cdof] = 0.0
+        Dk = sp.diags(keep)
+        A = (Dk @ A @ Dk + sp.diags(1.0 - keep)).tocsr()
+        b[cdof] = dv_c.ravel()
+    A.eliminate_zeros()
+    stats = dict(chi_zero_tets=int(np.sum(chi == 0.0)),
+                 degenerate_tets=int(np.sum(np.abs(el.J) < 0.05)))
+    return System(A, b, dv_c, chi, stats)
+
+
+def block_jacobi(A: sp.csr_matrix) -> sp.csr_matrix:
+    """Inverse of the 3x3 diagonal blocks of A, as a block-diagonal matrix."""
+    n = A.shape[0] // 3
+    blocks = np.zeros((n, 3, 3))
+    for r in range(3):
+        for c in range(3):
+            blocks[:, r, c] = A.diagonal(c - r)[np.arange(n) * 3 + min(r, c)]
+    inv = np.linalg.inv(blocks)
+    return sp.bsr_matrix((inv, np.arange(n), np.arange(n + 1)), shape=(3 * n, 3 * n)).tocsr()
+
+
+def pcg(A: sp.csr_matrix, b: np.ndarray, P: sp.csr_matrix, tol: float, max_iter: int):
+    """Preconditioned conjugate gradients from x0 = 0.  Converged when the true
+    residual satisfies |b - A x| <= tol |b|.  Returns (x, iters, rel_res, ok)."""
+    bn = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    if bn == 0.0:
+        return x, 0, 0.0, True
+    r = b.copy()
+    z = P @ r
+    p = z.copy()
+    rz = r @ z
+    it = 0
+    while it < max_iter:
+        q = A @ p
+        pq = p @ q
+        if pq <= 0:
+            break
+        al = rz / pq
+        x += al * p
+        r -= al * q
+        it += 1
+        if np.linalg.norm(r) <= tol * bn:
+            rt = np.linalg.norm(b - A @ x)
+            if rt <= tol * bn:
+                return x, it, rt / bn, True
+            r = b - A @ x
+        z = P @ r
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    rt = np.linalg.norm(b - A @ x)
+    return x, it, rt / bn, rt <= tol * bn
+
+
+def step(mesh: Mesh, state: State, dir_nodes, dir_vel, override: dict | None = None,
+         max_iter: int | None = None, solver: str = "pcg"):
+    """One timestep of Algorithm 1 (without collisions and visualisation):
+    damage -> plasticity -> build system -> solve -> update.  Returns
+    (new_state, stats); on non-convergence returns (state unchanged, stats)."""
+    p = mesh.params
+    zeta, near = damage_update(mesh, state.x, state.zeta, override=override)
+    Ep = plastic_update(mesh, state.x, state.Ep)
+    sysm = build_system(mesh, state, dir_nodes, dir_vel, zeta, Ep)
+    if solver == "direct":
+        import scipy.sparse.linalg as spla
+        dv = spla.spsolve(sysm.A.tocsc(), sysm.b)
+        it, ok = 0, True
+        rel = np.linalg.norm(sysm.b - sysm.A @ dv) / max(np.linalg.norm(sysm.b), 1e-300)
+    else:
+        P = block_jacobi(sysm.A)
+        dv, it, rel, ok = pcg(sysm.A, sysm.b, P, p["cg_rel_tol"], max_iter or p["cg_max_iter"])
+    stats = dict(iters=it, rel_residual=rel, converged=ok,
+                 new_broken=int(np.sum(zeta & ~state.zeta)), total_broken=int(zeta.sum()),
+                 near_threshold=near, **sysm.stats)
+    if not ok:
+        return state, stats
+    v = state.v + dv.reshape(-1, 3)
+    x = state.x + p["dt"] * v
+    return State(x, v, zeta, Ep, state.step + 1), stats
+
+
+def run(mesh: Mesh, state: State, dir_nodes, dir_vel, n_steps: int, overrides=None):
+    """n_steps of `step`; overrides[i] is the label override for step i."""
+    hist = []
+    for i in range(n_steps):
+        ov = overrides[i] if overrides is not None and i < len(overrides) else None
+        state, st = step(mesh, state, dir_nodes, dir_vel, override=ov)
+        hist.append(st)
+        if not st["converged"]:
+            break
+    return state, hist
