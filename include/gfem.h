@@ -1,0 +1,169 @@
+/*
+ * gfem.h -- C ABI of the MI355X (gfx950) graph-based FEM fracture library.
+ *
+ * Method: Mandal, Chaudhuri & Chaudhuri, "Remeshing-Free Graph-Based Finite
+ * Element Method for Ductile and Brittle Fracture".  One timestep is
+ * Algorithm 1 (Sec. 4.3) without collisions and visualisation:
+ *   1. per-edge damage update and relabel (Sec. 3.3, Eq. 20-21, local support),
+ *   2. per-tet energy fraction chi (Sec. 3.4, Eq. 22-25),
+ *   3. element pass: stable neo-Hookean energy (Sec. 5.1, Eq. 35) written in
+ *      the six squared edge lengths (Sec. 3.5, Theorem 3.1), nodal forces
+ *      along the edges (Sec. 3.2, Eq. 12), tangent stiffness (Eq. 10), both
+ *      scaled by chi (Sec. 3.6, Eq. 32-34), scattered into a block-sparse
+ *      system whose pattern never changes (Sec. 1),
+ *   4. one linearised backward-Euler step (Sec. 4.3) solved by preconditioned
+ *      conjugate gradients, x += dt v.
+ *
+ * Conventions (all entry points):
+ *   - Every function returns a gf_status; nothing throws across the ABI.  On
+ *     error, gf_last_error() returns a thread-local message that stays valid
+ *     until the next call on the same thread.
+ *   - Pointers named *_out are caller-allocated HOST buffers of the stated
+ *     size; inputs are host buffers that are copied (the caller keeps
+ *     ownership).  No device pointer crosses this boundary except the
+ *     optional HIP stream of gf_set_stream.
+ *   - Node ids are the caller's 0-based ids; edges are in canonical order
+ *     (i < j, lexicographic in caller node ids) as returned by gf_get_edges.
+ *   - Not thread-safe per mesh: calls on one gf_mesh must be serialised.
+ */
+#ifndef GFEM_H
+#define GFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gf_mesh gf_mesh; /* opaque; owned by the library from create to destroy */
+
+typedef enum {
+  GF_OK = 0,
+  GF_EINVAL = -1,         /* bad argument: null pointer, size or index out of range */
+  GF_EDEGENERATE = -2,    /* a tet with |volume| <= 1e-14 h^3 */
+  GF_ENOMEM = -3,         /* host or device allocation failed */
+  GF_EDEVICE = -4,        /* a HIP runtime call failed, or no gfx950 device */
+  GF_ENOTCONVERGED = -5,  /* PCG missed the tolerance; the step was not committed */
+  GF_ESTATE = -6          /* call not valid in the current state (e.g. no weights loaded) */
+} gf_status;
+
+typedef enum { GF_PREC_FP64 = 0, GF_PREC_SPLIT = 1 } gf_precision;
+typedef enum { GF_PC_BLOCK_JACOBI = 0, GF_PC_LEARNED = 1 } gf_precond;
+
+/* Material, integrator and solver parameters (copied at create). */
+typedef struct {
+  double youngs;          /* E [Pa]: small-strain Young's modulus */
+  double poisson;         /* nu in (-1, 0.5) */
+  double density;         /* rho [kg/m^3]: consistent mass of Eq. 5 */
+  double damage_strain;   /* an edge breaks when its Green normal strain >= this (Eq. 21) */
+  double yield_strain;    /* ductile yield on |dev E_elastic|_F; <= 0 disables plasticity */
+  double dt;              /* timestep [s] */
+  double rayleigh_alpha;  /* damping b = alpha M + beta K* (Sec. 3.1, Sec. 3.6) */
+  double rayleigh_beta;
+  double gravity[3];      /* body acceleration [m/s^2] (Eq. 6 with t = rho g) */
+  double cg_rel_tol;      /* accept a solve at FP64 |b - A dv|_2 <= tol |b|_2 */
+  int32_t cg_max_iter;    /* total inner PCG iterations allowed per step */
+  int32_t precision;      /* gf_precision: FP64 everything, or FP32 element/SpMV + FP64 dots/residual */
+  int32_t precond;        /* gf_precond */
+  int32_t net_every_n_steps; /* learned preconditioner: run the network every n steps (>= 1) */
+} gf_params;
+
+/* Per-call statistics (summed over the steps of one gf_step call, except
+ * rel_residual and total_broken which describe the last step). */
+typedef struct {
+  int32_t steps_done;       /* committed steps */
+  int32_t inner_iters;      /* PCG iterations */
+  int32_t outer_iters;      /* FP64 residual recomputations (iterative refinement) */
+  int32_t used_fallback;    /* learned -> block-Jacobi fallbacks */
+  int32_t new_broken;       /* edges newly labelled broken */
+  int32_t total_broken;     /* broken edges after the last step */
+  int32_t near_threshold;   /* edge evaluations with |strain - threshold| < 1e-6 */
+  int32_t chi_zero_tets;    /* tets with chi = 0 (disconnected) in the last step */
+  int32_t degenerate_tets;  /* tets with |J| < 0.05 in the last step */
+  int32_t n_launch[8];      /* kernel launches per timing category (timing on) */
+  double rel_residual;      /* final FP64 |b - A dv| / |b| of the last step */
+  double kernel_us[8];      /* device time per category (timing on), microseconds:
+                               0 damage, 1 element (+plasticity), 2 assembly (edge + row),
+                               3 preconditioner, 4 SpMV (PCG), 5 PCG vector updates,
+                               6 FP64 residual / refinement, 7 integrate */
+} gf_step_stats;
+
+/* Create a mesh.  rest_xyz: n_nodes*3 doubles (caller order); tets:
+ * n_tets*4 node ids in any orientation (reoriented inside by swapping local
+ * nodes 2 and 3 when the signed volume is negative).  Builds the edge list
+ * (the induced graph of Sec. 1 and 3.1), the fixed block-sparse pattern
+ * (one 3x3 block per node and two per edge), the consistent mass (Eq. 5)
+ * and all device buffers.  Selects HIP device 0 unless one is current.
+ * Returns GF_EINVAL for bad sizes/ids, GF_EDEGENERATE for a flat tet. */
+gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t* tets,
+                         int32_t n_tets, const gf_params* params, gf_mesh** out);
+gf_status gf_mesh_destroy(gf_mesh* m);
+
+/* Run all device work on this HIP stream (hipStream_t passed as void*;
+ * NULL = the library's own stream). The caller keeps ownership. */
+gf_status gf_set_stream(gf_mesh* m, void* hip_stream);
+
+/* Sizes: any output pointer may be NULL. n_blocks = stored 3x3 blocks. */
+gf_status gf_get_sizes(const gf_mesh* m, int32_t* n_nodes, int32_t* n_tets, int32_t* n_edges,
+                       int32_t* n_blocks);
+
+/* Canonical edge list: ij_out holds n_edges*2 node ids, i < j, lexicographic. */
+gf_status gf_get_edges(const gf_mesh* m, int32_t* ij_out);
+
+/* Prescribed velocities: nodes[n] (caller ids, distinct), vel[n*3] m/s.  These
+ * nodes move at exactly that velocity every step (their rows and columns are
+ * eliminated from the solve).  Replaces any previous set; n = 0 clears it. */
+gf_status gf_set_dirichlet(gf_mesh* m, const int32_t* nodes, int32_t n, const double* vel);
+
+/* OR labels into the damage variable zeta (Eq. 21): zeta[n_edges] in
+ * canonical edge order, nonzero = broken.  Labels never revert. */
+gf_status gf_set_edge_damage(gf_mesh* m, const uint8_t* zeta);
+
+/* Advance n_steps timesteps.  Each step is committed only when its solve
+ * reaches the FP64 tolerance; otherwise the call stops, leaves positions,
+ * velocities, damage and plastic state as they were before that step and
+ * returns GF_ENOTCONVERGED.  stats may be NULL. */
+gf_status gf_step(gf_mesh* m, int32_t n_steps, gf_step_stats* stats);
+
+/* Current positions (rest + displacement), n_nodes*3 doubles, caller order. */
+gf_status gf_get_positions(const gf_mesh* m, double* xyz_out);
+/* Current velocities, n_nodes*3 doubles, caller order. */
+gf_status gf_get_velocities(const gf_mesh* m, double* vel_out);
+/* Damage labels, n_edges bytes (0/1), canonical edge order. */
+gf_status gf_get_edge_damage(const gf_mesh* m, uint8_t* zeta_out);
+
+/* Test hook: restoring force f* = sum_e chi_e f_e (Eq. 12, 32) at the current
+ * state and labels, n_nodes*3 doubles, caller order. */
+gf_status gf_eval_forces(gf_mesh* m, double* f_out);
+
+/* Test hook: assemble (without solving or committing) the system of the
+ * next step at the current state and copy it out in COO block form:
+ * bi_out/bj_out[n_blocks] caller node ids, vals_out[n_blocks*9] row-major 3x3
+ * blocks, rhs_out[n_nodes*3].  Dirichlet rows/columns are eliminated as in
+ * the solve.  Any output may be NULL. */
+gf_status gf_get_system(gf_mesh* m, int32_t* bi_out, int32_t* bj_out, double* vals_out,
+                        double* rhs_out);
+
+/* Checkpoint: the step is Markov in (displacement, velocity, damage, plastic
+ * state, step index).  gf_get_state with buf == NULL reports the size. */
+gf_status gf_get_state(const gf_mesh* m, void* buf, size_t* bytes);
+gf_status gf_set_state(gf_mesh* m, const void* buf, size_t bytes);
+
+/* Per-kernel device timing with HIP events on the library's stream
+ * (fills gf_step_stats.kernel_us / n_launch).  Off by default. */
+gf_status gf_set_timing(gf_mesh* m, int32_t on);
+
+/* Time `reps` launches of the PCG SpMV kernel alone on the current operator
+ * (after at least one step or gf_get_system) with HIP events; returns the
+ * mean duration in microseconds and the algorithmic bytes per launch. */
+gf_status gf_bench_spmv(gf_mesh* m, int32_t reps, double* us_per_launch, double* bytes_per_launch);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* gf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GFEM_H */

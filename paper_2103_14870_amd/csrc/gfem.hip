@@ -1,0 +1,826 @@
+// C ABI of the graph-based FEM fracture library (include/gfem.h): device
+// buffers, the per-step kernel sequence and the iterative-refinement PCG
+// driver.  Citations are to Mandal, Chaudhuri & Chaudhuri, "Remeshing-Free
+// Graph-Based Finite Element Method for Ductile and Brittle Fracture".
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gfem.h"
+#include "kernels.hpp"
+#include "topo.hpp"
+
+using gfem::d4;
+using gfem::v4;
+
+namespace {
+
+thread_local std::string g_err;
+
+gf_status fail(gf_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+inline void hchk(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError{e, what};
+}
+
+struct Alloc {
+  std::vector<void*> ptrs;
+  template <typename P>
+  P* get(size_t count) {
+    void* p = nullptr;
+    size_t bytes = std::max<size_t>(count * sizeof(P), 256);
+    if (hipMalloc(&p, bytes) != hipSuccess) throw std::bad_alloc();
+    hchk(hipMemset(p, 0, bytes), "hipMemset");
+    ptrs.push_back(p);
+    return static_cast<P*>(p);
+  }
+  ~Alloc() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+// Disconnected-mask table, built here by union-find over the tet's six edges
+// (independently of any other implementation).
+unsigned long long disconnected_lut() {
+  unsigned long long lut = 0;
+  for (int mask = 0; mask < 64; ++mask) {
+    int parent[4] = {0, 1, 2, 3};
+    auto find = [&](int a) {
+      while (parent[a] != a) a = parent[a];
+      return a;
+    };
+    for (int k = 0; k < 6; ++k)
+      if (!((mask >> k) & 1)) parent[find(gfem::kEdgeA[k])] = find(gfem::kEdgeB[k]);
+    int roots = 0;
+    for (int a = 0; a < 4; ++a) roots += find(a) == a;
+    if (roots > 1) lut |= 1ull << mask;
+  }
+  return lut;
+}
+
+struct TimeRec {
+  int cat;
+  int solve;  // PCG solve index, -1 outside PCG
+  int k;      // iteration index inside the solve
+  hipEvent_t a, b;
+};
+
+int round_up8(int x) { return (x + 7) / 8 * 8; }
+
+}  // namespace
+
+struct gf_mesh {
+  gfem::Topology topo;
+  gf_params p{};
+  bool split = false;
+  bool plastic = false;
+  int dev = 0;
+  hipStream_t own = nullptr, stream = nullptr;
+  int n = 0, m = 0, ne = 0, nb = 0, nbp = 0, Gv = 8, Gs = 8;
+  double mu = 0, lam = 0, alpha_m1 = 0;
+  Alloc al;
+  // node data
+  d4 *X = nullptr, *U = nullptr, *V = nullptr, *dvel = nullptr, *b = nullptr, *X64 = nullptr, *R64 = nullptr,
+     *fbuf = nullptr;
+  uint8_t* dflag = nullptr;
+  double* lumped = nullptr;
+  // tets
+  int4* tets = nullptr;
+  int32_t* tet_edge = nullptr;
+  uint8_t* flip = nullptr;
+  void* pl[2] = {nullptr, nullptr};
+  int plcur = 0;
+  void* contrib = nullptr;
+  // edges
+  int2* edges = nullptr;
+  double *edge_S = nullptr, *edge_mass = nullptr;
+  uint8_t* zeta[2] = {nullptr, nullptr};
+  int zcur = 0;
+  int32_t *edge_ptr = nullptr, *edge_slot = nullptr, *blk_ij = nullptr, *blk_ji = nullptr;
+  void* edge_w = nullptr;
+  // block matrix
+  int32_t *row_ptr = nullptr, *col = nullptr, *diag_blk = nullptr, *blk_edge = nullptr;
+  void* val = nullptr;
+  void* binv = nullptr;
+  // PCG
+  void *vr = nullptr, *vz = nullptr, *vp[2] = {nullptr, nullptr}, *vq = nullptr, *vx = nullptr;
+  double *part_a = nullptr, *part_rz = nullptr, *part_pq = nullptr;
+  gfem::PcgCtl* ctl = nullptr;
+  gfem::Counters* ctr = nullptr;
+  // host side
+  double* h_part = nullptr;          // pinned
+  gfem::PcgCtl* h_ctl = nullptr;     // pinned
+  gfem::Counters* h_ctr = nullptr;   // pinned
+  std::vector<uint8_t> h_dflag;
+  std::vector<d4> h_dvel;
+  int step_index = 0;
+  int last_first_solve = 0;
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<TimeRec> recs;
+  std::vector<int> solve_iters;
+
+  ~gf_mesh() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (h_part) (void)hipHostFree(h_part);
+    if (h_ctl) (void)hipHostFree(h_ctl);
+    if (h_ctr) (void)hipHostFree(h_ctr);
+    if (own) (void)hipStreamDestroy(own);
+  }
+
+  gfem::MatView mat() const { return gfem::MatView{n, nbp, row_ptr, col, val}; }
+
+  hipEvent_t ev() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      hchk(hipEventCreate(&e), "hipEventCreate");
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
+  // Records events around one launch when timing is on.
+  template <typename F>
+  void timed(int cat, int solve, int k, F&& launch) {
+    if (!timing) {
+      launch();
+      return;
+    }
+    TimeRec r{cat, solve, k, ev(), ev()};
+    hchk(hipEventRecord(r.a, stream), "hipEventRecord");
+    launch();
+    hchk(hipEventRecord(r.b, stream), "hipEventRecord");
+    recs.push_back(r);
+  }
+  void flush_times(gf_step_stats* st) {
+    if (!timing) return;
+    for (const TimeRec& r : recs) {
+      if (r.solve >= 0 && (r.solve >= (int)solve_iters.size() || r.k >= solve_iters[r.solve])) continue;
+      float ms = 0;
+      hchk(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+      if (st) {
+        st->kernel_us[r.cat] += 1000.0 * ms;
+        st->n_launch[r.cat] += 1;
+      }
+    }
+    recs.clear();
+    ev_used = 0;
+    solve_iters.clear();
+  }
+  void sync() { hchk(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+  void check_launch() { hchk(hipGetLastError(), "kernel launch"); }
+};
+
+namespace {
+
+using gfem::kMaxPart;
+
+// Upload host vector to a fresh device buffer.
+template <typename P>
+P* upload(gf_mesh* M, const std::vector<P>& h) {
+  P* d = M->al.get<P>(h.size());
+  if (!h.empty()) hchk(hipMemcpy(d, h.data(), h.size() * sizeof(P), hipMemcpyHostToDevice), "hipMemcpy H2D");
+  return d;
+}
+
+template <typename T>
+void alloc_precision(gf_mesh* M) {
+  const int n = M->n, m = M->m;
+  M->val = M->al.get<T>((size_t)9 * M->nbp);
+  M->contrib = M->al.get<T>((size_t)60 * m);
+  M->edge_w = M->al.get<T>(M->ne);
+  M->binv = M->al.get<T>((size_t)6 * n);
+  if (M->plastic) {
+    M->pl[0] = M->al.get<T>((size_t)6 * m);
+    M->pl[1] = M->al.get<T>((size_t)6 * m);
+  }
+  M->vr = M->al.get<v4<T>>(n);
+  M->vz = M->al.get<v4<T>>(n);
+  M->vp[0] = M->al.get<v4<T>>(n);
+  M->vp[1] = M->al.get<v4<T>>(n);
+  M->vq = M->al.get<v4<T>>(n);
+  M->vx = M->al.get<v4<T>>(n);
+}
+
+// Damage (into the spare label buffer), element pass (+ plastic flow into the
+// spare plastic buffer), edge pass and row pass: the system of the next step.
+template <typename T>
+void assemble(gf_mesh* M, bool flow, d4* f_out) {
+  hipStream_t s = M->stream;
+  hchk(hipMemsetAsync(M->ctr, 0, sizeof(gfem::Counters), s), "hipMemsetAsync");
+  const int zi = M->zcur, zo = 1 - M->zcur;
+  M->timed(0, -1, 0, [&] {
+    gfem::launch_damage(s, M->ne, M->edges, M->X, M->U, M->edge_S, M->zeta[zi], M->zeta[zo], M->p.damage_strain,
+                        M->ctr);
+  });
+  gfem::ElemConst ec{M->mu, M->lam, M->alpha_m1, flow ? M->p.yield_strain : 0.0};
+  const T* pin = M->plastic ? static_cast<const T*>(M->pl[M->plcur]) : nullptr;
+  T* pout = (M->plastic && flow) ? static_cast<T*>(M->pl[1 - M->plcur]) : nullptr;
+  M->timed(1, -1, 0, [&] {
+    gfem::launch_element<T>(s, M->m, M->tets, M->tet_edge, M->flip, M->X, M->U, M->zeta[flow ? zo : zi], pin,
+                            pout, ec, static_cast<T*>(M->contrib), M->ctr);
+  });
+  const double dt = M->p.dt;
+  const double mass_fac = 1.0 + dt * M->p.rayleigh_alpha;
+  const double stiff_fac = dt * dt + dt * M->p.rayleigh_beta;
+  M->timed(2, -1, 0, [&] {
+    gfem::launch_edge<T>(s, M->ne, M->m, M->edge_ptr, M->edge_slot, static_cast<const T*>(M->contrib),
+                         M->edge_mass, mass_fac, stiff_fac, M->blk_ij, M->blk_ji, static_cast<T*>(M->val), M->nbp,
+                         static_cast<T*>(M->edge_w));
+  });
+  gfem::RowConst rc{dt, M->p.rayleigh_alpha, mass_fac, {M->p.gravity[0], M->p.gravity[1], M->p.gravity[2]}};
+  M->timed(2, -1, 0, [&] {
+    gfem::launch_row<T>(s, M->n, M->Gv, M->mat(), M->diag_blk, M->blk_edge, M->edge_mass,
+                        static_cast<const T*>(M->edge_w), M->lumped, M->X, M->U, M->V, M->dflag, M->dvel, rc,
+                        static_cast<T*>(M->val), M->b, M->X64, static_cast<T*>(M->binv), f_out, M->part_a);
+  });
+  M->check_launch();
+}
+
+double read_partials(gf_mesh* M, const double* dpart, int count) {
+  hchk(hipMemcpyAsync(M->h_part, dpart, sizeof(double) * count, hipMemcpyDeviceToHost, M->stream), "D2H");
+  M->sync();
+  double s = 0;
+  for (int i = 0; i < count; ++i) s += M->h_part[i];
+  return s;
+}
+
+struct SolveResult {
+  bool ok;
+  int inner, outer;
+  double rel;
+};
+
+// Mixed-precision iterative refinement around block-Jacobi PCG.  Outer loop
+// in FP64: R = b - A X64 until |R| <= tol |b|; inner PCG on A d = R with T
+// vectors, FP64 dot products, device-side scalars and early exit, launched in
+// chunks so the host only synchronises once per chunk.
+template <typename T>
+SolveResult solve(gf_mesh* M, double bb) {
+  hipStream_t s = M->stream;
+  const double tol = M->p.cg_rel_tol;
+  SolveResult res{false, 0, 0, 0.0};
+  if (!(bb > 0.0)) {  // b = 0: dv = 0 (X64 already zeroed by the row pass)
+    res.ok = std::isfinite(bb);
+    return res;
+  }
+  const double floor_rel = M->split ? 1e-7 : 0.0;
+  double rr = bb;
+  const d4* src = M->b;
+  int budget = std::max(1, (int)M->p.cg_max_iter);
+  const gfem::MatView A = M->mat();
+  v4<T>* r = static_cast<v4<T>*>(M->vr);
+  v4<T>* z = static_cast<v4<T>*>(M->vz);
+  v4<T>* q = static_cast<v4<T>*>(M->vq);
+  v4<T>* x = static_cast<v4<T>*>(M->vx);
+  v4<T>* pb[2] = {static_cast<v4<T>*>(M->vp[0]), static_cast<v4<T>*>(M->vp[1])};
+  const T* binv = static_cast<const T*>(M->binv);
+  for (int outer = 0;; ++outer) {
+    res.rel = std::sqrt(rr / bb);
+    if (res.rel <= tol) {
+      res.ok = true;
+      break;
+    }
+    if (outer >= 30 || res.inner >= budget || !std::isfinite(rr)) break;
+    const double rel_in = std::max(0.5 * tol * std::sqrt(bb / rr), floor_rel);
+    const double thr2 = rel_in * rel_in * rr;
+    const int solve_id = (int)M->solve_iters.size();
+    hchk(hipMemsetAsync(M->ctl, 0, sizeof(gfem::PcgCtl), s), "hipMemsetAsync");
+    M->timed(5, -1, 0, [&] { gfem::launch_pcg_init<T>(s, M->n, M->Gv, src, binv, r, z, pb[0], x, M->part_rz); });
+    const int left = budget - res.inner;
+    int k = 0;
+    int chunk = (outer == 0 && M->last_first_solve > 0) ? std::min(M->last_first_solve, left) : std::min(16, left);
+    chunk = std::max(chunk, 1);
+    int iters = 0;
+    bool failed = false;
+    while (true) {
+      const int kend = std::min(k + chunk, left);
+      for (; k < kend; ++k) {
+        M->timed(4, solve_id, k, [&] {
+          gfem::launch_pcg_spmv<T>(s, k, M->Gs, M->Gv, A, z, pb[(k + 1) & 1], pb[k & 1], q, M->ctl, M->part_rz,
+                                   M->part_pq, thr2);
+        });
+        M->timed(5, solve_id, k, [&] {
+          gfem::launch_pcg_update<T>(s, k, M->n, M->Gv, M->Gs, pb[k & 1], q, x, r, z, binv, M->ctl, M->part_pq,
+                                     M->part_rz);
+        });
+      }
+      M->check_launch();
+      hchk(hipMemcpyAsync(M->h_ctl, M->ctl, sizeof(gfem::PcgCtl), hipMemcpyDeviceToHost, s), "D2H");
+      M->sync();
+      iters = M->h_ctl->iters;
+      failed = M->h_ctl->fail != 0;
+      if (M->h_ctl->done || k >= left) break;
+      chunk = 16;
+    }
+    M->solve_iters.push_back(iters);
+    if (outer == 0) M->last_first_solve = iters;
+    res.inner += iters;
+    res.outer = outer + 1;
+    if (iters > 0) {
+      M->timed(6, -1, 0, [&] { gfem::launch_addcorr<T>(s, M->n, M->Gv, x, M->X64); });
+    }
+    M->timed(6, -1, 0, [&] { gfem::launch_resid<T>(s, M->Gs, A, M->b, M->X64, M->R64, M->part_a); });
+    M->check_launch();
+    rr = read_partials(M, M->part_a, M->Gs);
+    src = M->R64;
+    if (failed && iters == 0) {
+      res.rel = std::sqrt(rr / bb);
+      res.ok = res.rel <= tol;
+      break;
+    }
+  }
+  return res;
+}
+
+template <typename T>
+gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
+  for (int i = 0; i < n_steps; ++i) {
+    assemble<T>(M, true, nullptr);
+    hchk(hipMemcpyAsync(M->h_ctr, M->ctr, sizeof(gfem::Counters), hipMemcpyDeviceToHost, M->stream), "D2H");
+    const double bb = read_partials(M, M->part_a, M->Gv);
+    SolveResult r = solve<T>(M, bb);
+    if (st) {
+      st->inner_iters += r.inner;
+      st->outer_iters += r.outer;
+      st->rel_residual = r.rel;
+      st->new_broken += M->h_ctr->new_broken;
+      st->total_broken = M->h_ctr->total_broken;
+      st->near_threshold += M->h_ctr->near_threshold;
+      st->chi_zero_tets = M->h_ctr->chi_zero;
+      st->degenerate_tets = M->h_ctr->degenerate;
+    }
+    if (!r.ok) {
+      M->flush_times(st);
+      char buf[160];
+      snprintf(buf, sizeof buf, "step %d: PCG reached rel. residual %.3e > tol %.3e after %d iterations",
+               M->step_index, r.rel, M->p.cg_rel_tol, r.inner);
+      return fail(GF_ENOTCONVERGED, buf);
+    }
+    M->timed(7, -1, 0, [&] { gfem::launch_integrate(M->stream, M->n, M->X64, M->V, M->U, M->dflag, M->dvel, M->p.dt); });
+    M->check_launch();
+    M->zcur = 1 - M->zcur;
+    if (M->plastic) M->plcur = 1 - M->plcur;
+    ++M->step_index;
+    M->sync();
+    M->flush_times(st);
+    if (st) st->steps_done += 1;
+  }
+  return GF_OK;
+}
+
+gf_status guard(gf_mesh* m, const char* what) {
+  if (!m) return fail(GF_EINVAL, std::string(what) + ": null mesh");
+  return GF_OK;
+}
+
+#define GF_TRY(...)                                                                      \
+  try {                                                                                  \
+    __VA_ARGS__                                                                          \
+  } catch (const HipError& e) {                                                          \
+    return fail(GF_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));        \
+  } catch (const std::bad_alloc&) {                                                      \
+    return fail(GF_ENOMEM, "allocation failed");                                         \
+  } catch (const std::exception& e) {                                                    \
+    return fail(GF_EINVAL, e.what());                                                    \
+  }
+
+}  // namespace
+
+extern "C" {
+
+const char* gf_last_error(void) { return g_err.c_str(); }
+
+gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t* tets, int32_t n_tets,
+                         const gf_params* params, gf_mesh** out) {
+  g_err.clear();
+  if (!rest_xyz || !tets || !params || !out) return fail(GF_EINVAL, "gf_mesh_create: null argument");
+  *out = nullptr;
+  const gf_params& p = *params;
+  if (!(p.youngs > 0) || !(p.poisson > -1.0 && p.poisson < 0.5) || !(p.density > 0) || !(p.dt > 0) ||
+      !(p.cg_rel_tol > 0) || p.cg_max_iter <= 0 || (p.precision != GF_PREC_FP64 && p.precision != GF_PREC_SPLIT) ||
+      (p.precond != GF_PC_BLOCK_JACOBI && p.precond != GF_PC_LEARNED) || !std::isfinite(p.damage_strain))
+    return fail(GF_EINVAL, "gf_mesh_create: invalid parameters");
+  if (p.precond == GF_PC_LEARNED) return fail(GF_ESTATE, "gf_mesh_create: learned preconditioner needs weights");
+  std::unique_ptr<gf_mesh> holder;
+  GF_TRY({
+    // Host-side validation and topology first: errors in the input are
+    // reported the same way with or without a device.
+    std::unique_ptr<gfem::Topology> topo(new gfem::Topology());
+    bool degen = false;
+    std::string err = gfem::build_topology(rest_xyz, n_nodes, tets, n_tets, p.density, topo.get(), &degen);
+    if (!err.empty()) return fail(degen ? GF_EDEGENERATE : GF_EINVAL, "gf_mesh_create: " + err);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(GF_EDEVICE, "no HIP device");
+    int dev = 0;
+    hchk(hipGetDevice(&dev), "hipGetDevice");
+    hipDeviceProp_t prop;
+    hchk(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      return fail(GF_EDEVICE, std::string("device is ") + prop.gcnArchName + ", library built for gfx950");
+    holder.reset(new gf_mesh());
+    gf_mesh* M = holder.get();
+    M->dev = dev;
+    M->p = p;
+    M->split = p.precision == GF_PREC_SPLIT;
+    M->plastic = p.yield_strain > 0;
+    M->topo = std::move(*topo);
+    const gfem::Topology& T = M->topo;
+    M->n = T.n;
+    M->m = T.m;
+    M->ne = T.ne;
+    M->nb = T.nb;
+    M->nbp = (T.nb + 63) / 64 * 64;
+    M->Gv = std::min(kMaxPart, std::max(8, round_up8((T.n + gfem::kThreads - 1) / gfem::kThreads)));
+    M->Gs = std::min(kMaxPart, std::max(8, round_up8((T.n * gfem::kRowLanes + gfem::kThreads - 1) / gfem::kThreads)));
+    const double E = p.youngs, nu = p.poisson;
+    const double mu0 = E / (2 * (1 + nu)), lam0 = E * nu / ((1 + nu) * (1 - 2 * nu));
+    M->mu = 4.0 * mu0 / 3.0;             // Smith et al. reparametrisation of Eq. 35
+    M->lam = lam0 + 5.0 * mu0 / 6.0;
+    M->alpha_m1 = 0.75 * M->mu / M->lam;  // alpha - 1 = mu/lam - mu/(4 lam)
+    hchk(hipStreamCreate(&M->own), "hipStreamCreate");
+    M->stream = M->own;
+    gfem::set_disconnected_lut(disconnected_lut());
+
+    std::vector<d4> hX(T.n);
+    for (int i = 0; i < T.n; ++i) hX[i] = d4{T.X[3 * i], T.X[3 * i + 1], T.X[3 * i + 2], 0.0};
+    M->X = upload(M, hX);
+    M->U = M->al.get<d4>(T.n);
+    M->V = M->al.get<d4>(T.n);
+    M->dvel = M->al.get<d4>(T.n);
+    M->b = M->al.get<d4>(T.n);
+    M->X64 = M->al.get<d4>(T.n);
+    M->R64 = M->al.get<d4>(T.n);
+    M->fbuf = M->al.get<d4>(T.n);
+    M->dflag = M->al.get<uint8_t>(T.n);
+    M->lumped = upload(M, T.lumped);
+    std::vector<int4> ht(T.m);
+    for (int t = 0; t < T.m; ++t) ht[t] = int4{T.tets[4 * t], T.tets[4 * t + 1], T.tets[4 * t + 2], T.tets[4 * t + 3]};
+    M->tets = upload(M, ht);
+    M->tet_edge = upload(M, T.tet_edge);
+    M->flip = upload(M, T.tet_flip);
+    std::vector<int2> he(T.ne);
+    for (int e = 0; e < T.ne; ++e) he[e] = int2{T.edges[2 * e], T.edges[2 * e + 1]};
+    M->edges = upload(M, he);
+    M->edge_S = upload(M, T.edge_S);
+    M->edge_mass = upload(M, T.edge_mass);
+    M->zeta[0] = M->al.get<uint8_t>(T.ne);
+    M->zeta[1] = M->al.get<uint8_t>(T.ne);
+    M->edge_ptr = upload(M, T.edge_ptr);
+    M->edge_slot = upload(M, T.edge_slot);
+    M->blk_ij = upload(M, T.blk_ij);
+    M->blk_ji = upload(M, T.blk_ji);
+    M->row_ptr = upload(M, T.row_ptr);
+    M->col = upload(M, T.col);
+    M->diag_blk = upload(M, T.diag_blk);
+    M->blk_edge = upload(M, T.blk_edge);
+    if (M->split)
+      alloc_precision<float>(M);
+    else
+      alloc_precision<double>(M);
+    M->part_a = M->al.get<double>(kMaxPart);
+    M->part_rz = M->al.get<double>(4 * kMaxPart);
+    M->part_pq = M->al.get<double>(kMaxPart);
+    M->ctl = M->al.get<gfem::PcgCtl>(1);
+    M->ctr = M->al.get<gfem::Counters>(1);
+    hchk(hipHostMalloc((void**)&M->h_part, sizeof(double) * kMaxPart, hipHostMallocDefault), "hipHostMalloc");
+    hchk(hipHostMalloc((void**)&M->h_ctl, sizeof(gfem::PcgCtl), hipHostMallocDefault), "hipHostMalloc");
+    hchk(hipHostMalloc((void**)&M->h_ctr, sizeof(gfem::Counters), hipHostMallocDefault), "hipHostMalloc");
+    M->h_dflag.assign(T.n, 0);
+    M->h_dvel.assign(T.n, d4{0, 0, 0, 0});
+    hchk(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    *out = holder.release();
+    return GF_OK;
+  })
+}
+
+gf_status gf_mesh_destroy(gf_mesh* m) {
+  if (!m) return GF_OK;
+  delete m;
+  return GF_OK;
+}
+
+gf_status gf_set_stream(gf_mesh* m, void* hip_stream) {
+  if (gf_status s = guard(m, "gf_set_stream")) return s;
+  GF_TRY({
+    m->sync();
+    m->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : m->own;
+    return GF_OK;
+  })
+}
+
+gf_status gf_get_sizes(const gf_mesh* m, int32_t* n_nodes, int32_t* n_tets, int32_t* n_edges, int32_t* n_blocks) {
+  if (!m) return fail(GF_EINVAL, "gf_get_sizes: null mesh");
+  if (n_nodes) *n_nodes = m->n;
+  if (n_tets) *n_tets = m->m;
+  if (n_edges) *n_edges = m->ne;
+  if (n_blocks) *n_blocks = m->nb;
+  return GF_OK;
+}
+
+gf_status gf_get_edges(const gf_mesh* m, int32_t* ij_out) {
+  if (!m || !ij_out) return fail(GF_EINVAL, "gf_get_edges: null argument");
+  const gfem::Topology& T = m->topo;
+  for (int c = 0; c < T.ne; ++c) {
+    int e = T.edge_internal[c];
+    int a = T.perm_old[T.edges[2 * e]], b = T.perm_old[T.edges[2 * e + 1]];
+    ij_out[2 * c] = std::min(a, b);
+    ij_out[2 * c + 1] = std::max(a, b);
+  }
+  return GF_OK;
+}
+
+gf_status gf_set_dirichlet(gf_mesh* m, const int32_t* nodes, int32_t n, const double* vel) {
+  if (gf_status s = guard(m, "gf_set_dirichlet")) return s;
+  if (n < 0 || (n > 0 && (!nodes || !vel))) return fail(GF_EINVAL, "gf_set_dirichlet: bad arguments");
+  std::vector<uint8_t> fl(m->n, 0);
+  std::vector<d4> dv(m->n, d4{0, 0, 0, 0});
+  for (int i = 0; i < n; ++i) {
+    int id = nodes[i];
+    if (id < 0 || id >= m->n) return fail(GF_EINVAL, "gf_set_dirichlet: node id out of range");
+    int k = m->topo.perm_new[id];
+    if (fl[k]) return fail(GF_EINVAL, "gf_set_dirichlet: repeated node");
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(vel[3 * i + d])) return fail(GF_EINVAL, "gf_set_dirichlet: non-finite velocity");
+    fl[k] = 1;
+    dv[k] = d4{vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.0};
+  }
+  GF_TRY({
+    m->sync();
+    hchk(hipMemcpy(m->dflag, fl.data(), m->n, hipMemcpyHostToDevice), "H2D");
+    hchk(hipMemcpy(m->dvel, dv.data(), sizeof(d4) * m->n, hipMemcpyHostToDevice), "H2D");
+    m->h_dflag = fl;
+    m->h_dvel = dv;
+    return GF_OK;
+  })
+}
+
+gf_status gf_set_edge_damage(gf_mesh* m, const uint8_t* zeta) {
+  if (gf_status s = guard(m, "gf_set_edge_damage")) return s;
+  if (!zeta) return fail(GF_EINVAL, "gf_set_edge_damage: null labels");
+  GF_TRY({
+    m->sync();
+    std::vector<uint8_t> cur(m->ne);
+    hchk(hipMemcpy(cur.data(), m->zeta[m->zcur], m->ne, hipMemcpyDeviceToHost), "D2H");
+    for (int c = 0; c < m->ne; ++c)
+      if (zeta[c]) cur[m->topo.edge_internal[c]] = 1;
+    hchk(hipMemcpy(m->zeta[m->zcur], cur.data(), m->ne, hipMemcpyHostToDevice), "H2D");
+    return GF_OK;
+  })
+}
+
+gf_status gf_step(gf_mesh* m, int32_t n_steps, gf_step_stats* stats) {
+  if (gf_status s = guard(m, "gf_step")) return s;
+  if (n_steps < 0) return fail(GF_EINVAL, "gf_step: negative step count");
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  GF_TRY({
+    return m->split ? step_impl<float>(m, n_steps, stats) : step_impl<double>(m, n_steps, stats);
+  })
+}
+
+static gf_status get_node_vec(const gf_mesh* m, const d4* src, bool add_rest, double* out, const char* who) {
+  if (!m || !out) return fail(GF_EINVAL, std::string(who) + ": null argument");
+  GF_TRY({
+    std::vector<d4> h(m->n);
+    hchk(hipStreamSynchronize(m->stream), "sync");
+    hchk(hipMemcpy(h.data(), src, sizeof(d4) * m->n, hipMemcpyDeviceToHost), "D2H");
+    for (int c = 0; c < m->n; ++c) {
+      const int i = m->topo.perm_new[c];
+      const double* X = &m->topo.X[3 * (size_t)i];
+      out[3 * (size_t)c] = h[i].x + (add_rest ? X[0] : 0.0);
+      out[3 * (size_t)c + 1] = h[i].y + (add_rest ? X[1] : 0.0);
+      out[3 * (size_t)c + 2] = h[i].z + (add_rest ? X[2] : 0.0);
+    }
+    return GF_OK;
+  })
+}
+
+gf_status gf_get_positions(const gf_mesh* m, double* xyz_out) {
+  return get_node_vec(m, m ? m->U : nullptr, true, xyz_out, "gf_get_positions");
+}
+
+gf_status gf_get_velocities(const gf_mesh* m, double* vel_out) {
+  return get_node_vec(m, m ? m->V : nullptr, false, vel_out, "gf_get_velocities");
+}
+
+gf_status gf_get_edge_damage(const gf_mesh* m, uint8_t* zeta_out) {
+  if (!m || !zeta_out) return fail(GF_EINVAL, "gf_get_edge_damage: null argument");
+  GF_TRY({
+    std::vector<uint8_t> h(m->ne);
+    hchk(hipStreamSynchronize(m->stream), "sync");
+    hchk(hipMemcpy(h.data(), m->zeta[m->zcur], m->ne, hipMemcpyDeviceToHost), "D2H");
+    for (int c = 0; c < m->ne; ++c) zeta_out[c] = h[m->topo.edge_internal[c]] ? 1 : 0;
+    return GF_OK;
+  })
+}
+
+gf_status gf_eval_forces(gf_mesh* m, double* f_out) {
+  if (gf_status s = guard(m, "gf_eval_forces")) return s;
+  if (!f_out) return fail(GF_EINVAL, "gf_eval_forces: null output");
+  GF_TRY({
+    if (m->split)
+      assemble<float>(m, false, m->fbuf);
+    else
+      assemble<double>(m, false, m->fbuf);
+    m->sync();
+    m->recs.clear();
+    m->ev_used = 0;
+    return get_node_vec(m, m->fbuf, false, f_out, "gf_eval_forces");
+  })
+}
+
+gf_status gf_get_system(gf_mesh* m, int32_t* bi_out, int32_t* bj_out, double* vals_out, double* rhs_out) {
+  if (gf_status s = guard(m, "gf_get_system")) return s;
+  GF_TRY({
+    if (m->split)
+      assemble<float>(m, true, nullptr);
+    else
+      assemble<double>(m, true, nullptr);
+    m->sync();
+    m->recs.clear();
+    m->ev_used = 0;
+    const gfem::Topology& T = m->topo;
+    if (vals_out) {
+      std::vector<double> hv((size_t)9 * m->nbp);
+      if (m->split) {
+        std::vector<float> hf((size_t)9 * m->nbp);
+        hchk(hipMemcpy(hf.data(), m->val, sizeof(float) * hf.size(), hipMemcpyDeviceToHost), "D2H");
+        for (size_t i = 0; i < hf.size(); ++i) hv[i] = hf[i];
+      } else {
+        hchk(hipMemcpy(hv.data(), m->val, sizeof(double) * hv.size(), hipMemcpyDeviceToHost), "D2H");
+      }
+      for (int bk = 0; bk < m->nb; ++bk)
+        for (int c = 0; c < 9; ++c) vals_out[9 * (size_t)bk + c] = hv[(size_t)c * m->nbp + bk];
+    }
+    if (bi_out || bj_out)
+      for (int i = 0; i < m->n; ++i)
+        for (int bk = T.row_ptr[i]; bk < T.row_ptr[i + 1]; ++bk) {
+          if (bi_out) bi_out[bk] = T.perm_old[i];
+          if (bj_out) bj_out[bk] = T.perm_old[T.col[bk]];
+        }
+    if (rhs_out) return get_node_vec(m, m->b, false, rhs_out, "gf_get_system");
+    return GF_OK;
+  })
+}
+
+namespace {
+struct StateHeader {
+  uint32_t magic, version;
+  int32_t n, ne, m, step, plastic, split;
+};
+constexpr uint32_t kMagic = 0x4d454647;  // "GFEM"
+
+size_t state_bytes(const gf_mesh* m) {
+  return sizeof(StateHeader) + sizeof(double) * 6 * (size_t)m->n + (size_t)m->ne +
+         (m->plastic ? sizeof(double) * 6 * (size_t)m->m : 0);
+}
+}  // namespace
+
+// Checkpoint blob: header | U (n*3 f64, caller order) | V (n*3 f64) |
+// zeta (n_edges u8, canonical order) | plastic Gram offset (6*n_tets f64, SoA).
+gf_status gf_get_state(const gf_mesh* m, void* buf, size_t* bytes) {
+  if (!m || !bytes) return fail(GF_EINVAL, "gf_get_state: null argument");
+  const size_t need = state_bytes(m);
+  if (!buf) {
+    *bytes = need;
+    return GF_OK;
+  }
+  if (*bytes < need) return fail(GF_EINVAL, "gf_get_state: buffer too small");
+  char* o = static_cast<char*>(buf);
+  StateHeader h{kMagic, 2, m->n, m->ne, m->m, m->step_index, m->plastic, m->split};
+  std::memcpy(o, &h, sizeof h);
+  o += sizeof h;
+  if (gf_status s = get_node_vec(m, m->U, false, reinterpret_cast<double*>(o), "gf_get_state")) return s;
+  o += sizeof(double) * 3 * m->n;
+  if (gf_status s = get_node_vec(m, m->V, false, reinterpret_cast<double*>(o), "gf_get_state")) return s;
+  o += sizeof(double) * 3 * m->n;
+  if (gf_status s = gf_get_edge_damage(m, reinterpret_cast<uint8_t*>(o))) return s;
+  o += m->ne;
+  GF_TRY({
+    if (m->plastic) {
+      std::vector<double> d((size_t)6 * m->m);
+      if (m->split) {
+        std::vector<float> f((size_t)6 * m->m);
+        hchk(hipMemcpy(f.data(), m->pl[m->plcur], sizeof(float) * f.size(), hipMemcpyDeviceToHost), "D2H");
+        std::copy(f.begin(), f.end(), d.begin());
+      } else {
+        hchk(hipMemcpy(d.data(), m->pl[m->plcur], sizeof(double) * d.size(), hipMemcpyDeviceToHost), "D2H");
+      }
+      std::memcpy(o, d.data(), sizeof(double) * d.size());
+    }
+    *bytes = need;
+    return GF_OK;
+  })
+}
+
+gf_status gf_set_state(gf_mesh* m, const void* buf, size_t bytes) {
+  if (!m || !buf) return fail(GF_EINVAL, "gf_set_state: null argument");
+  StateHeader h;
+  if (bytes < sizeof h) return fail(GF_EINVAL, "gf_set_state: buffer too small");
+  std::memcpy(&h, buf, sizeof h);
+  if (h.magic != kMagic || h.version != 2 || h.n != m->n || h.ne != m->ne || h.m != m->m ||
+      h.plastic != (int)m->plastic || h.split != (int)m->split || bytes < state_bytes(m))
+    return fail(GF_EINVAL, "gf_set_state: state does not match this mesh");
+  const char* o = static_cast<const char*>(buf) + sizeof h;
+  std::vector<d4> U(m->n), V(m->n);
+  for (int c = 0; c < m->n; ++c) {
+    double u[3], v[3];
+    std::memcpy(u, o + sizeof(double) * 3 * c, sizeof u);
+    std::memcpy(v, o + sizeof(double) * 3 * ((size_t)m->n + c), sizeof v);
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(u[d]) || !std::isfinite(v[d])) return fail(GF_EINVAL, "gf_set_state: non-finite state");
+    const int i = m->topo.perm_new[c];
+    U[i] = d4{u[0], u[1], u[2], 0.0};
+    V[i] = d4{v[0], v[1], v[2], 0.0};
+  }
+  o += sizeof(double) * 6 * m->n;
+  std::vector<uint8_t> z(m->ne);
+  for (int c = 0; c < m->ne; ++c) z[m->topo.edge_internal[c]] = o[c] ? 1 : 0;
+  o += m->ne;
+  GF_TRY({
+    m->sync();
+    hchk(hipMemcpy(m->U, U.data(), sizeof(d4) * m->n, hipMemcpyHostToDevice), "H2D");
+    hchk(hipMemcpy(m->V, V.data(), sizeof(d4) * m->n, hipMemcpyHostToDevice), "H2D");
+    hchk(hipMemcpy(m->zeta[m->zcur], z.data(), m->ne, hipMemcpyHostToDevice), "H2D");
+    if (m->plastic) {
+      std::vector<double> d((size_t)6 * m->m);
+      std::memcpy(d.data(), o, sizeof(double) * d.size());
+      if (m->split) {
+        std::vector<float> f(d.begin(), d.end());
+        hchk(hipMemcpy(m->pl[m->plcur], f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice), "H2D");
+      } else {
+        hchk(hipMemcpy(m->pl[m->plcur], d.data(), sizeof(double) * d.size(), hipMemcpyHostToDevice), "H2D");
+      }
+    }
+    m->step_index = h.step;
+    return GF_OK;
+  })
+}
+
+gf_status gf_set_timing(gf_mesh* m, int32_t on) {
+  if (gf_status s = guard(m, "gf_set_timing")) return s;
+  m->timing = on != 0;
+  return GF_OK;
+}
+
+gf_status gf_bench_spmv(gf_mesh* m, int32_t reps, double* us_per_launch, double* bytes_per_launch) {
+  if (gf_status s = guard(m, "gf_bench_spmv")) return s;
+  if (reps <= 0 || !us_per_launch) return fail(GF_EINVAL, "gf_bench_spmv: bad arguments");
+  GF_TRY({
+    const size_t vb = m->split ? 12 : 24, ab = m->split ? 4 : 8;
+    if (bytes_per_launch) *bytes_per_launch = (double)m->nb * (9 * ab + 4) + (double)m->n * (4 * vb + 4);
+    hipStream_t s = m->stream;
+    hipEvent_t a, b;
+    hchk(hipEventCreate(&a), "hipEventCreate");
+    hchk(hipEventCreate(&b), "hipEventCreate");
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      v4<T>* pb[2] = {static_cast<v4<T>*>(m->vp[0]), static_cast<v4<T>*>(m->vp[1])};
+      v4<T>* z = static_cast<v4<T>*>(m->vz);
+      hchk(hipMemsetAsync(m->ctl, 0, sizeof(gfem::PcgCtl), s), "hipMemsetAsync");
+      gfem::launch_pcg_init<T>(s, m->n, m->Gv, m->b, static_cast<const T*>(m->binv), static_cast<v4<T>*>(m->vr), z,
+                               pb[0], static_cast<v4<T>*>(m->vx), m->part_rz);
+      gfem::launch_pcg_spmv<T>(s, 0, m->Gs, m->Gv, m->mat(), z, pb[1], pb[0], static_cast<v4<T>*>(m->vq), m->ctl,
+                               m->part_rz, m->part_pq, -1.0);
+      gfem::launch_pcg_update<T>(s, 0, m->n, m->Gv, m->Gs, pb[0], static_cast<v4<T>*>(m->vq),
+                                 static_cast<v4<T>*>(m->vx), static_cast<v4<T>*>(m->vr), z,
+                                 static_cast<const T*>(m->binv), m->ctl, m->part_pq, m->part_rz);
+      hchk(hipEventRecord(a, s), "hipEventRecord");
+      for (int i = 0; i < reps; ++i)
+        gfem::launch_pcg_spmv<T>(s, 1, m->Gs, m->Gv, m->mat(), z, pb[0], pb[1], static_cast<v4<T>*>(m->vq),
+                                 m->ctl, m->part_rz, m->part_pq, -1.0);
+      hchk(hipEventRecord(b, s), "hipEventRecord");
+    };
+    if (m->split)
+      run(float{});
+    else
+      run(double{});
+    m->check_launch();
+    m->sync();
+    float ms = 0;
+    hchk(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *us_per_launch = 1000.0 * ms / reps;
+    return GF_OK;
+  })
+}
+
+}  // extern "C"

@@ -1,0 +1,1015 @@
+// Device kernels of the graph-based FEM step for gfx950 (CDNA4, wave64).
+// See kernels.hpp for the data layout.  Citations are to Mandal, Chaudhuri &
+// Chaudhuri, "Remeshing-Free Graph-Based Finite Element Method for Ductile
+// and Brittle Fracture".
+#include "kernels.hpp"
+
+#include <cmath>
+
+namespace gfem {
+
+namespace {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Deterministic sum over the 256 threads of a workgroup (fixed tree).
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sh[threadIdx.x >> 6] = a;
+    sh[4 + (threadIdx.x >> 6)] = b;
+  }
+  __syncthreads();
+  a = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  b = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+}
+
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sh[threadIdx.x >> 6] = a;
+    sh[4 + (threadIdx.x >> 6)] = b;
+    sh[8 + (threadIdx.x >> 6)] = c;
+  }
+  __syncthreads();
+  a = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  b = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+  c = (sh[8] + sh[9]) + (sh[10] + sh[11]);
+}
+
+// Count lanes of the calling wave with `pred` set; one integer atomic per wave.
+__device__ __forceinline__ void wave_count(int* ctr, bool pred) {
+  unsigned long long bits = __ballot(pred);
+  unsigned long long act = __ballot(1);
+  int leader = __ffsll((long long)act) - 1;
+  if ((int)(threadIdx.x & 63) == leader && bits) atomicAdd(ctr, (int)__popcll(bits));
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Map them so that
+// each XCD owns one contiguous slab of rows: its L2 then holds the vector
+// entries its rows gather.  G must be a multiple of 8.
+__device__ __forceinline__ int xcd_logical(int b, int G) { return (b & 7) * (G >> 3) + (b >> 3); }
+
+template <typename T>
+__device__ __forceinline__ v4<T> ld(const v4<T>* p, int i) {
+  return p[i];
+}
+
+// p_k = z_k + beta p_{k-1}: written once here so that the copy stored by the
+// owning row and the copies formed on the fly by neighbouring rows agree bitwise.
+template <typename T>
+__device__ __forceinline__ v4<T> dir_comb(v4<T> z, T beta, v4<T> p) {
+  v4<T> r;
+  r.x = fmadd(beta, p.x, z.x);
+  r.y = fmadd(beta, p.y, z.y);
+  r.z = fmadd(beta, p.z, z.z);
+  r.w = 0;
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T sym3_det(T a00, T a11, T a22, T a01, T a02, T a12) {
+  return a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) + a02 * (a01 * a12 - a11 * a02);
+}
+
+// Inverse of a symmetric 3x3 from its adjugate, given its determinant.
+template <typename T>
+__device__ __forceinline__ void sym3_inv(const T* a, T det, T* o) {
+  // a: 00,11,22,01,02,12
+  T id = T(1) / det;
+  o[0] = (a[1] * a[2] - a[5] * a[5]) * id;
+  o[1] = (a[0] * a[2] - a[4] * a[4]) * id;
+  o[2] = (a[0] * a[1] - a[3] * a[3]) * id;
+  o[3] = (a[4] * a[5] - a[3] * a[2]) * id;
+  o[4] = (a[3] * a[5] - a[4] * a[1]) * id;
+  o[5] = (a[3] * a[4] - a[0] * a[5]) * id;
+}
+
+template <typename T>
+__device__ __forceinline__ void sym_full(const T* s, T (*f)[3]) {
+  f[0][0] = s[0];
+  f[1][1] = s[1];
+  f[2][2] = s[2];
+  f[0][1] = f[1][0] = s[3];
+  f[0][2] = f[2][0] = s[4];
+  f[1][2] = f[2][1] = s[5];
+}
+
+// 4x4 Gram matrix of the reference barycentric gradients n_a under a
+// symmetric 3x3 bilinear form B (n_0 = -(e1+e2+e3), n_i = e_i):
+// Gam[a][b] = n_a^T B n_b.  With E_k = dG/ds_k = -(n_a n_b^T + n_b n_a^T)/2
+// for local edge k = (a,b), tr(E_k B) = -Gam[a][b].
+template <typename T>
+__device__ __forceinline__ void gram4(const T* s, T (*g)[4]) {
+  T B[3][3];
+  sym_full(s, B);
+  T rs[3];
+  for (int i = 0; i < 3; ++i) rs[i] = B[i][0] + B[i][1] + B[i][2];
+  g[0][0] = rs[0] + rs[1] + rs[2];
+  for (int i = 0; i < 3; ++i) {
+    g[0][i + 1] = g[i + 1][0] = -rs[i];
+    for (int j = 0; j < 3; ++j) g[i + 1][j + 1] = B[i][j];
+  }
+}
+
+// Local edge k joins local nodes EA(k) -> EB(k) (the 12,13,14,23,24,34 order of Eq. 15).
+__device__ __forceinline__ constexpr int EA(int k) { return k < 3 ? 0 : (k < 5 ? 1 : 2); }
+__device__ __forceinline__ constexpr int EB(int k) { return k < 3 ? k + 1 : (k == 3 ? 2 : 3); }
+
+// ---------------------------------------------------------------- damage
+
+// Per edge: Green normal strain along the rest edge, (s - S) / (2 S) with
+// s - S = 2 dX.dU + dU.dU from the displacement (no cancellation of the
+// absolute positions); zeta <- zeta OR (strain >= threshold) (Eq. 21; labels
+// are irreversible, Sec. 3.3).
+__global__ __launch_bounds__(kThreads) void k_damage(int ne, const int2* __restrict__ edges,
+                                                     const d4* __restrict__ X, const d4* __restrict__ U,
+                                                     const double* __restrict__ S,
+                                                     const uint8_t* __restrict__ z_in,
+                                                     uint8_t* __restrict__ z_out, double thr,
+                                                     Counters* ctr) {
+  int e = blockIdx.x * kThreads + threadIdx.x;
+  bool act = e < ne;
+  bool hit = false, was = false, near = false;
+  if (act) {
+    int2 ij = edges[e];
+    d4 xi = X[ij.x], xj = X[ij.y], ui = U[ij.x], uj = U[ij.y];
+    double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+    double ux = uj.x - ui.x, uy = uj.y - ui.y, uz = uj.z - ui.z;
+    double ds = 2.0 * (dx * ux + dy * uy + dz * uz) + (ux * ux + uy * uy + uz * uz);
+    double eps = ds / (2.0 * S[e]);
+    was = z_in[e] != 0;
+    hit = eps >= thr;
+    near = fabs(eps - thr) < 1e-6;
+    z_out[e] = (uint8_t)(was || hit);
+  }
+  wave_count(&ctr->new_broken, act && hit && !was);
+  wave_count(&ctr->total_broken, act && (hit || was));
+  wave_count(&ctr->near_threshold, act && near);
+}
+
+// ---------------------------------------------------------------- element
+
+__constant__ unsigned long long c_disc_lut;  // bit mask set: broken-edge mask disconnects the tet
+
+// One thread per tet.  Kinematics (edge vectors, squared-length changes) in
+// FP64, the rest in T.  Writes, per local edge k, the 3x3 stiffness block
+// K(i,j) in global orientation (i < j) and the force weight w_k = 2 V chi g_k.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restrict__ tets,
+                                                      const int32_t* __restrict__ tet_edge,
+                                                      const uint8_t* __restrict__ flip,
+                                                      const d4* __restrict__ X, const d4* __restrict__ U,
+                                                      const uint8_t* __restrict__ zeta,
+                                                      const T* __restrict__ pl_in, T* __restrict__ pl_out,
+                                                      ElemConst cst, T* __restrict__ contrib,
+                                                      Counters* ctr) {
+  const int t0 = blockIdx.x * kThreads + threadIdx.x;
+  const bool act = t0 < m;
+  const int t = act ? t0 : m - 1;
+  const T mu = (T)cst.mu, lam = (T)cst.lam, am1 = (T)cst.alpha_m1;
+
+  int4 nd = tets[t];
+  d4 Xa[4] = {X[nd.x], X[nd.y], X[nd.z], X[nd.w]};
+  d4 Ua[4] = {U[nd.x], U[nd.y], U[nd.z], U[nd.w]};
+
+  // Rest and current edge vectors; squared lengths S_k and their change ds_k
+  // (Theorem 3.1: the energy is a function of these six lengths).
+  T Dr[6][3], dcur[6][3], S[6], ds[6];
+  double Dsd[3][3];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int a = EA(k), b = EB(k);
+    const double* xa = &Xa[a].x;
+    const double* xb = &Xa[b].x;
+    const double* ua = &Ua[a].x;
+    const double* ub = &Ua[b].x;
+    double D[3], dU[3];
+    for (int d = 0; d < 3; ++d) {
+      D[d] = xb[d] - xa[d];
+      dU[d] = ub[d] - ua[d];
+    }
+    double s0 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+    double dsk = 2.0 * (D[0] * dU[0] + D[1] * dU[1] + D[2] * dU[2]) + (dU[0] * dU[0] + dU[1] * dU[1] + dU[2] * dU[2]);
+    S[k] = (T)s0;
+    ds[k] = (T)dsk;
+    for (int d = 0; d < 3; ++d) {
+      Dr[k][d] = (T)D[d];
+      dcur[k][d] = (T)(D[d] + dU[d]);
+    }
+    if (k < 3)
+      for (int d = 0; d < 3; ++d) Dsd[k][d] = D[d] + dU[d];
+  }
+  // Rest Gram matrix G0 = Dm^T Dm (symmetric: 00,11,22,01,02,12) and its inverse.
+  T G0[6];
+  G0[0] = S[0];
+  G0[1] = S[1];
+  G0[2] = S[2];
+  G0[3] = Dr[0][0] * Dr[1][0] + Dr[0][1] * Dr[1][1] + Dr[0][2] * Dr[1][2];
+  G0[4] = Dr[0][0] * Dr[2][0] + Dr[0][1] * Dr[2][1] + Dr[0][2] * Dr[2][2];
+  G0[5] = Dr[1][0] * Dr[2][0] + Dr[1][1] * Dr[2][1] + Dr[1][2] * Dr[2][2];
+  const T det0 = sym3_det(G0[0], G0[1], G0[2], G0[3], G0[4], G0[5]);
+  T G0i[6];
+  sym3_inv(G0, det0, G0i);
+  // signed rest volume (positive after reorientation)
+  const T Dm[3][3] = {{Dr[0][0], Dr[1][0], Dr[2][0]}, {Dr[0][1], Dr[1][1], Dr[2][1]}, {Dr[0][2], Dr[1][2], Dr[2][2]}};
+  const T detDm = Dm[0][0] * (Dm[1][1] * Dm[2][2] - Dm[1][2] * Dm[2][1]) -
+                  Dm[0][1] * (Dm[1][0] * Dm[2][2] - Dm[1][2] * Dm[2][0]) +
+                  Dm[0][2] * (Dm[1][0] * Dm[2][1] - Dm[1][1] * Dm[2][0]);
+  const T vol = detDm / T(6);
+
+  // Gram change from the squared-length changes by polarisation:
+  // dG_ii = ds_0i, dG_ij = (ds_0i + ds_0j - ds_ij) / 2.
+  T dG[6];
+  dG[0] = ds[0];
+  dG[1] = ds[1];
+  dG[2] = ds[2];
+  dG[3] = T(0.5) * (ds[0] + ds[1] - ds[3]);
+  dG[4] = T(0.5) * (ds[0] + ds[2] - ds[4]);
+  dG[5] = T(0.5) * (ds[1] + ds[2] - ds[5]);
+
+  // Ductile case: additive Green-strain plasticity held as a Gram offset P
+  // (elastic Gram = G - P); instant return of the deviatoric excess.
+  if (pl_in) {
+    T P[6];
+    for (int c = 0; c < 6; ++c) P[c] = pl_in[(size_t)c * m + t];
+    if (cst.yield > 0) {
+    T Di[3][3];  // Dm^-1
+    const T idm = T(1) / detDm;
+    Di[0][0] = (Dm[1][1] * Dm[2][2] - Dm[1][2] * Dm[2][1]) * idm;
+    Di[0][1] = (Dm[0][2] * Dm[2][1] - Dm[0][1] * Dm[2][2]) * idm;
+    Di[0][2] = (Dm[0][1] * Dm[1][2] - Dm[0][2] * Dm[1][1]) * idm;
+    Di[1][0] = (Dm[1][2] * Dm[2][0] - Dm[1][0] * Dm[2][2]) * idm;
+    Di[1][1] = (Dm[0][0] * Dm[2][2] - Dm[0][2] * Dm[2][0]) * idm;
+    Di[1][2] = (Dm[0][2] * Dm[1][0] - Dm[0][0] * Dm[1][2]) * idm;
+    Di[2][0] = (Dm[1][0] * Dm[2][1] - Dm[1][1] * Dm[2][0]) * idm;
+    Di[2][1] = (Dm[0][1] * Dm[2][0] - Dm[0][0] * Dm[2][1]) * idm;
+    Di[2][2] = (Dm[0][0] * Dm[1][1] - Dm[0][1] * Dm[1][0]) * idm;
+    T Q[3][3], Qs[6];
+    for (int c = 0; c < 6; ++c) Qs[c] = dG[c] - P[c];
+    sym_full(Qs, Q);
+    // Ee = 1/2 Dm^-T Q Dm^-1
+    T QD[3][3], Ee[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) QD[i][j] = Q[i][0] * Di[0][j] + Q[i][1] * Di[1][j] + Q[i][2] * Di[2][j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        Ee[i][j] = T(0.5) * (Di[0][i] * QD[0][j] + Di[1][i] * QD[1][j] + Di[2][i] * QD[2][j]);
+    const T tr3 = (Ee[0][0] + Ee[1][1] + Ee[2][2]) / T(3);
+    T dev[3][3];
+    T nrm2 = 0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        dev[i][j] = T(0.5) * (Ee[i][j] + Ee[j][i]) - (i == j ? tr3 : T(0));
+        nrm2 += dev[i][j] * dev[i][j];
+      }
+    const T nrm = sqrt(nrm2);
+    const T ey = (T)cst.yield;
+    if (nrm > ey) {
+      const T fac = T(2) * (T(1) - ey / nrm);
+      // P += 2 fac' Dm^T dev Dm
+      T DvD[3][3], tmp[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) tmp[i][j] = dev[i][0] * Dm[0][j] + dev[i][1] * Dm[1][j] + dev[i][2] * Dm[2][j];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) DvD[i][j] = Dm[0][i] * tmp[0][j] + Dm[1][i] * tmp[1][j] + Dm[2][i] * tmp[2][j];
+      P[0] += fac * DvD[0][0];
+      P[1] += fac * DvD[1][1];
+      P[2] += fac * DvD[2][2];
+      P[3] += fac * T(0.5) * (DvD[0][1] + DvD[1][0]);
+      P[4] += fac * T(0.5) * (DvD[0][2] + DvD[2][0]);
+      P[5] += fac * T(0.5) * (DvD[1][2] + DvD[2][1]);
+    }
+    }
+    if (act && pl_out)
+      for (int c = 0; c < 6; ++c) pl_out[(size_t)c * m + t] = P[c];
+    for (int c = 0; c < 6; ++c) dG[c] -= P[c];
+  }
+
+  // Invariants without cancellation at the stress-free state:
+  //   a = I_C - 3 = tr(dG G0^-1),  J^2 - 1 = det(I + G0^-1 dG) - 1.
+  T A[3][3], B[3][3];
+  sym_full(G0i, A);
+  sym_full(dG, B);
+  T Xm[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Xm[i][j] = A[i][0] * B[0][j] + A[i][1] * B[1][j] + A[i][2] * B[2][j];
+  T aI = Xm[0][0] + Xm[1][1] + Xm[2][2];
+  T trX2 = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) trX2 += Xm[i][j] * Xm[j][i];
+  const T detX = Xm[0][0] * (Xm[1][1] * Xm[2][2] - Xm[1][2] * Xm[2][1]) -
+                 Xm[0][1] * (Xm[1][0] * Xm[2][2] - Xm[1][2] * Xm[2][0]) +
+                 Xm[0][2] * (Xm[1][0] * Xm[2][1] - Xm[1][1] * Xm[2][0]);
+  T jm1 = aI + T(0.5) * (aI * aI - trX2) + detX;
+  // orientation of the current tet (six lengths cannot see inversion)
+  const double detDs = Dsd[0][0] * (Dsd[1][1] * Dsd[2][2] - Dsd[1][2] * Dsd[2][1]) -
+                       Dsd[0][1] * (Dsd[1][0] * Dsd[2][2] - Dsd[1][2] * Dsd[2][0]) +
+                       Dsd[0][2] * (Dsd[1][0] * Dsd[2][1] - Dsd[1][1] * Dsd[2][0]);
+  const bool collapsed = (T(1) + jm1) <= T(1e-12);
+  if (collapsed) {  // evaluated at the rest Gram matrix; such a tet must carry chi = 0
+    for (int c = 0; c < 6; ++c) dG[c] = 0;
+    aI = 0;
+    jm1 = 0;
+  }
+  const T Jsq = T(1) + jm1;
+  T J, delta;
+  if (detDs >= 0.0) {
+    J = sqrt(Jsq);
+    delta = jm1 / (J + T(1));
+  } else {
+    J = -sqrt(Jsq);
+    delta = J - T(1);
+  }
+  T G[6], Gi[6];
+  for (int c = 0; c < 6; ++c) G[c] = G0[c] + dG[c];
+  sym3_inv(G, det0 * Jsq, Gi);
+  // Y = G0^-1 - G^-1 = G^-1 dG G0^-1 (formed as a product, never as the difference)
+  T Ys[6];
+  {
+    T Gf[3][3], M1[3][3], Y[3][3];
+    sym_full(Gi, Gf);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) M1[i][j] = B[i][0] * A[0][j] + B[i][1] * A[1][j] + B[i][2] * A[2][j];
+    if (collapsed)
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M1[i][j] = 0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Y[i][j] = Gf[i][0] * M1[0][j] + Gf[i][1] * M1[1][j] + Gf[i][2] * M1[2][j];
+    Ys[0] = Y[0][0];
+    Ys[1] = Y[1][1];
+    Ys[2] = Y[2][2];
+    Ys[3] = T(0.5) * (Y[0][1] + Y[1][0]);
+    Ys[4] = T(0.5) * (Y[0][2] + Y[2][0]);
+    Ys[5] = T(0.5) * (Y[1][2] + Y[2][1]);
+  }
+  T Gam[4][4], Gam0[4][4], GamY[4][4];
+  gram4(Gi, Gam);
+  gram4(G0i, Gam0);
+  gram4(Ys, GamY);
+
+  // Edge-space gradient of Eq. 35 (squared (J - alpha) term, reparametrised
+  // Lame constants), rewritten so that the rest-state cancellation happens
+  // analytically:  dPsi/ds_k = 3mu/8 t_k + mu a/(8(4+a)) c_k + lam/2 (d(2-alpha)+d^2) v_k
+  // with c_k = tr(E_k G0^-1), v_k = tr(E_k G^-1), t_k = tr(E_k Y) = c_k - v_k.
+  const T IC1 = T(4) + aI;  // I_C + 1
+  const T cmu = mu * aI / (T(8) * IC1);
+  const T dj = delta * (T(1) - am1) + delta * delta;  // (J - alpha) J - (1 - alpha)
+  const T lamt = T(0.5) * lam * dj;
+  T cc[6], vv[6], g[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int a = EA(k), b = EB(k);
+    cc[k] = -Gam0[a][b];
+    vv[k] = -Gam[a][b];
+    const T tk = -GamY[a][b];
+    g[k] = T(0.375) * mu * tk + cmu * cc[k] + lamt * vv[k];
+  }
+
+  // Energy fraction chi (Eq. 22-25): 2nd Piola-Kirchhoff stress projected on
+  // the rest unit edge directions, sigma' = (1 - zeta) sigma; 0 when the
+  // unbroken edges leave the tet in pieces.
+  int mask = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) mask |= (zeta[tet_edge[(size_t)k * m + t]] != 0) << k;
+  T chi = T(1);
+  if (mask) {
+    if ((c_disc_lut >> mask) & 1ull) {
+      chi = T(0);
+    } else {
+      // sigma_k = mu (1 - 1/(I_C+1)) + lam (J - alpha) J w_k, w_k = q^T C^-1 q,
+      // with 1 - w_k = e_k^T G0 Y G0 e_k / S_k (e_k: reference edge)
+      T Yf[3][3], G0f[3][3], GY[3][3], Z[3][3];
+      sym_full(Ys, Yf);
+      sym_full(G0, G0f);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) GY[i][j] = G0f[i][0] * Yf[0][j] + G0f[i][1] * Yf[1][j] + G0f[i][2] * Yf[2][j];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Z[i][j] = GY[i][0] * G0f[0][j] + GY[i][1] * G0f[1][j] + GY[i][2] * G0f[2][j];
+      T num = 0, den = 0;
+      int nub = 0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const int a = EA(k), b = EB(k);
+        T q;
+        if (a == 0)
+          q = Z[b - 1][b - 1];
+        else
+          q = Z[a - 1][a - 1] + Z[b - 1][b - 1] - T(0.5) * (Z[a - 1][b - 1] + Z[b - 1][a - 1]) * T(2);
+        const T omw = q / S[k];
+        const T sig = T(0.75) * mu * omw + mu * aI / (T(4) * IC1) + lam * dj * (T(1) - omw);
+        const T as = fabs(sig);
+        den += as;
+        if (!((mask >> k) & 1)) {
+          num += as;
+          ++nub;
+        }
+      }
+      chi = (den <= T(1e-12) * (mu + lam)) ? T(nub) / T(6) : num / den;
+    }
+  }
+
+  wave_count(&ctr->chi_zero, act && chi == T(0));
+  wave_count(&ctr->degenerate, act && fabs(J) < T(0.05));
+  if (!act) return;
+
+  const size_t m6 = (size_t)6 * m;
+  T* out = contrib + t;
+  if (chi == T(0)) {
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) out[c * m6 + (size_t)k * m] = T(0);
+    return;
+  }
+
+  // Clamped edge Hessian: H = A1 c c^T + A2 v v^T + A3 M, M_kl = tr(G^-1 E_k G^-1 E_l)
+  // = (Gam_ac Gam_bd + Gam_ad Gam_bc)/2; each coefficient clamped at >= 0.
+  const T Vc = vol * chi;
+  const T A1 = T(0.5) * mu / (IC1 * IC1);
+  const T JmA = delta - am1;              // J - alpha
+  const T A2 = fmax(T(0.25) * lam * (T(2) * J - T(1) - am1) * J, T(0));
+  const T A3 = fmax(T(-0.5) * lam * JmA * J, T(0));
+  T H[6][6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+#pragma unroll
+    for (int l = k; l < 6; ++l) {
+      const int a = EA(k), b = EB(k), c = EA(l), d = EB(l);
+      const T Mkl = T(0.5) * (Gam[a][c] * Gam[b][d] + Gam[a][d] * Gam[b][c]);
+      H[k][l] = H[l][k] = A1 * cc[k] * cc[l] + A2 * vv[k] * vv[l] + A3 * Mkl;
+    }
+
+  // Stiffness (Eq. 10, 33): K(a,b) = V chi [ sum_{p at a, q at b} H_pq ds_p/dx_a ds_q/dx_b^T
+  //                                          - 2 max(g_ab, 0) I ],  ds_p/dx = +-2 d_p.
+  // Node incidence: (edge, sign) with sign +1 when the node is the edge's head.
+  constexpr int inc_e[4][3] = {{0, 1, 2}, {0, 3, 4}, {1, 3, 5}, {2, 4, 5}};
+  constexpr int inc_s[4][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {1, 1, 1}};
+  const uint8_t fl = flip[t];
+#pragma unroll
+  for (int b = 1; b < 4; ++b) {
+    T Tb[6][3];
+#pragma unroll
+    for (int p = 0; p < 6; ++p)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        T acc = 0;
+#pragma unroll
+        for (int jq = 0; jq < 3; ++jq) {
+          const int q = inc_e[b][jq];
+          acc += (T)inc_s[b][jq] * H[p][q] * dcur[q][d];
+        }
+        Tb[p][d] = acc;
+      }
+#pragma unroll
+    for (int a = 0; a < b; ++a) {
+      const int k = (a == 0) ? (b - 1) : (a == 1 ? (b == 2 ? 3 : 4) : 5);
+      T Kab[3][3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T acc = 0;
+#pragma unroll
+          for (int jp = 0; jp < 3; ++jp) {
+            const int p = inc_e[a][jp];
+            acc += (T)inc_s[a][jp] * dcur[p][r] * Tb[p][c];
+          }
+          Kab[r][c] = T(4) * Vc * acc;
+        }
+      const T lap = T(2) * Vc * fmax(g[k], T(0));
+      Kab[0][0] -= lap;
+      Kab[1][1] -= lap;
+      Kab[2][2] -= lap;
+      const bool tr = (fl >> k) & 1;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[(size_t)(3 * r + c) * m6 + (size_t)k * m] = tr ? Kab[c][r] : Kab[r][c];
+      out[(size_t)9 * m6 + (size_t)k * m] = T(2) * Vc * g[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- edge pass
+
+// One thread per edge: sum the tets' contributions in slot order (fixed), add
+// the consistent mass, and write A_ij and A_ji = A_ij^T into the block matrix:
+// A_ij = m_ij (1 + dt alpha) I + (dt^2 + dt beta) K_ij.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_edge(int ne, int m6, const int32_t* __restrict__ edge_ptr,
+                                                   const int32_t* __restrict__ edge_slot,
+                                                   const T* __restrict__ contrib,
+                                                   const double* __restrict__ edge_mass, double mass_fac,
+                                                   double stiff_fac, const int32_t* __restrict__ blk_ij,
+                                                   const int32_t* __restrict__ blk_ji, T* __restrict__ val,
+                                                   int nbp, T* __restrict__ edge_w) {
+  int e = blockIdx.x * kThreads + threadIdx.x;
+  if (e >= ne) return;
+  T acc[10];
+#pragma unroll
+  for (int c = 0; c < 10; ++c) acc[c] = 0;
+  const int s0 = edge_ptr[e], s1 = edge_ptr[e + 1];
+  for (int s = s0; s < s1; ++s) {
+    const int idx = edge_slot[s];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) acc[c] += contrib[(size_t)c * m6 + idx];
+  }
+  const double md = edge_mass[e] * mass_fac;
+  const int bij = blk_ij[e], bji = blk_ji[e];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T v = (T)(stiff_fac * (double)acc[3 * r + c] + (r == c ? md : 0.0));
+      val[(size_t)(3 * r + c) * nbp + bij] = v;
+      val[(size_t)(3 * c + r) * nbp + bji] = v;
+    }
+  edge_w[e] = acc[9];
+}
+
+// ---------------------------------------------------------------- row pass
+
+// One thread per node (block row i):
+//   A_ii = (1 + dt alpha) m_i I - sum_j A_ij   (translation invariance of K)
+//   f_i  = sum_j w_ij (x_j - x_i)              (Eq. 12: forces along edges)
+//   b_i  = dt (m_i g + f_i) - dt alpha (M v)_i - sum_j (A_ij - m_ij (1 + dt alpha) I)(v_j - v_i)
+// then Dirichlet elimination (b_f -= A_fc dv_c; rows/columns of c -> identity),
+// block-Jacobi inverse of A_ii, X64 = 0 and the partial |b|^2.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32_t* __restrict__ diag_blk,
+                                                  const int32_t* __restrict__ blk_edge,
+                                                  const double* __restrict__ edge_mass,
+                                                  const T* __restrict__ edge_w, const double* __restrict__ lumped,
+                                                  const d4* __restrict__ X, const d4* __restrict__ U,
+                                                  const d4* __restrict__ V, const uint8_t* __restrict__ dflag,
+                                                  const d4* __restrict__ dvel, RowConst cst, T* __restrict__ val,
+                                                  d4* __restrict__ bvec, d4* __restrict__ X64,
+                                                  T* __restrict__ binv, d4* __restrict__ f_out,
+                                                  double* __restrict__ part_bb) {
+  __shared__ double sh[16];
+  const int G = gridDim.x;
+  const int L = xcd_logical(blockIdx.x, G);
+  const int chunk = (n + G - 1) / G;
+  const int r0 = L * chunk, r1 = min(n, r0 + chunk);
+  const int nbp = Am.nbp;
+  double bb = 0;
+  for (int i = r0 + threadIdx.x; i < r1; i += kThreads) {
+    const int s = Am.row_ptr[i], e = Am.row_ptr[i + 1], db = diag_blk[i];
+    const d4 Xi = X[i], Ui = U[i], vi = V[i];
+    const bool ci = dflag[i] != 0;
+    double f[3] = {0, 0, 0}, kv[3] = {0, 0, 0}, mv[3] = {0, 0, 0}, bd[3] = {0, 0, 0};
+    double As[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double msum = 0;
+    for (int b = s; b < e; ++b) {
+      if (b == db) continue;
+      const int j = Am.col[b];
+      const int ed = blk_edge[b];
+      const double me = edge_mass[ed];
+      const double w = (double)edge_w[ed];
+      const d4 Xj = X[j], Uj = U[j], vj = V[j];
+      const double dx[3] = {(Xj.x - Xi.x) + (Uj.x - Ui.x), (Xj.y - Xi.y) + (Uj.y - Ui.y),
+                            (Xj.z - Xi.z) + (Uj.z - Ui.z)};
+      const double dv[3] = {vj.x - vi.x, vj.y - vi.y, vj.z - vi.z};
+      double a[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        a[c] = (double)val[(size_t)c * nbp + b];
+        As[c] += a[c];
+      }
+      msum += me;
+      const double mf = me * cst.mass_fac;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        f[r] += w * dx[r];
+        double acc = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc += (a[3 * r + c] - (r == c ? mf : 0.0)) * dv[c];
+        kv[r] += acc;
+      }
+      mv[0] += me * vj.x;
+      mv[1] += me * vj.y;
+      mv[2] += me * vj.z;
+      if (dflag[j]) {
+        const d4 pj = dvel[j];
+        const double dvc[3] = {pj.x - vj.x, pj.y - vj.y, pj.z - vj.z};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) bd[r] += a[3 * r] * dvc[0] + a[3 * r + 1] * dvc[1] + a[3 * r + 2] * dvc[2];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) val[(size_t)c * nbp + b] = T(0);
+      } else if (ci) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) val[(size_t)c * nbp + b] = T(0);
+      }
+    }
+    const double mi = lumped[i];
+    const double mii = mi - msum;
+    mv[0] += mii * vi.x;
+    mv[1] += mii * vi.y;
+    mv[2] += mii * vi.z;
+    const double vi3[3] = {vi.x, vi.y, vi.z};
+    double Aii[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Aii[3 * r + c] = (r == c ? cst.mass_fac * mi : 0.0) - As[3 * r + c];
+    double bi[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      bi[r] = cst.dt * (mi * cst.g[r] + f[r]) - cst.dt * cst.ra * mv[r] - kv[r] - bd[r];
+    if (f_out) f_out[i] = d4{f[0], f[1], f[2], 0.0};
+    if (ci) {
+      const d4 pv = dvel[i];
+      bi[0] = pv.x - vi3[0];
+      bi[1] = pv.y - vi3[1];
+      bi[2] = pv.z - vi3[2];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) Aii[c] = (c % 4 == 0) ? 1.0 : 0.0;
+    }
+    // symmetric part of the diagonal block (exactly symmetric up to rounding)
+    const double s01 = 0.5 * (Aii[1] + Aii[3]), s02 = 0.5 * (Aii[2] + Aii[6]), s12 = 0.5 * (Aii[5] + Aii[7]);
+    Aii[1] = Aii[3] = s01;
+    Aii[2] = Aii[6] = s02;
+    Aii[5] = Aii[7] = s12;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) val[(size_t)c * nbp + db] = (T)Aii[c];
+    const double sd[6] = {Aii[0], Aii[4], Aii[8], s01, s02, s12};
+    const double det = sym3_det(sd[0], sd[1], sd[2], sd[3], sd[4], sd[5]);
+    double inv[6];
+    sym3_inv(sd, det, inv);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) binv[(size_t)c * n + i] = (T)inv[c];
+    bvec[i] = d4{bi[0], bi[1], bi[2], 0.0};
+    X64[i] = d4{0.0, 0.0, 0.0, 0.0};
+    bb += bi[0] * bi[0] + bi[1] * bi[1] + bi[2] * bi[2];
+  }
+  bb = block_sum(bb, sh);
+  if (threadIdx.x == 0) part_bb[L] = bb;
+}
+
+// ---------------------------------------------------------------- PCG
+
+template <typename T>
+__device__ __forceinline__ v4<T> bj_apply(const T* __restrict__ binv, int n, int i, v4<T> r) {
+  const T b00 = binv[i], b11 = binv[(size_t)n + i], b22 = binv[2 * (size_t)n + i];
+  const T b01 = binv[3 * (size_t)n + i], b02 = binv[4 * (size_t)n + i], b12 = binv[5 * (size_t)n + i];
+  v4<T> z;
+  z.x = b00 * r.x + b01 * r.y + b02 * r.z;
+  z.y = b01 * r.x + b11 * r.y + b12 * r.z;
+  z.z = b02 * r.x + b12 * r.y + b22 * r.z;
+  z.w = 0;
+  return z;
+}
+
+// r = src (rounded to T), z = B r, p_0 = z, x = 0; partials of r.z and r.r.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pcg_init(int n, const d4* __restrict__ src,
+                                                       const T* __restrict__ binv, v4<T>* __restrict__ r,
+                                                       v4<T>* __restrict__ z, v4<T>* __restrict__ p0,
+                                                       v4<T>* __restrict__ x, double* __restrict__ part_rz) {
+  __shared__ double sh[16];
+  const int G = gridDim.x;
+  const int L = xcd_logical(blockIdx.x, G);
+  const int chunk = (n + G - 1) / G;
+  const int r0 = L * chunk, r1 = min(n, r0 + chunk);
+  double rz = 0, rr = 0;
+  for (int i = r0 + threadIdx.x; i < r1; i += kThreads) {
+    const d4 s = src[i];
+    v4<T> ri{(T)s.x, (T)s.y, (T)s.z, T(0)};
+    v4<T> zi = bj_apply(binv, n, i, ri);
+    r[i] = ri;
+    z[i] = zi;
+    p0[i] = zi;
+    x[i] = v4<T>{T(0), T(0), T(0), T(0)};
+    rz += (double)ri.x * zi.x + (double)ri.y * zi.y + (double)ri.z * zi.z;
+    rr += (double)ri.x * ri.x + (double)ri.y * ri.y + (double)ri.z * ri.z;
+  }
+  block_sum2(rz, rr, sh);
+  if (threadIdx.x == 0) {
+    part_rz[L] = rz;
+    part_rz[kMaxPart + L] = rr;
+  }
+}
+
+// Iteration k, first kernel.  Reduces r_k.z_k and r_k.r_k (and r_{k-1}.z_{k-1}),
+// stops when |r_k|^2 <= thr2, else forms p_k = z_k + beta_k p_{k-1} into p_new
+// (k > 0; for k = 0, p_new already holds p_0 = z_0 and is only read),
+// q = A p_k (FP32 or FP64 block matrix, 16 lanes per block row) and the
+// partial p_k.q (FP64).
+template <typename T, bool DIR>
+__global__ __launch_bounds__(kThreads) void k_pcg_spmv(int k, int Gv, MatView Am, const v4<T>* __restrict__ z,
+                                                       const v4<T>* __restrict__ p_old,
+                                                       v4<T>* __restrict__ p_new, v4<T>* __restrict__ q,
+                                                       PcgCtl* ctl, const double* __restrict__ part_rz,
+                                                       double* __restrict__ part_pq, double thr2) {
+  __shared__ double sh[16];
+  if (ctl->done) return;
+  const double* cur = part_rz + (size_t)(k & 1) * 2 * kMaxPart;
+  const double* prv = part_rz + (size_t)((k + 1) & 1) * 2 * kMaxPart;
+  double rz = 0, rr = 0, rzp = 0;
+  for (int i = threadIdx.x; i < Gv; i += kThreads) {
+    rz += cur[i];
+    rr += cur[kMaxPart + i];
+    if (DIR) rzp += prv[i];
+  }
+  block_sum3(rz, rr, rzp, sh);
+  if (!(rr > thr2) || rz == 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->done = 1;
+    return;
+  }
+  const T beta = DIR ? (T)(rz / rzp) : T(0);
+  const int n = Am.n, nbp = Am.nbp;
+  const int G = gridDim.x;
+  const int L = xcd_logical(blockIdx.x, G);
+  const int chunk = (n + G - 1) / G;
+  const int r0 = L * chunk, r1 = min(n, r0 + chunk);
+  const int lane = threadIdx.x & (kRowLanes - 1);
+  const int grp = threadIdx.x / kRowLanes;
+  const T* __restrict__ val = static_cast<const T*>(Am.val);
+  double dot = 0;
+  for (int row = r0 + grp; row < r1; row += kThreads / kRowLanes) {
+    const int s = Am.row_ptr[row], e = Am.row_ptr[row + 1];
+    T ax = 0, ay = 0, az = 0;
+    for (int b = s + lane; b < e; b += kRowLanes) {
+      const int j = Am.col[b];
+      const v4<T> pj = DIR ? dir_comb(z[j], beta, p_old[j]) : p_new[j];
+      const T a0 = val[b], a1 = val[(size_t)nbp + b], a2 = val[2 * (size_t)nbp + b];
+      const T a3 = val[3 * (size_t)nbp + b], a4 = val[4 * (size_t)nbp + b], a5 = val[5 * (size_t)nbp + b];
+      const T a6 = val[6 * (size_t)nbp + b], a7 = val[7 * (size_t)nbp + b], a8 = val[8 * (size_t)nbp + b];
+      ax = fmadd(a0, pj.x, fmadd(a1, pj.y, fmadd(a2, pj.z, ax)));
+      ay = fmadd(a3, pj.x, fmadd(a4, pj.y, fmadd(a5, pj.z, ay)));
+      az = fmadd(a6, pj.x, fmadd(a7, pj.y, fmadd(a8, pj.z, az)));
+    }
+#pragma unroll
+    for (int o = kRowLanes / 2; o > 0; o >>= 1) {
+      ax += __shfl_xor(ax, o, kRowLanes);
+      ay += __shfl_xor(ay, o, kRowLanes);
+      az += __shfl_xor(az, o, kRowLanes);
+    }
+    if (lane == 0) {
+      const v4<T> pi = DIR ? dir_comb(z[row], beta, p_old[row]) : p_new[row];
+      if (DIR) p_new[row] = pi;
+      q[row] = v4<T>{ax, ay, az, T(0)};
+      dot += (double)pi.x * ax + (double)pi.y * ay + (double)pi.z * az;
+    }
+  }
+  dot = block_sum(dot, sh);
+  if (threadIdx.x == 0) part_pq[L] = dot;
+}
+
+// Iteration k, second kernel: alpha = r.z / p.q; x += alpha p; r -= alpha q;
+// z = B r; partials of r.z and r.r for iteration k+1.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pcg_update(int k, int n, int Gs, const v4<T>* __restrict__ p,
+                                                         const v4<T>* __restrict__ q, v4<T>* __restrict__ x,
+                                                         v4<T>* __restrict__ r, v4<T>* __restrict__ z,
+                                                         const T* __restrict__ binv, PcgCtl* ctl,
+                                                         const double* __restrict__ part_pq,
+                                                         double* __restrict__ part_rz) {
+  __shared__ double sh[16];
+  if (ctl->done) return;
+  const int G = gridDim.x;
+  const double* cur = part_rz + (size_t)(k & 1) * 2 * kMaxPart;
+  double pq = 0, rz = 0;
+  for (int i = threadIdx.x; i < Gs; i += kThreads) pq += part_pq[i];
+  for (int i = threadIdx.x; i < G; i += kThreads) rz += cur[i];
+  block_sum2(pq, rz, sh);
+  if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctl->fail = 1;
+      ctl->done = 1;
+    }
+    return;
+  }
+  const T al = (T)(rz / pq);
+  const int L = xcd_logical(blockIdx.x, G);
+  const int chunk = (n + G - 1) / G;
+  const int r0 = L * chunk, r1 = min(n, r0 + chunk);
+  double rzn = 0, rrn = 0;
+  for (int i = r0 + threadIdx.x; i < r1; i += kThreads) {
+    const v4<T> pi = p[i], qi = q[i];
+    v4<T> xi = x[i], ri = r[i];
+    xi.x = fmadd(al, pi.x, xi.x);
+    xi.y = fmadd(al, pi.y, xi.y);
+    xi.z = fmadd(al, pi.z, xi.z);
+    ri.x = fmadd(-al, qi.x, ri.x);
+    ri.y = fmadd(-al, qi.y, ri.y);
+    ri.z = fmadd(-al, qi.z, ri.z);
+    const v4<T> zi = bj_apply(binv, n, i, ri);
+    x[i] = xi;
+    r[i] = ri;
+    z[i] = zi;
+    rzn += (double)ri.x * zi.x + (double)ri.y * zi.y + (double)ri.z * zi.z;
+    rrn += (double)ri.x * ri.x + (double)ri.y * ri.y + (double)ri.z * ri.z;
+  }
+  block_sum2(rzn, rrn, sh);
+  double* nxt = part_rz + (size_t)((k + 1) & 1) * 2 * kMaxPart;
+  if (threadIdx.x == 0) {
+    nxt[L] = rzn;
+    nxt[kMaxPart + L] = rrn;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->iters = k + 1;
+}
+
+// FP64 residual of the outer (iterative refinement) loop: R = b - A X64 with
+// the stored (FP32 or FP64) block values promoted to FP64; partial |R|^2.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_resid(MatView Am, const d4* __restrict__ bvec,
+                                                    const d4* __restrict__ X64, d4* __restrict__ R64,
+                                                    double* __restrict__ part_rr) {
+  __shared__ double sh[16];
+  const int n = Am.n, nbp = Am.nbp;
+  const int G = gridDim.x;
+  const int L = xcd_logical(blockIdx.x, G);
+  const int chunk = (n + G - 1) / G;
+  const int r0 = L * chunk, r1 = min(n, r0 + chunk);
+  const int lane = threadIdx.x & (kRowLanes - 1);
+  const int grp = threadIdx.x / kRowLanes;
+  const T* __restrict__ val = static_cast<const T*>(Am.val);
+  double rr = 0;
+  for (int row = r0 + grp; row < r1; row += kThreads / kRowLanes) {
+    const int s = Am.row_ptr[row], e = Am.row_ptr[row + 1];
+    double ax = 0, ay = 0, az = 0;
+    for (int b = s + lane; b < e; b += kRowLanes) {
+      const int j = Am.col[b];
+      const d4 xj = X64[j];
+      double a[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) a[c] = (double)val[(size_t)c * nbp + b];
+      ax = fmadd(a[0], xj.x, fmadd(a[1], xj.y, fmadd(a[2], xj.z, ax)));
+      ay = fmadd(a[3], xj.x, fmadd(a[4], xj.y, fmadd(a[5], xj.z, ay)));
+      az = fmadd(a[6], xj.x, fmadd(a[7], xj.y, fmadd(a[8], xj.z, az)));
+    }
+#pragma unroll
+    for (int o = kRowLanes / 2; o > 0; o >>= 1) {
+      ax += __shfl_xor(ax, o, kRowLanes);
+      ay += __shfl_xor(ay, o, kRowLanes);
+      az += __shfl_xor(az, o, kRowLanes);
+    }
+    if (lane == 0) {
+      const d4 bi = bvec[row];
+      const d4 ri{bi.x - ax, bi.y - ay, bi.z - az, 0.0};
+      R64[row] = ri;
+      rr += ri.x * ri.x + ri.y * ri.y + ri.z * ri.z;
+    }
+  }
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) part_rr[L] = rr;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_addcorr(int n, const v4<T>* __restrict__ x, d4* __restrict__ X64) {
+  int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const v4<T> xi = x[i];
+  d4 X = X64[i];
+  X.x += (double)xi.x;
+  X.y += (double)xi.y;
+  X.z += (double)xi.z;
+  X64[i] = X;
+}
+
+// v <- v + dv (prescribed nodes: exactly the prescribed velocity); U <- U + dt v.
+__global__ __launch_bounds__(kThreads) void k_integrate(int n, const d4* __restrict__ X64, d4* __restrict__ V,
+                                                        d4* __restrict__ U, const uint8_t* __restrict__ dflag,
+                                                        const d4* __restrict__ dvel, double dt) {
+  int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  d4 v = V[i];
+  if (dflag[i]) {
+    const d4 p = dvel[i];
+    v = d4{p.x, p.y, p.z, 0.0};
+  } else {
+    const d4 d = X64[i];
+    v.x += d.x;
+    v.y += d.y;
+    v.z += d.z;
+  }
+  V[i] = v;
+  d4 u = U[i];
+  u.x += dt * v.x;
+  u.y += dt * v.y;
+  u.z += dt * v.z;
+  U[i] = u;
+}
+
+inline int blocks_for(long n) { return (int)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+void set_disconnected_lut(unsigned long long lut) {
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_disc_lut), &lut, sizeof lut);
+}
+
+void launch_damage(hipStream_t s, int ne, const int2* edges, const d4* X, const d4* U, const double* S,
+                   const uint8_t* z_in, uint8_t* z_out, double thr, Counters* ctr) {
+  if (ne <= 0) return;
+  k_damage<<<blocks_for(ne), kThreads, 0, s>>>(ne, edges, X, U, S, z_in, z_out, thr, ctr);
+}
+
+template <typename T>
+void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_edge, const uint8_t* flip,
+                    const d4* X, const d4* U, const uint8_t* zeta, const T* pl_in, T* pl_out, ElemConst c,
+                    T* contrib, Counters* ctr) {
+  k_element<T><<<blocks_for(m), kThreads, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta, pl_in, pl_out, c,
+                                                  contrib, ctr);
+}
+
+template <typename T>
+void launch_edge(hipStream_t s, int ne, int m, const int32_t* edge_ptr, const int32_t* edge_slot,
+                 const T* contrib, const double* edge_mass, double mass_fac, double stiff_fac,
+                 const int32_t* blk_ij, const int32_t* blk_ji, T* val, int nbp, T* edge_w) {
+  k_edge<T><<<blocks_for(ne), kThreads, 0, s>>>(ne, 6 * m, edge_ptr, edge_slot, contrib, edge_mass, mass_fac,
+                                               stiff_fac, blk_ij, blk_ji, val, nbp, edge_w);
+}
+
+template <typename T>
+void launch_row(hipStream_t s, int n, int G, MatView A, const int32_t* diag_blk, const int32_t* blk_edge,
+                const double* edge_mass, const T* edge_w, const double* lumped, const d4* X, const d4* U,
+                const d4* V, const uint8_t* dflag, const d4* dvel, RowConst c, T* val_mut, d4* b, d4* X64,
+                T* binv, d4* f_out, double* part_bb) {
+  k_row<T><<<G, kThreads, 0, s>>>(n, A, diag_blk, blk_edge, edge_mass, edge_w, lumped, X, U, V, dflag, dvel, c,
+                                  val_mut, b, X64, binv, f_out, part_bb);
+}
+
+template <typename T>
+void launch_pcg_init(hipStream_t s, int n, int G, const d4* src, const T* binv, v4<T>* r, v4<T>* z, v4<T>* p0,
+                     v4<T>* x, double* part_rz0) {
+  k_pcg_init<T><<<G, kThreads, 0, s>>>(n, src, binv, r, z, p0, x, part_rz0);
+}
+
+template <typename T>
+void launch_pcg_spmv(hipStream_t s, int k, int Gs, int Gv, MatView A, const v4<T>* z, const v4<T>* p_old,
+                     v4<T>* p_new, v4<T>* q, PcgCtl* ctl, const double* part_rz, double* part_pq, double thr2) {
+  if (k == 0)
+    k_pcg_spmv<T, false><<<Gs, kThreads, 0, s>>>(k, Gv, A, z, p_old, p_new, q, ctl, part_rz, part_pq, thr2);
+  else
+    k_pcg_spmv<T, true><<<Gs, kThreads, 0, s>>>(k, Gv, A, z, p_old, p_new, q, ctl, part_rz, part_pq, thr2);
+}
+
+template <typename T>
+void launch_pcg_update(hipStream_t s, int k, int n, int Gv, int Gs, const v4<T>* p, const v4<T>* q, v4<T>* x,
+                       v4<T>* r, v4<T>* z, const T* binv, PcgCtl* ctl, const double* part_pq, double* part_rz) {
+  k_pcg_update<T><<<Gv, kThreads, 0, s>>>(k, n, Gs, p, q, x, r, z, binv, ctl, part_pq, part_rz);
+}
+
+template <typename T>
+void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, d4* R64, double* part_rr) {
+  k_resid<T><<<Gs, kThreads, 0, s>>>(A, b, X64, R64, part_rr);
+}
+
+template <typename T>
+void launch_addcorr(hipStream_t s, int n, int, const v4<T>* x, d4* X64) {
+  k_addcorr<T><<<blocks_for(n), kThreads, 0, s>>>(n, x, X64);
+}
+
+void launch_integrate(hipStream_t s, int n, const d4* X64, d4* V, d4* U, const uint8_t* dflag, const d4* dvel,
+                      double dt) {
+  k_integrate<<<blocks_for(n), kThreads, 0, s>>>(n, X64, V, U, dflag, dvel, dt);
+}
+
+#define GFEM_INST(T)                                                                                         \
+  template void launch_element<T>(hipStream_t, int, const int4*, const int32_t*, const uint8_t*, const d4*,  \
+                                  const d4*, const uint8_t*, const T*, T*, ElemConst, T*, Counters*);        \
+  template void launch_edge<T>(hipStream_t, int, int, const int32_t*, const int32_t*, const T*,              \
+                               const double*, double, double, const int32_t*, const int32_t*, T*, int, T*);  \
+  template void launch_row<T>(hipStream_t, int, int, MatView, const int32_t*, const int32_t*, const double*, \
+                              const T*, const double*, const d4*, const d4*, const d4*, const uint8_t*,      \
+                              const d4*, RowConst, T*, d4*, d4*, T*, d4*, double*);                          \
+  template void launch_pcg_init<T>(hipStream_t, int, int, const d4*, const T*, v4<T>*, v4<T>*, v4<T>*,      \
+                                   v4<T>*, double*);                                                         \
+  template void launch_pcg_spmv<T>(hipStream_t, int, int, int, MatView, const v4<T>*, const v4<T>*, v4<T>*, \
+                                   v4<T>*, PcgCtl*, const double*, double*, double);                        \
+  template void launch_pcg_update<T>(hipStream_t, int, int, int, int, const v4<T>*, const v4<T>*, v4<T>*,   \
+                                     v4<T>*, v4<T>*, const T*, PcgCtl*, const double*, double*);            \
+  template void launch_resid<T>(hipStream_t, int, MatView, const d4*, const d4*, d4*, double*);             \
+  template void launch_addcorr<T>(hipStream_t, int, int, const v4<T>*, d4*);
+
+GFEM_INST(float)
+GFEM_INST(double)
+
+}  // namespace gfem

@@ -1,0 +1,110 @@
+// Device kernels of the graph-based FEM step (gfx950, wave64).
+//
+// Data layout in HBM (internal node order):
+//   node vectors   : v4<double> / v4<T> records (x, y, z, pad) -> one 32 B or 16 B load per gather
+//   tets           : int4 node ids; tet_edge SoA [6][m]; flip bits [m]
+//   block matrix   : BSR 3x3, values SoA [9][nbp] (component-major, so the
+//                    lanes of a wave read consecutive blocks with unit stride)
+//   contributions  : SoA [10][6][m] (9 block entries + 1 force weight per
+//                    tet edge), written coalesced by the element pass and
+//                    gathered per edge by the edge pass
+// No floating-point atomics anywhere: every sum has a fixed order, so a step
+// is bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gfem {
+
+template <typename T>
+struct alignas(4 * sizeof(T)) v4 {
+  T x, y, z, w;
+};
+using d4 = v4<double>;
+
+constexpr int kThreads = 256;     // 4 waves of 64
+constexpr int kMaxPart = 1024;    // max workgroups that leave a reduction partial
+constexpr int kRowLanes = 16;     // lanes cooperating on one block row in the SpMV
+
+struct PcgCtl {
+  int done;   // set once converged or broken down; every later PCG kernel exits at entry
+  int fail;   // 1: p.Ap <= 0 (operator not SPD on the Krylov space)
+  int iters;  // iterations completed (x holds x_iters)
+  int pad;
+};
+
+struct MatView {
+  int n, nbp;
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const void* val;  // T[9][nbp]
+};
+
+struct Counters {
+  int new_broken, total_broken, near_threshold, chi_zero, degenerate, pad[3];
+};
+
+struct ElemConst {
+  double mu, lam, alpha_m1;  // mu', lambda', alpha - 1 (Eq. 35 with the reparametrised constants)
+  double yield;              // <= 0: no plasticity
+};
+
+// 64-bit table: bit `mask` set when that broken-edge mask leaves the tet's
+// unbroken edges disconnected (chi = 0).  Uploaded once per process.
+void set_disconnected_lut(unsigned long long lut);
+
+// Launch helpers (defined in kernels.hip).  All are asynchronous on `s`.
+void launch_damage(hipStream_t s, int ne, const int2* edges, const d4* X, const d4* U,
+                   const double* S, const uint8_t* z_in, uint8_t* z_out, double thr,
+                   Counters* ctr);
+
+template <typename T>
+void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_edge,
+                    const uint8_t* flip, const d4* X, const d4* U, const uint8_t* zeta,
+                    const T* pl_in, T* pl_out, ElemConst c, T* contrib, Counters* ctr);
+
+template <typename T>
+void launch_edge(hipStream_t s, int ne, int m, const int32_t* edge_ptr, const int32_t* edge_slot,
+                 const T* contrib, const double* edge_mass, double mass_fac, double stiff_fac,
+                 const int32_t* blk_ij, const int32_t* blk_ji, T* val, int nbp, T* edge_w);
+
+struct RowConst {
+  double dt, ra;      // dt, Rayleigh alpha
+  double mass_fac;    // 1 + dt * alpha
+  double g[3];
+};
+
+template <typename T>
+void launch_row(hipStream_t s, int n, int G, MatView A, const int32_t* diag_blk,
+                const int32_t* blk_edge, const double* edge_mass, const T* edge_w,
+                const double* lumped, const d4* X, const d4* U, const d4* V,
+                const uint8_t* dflag, const d4* dvel, RowConst c, T* val_mut, d4* b,
+                d4* X64, T* binv, d4* f_out, double* part_bb);
+
+template <typename T>
+void launch_pcg_init(hipStream_t s, int n, int G, const d4* src, const T* binv, v4<T>* r,
+                     v4<T>* z, v4<T>* p0, v4<T>* x, double* part_rz0);
+
+template <typename T>
+void launch_pcg_spmv(hipStream_t s, int k, int Gs, int Gv, MatView A, const v4<T>* z,
+                     const v4<T>* p_old, v4<T>* p_new, v4<T>* q, PcgCtl* ctl,
+                     const double* part_rz, double* part_pq, double thr2);
+
+template <typename T>
+void launch_pcg_update(hipStream_t s, int k, int n, int Gv, int Gs, const v4<T>* p,
+                       const v4<T>* q, v4<T>* x, v4<T>* r, v4<T>* z, const T* binv, PcgCtl* ctl,
+                       const double* part_pq, double* part_rz);
+
+template <typename T>
+void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, d4* R64,
+                  double* part_rr);
+
+template <typename T>
+void launch_addcorr(hipStream_t s, int n, int G, const v4<T>* x, d4* X64);
+
+void launch_integrate(hipStream_t s, int n, const d4* X64, d4* V, d4* U, const uint8_t* dflag,
+                      const d4* dvel, double dt);
+
+}  // namespace gfem

@@ -1,0 +1,208 @@
+// Host-side topology construction (see topo.hpp).
+#include "topo.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <numeric>
+
+namespace gfem {
+
+namespace {
+
+double det3(const double* a, const double* b, const double* c) {
+  return a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+         a[2] * (b[0] * c[1] - b[1] * c[0]);
+}
+
+}  // namespace
+
+std::string build_topology(const double* xyz, int n, const int32_t* tets_in, int m, double density,
+                           Topology* out, bool* degenerate) {
+  *degenerate = false;
+  Topology& T = *out;
+  if (n <= 0 || m <= 0) return "n_nodes and n_tets must be positive";
+  for (int i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(xyz[i])) return "non-finite rest coordinate";
+  T.n = n;
+  T.m = m;
+
+  // Node numbering (identity: the caller's order is kept internally).
+  T.perm_new.resize(n);
+  T.perm_old.resize(n);
+  std::iota(T.perm_new.begin(), T.perm_new.end(), 0);
+  std::iota(T.perm_old.begin(), T.perm_old.end(), 0);
+  T.X.resize(3 * (size_t)n);
+  for (int i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) T.X[3 * (size_t)T.perm_new[i] + d] = xyz[3 * (size_t)i + d];
+
+  // Validate ids, reorient negative tets (swap local nodes 2 and 3), reject flat ones.
+  T.tets.resize(4 * (size_t)m);
+  T.vol.resize(m);
+  T.reoriented = 0;
+  for (int t = 0; t < m; ++t) {
+    int v[4];
+    for (int a = 0; a < 4; ++a) {
+      int id = tets_in[4 * (size_t)t + a];
+      if (id < 0 || id >= n) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "tet %d references node %d outside [0,%d)", t, id, n);
+        return buf;
+      }
+      v[a] = T.perm_new[id];
+    }
+    if (v[0] == v[1] || v[0] == v[2] || v[0] == v[3] || v[1] == v[2] || v[1] == v[3] || v[2] == v[3]) {
+      *degenerate = true;
+      char buf[96];
+      snprintf(buf, sizeof buf, "tet %d repeats a node", t);
+      return buf;
+    }
+    double e[3][3];
+    double lmax = 0.0;
+    for (int i = 1; i < 4; ++i)
+      for (int d = 0; d < 3; ++d) e[i - 1][d] = T.X[3 * (size_t)v[i] + d] - T.X[3 * (size_t)v[0] + d];
+    for (int k = 0; k < 6; ++k) {
+      double s = 0;
+      for (int d = 0; d < 3; ++d) {
+        double q = T.X[3 * (size_t)v[kEdgeB[k]] + d] - T.X[3 * (size_t)v[kEdgeA[k]] + d];
+        s += q * q;
+      }
+      lmax = std::max(lmax, std::sqrt(s));
+    }
+    double vol6 = det3(e[0], e[1], e[2]);
+    if (std::fabs(vol6 / 6.0) <= 1e-14 * lmax * lmax * lmax) {
+      *degenerate = true;
+      char buf[96];
+      snprintf(buf, sizeof buf, "tet %d has (near) zero volume", t);
+      return buf;
+    }
+    if (vol6 < 0) {
+      std::swap(v[2], v[3]);
+      vol6 = -vol6;
+      ++T.reoriented;
+    }
+    T.vol[t] = vol6 / 6.0;
+    for (int a = 0; a < 4; ++a) T.tets[4 * (size_t)t + a] = v[a];
+  }
+
+  // Unique edges: sort the 6m (min, max, slot) records.
+  struct Rec {
+    int32_t i, j, t, k;
+  };
+  std::vector<Rec> rec(6 * (size_t)m);
+  for (int t = 0; t < m; ++t)
+    for (int k = 0; k < 6; ++k) {
+      int a = T.tets[4 * (size_t)t + kEdgeA[k]], b = T.tets[4 * (size_t)t + kEdgeB[k]];
+      rec[6 * (size_t)t + k] = {std::min(a, b), std::max(a, b), t, k};
+    }
+  std::sort(rec.begin(), rec.end(), [](const Rec& x, const Rec& y) {
+    if (x.i != y.i) return x.i < y.i;
+    if (x.j != y.j) return x.j < y.j;
+    if (x.t != y.t) return x.t < y.t;
+    return x.k < y.k;
+  });
+  T.tet_edge.assign(6 * (size_t)m, -1);
+  T.tet_flip.assign(m, 0);
+  T.edge_slot.resize(6 * (size_t)m);
+  T.edges.clear();
+  T.edge_ptr.clear();
+  for (size_t r = 0; r < rec.size(); ++r) {
+    if (r == 0 || rec[r].i != rec[r - 1].i || rec[r].j != rec[r - 1].j) {
+      T.edge_ptr.push_back((int32_t)r);
+      T.edges.push_back(rec[r].i);
+      T.edges.push_back(rec[r].j);
+    }
+    int e = (int)T.edge_ptr.size() - 1;
+    const Rec& q = rec[r];
+    T.tet_edge[(size_t)q.k * m + q.t] = e;
+    T.edge_slot[r] = q.k * m + q.t;
+    if (T.tets[4 * (size_t)q.t + kEdgeA[q.k]] > T.tets[4 * (size_t)q.t + kEdgeB[q.k]])
+      T.tet_flip[q.t] |= (uint8_t)(1u << q.k);
+  }
+  T.ne = (int)T.edge_ptr.size();
+  T.edge_ptr.push_back((int32_t)rec.size());
+  T.nb = T.n + 2 * T.ne;
+
+  // Block pattern: row i holds i itself and every edge neighbour, sorted.
+  std::vector<int32_t> deg(n, 1);
+  for (int e = 0; e < T.ne; ++e) {
+    ++deg[T.edges[2 * e]];
+    ++deg[T.edges[2 * e + 1]];
+  }
+  T.row_ptr.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) T.row_ptr[i + 1] = T.row_ptr[i] + deg[i];
+  T.col.assign(T.nb, -1);
+  T.blk_edge.assign(T.nb, -1);
+  std::vector<int32_t> fill(T.row_ptr.begin(), T.row_ptr.end() - 1);
+  // Edges are sorted by (i, j): for row i, neighbours j > i arrive in order;
+  // neighbours j < i arrive in order of their own row.  Insert then sort.
+  for (int i = 0; i < n; ++i) T.col[fill[i]++] = i;
+  for (int e = 0; e < T.ne; ++e) {
+    int i = T.edges[2 * e], j = T.edges[2 * e + 1];
+    T.blk_edge[fill[i]] = e;
+    T.col[fill[i]++] = j;
+    T.blk_edge[fill[j]] = e;
+    T.col[fill[j]++] = i;
+  }
+  T.diag_blk.resize(n);
+  T.blk_ij.resize(T.ne);
+  T.blk_ji.resize(T.ne);
+  std::vector<std::pair<int32_t, int32_t>> tmp;
+  for (int i = 0; i < n; ++i) {
+    int s = T.row_ptr[i], e = T.row_ptr[i + 1];
+    tmp.clear();
+    for (int b = s; b < e; ++b) tmp.push_back({T.col[b], T.blk_edge[b]});
+    std::sort(tmp.begin(), tmp.end());
+    for (int b = s; b < e; ++b) {
+      T.col[b] = tmp[b - s].first;
+      T.blk_edge[b] = tmp[b - s].second;
+      if (T.col[b] == i) {
+        T.diag_blk[i] = b;
+      } else {
+        int ed = T.blk_edge[b];
+        if (i < T.col[b])
+          T.blk_ij[ed] = b;
+        else
+          T.blk_ji[ed] = b;
+      }
+    }
+  }
+
+  // Rest squared edge lengths and the consistent mass (Eq. 5):
+  // m_ab = rho V (1 + delta_ab) / 20 per tet; off-diagonal per edge, row sums per node.
+  T.edge_S.resize(T.ne);
+  for (int e = 0; e < T.ne; ++e) {
+    double s = 0;
+    for (int d = 0; d < 3; ++d) {
+      double q = T.X[3 * (size_t)T.edges[2 * e + 1] + d] - T.X[3 * (size_t)T.edges[2 * e] + d];
+      s += q * q;
+    }
+    T.edge_S[e] = s;
+  }
+  T.edge_mass.assign(T.ne, 0.0);
+  T.lumped.assign(n, 0.0);
+  for (int e = 0; e < T.ne; ++e)
+    for (int r = T.edge_ptr[e]; r < T.edge_ptr[e + 1]; ++r) {
+      int t = T.edge_slot[r] % m;
+      T.edge_mass[e] += density * T.vol[t] / 20.0;
+    }
+  for (int t = 0; t < m; ++t)
+    for (int a = 0; a < 4; ++a) T.lumped[T.tets[4 * (size_t)t + a]] += density * T.vol[t] / 4.0;
+
+  // Canonical edge order (caller ids, i < j, lexicographic).
+  std::vector<std::pair<std::pair<int32_t, int32_t>, int32_t>> ce(T.ne);
+  for (int e = 0; e < T.ne; ++e) {
+    int a = T.perm_old[T.edges[2 * e]], b = T.perm_old[T.edges[2 * e + 1]];
+    ce[e] = {{std::min(a, b), std::max(a, b)}, e};
+  }
+  std::sort(ce.begin(), ce.end());
+  T.edge_canon.resize(T.ne);
+  T.edge_internal.resize(T.ne);
+  for (int c = 0; c < T.ne; ++c) {
+    T.edge_internal[c] = ce[c].second;
+    T.edge_canon[ce[c].second] = c;
+  }
+  return "";
+}
+
+}  // namespace gfem

@@ -1,0 +1,55 @@
+// Host-side mesh topology for the graph-based FEM library: validation,
+// reorientation, the induced graph (nodes + unique tet edges, Sec. 1 and
+// Sec. 3.1), the fixed 3x3 block-sparse pattern (one block per node and two
+// per edge), the edge -> contribution-slot map used by the deterministic
+// assembly, and the consistent mass of Eq. 5.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace gfem {
+
+// Local edge k of a tet joins local nodes kEdgeA[k] -> kEdgeB[k]; this is the
+// 12,13,14,23,24,34 order of Eq. 15.
+constexpr int kEdgeA[6] = {0, 0, 0, 1, 1, 2};
+constexpr int kEdgeB[6] = {1, 2, 3, 2, 3, 3};
+
+struct Topology {
+  int n = 0;   // nodes
+  int m = 0;   // tets
+  int ne = 0;  // edges
+  int nb = 0;  // stored 3x3 blocks = n + 2 ne
+
+  std::vector<double> X;          // n*3 rest positions (internal order)
+  std::vector<int32_t> tets;      // m*4, positively oriented (internal ids)
+  std::vector<int32_t> edges;     // ne*2, i < j, sorted (internal ids)
+  std::vector<int32_t> tet_edge;  // 6*m, SoA: tet_edge[k*m + t]
+  std::vector<uint8_t> tet_flip;  // m: bit k set when the global edge runs b -> a
+  std::vector<int32_t> edge_ptr;  // ne+1: contributions of edge e are
+  std::vector<int32_t> edge_slot; //   edge_slot[edge_ptr[e] .. edge_ptr[e+1]) = k*m + t
+  std::vector<int32_t> row_ptr;   // n+1 block rows
+  std::vector<int32_t> col;       // nb block columns, sorted per row
+  std::vector<int32_t> diag_blk;  // n
+  std::vector<int32_t> blk_ij;    // ne: block (i,j) of edge e, i < j
+  std::vector<int32_t> blk_ji;    // ne: block (j,i)
+  std::vector<int32_t> blk_edge;  // nb: edge of an off-diagonal block, -1 on the diagonal
+  std::vector<double> edge_S;     // ne: rest squared length
+  std::vector<double> edge_mass;  // ne: consistent off-diagonal mass, sum rho V / 20
+  std::vector<double> lumped;     // n: row sum of the consistent mass, sum rho V / 4
+  std::vector<double> vol;        // m: rest volume
+  int reoriented = 0;
+
+  // Node numbering: internal id = perm_new[caller id]; caller = perm_old[internal].
+  std::vector<int32_t> perm_new, perm_old;
+  // Canonical (caller-order) edge index of each internal edge, and inverse.
+  std::vector<int32_t> edge_canon, edge_internal;
+};
+
+// Builds the topology.  Returns "" on success, otherwise an error message;
+// *degenerate is set when the failure is a flat tet.
+std::string build_topology(const double* xyz, int n, const int32_t* tets, int m, double density,
+                           Topology* out, bool* degenerate);
+
+}  // namespace gfem
