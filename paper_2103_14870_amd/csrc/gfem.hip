@@ -92,7 +92,7 @@ struct gf_mesh {
   bool plastic = false;
   int dev = 0;
   hipStream_t own = nullptr, stream = nullptr;
-  int n = 0, m = 0, ne = 0, nb = 0, nbp = 0, Gv = 8, Gs = 8;
+  int n = 0, m = 0, ne = 0, nb = 0, nbp = 0, Gv = 8, Gs = 8, Ga = 8, Gb = 8;
   double mu = 0, lam = 0, alpha_m1 = 0;
   Alloc al;
   // node data
@@ -247,7 +247,7 @@ void assemble(gf_mesh* M, bool flow, d4* f_out) {
   });
   gfem::RowConst rc{dt, M->p.rayleigh_alpha, mass_fac, {M->p.gravity[0], M->p.gravity[1], M->p.gravity[2]}};
   M->timed(2, -1, 0, [&] {
-    gfem::launch_row<T>(s, M->n, M->Gv, M->mat(), M->diag_blk, M->blk_edge, M->edge_mass,
+    gfem::launch_row<T>(s, M->n, M->Gs, M->mat(), M->diag_blk, M->blk_edge, M->edge_mass,
                         static_cast<const T*>(M->edge_w), M->lumped, M->X, M->U, M->V, M->dflag, M->dvel, rc,
                         static_cast<T*>(M->val), M->b, M->X64, static_cast<T*>(M->binv), f_out, M->part_a);
   });
@@ -273,16 +273,12 @@ struct SolveResult {
 // vectors, FP64 dot products, device-side scalars and early exit, launched in
 // chunks so the host only synchronises once per chunk.
 template <typename T>
-SolveResult solve(gf_mesh* M, double bb) {
+SolveResult solve(gf_mesh* M) {
   hipStream_t s = M->stream;
   const double tol = M->p.cg_rel_tol;
   SolveResult res{false, 0, 0, 0.0};
-  if (!(bb > 0.0)) {  // b = 0: dv = 0 (X64 already zeroed by the row pass)
-    res.ok = std::isfinite(bb);
-    return res;
-  }
   const double floor_rel = M->split ? 1e-7 : 0.0;
-  double rr = bb;
+  double bb = -1.0, rr = -1.0;  // |b|^2 is read back with the first chunk
   const d4* src = M->b;
   int budget = std::max(1, (int)M->p.cg_max_iter);
   const gfem::MatView A = M->mat();
@@ -293,47 +289,61 @@ SolveResult solve(gf_mesh* M, double bb) {
   v4<T>* pb[2] = {static_cast<v4<T>*>(M->vp[0]), static_cast<v4<T>*>(M->vp[1])};
   const T* binv = static_cast<const T*>(M->binv);
   for (int outer = 0;; ++outer) {
-    res.rel = std::sqrt(rr / bb);
-    if (res.rel <= tol) {
-      res.ok = true;
-      break;
+    if (outer > 0) {
+      res.rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+      if (res.rel <= tol || bb == 0.0) {
+        res.ok = std::isfinite(bb);
+        break;
+      }
+      if (outer >= 30 || res.inner >= budget || !std::isfinite(rr)) break;
     }
-    if (outer >= 30 || res.inner >= budget || !std::isfinite(rr)) break;
-    const double rel_in = std::max(0.5 * tol * std::sqrt(bb / rr), floor_rel);
-    const double thr2 = rel_in * rel_in * rr;
+    const double rel_in = outer == 0 ? std::max(0.5 * tol, floor_rel) : std::max(0.5 * tol * std::sqrt(bb / rr), floor_rel);
     const int solve_id = (int)M->solve_iters.size();
     hchk(hipMemsetAsync(M->ctl, 0, sizeof(gfem::PcgCtl), s), "hipMemsetAsync");
-    M->timed(5, -1, 0, [&] { gfem::launch_pcg_init<T>(s, M->n, M->Gv, src, binv, r, z, pb[0], x, M->part_rz); });
+    M->timed(5, -1, 0, [&] { gfem::launch_pcg_init<T>(s, M->n, M->Ga, src, binv, r, z, pb[0], x, M->part_rz); });
     const int left = budget - res.inner;
     int k = 0;
-    int chunk = (outer == 0 && M->last_first_solve > 0) ? std::min(M->last_first_solve, left) : std::min(16, left);
-    chunk = std::max(chunk, 1);
+    // the first chunk covers the iteration count of the previous step's first solve (+10 %)
+    int chunk = (outer == 0 && M->last_first_solve > 0) ? M->last_first_solve + M->last_first_solve / 10 + 1 : 16;
+    chunk = std::max(1, std::min(chunk, left));
     int iters = 0;
     bool failed = false;
     while (true) {
       const int kend = std::min(k + chunk, left);
       for (; k < kend; ++k) {
         M->timed(4, solve_id, k, [&] {
-          gfem::launch_pcg_spmv<T>(s, k, M->Gs, M->Gv, A, z, pb[(k + 1) & 1], pb[k & 1], q, M->ctl, M->part_rz,
-                                   M->part_pq, thr2);
+          gfem::launch_pcg_spmv<T>(s, k, M->Gb, M->Ga, A, z, pb[(k + 1) & 1], pb[k & 1], q, M->ctl, M->part_rz,
+                                   M->part_pq, rel_in * rel_in);
         });
         M->timed(5, solve_id, k, [&] {
-          gfem::launch_pcg_update<T>(s, k, M->n, M->Gv, M->Gs, pb[k & 1], q, x, r, z, binv, M->ctl, M->part_pq,
+          gfem::launch_pcg_update<T>(s, k, M->n, M->Ga, M->Gb, pb[k & 1], q, x, r, z, binv, M->ctl, M->part_pq,
                                      M->part_rz);
         });
       }
       M->check_launch();
       hchk(hipMemcpyAsync(M->h_ctl, M->ctl, sizeof(gfem::PcgCtl), hipMemcpyDeviceToHost, s), "D2H");
+      if (bb < 0.0)
+        hchk(hipMemcpyAsync(M->h_part, M->part_a, sizeof(double) * M->Gs, hipMemcpyDeviceToHost, s), "D2H");
       M->sync();
+      if (bb < 0.0) {
+        bb = 0.0;
+        for (int i = 0; i < M->Gs; ++i) bb += M->h_part[i];
+        rr = bb;
+      }
       iters = M->h_ctl->iters;
       failed = M->h_ctl->fail != 0;
-      if (M->h_ctl->done || k >= left) break;
-      chunk = 16;
+      if (M->h_ctl->done || k >= left || bb == 0.0) break;
+      chunk = 8;
     }
     M->solve_iters.push_back(iters);
     if (outer == 0) M->last_first_solve = iters;
     res.inner += iters;
     res.outer = outer + 1;
+    if (bb == 0.0) {  // b = 0: dv = 0 (X64 was zeroed by the row pass)
+      res.ok = true;
+      res.rel = 0.0;
+      break;
+    }
     if (iters > 0) {
       M->timed(6, -1, 0, [&] { gfem::launch_addcorr<T>(s, M->n, M->Gv, x, M->X64); });
     }
@@ -347,6 +357,7 @@ SolveResult solve(gf_mesh* M, double bb) {
       break;
     }
   }
+  if (res.outer > 0 && !res.ok && bb > 0) res.rel = std::sqrt(rr / bb);
   return res;
 }
 
@@ -355,17 +366,19 @@ gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
   for (int i = 0; i < n_steps; ++i) {
     assemble<T>(M, true, nullptr);
     hchk(hipMemcpyAsync(M->h_ctr, M->ctr, sizeof(gfem::Counters), hipMemcpyDeviceToHost, M->stream), "D2H");
-    const double bb = read_partials(M, M->part_a, M->Gv);
-    SolveResult r = solve<T>(M, bb);
+    SolveResult r = solve<T>(M);
+    int cnt[gfem::kNumCounters] = {0, 0, 0, 0, 0};
+    for (int sl = 0; sl < gfem::kCtrSlots; ++sl)
+      for (int c = 0; c < gfem::kNumCounters; ++c) cnt[c] += M->h_ctr->v[sl * gfem::kCtrStride + c];
     if (st) {
       st->inner_iters += r.inner;
       st->outer_iters += r.outer;
       st->rel_residual = r.rel;
-      st->new_broken += M->h_ctr->new_broken;
-      st->total_broken = M->h_ctr->total_broken;
-      st->near_threshold += M->h_ctr->near_threshold;
-      st->chi_zero_tets = M->h_ctr->chi_zero;
-      st->degenerate_tets = M->h_ctr->degenerate;
+      st->new_broken += cnt[gfem::kNewBroken];
+      st->total_broken = cnt[gfem::kTotalBroken];
+      st->near_threshold += cnt[gfem::kNearThreshold];
+      st->chi_zero_tets = cnt[gfem::kChiZero];
+      st->degenerate_tets = cnt[gfem::kDegenerate];
     }
     if (!r.ok) {
       M->flush_times(st);
@@ -450,6 +463,10 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     M->nbp = (T.nb + 63) / 64 * 64;
     M->Gv = std::min(kMaxPart, std::max(8, round_up8((T.n + gfem::kThreads - 1) / gfem::kThreads)));
     M->Gs = std::min(kMaxPart, std::max(8, round_up8((T.n * gfem::kRowLanes + gfem::kThreads - 1) / gfem::kThreads)));
+    // PCG SpMV grid: one 16-lane group per block row, capped at 1024
+    // workgroups (four resident per CU) so the update kernel reduces few partials.
+    M->Gb = std::min(1024, std::max(8, round_up8((T.n * gfem::kRowLanes + gfem::kSpmvThreads - 1) / gfem::kSpmvThreads)));
+    M->Ga = std::min(kMaxPart, std::max(8, round_up8((T.n + gfem::kVecThreads - 1) / gfem::kVecThreads)));
     const double E = p.youngs, nu = p.poisson;
     const double mu0 = E / (2 * (1 + nu)), lam0 = E * nu / ((1 + nu) * (1 - 2 * nu));
     M->mu = 4.0 * mu0 / 3.0;             // Smith et al. reparametrisation of Eq. 35
@@ -785,6 +802,9 @@ gf_status gf_bench_spmv(gf_mesh* m, int32_t reps, double* us_per_launch, double*
   if (reps <= 0 || !us_per_launch) return fail(GF_EINVAL, "gf_bench_spmv: bad arguments");
   GF_TRY({
     const size_t vb = m->split ? 12 : 24, ab = m->split ? 4 : 8;
+    // algorithmic bytes of one SpMV launch (iteration k > 0): 3x3 values +
+    // column index per block; z and p_{k-1} read once, p_k and q written and
+    // row_ptr per block row
     if (bytes_per_launch) *bytes_per_launch = (double)m->nb * (9 * ab + 4) + (double)m->n * (4 * vb + 4);
     hipStream_t s = m->stream;
     hipEvent_t a, b;
@@ -794,18 +814,19 @@ gf_status gf_bench_spmv(gf_mesh* m, int32_t reps, double* us_per_launch, double*
       using T = decltype(tag);
       v4<T>* pb[2] = {static_cast<v4<T>*>(m->vp[0]), static_cast<v4<T>*>(m->vp[1])};
       v4<T>* z = static_cast<v4<T>*>(m->vz);
+      v4<T>* q = static_cast<v4<T>*>(m->vq);
+      const T* binv = static_cast<const T*>(m->binv);
       hchk(hipMemsetAsync(m->ctl, 0, sizeof(gfem::PcgCtl), s), "hipMemsetAsync");
-      gfem::launch_pcg_init<T>(s, m->n, m->Gv, m->b, static_cast<const T*>(m->binv), static_cast<v4<T>*>(m->vr), z,
-                               pb[0], static_cast<v4<T>*>(m->vx), m->part_rz);
-      gfem::launch_pcg_spmv<T>(s, 0, m->Gs, m->Gv, m->mat(), z, pb[1], pb[0], static_cast<v4<T>*>(m->vq), m->ctl,
-                               m->part_rz, m->part_pq, -1.0);
-      gfem::launch_pcg_update<T>(s, 0, m->n, m->Gv, m->Gs, pb[0], static_cast<v4<T>*>(m->vq),
-                                 static_cast<v4<T>*>(m->vx), static_cast<v4<T>*>(m->vr), z,
-                                 static_cast<const T*>(m->binv), m->ctl, m->part_pq, m->part_rz);
+      gfem::launch_pcg_init<T>(s, m->n, m->Ga, m->b, binv, static_cast<v4<T>*>(m->vr), z, pb[0],
+                               static_cast<v4<T>*>(m->vx), m->part_rz);
+      gfem::launch_pcg_spmv<T>(s, 0, m->Gb, m->Ga, m->mat(), z, pb[1], pb[0], q, m->ctl, m->part_rz, m->part_pq,
+                               -1.0);  // negative threshold: never converges
+      gfem::launch_pcg_update<T>(s, 0, m->n, m->Ga, m->Gb, pb[0], q, static_cast<v4<T>*>(m->vx),
+                                 static_cast<v4<T>*>(m->vr), z, binv, m->ctl, m->part_pq, m->part_rz);
       hchk(hipEventRecord(a, s), "hipEventRecord");
       for (int i = 0; i < reps; ++i)
-        gfem::launch_pcg_spmv<T>(s, 1, m->Gs, m->Gv, m->mat(), z, pb[0], pb[1], static_cast<v4<T>*>(m->vq),
-                                 m->ctl, m->part_rz, m->part_pq, -1.0);
+        gfem::launch_pcg_spmv<T>(s, 1, m->Gb, m->Ga, m->mat(), z, pb[0], pb[1], q, m->ctl, m->part_rz, m->part_pq,
+                                 -1.0);
       hchk(hipEventRecord(b, s), "hipEventRecord");
     };
     if (m->split)

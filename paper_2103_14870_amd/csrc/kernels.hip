@@ -30,41 +30,24 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
-__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
-    sh[threadIdx.x >> 6] = a;
-    sh[4 + (threadIdx.x >> 6)] = b;
+// Per-workgroup event counts: one ballot per wave, one atomic per counter per
+// workgroup, into slot (workgroup % kCtrSlots).  Every thread must call it.
+template <int NC>
+__device__ __forceinline__ void block_counts(Counters* ctr, int first_field, const bool (&pred)[NC]) {
+  __shared__ int sc[kThreads / 64][NC];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const unsigned long long b = __ballot(pred[c]);
+    if (l == 0) sc[w][c] = (int)__popcll(b);
   }
   __syncthreads();
-  a = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-  b = (sh[4] + sh[5]) + (sh[6] + sh[7]);
-}
-
-__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  c = wave_sum(c);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
-    sh[threadIdx.x >> 6] = a;
-    sh[4 + (threadIdx.x >> 6)] = b;
-    sh[8 + (threadIdx.x >> 6)] = c;
+  if (threadIdx.x < NC) {
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kThreads / 64; ++i) s += sc[i][threadIdx.x];
+    if (s) atomicAdd(&ctr->v[(blockIdx.x % kCtrSlots) * kCtrStride + first_field + threadIdx.x], s);
   }
-  __syncthreads();
-  a = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-  b = (sh[4] + sh[5]) + (sh[6] + sh[7]);
-  c = (sh[8] + sh[9]) + (sh[10] + sh[11]);
-}
-
-// Count lanes of the calling wave with `pred` set; one integer atomic per wave.
-__device__ __forceinline__ void wave_count(int* ctr, bool pred) {
-  unsigned long long bits = __ballot(pred);
-  unsigned long long act = __ballot(1);
-  int leader = __ffsll((long long)act) - 1;
-  if ((int)(threadIdx.x & 63) == leader && bits) atomicAdd(ctr, (int)__popcll(bits));
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Map them so that
@@ -72,13 +55,7 @@ __device__ __forceinline__ void wave_count(int* ctr, bool pred) {
 // entries its rows gather.  G must be a multiple of 8.
 __device__ __forceinline__ int xcd_logical(int b, int G) { return (b & 7) * (G >> 3) + (b >> 3); }
 
-template <typename T>
-__device__ __forceinline__ v4<T> ld(const v4<T>* p, int i) {
-  return p[i];
-}
-
-// p_k = z_k + beta p_{k-1}: written once here so that the copy stored by the
-// owning row and the copies formed on the fly by neighbouring rows agree bitwise.
+// a + beta b per component (fused multiply-add).
 template <typename T>
 __device__ __forceinline__ v4<T> dir_comb(v4<T> z, T beta, v4<T> p) {
   v4<T> r;
@@ -165,9 +142,8 @@ __global__ __launch_bounds__(kThreads) void k_damage(int ne, const int2* __restr
     near = fabs(eps - thr) < 1e-6;
     z_out[e] = (uint8_t)(was || hit);
   }
-  wave_count(&ctr->new_broken, act && hit && !was);
-  wave_count(&ctr->total_broken, act && (hit || was));
-  wave_count(&ctr->near_threshold, act && near);
+  const bool pr[3] = {act && hit && !was, act && (hit || was), act && near};
+  block_counts<3>(ctr, kNewBroken, pr);
 }
 
 // ---------------------------------------------------------------- element
@@ -431,17 +407,19 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
     }
   }
 
-  wave_count(&ctr->chi_zero, act && chi == T(0));
-  wave_count(&ctr->degenerate, act && fabs(J) < T(0.05));
+  {
+    const bool pr[2] = {act && chi == T(0), act && fabs(J) < T(0.05)};
+    block_counts<2>(ctr, kChiZero, pr);
+  }
   if (!act) return;
 
-  const size_t m6 = (size_t)6 * m;
-  T* out = contrib + t;
   if (chi == T(0)) {
 #pragma unroll
-    for (int c = 0; c < 10; ++c)
+    for (int k = 0; k < 6; ++k) {
+      T* rec = contrib + ((size_t)k * m + t) * 10;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) out[c * m6 + (size_t)k * m] = T(0);
+      for (int c = 0; c < 10; ++c) rec[c] = T(0);
+    }
     return;
   }
 
@@ -504,11 +482,12 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
       Kab[1][1] -= lap;
       Kab[2][2] -= lap;
       const bool tr = (fl >> k) & 1;
+      T* rec = contrib + ((size_t)k * m + t) * 10;
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) out[(size_t)(3 * r + c) * m6 + (size_t)k * m] = tr ? Kab[c][r] : Kab[r][c];
-      out[(size_t)9 * m6 + (size_t)k * m] = T(2) * Vc * g[k];
+        for (int c = 0; c < 3; ++c) rec[3 * r + c] = tr ? Kab[c][r] : Kab[r][c];
+      rec[9] = T(2) * Vc * g[k];
     }
   }
 }
@@ -533,9 +512,9 @@ __global__ __launch_bounds__(kThreads) void k_edge(int ne, int m6, const int32_t
   for (int c = 0; c < 10; ++c) acc[c] = 0;
   const int s0 = edge_ptr[e], s1 = edge_ptr[e + 1];
   for (int s = s0; s < s1; ++s) {
-    const int idx = edge_slot[s];
+    const T* rec = contrib + (size_t)edge_slot[s] * 10;
 #pragma unroll
-    for (int c = 0; c < 10; ++c) acc[c] += contrib[(size_t)c * m6 + idx];
+    for (int c = 0; c < 10; ++c) acc[c] += rec[c];
   }
   const double md = edge_mass[e] * mass_fac;
   const int bij = blk_ij[e], bji = blk_ji[e];
@@ -552,12 +531,20 @@ __global__ __launch_bounds__(kThreads) void k_edge(int ne, int m6, const int32_t
 
 // ---------------------------------------------------------------- row pass
 
-// One thread per node (block row i):
+template <int W>
+__device__ __forceinline__ double seg_sum(double v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  return v;
+}
+
+// One block row per kRowLanes lanes; each lane takes one off-diagonal block
+// (i, j) of the row and the lanes then sum:
 //   A_ii = (1 + dt alpha) m_i I - sum_j A_ij   (translation invariance of K)
 //   f_i  = sum_j w_ij (x_j - x_i)              (Eq. 12: forces along edges)
 //   b_i  = dt (m_i g + f_i) - dt alpha (M v)_i - sum_j (A_ij - m_ij (1 + dt alpha) I)(v_j - v_i)
 // then Dirichlet elimination (b_f -= A_fc dv_c; rows/columns of c -> identity),
-// block-Jacobi inverse of A_ii, X64 = 0 and the partial |b|^2.
+// the block-Jacobi inverse of A_ii, X64 = 0 and the partial |b|^2.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32_t* __restrict__ diag_blk,
                                                   const int32_t* __restrict__ blk_edge,
@@ -575,15 +562,18 @@ __global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32
   const int chunk = (n + G - 1) / G;
   const int r0 = L * chunk, r1 = min(n, r0 + chunk);
   const int nbp = Am.nbp;
+  const int lane = threadIdx.x & (kRowLanes - 1);
+  const int grp = threadIdx.x / kRowLanes;
   double bb = 0;
-  for (int i = r0 + threadIdx.x; i < r1; i += kThreads) {
+  for (int i = r0 + grp; i < r1; i += kThreads / kRowLanes) {
     const int s = Am.row_ptr[i], e = Am.row_ptr[i + 1], db = diag_blk[i];
     const d4 Xi = X[i], Ui = U[i], vi = V[i];
     const bool ci = dflag[i] != 0;
-    double f[3] = {0, 0, 0}, kv[3] = {0, 0, 0}, mv[3] = {0, 0, 0}, bd[3] = {0, 0, 0};
-    double As[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double msum = 0;
-    for (int b = s; b < e; ++b) {
+    // per-lane partial sums: f(3) kv(3) mv(3) bd(3) As(9) msum(1)
+    double acc[22];
+#pragma unroll
+    for (int c = 0; c < 22; ++c) acc[c] = 0.0;
+    for (int b = s + lane; b < e; b += kRowLanes) {
       if (b == db) continue;
       const int j = Am.col[b];
       const int ed = blk_edge[b];
@@ -597,73 +587,74 @@ __global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         a[c] = (double)val[(size_t)c * nbp + b];
-        As[c] += a[c];
+        acc[12 + c] += a[c];
       }
-      msum += me;
+      acc[21] += me;
       const double mf = me * cst.mass_fac;
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        f[r] += w * dx[r];
-        double acc = 0;
+        acc[r] += w * dx[r];
+        double t = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc += (a[3 * r + c] - (r == c ? mf : 0.0)) * dv[c];
-        kv[r] += acc;
+        for (int c = 0; c < 3; ++c) t += (a[3 * r + c] - (r == c ? mf : 0.0)) * dv[c];
+        acc[3 + r] += t;
       }
-      mv[0] += me * vj.x;
-      mv[1] += me * vj.y;
-      mv[2] += me * vj.z;
-      if (dflag[j]) {
+      acc[6] += me * vj.x;
+      acc[7] += me * vj.y;
+      acc[8] += me * vj.z;
+      const bool cj = dflag[j] != 0;
+      if (cj) {
         const d4 pj = dvel[j];
         const double dvc[3] = {pj.x - vj.x, pj.y - vj.y, pj.z - vj.z};
 #pragma unroll
-        for (int r = 0; r < 3; ++r) bd[r] += a[3 * r] * dvc[0] + a[3 * r + 1] * dvc[1] + a[3 * r + 2] * dvc[2];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) val[(size_t)c * nbp + b] = T(0);
-      } else if (ci) {
+        for (int r = 0; r < 3; ++r) acc[9 + r] += a[3 * r] * dvc[0] + a[3 * r + 1] * dvc[1] + a[3 * r + 2] * dvc[2];
+      }
+      if (cj || ci) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) val[(size_t)c * nbp + b] = T(0);
       }
     }
-    const double mi = lumped[i];
-    const double mii = mi - msum;
-    mv[0] += mii * vi.x;
-    mv[1] += mii * vi.y;
-    mv[2] += mii * vi.z;
-    const double vi3[3] = {vi.x, vi.y, vi.z};
-    double Aii[9];
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 22; ++c) acc[c] = seg_sum<kRowLanes>(acc[c]);
+    if (lane == 0) {
+      const double mi = lumped[i];
+      const double mii = mi - acc[21];
+      const double mv[3] = {acc[6] + mii * vi.x, acc[7] + mii * vi.y, acc[8] + mii * vi.z};
+      double Aii[9];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) Aii[3 * r + c] = (r == c ? cst.mass_fac * mi : 0.0) - As[3 * r + c];
-    double bi[3];
+      for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
-      bi[r] = cst.dt * (mi * cst.g[r] + f[r]) - cst.dt * cst.ra * mv[r] - kv[r] - bd[r];
-    if (f_out) f_out[i] = d4{f[0], f[1], f[2], 0.0};
-    if (ci) {
-      const d4 pv = dvel[i];
-      bi[0] = pv.x - vi3[0];
-      bi[1] = pv.y - vi3[1];
-      bi[2] = pv.z - vi3[2];
+        for (int c = 0; c < 3; ++c) Aii[3 * r + c] = (r == c ? cst.mass_fac * mi : 0.0) - acc[12 + 3 * r + c];
+      double bi[3];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) Aii[c] = (c % 4 == 0) ? 1.0 : 0.0;
+      for (int r = 0; r < 3; ++r)
+        bi[r] = cst.dt * (mi * cst.g[r] + acc[r]) - cst.dt * cst.ra * mv[r] - acc[3 + r] - acc[9 + r];
+      if (f_out) f_out[i] = d4{acc[0], acc[1], acc[2], 0.0};
+      if (ci) {
+        const d4 pv = dvel[i];
+        bi[0] = pv.x - vi.x;
+        bi[1] = pv.y - vi.y;
+        bi[2] = pv.z - vi.z;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) Aii[c] = (c % 4 == 0) ? 1.0 : 0.0;
+      }
+      // symmetric part of the diagonal block (exactly symmetric up to rounding)
+      const double s01 = 0.5 * (Aii[1] + Aii[3]), s02 = 0.5 * (Aii[2] + Aii[6]), s12 = 0.5 * (Aii[5] + Aii[7]);
+      Aii[1] = Aii[3] = s01;
+      Aii[2] = Aii[6] = s02;
+      Aii[5] = Aii[7] = s12;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) val[(size_t)c * nbp + db] = (T)Aii[c];
+      const double sd[6] = {Aii[0], Aii[4], Aii[8], s01, s02, s12};
+      const double det = sym3_det(sd[0], sd[1], sd[2], sd[3], sd[4], sd[5]);
+      double inv[6];
+      sym3_inv(sd, det, inv);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) binv[(size_t)c * n + i] = (T)inv[c];
+      bvec[i] = d4{bi[0], bi[1], bi[2], 0.0};
+      X64[i] = d4{0.0, 0.0, 0.0, 0.0};
+      bb += bi[0] * bi[0] + bi[1] * bi[1] + bi[2] * bi[2];
     }
-    // symmetric part of the diagonal block (exactly symmetric up to rounding)
-    const double s01 = 0.5 * (Aii[1] + Aii[3]), s02 = 0.5 * (Aii[2] + Aii[6]), s12 = 0.5 * (Aii[5] + Aii[7]);
-    Aii[1] = Aii[3] = s01;
-    Aii[2] = Aii[6] = s02;
-    Aii[5] = Aii[7] = s12;
-#pragma unroll
-    for (int c = 0; c < 9; ++c) val[(size_t)c * nbp + db] = (T)Aii[c];
-    const double sd[6] = {Aii[0], Aii[4], Aii[8], s01, s02, s12};
-    const double det = sym3_det(sd[0], sd[1], sd[2], sd[3], sd[4], sd[5]);
-    double inv[6];
-    sym3_inv(sd, det, inv);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) binv[(size_t)c * n + i] = (T)inv[c];
-    bvec[i] = d4{bi[0], bi[1], bi[2], 0.0};
-    X64[i] = d4{0.0, 0.0, 0.0, 0.0};
-    bb += bi[0] * bi[0] + bi[1] * bi[1] + bi[2] * bi[2];
   }
   bb = block_sum(bb, sh);
   if (threadIdx.x == 0) part_bb[L] = bb;
@@ -683,22 +674,75 @@ __device__ __forceinline__ v4<T> bj_apply(const T* __restrict__ binv, int n, int
   return z;
 }
 
-// r = src (rounded to T), z = B r, p_0 = z, x = 0; partials of r.z and r.r.
+// Deterministic sum over an NT-thread workgroup (fixed tree), three values.
+template <int NT>
+__device__ __forceinline__ void block_sum3n(double& a, double& b, double& c, double* sh) {
+  constexpr int NW = NT / 64;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sh[threadIdx.x >> 6] = a;
+    sh[NW + (threadIdx.x >> 6)] = b;
+    sh[2 * NW + (threadIdx.x >> 6)] = c;
+  }
+  __syncthreads();
+  double ra = 0, rb = 0, rc = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    ra += sh[w];
+    rb += sh[NW + w];
+    rc += sh[2 * NW + w];
+  }
+  a = ra;
+  b = rb;
+  c = rc;
+}
+
+// Block-Jacobi preconditioned conjugate gradients, two kernels per
+// iteration.  Dot products are accumulated in FP64 per workgroup and each
+// consumer kernel reduces the producer's partials itself (fixed order, so
+// every workgroup computes identical scalars and the run is reproducible).
+// Partial layout: part_rz[parity][component][workgroup], component 0 = r.z,
+// 1 = r.r; part_pq[workgroup].
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_pcg_init(int n, const d4* __restrict__ src,
-                                                       const T* __restrict__ binv, v4<T>* __restrict__ r,
-                                                       v4<T>* __restrict__ z, v4<T>* __restrict__ p0,
-                                                       v4<T>* __restrict__ x, double* __restrict__ part_rz) {
-  __shared__ double sh[16];
+struct Blk {
+  T a[9];
+};
+
+template <typename T>
+__device__ __forceinline__ Blk<T> load_blk(const T* __restrict__ val, int nbp, int b) {
+  Blk<T> k;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) k.a[c] = val[(size_t)c * nbp + b];
+  return k;
+}
+
+template <typename T>
+__device__ __forceinline__ void blk_fma(const Blk<T>& k, const v4<T>& x, T& ax, T& ay, T& az) {
+  ax = fmadd(k.a[0], x.x, fmadd(k.a[1], x.y, fmadd(k.a[2], x.z, ax)));
+  ay = fmadd(k.a[3], x.x, fmadd(k.a[4], x.y, fmadd(k.a[5], x.z, ay)));
+  az = fmadd(k.a[6], x.x, fmadd(k.a[7], x.y, fmadd(k.a[8], x.z, az)));
+}
+
+// r = src (rounded to T), z = B r, p_0 = z, x = 0; partials of r.z and r.r.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_pcg_init(int n, const d4* __restrict__ src, const T* __restrict__ binv,
+                                                 v4<T>* __restrict__ r, v4<T>* __restrict__ z,
+                                                 v4<T>* __restrict__ p0, v4<T>* __restrict__ x,
+                                                 double* __restrict__ part_rz) {
+  __shared__ double sh[3 * (NT / 64)];
   const int G = gridDim.x;
   const int L = xcd_logical(blockIdx.x, G);
   const int chunk = (n + G - 1) / G;
   const int r0 = L * chunk, r1 = min(n, r0 + chunk);
-  double rz = 0, rr = 0;
-  for (int i = r0 + threadIdx.x; i < r1; i += kThreads) {
+  double rz = 0, rr = 0, unused = 0;
+  for (int i = r0 + threadIdx.x; i < r1; i += NT) {
     const d4 s = src[i];
-    v4<T> ri{(T)s.x, (T)s.y, (T)s.z, T(0)};
-    v4<T> zi = bj_apply(binv, n, i, ri);
+    const v4<T> ri{(T)s.x, (T)s.y, (T)s.z, T(0)};
+    const v4<T> zi = bj_apply(binv, n, i, ri);
     r[i] = ri;
     z[i] = zi;
     p0[i] = zi;
@@ -706,96 +750,181 @@ __global__ __launch_bounds__(kThreads) void k_pcg_init(int n, const d4* __restri
     rz += (double)ri.x * zi.x + (double)ri.y * zi.y + (double)ri.z * zi.z;
     rr += (double)ri.x * ri.x + (double)ri.y * ri.y + (double)ri.z * ri.z;
   }
-  block_sum2(rz, rr, sh);
+  block_sum3n<NT>(rz, rr, unused, sh);
   if (threadIdx.x == 0) {
     part_rz[L] = rz;
     part_rz[kMaxPart + L] = rr;
   }
 }
 
-// Iteration k, first kernel.  Reduces r_k.z_k and r_k.r_k (and r_{k-1}.z_{k-1}),
-// stops when |r_k|^2 <= thr2, else forms p_k = z_k + beta_k p_{k-1} into p_new
-// (k > 0; for k = 0, p_new already holds p_0 = z_0 and is only read),
-// q = A p_k (FP32 or FP64 block matrix, 16 lanes per block row) and the
-// partial p_k.q (FP64).
+// Iteration k, first kernel: reduce r_k.z_k, r_k.r_k (and r_{k-1}.z_{k-1});
+// stop when |r_k|^2 <= rel2 |r_0|^2 (threshold fixed by the k = 0 launch);
+// else p_k = z_k + beta_k p_{k-1} (k > 0; for k = 0 p_new already holds
+// p_0 = z_0 and is only read), q = A p_k and the partial p_k.q.
+// kRowLanes lanes share a block row, two rows in flight per lane group; each
+// neighbour's p_k entry is formed on the fly with the same fused operation as
+// its owner uses, so all copies agree bitwise.  The first row pair's loads
+// (row bounds, column, block, gathered z and p_{k-1}) are issued before the
+// scalar reduction so the two memory latencies overlap.
 template <typename T, bool DIR>
-__global__ __launch_bounds__(kThreads) void k_pcg_spmv(int k, int Gv, MatView Am, const v4<T>* __restrict__ z,
-                                                       const v4<T>* __restrict__ p_old,
-                                                       v4<T>* __restrict__ p_new, v4<T>* __restrict__ q,
-                                                       PcgCtl* ctl, const double* __restrict__ part_rz,
-                                                       double* __restrict__ part_pq, double thr2) {
-  __shared__ double sh[16];
+struct SpmvSlot {
+  bool on;
+  Blk<T> k;
+  v4<T> z, p;
+};
+
+template <typename T, bool DIR>
+__device__ __forceinline__ SpmvSlot<T, DIR> spmv_load(const MatView& Am, const T* __restrict__ val, int b, bool on,
+                                                      const v4<T>* __restrict__ z, const v4<T>* __restrict__ p_old,
+                                                      const v4<T>* __restrict__ p_new) {
+  SpmvSlot<T, DIR> s;
+  s.on = on;
+  if (on) {
+    const int j = Am.col[b];
+    s.k = load_blk(val, Am.nbp, b);
+    if (DIR) {
+      s.z = z[j];
+      s.p = p_old[j];
+    } else {
+      s.p = p_new[j];
+    }
+  }
+  return s;
+}
+
+template <typename T, bool DIR, int NT>
+__global__ __launch_bounds__(NT) void k_pcg_spmv(int k, int Ga, MatView Am, const v4<T>* __restrict__ z,
+                                                 const v4<T>* __restrict__ p_old, v4<T>* __restrict__ p_new,
+                                                 v4<T>* __restrict__ q, PcgCtl* ctl,
+                                                 const double* __restrict__ part_rz,
+                                                 double* __restrict__ part_pq, double rel2) {
+  __shared__ double sh[3 * (NT / 64)];
   if (ctl->done) return;
+  const int n = Am.n;
+  const int G = gridDim.x;
+  const int L = xcd_logical(blockIdx.x, G);
+  const int chunk = (n + G - 1) / G;
+  const int r0 = min(n, L * chunk), r1 = min(n, r0 + chunk);
+  const int lane = threadIdx.x & (kRowLanes - 1);
+  const int grp = threadIdx.x / kRowLanes;
+  constexpr int NG = NT / kRowLanes;
+  const T* __restrict__ val = static_cast<const T*>(Am.val);
+  // peeled first pair: bounds and first slot of each row
+  int ra = r0 + grp;
+  int sa = 0, ea = 0, sb = 0, eb = 0;
+  if (ra < r1) {
+    sa = Am.row_ptr[ra];
+    ea = Am.row_ptr[ra + 1];
+    if (ra + NG < r1) {
+      sb = Am.row_ptr[ra + NG];
+      eb = Am.row_ptr[ra + NG + 1];
+    }
+  }
+  SpmvSlot<T, DIR> fa = spmv_load<T, DIR>(Am, val, sa + lane, lane < ea - sa, z, p_old, p_new);
+  SpmvSlot<T, DIR> fb = spmv_load<T, DIR>(Am, val, sb + lane, lane < eb - sb, z, p_old, p_new);
+
   const double* cur = part_rz + (size_t)(k & 1) * 2 * kMaxPart;
   const double* prv = part_rz + (size_t)((k + 1) & 1) * 2 * kMaxPart;
   double rz = 0, rr = 0, rzp = 0;
-  for (int i = threadIdx.x; i < Gv; i += kThreads) {
+  for (int i = threadIdx.x; i < Ga; i += NT) {
     rz += cur[i];
     rr += cur[kMaxPart + i];
     if (DIR) rzp += prv[i];
   }
-  block_sum3(rz, rr, rzp, sh);
+  block_sum3n<NT>(rz, rr, rzp, sh);
+  double thr2;
+  if (k == 0) {
+    thr2 = rel2 * rr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->thr2 = thr2;
+  } else {
+    thr2 = ctl->thr2;
+  }
   if (!(rr > thr2) || rz == 0.0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->done = 1;
     return;
   }
   const T beta = DIR ? (T)(rz / rzp) : T(0);
-  const int n = Am.n, nbp = Am.nbp;
-  const int G = gridDim.x;
-  const int L = xcd_logical(blockIdx.x, G);
-  const int chunk = (n + G - 1) / G;
-  const int r0 = L * chunk, r1 = min(n, r0 + chunk);
-  const int lane = threadIdx.x & (kRowLanes - 1);
-  const int grp = threadIdx.x / kRowLanes;
-  const T* __restrict__ val = static_cast<const T*>(Am.val);
   double dot = 0;
-  for (int row = r0 + grp; row < r1; row += kThreads / kRowLanes) {
-    const int s = Am.row_ptr[row], e = Am.row_ptr[row + 1];
-    T ax = 0, ay = 0, az = 0;
-    for (int b = s + lane; b < e; b += kRowLanes) {
-      const int j = Am.col[b];
-      const v4<T> pj = DIR ? dir_comb(z[j], beta, p_old[j]) : p_new[j];
-      const T a0 = val[b], a1 = val[(size_t)nbp + b], a2 = val[2 * (size_t)nbp + b];
-      const T a3 = val[3 * (size_t)nbp + b], a4 = val[4 * (size_t)nbp + b], a5 = val[5 * (size_t)nbp + b];
-      const T a6 = val[6 * (size_t)nbp + b], a7 = val[7 * (size_t)nbp + b], a8 = val[8 * (size_t)nbp + b];
-      ax = fmadd(a0, pj.x, fmadd(a1, pj.y, fmadd(a2, pj.z, ax)));
-      ay = fmadd(a3, pj.x, fmadd(a4, pj.y, fmadd(a5, pj.z, ay)));
-      az = fmadd(a6, pj.x, fmadd(a7, pj.y, fmadd(a8, pj.z, az)));
+  bool first = true;
+  for (; ra < r1; ra += 2 * NG) {
+    const int rb = ra + NG;
+    const bool hb = rb < r1;
+    if (!first) {
+      sa = Am.row_ptr[ra];
+      ea = Am.row_ptr[ra + 1];
+      sb = hb ? Am.row_ptr[rb] : 0;
+      eb = hb ? Am.row_ptr[rb + 1] : 0;
+      fa = spmv_load<T, DIR>(Am, val, sa + lane, lane < ea - sa, z, p_old, p_new);
+      fb = spmv_load<T, DIR>(Am, val, sb + lane, lane < eb - sb, z, p_old, p_new);
+    }
+    first = false;
+    T ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
+    if (fa.on) blk_fma(fa.k, DIR ? dir_comb(fa.z, beta, fa.p) : fa.p, ax, ay, az);
+    if (fb.on) blk_fma(fb.k, DIR ? dir_comb(fb.z, beta, fb.p) : fb.p, bx, by, bz);
+    // rows longer than kRowLanes blocks
+    const int len = max(ea - sa, eb - sb);
+    for (int o = lane + kRowLanes; o < len; o += kRowLanes) {
+      const SpmvSlot<T, DIR> ta = spmv_load<T, DIR>(Am, val, sa + o, o < ea - sa, z, p_old, p_new);
+      const SpmvSlot<T, DIR> tb = spmv_load<T, DIR>(Am, val, sb + o, o < eb - sb, z, p_old, p_new);
+      if (ta.on) blk_fma(ta.k, DIR ? dir_comb(ta.z, beta, ta.p) : ta.p, ax, ay, az);
+      if (tb.on) blk_fma(tb.k, DIR ? dir_comb(tb.z, beta, tb.p) : tb.p, bx, by, bz);
     }
 #pragma unroll
     for (int o = kRowLanes / 2; o > 0; o >>= 1) {
       ax += __shfl_xor(ax, o, kRowLanes);
       ay += __shfl_xor(ay, o, kRowLanes);
       az += __shfl_xor(az, o, kRowLanes);
+      bx += __shfl_xor(bx, o, kRowLanes);
+      by += __shfl_xor(by, o, kRowLanes);
+      bz += __shfl_xor(bz, o, kRowLanes);
     }
     if (lane == 0) {
-      const v4<T> pi = DIR ? dir_comb(z[row], beta, p_old[row]) : p_new[row];
-      if (DIR) p_new[row] = pi;
-      q[row] = v4<T>{ax, ay, az, T(0)};
-      dot += (double)pi.x * ax + (double)pi.y * ay + (double)pi.z * az;
+      const v4<T> pa = DIR ? dir_comb(z[ra], beta, p_old[ra]) : p_new[ra];
+      if (DIR) p_new[ra] = pa;
+      q[ra] = v4<T>{ax, ay, az, T(0)};
+      dot += (double)pa.x * ax + (double)pa.y * ay + (double)pa.z * az;
+      if (hb) {
+        const v4<T> pb = DIR ? dir_comb(z[rb], beta, p_old[rb]) : p_new[rb];
+        if (DIR) p_new[rb] = pb;
+        q[rb] = v4<T>{bx, by, bz, T(0)};
+        dot += (double)pb.x * bx + (double)pb.y * by + (double)pb.z * bz;
+      }
     }
   }
-  dot = block_sum(dot, sh);
+  double u1 = 0, u2 = 0;
+  block_sum3n<NT>(dot, u1, u2, sh);
   if (threadIdx.x == 0) part_pq[L] = dot;
 }
 
 // Iteration k, second kernel: alpha = r.z / p.q; x += alpha p; r -= alpha q;
-// z = B r; partials of r.z and r.r for iteration k+1.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_pcg_update(int k, int n, int Gs, const v4<T>* __restrict__ p,
-                                                         const v4<T>* __restrict__ q, v4<T>* __restrict__ x,
-                                                         v4<T>* __restrict__ r, v4<T>* __restrict__ z,
-                                                         const T* __restrict__ binv, PcgCtl* ctl,
-                                                         const double* __restrict__ part_pq,
-                                                         double* __restrict__ part_rz) {
-  __shared__ double sh[16];
+// z = B r; partials of r.z and r.r for iteration k+1.  The first row's
+// operands are loaded before the reduction so the two latencies overlap.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_pcg_update(int k, int n, int Gb, const v4<T>* __restrict__ p,
+                                                   const v4<T>* __restrict__ q, v4<T>* __restrict__ x,
+                                                   v4<T>* __restrict__ r, v4<T>* __restrict__ z,
+                                                   const T* __restrict__ binv, PcgCtl* ctl,
+                                                   const double* __restrict__ part_pq,
+                                                   double* __restrict__ part_rz) {
+  __shared__ double sh[3 * (NT / 64)];
   if (ctl->done) return;
   const int G = gridDim.x;
+  const int L = xcd_logical(blockIdx.x, G);
+  const int chunk = (n + G - 1) / G;
+  const int r0 = L * chunk, r1 = min(n, r0 + chunk);
+  int i = r0 + threadIdx.x;
+  v4<T> pi{}, qi{}, xi{}, ri{};
+  if (i < r1) {
+    pi = p[i];
+    qi = q[i];
+    xi = x[i];
+    ri = r[i];
+  }
   const double* cur = part_rz + (size_t)(k & 1) * 2 * kMaxPart;
-  double pq = 0, rz = 0;
-  for (int i = threadIdx.x; i < Gs; i += kThreads) pq += part_pq[i];
-  for (int i = threadIdx.x; i < G; i += kThreads) rz += cur[i];
-  block_sum2(pq, rz, sh);
+  double pq = 0, rz = 0, unused = 0;
+  for (int t = threadIdx.x; t < Gb; t += NT) pq += part_pq[t];
+  for (int t = threadIdx.x; t < G; t += NT) rz += cur[t];
+  block_sum3n<NT>(pq, rz, unused, sh);
   if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       ctl->fail = 1;
@@ -804,13 +933,14 @@ __global__ __launch_bounds__(kThreads) void k_pcg_update(int k, int n, int Gs, c
     return;
   }
   const T al = (T)(rz / pq);
-  const int L = xcd_logical(blockIdx.x, G);
-  const int chunk = (n + G - 1) / G;
-  const int r0 = L * chunk, r1 = min(n, r0 + chunk);
   double rzn = 0, rrn = 0;
-  for (int i = r0 + threadIdx.x; i < r1; i += kThreads) {
-    const v4<T> pi = p[i], qi = q[i];
-    v4<T> xi = x[i], ri = r[i];
+  for (; i < r1; i += NT) {
+    if (i != r0 + (int)threadIdx.x) {
+      pi = p[i];
+      qi = q[i];
+      xi = x[i];
+      ri = r[i];
+    }
     xi.x = fmadd(al, pi.x, xi.x);
     xi.y = fmadd(al, pi.y, xi.y);
     xi.z = fmadd(al, pi.z, xi.z);
@@ -824,7 +954,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg_update(int k, int n, int Gs, c
     rzn += (double)ri.x * zi.x + (double)ri.y * zi.y + (double)ri.z * zi.z;
     rrn += (double)ri.x * ri.x + (double)ri.y * ri.y + (double)ri.z * ri.z;
   }
-  block_sum2(rzn, rrn, sh);
+  block_sum3n<NT>(rzn, rrn, unused, sh);
   double* nxt = part_rz + (size_t)((k + 1) & 1) * 2 * kMaxPart;
   if (threadIdx.x == 0) {
     nxt[L] = rzn;
@@ -957,24 +1087,26 @@ void launch_row(hipStream_t s, int n, int G, MatView A, const int32_t* diag_blk,
 }
 
 template <typename T>
-void launch_pcg_init(hipStream_t s, int n, int G, const d4* src, const T* binv, v4<T>* r, v4<T>* z, v4<T>* p0,
-                     v4<T>* x, double* part_rz0) {
-  k_pcg_init<T><<<G, kThreads, 0, s>>>(n, src, binv, r, z, p0, x, part_rz0);
+void launch_pcg_init(hipStream_t s, int n, int Ga, const d4* src, const T* binv, v4<T>* r, v4<T>* z, v4<T>* p0,
+                     v4<T>* x, double* part_rz) {
+  k_pcg_init<T, kVecThreads><<<Ga, kVecThreads, 0, s>>>(n, src, binv, r, z, p0, x, part_rz);
 }
 
 template <typename T>
-void launch_pcg_spmv(hipStream_t s, int k, int Gs, int Gv, MatView A, const v4<T>* z, const v4<T>* p_old,
-                     v4<T>* p_new, v4<T>* q, PcgCtl* ctl, const double* part_rz, double* part_pq, double thr2) {
+void launch_pcg_spmv(hipStream_t s, int k, int Gb, int Ga, MatView A, const v4<T>* z, const v4<T>* p_old,
+                     v4<T>* p_new, v4<T>* q, PcgCtl* ctl, const double* part_rz, double* part_pq, double rel2) {
   if (k == 0)
-    k_pcg_spmv<T, false><<<Gs, kThreads, 0, s>>>(k, Gv, A, z, p_old, p_new, q, ctl, part_rz, part_pq, thr2);
+    k_pcg_spmv<T, false, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(k, Ga, A, z, p_old, p_new, q, ctl, part_rz, part_pq,
+                                                               rel2);
   else
-    k_pcg_spmv<T, true><<<Gs, kThreads, 0, s>>>(k, Gv, A, z, p_old, p_new, q, ctl, part_rz, part_pq, thr2);
+    k_pcg_spmv<T, true, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(k, Ga, A, z, p_old, p_new, q, ctl, part_rz, part_pq,
+                                                              rel2);
 }
 
 template <typename T>
-void launch_pcg_update(hipStream_t s, int k, int n, int Gv, int Gs, const v4<T>* p, const v4<T>* q, v4<T>* x,
+void launch_pcg_update(hipStream_t s, int k, int n, int Ga, int Gb, const v4<T>* p, const v4<T>* q, v4<T>* x,
                        v4<T>* r, v4<T>* z, const T* binv, PcgCtl* ctl, const double* part_pq, double* part_rz) {
-  k_pcg_update<T><<<Gv, kThreads, 0, s>>>(k, n, Gs, p, q, x, r, z, binv, ctl, part_pq, part_rz);
+  k_pcg_update<T, kVecThreads><<<Ga, kVecThreads, 0, s>>>(k, n, Gb, p, q, x, r, z, binv, ctl, part_pq, part_rz);
 }
 
 template <typename T>

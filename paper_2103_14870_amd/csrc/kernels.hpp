@@ -5,9 +5,9 @@
 //   tets           : int4 node ids; tet_edge SoA [6][m]; flip bits [m]
 //   block matrix   : BSR 3x3, values SoA [9][nbp] (component-major, so the
 //                    lanes of a wave read consecutive blocks with unit stride)
-//   contributions  : SoA [10][6][m] (9 block entries + 1 force weight per
-//                    tet edge), written coalesced by the element pass and
-//                    gathered per edge by the edge pass
+//   contributions  : [6][m][10] (9 block entries + 1 force weight per tet
+//                    edge, 40 B per record), written tet-major by the element
+//                    pass and read as whole records per edge by the edge pass
 // No floating-point atomics anywhere: every sum has a fixed order, so a step
 // is bitwise reproducible.
 #pragma once
@@ -25,14 +25,17 @@ struct alignas(4 * sizeof(T)) v4 {
 using d4 = v4<double>;
 
 constexpr int kThreads = 256;     // 4 waves of 64
-constexpr int kMaxPart = 1024;    // max workgroups that leave a reduction partial
+constexpr int kMaxPart = 2048;    // max workgroups that leave a reduction partial
 constexpr int kRowLanes = 16;     // lanes cooperating on one block row in the SpMV
+constexpr int kSpmvThreads = 256; // workgroup size of the PCG SpMV
+constexpr int kVecThreads = 256;  // workgroup size of the PCG vector kernels
 
 struct PcgCtl {
   int done;   // set once converged or broken down; every later PCG kernel exits at entry
   int fail;   // 1: p.Ap <= 0 (operator not SPD on the Krylov space)
   int iters;  // iterations completed (x holds x_iters)
   int pad;
+  double thr2;  // stopping threshold on |r|^2, set by the first SpMV of a solve
 };
 
 struct MatView {
@@ -42,8 +45,13 @@ struct MatView {
   const void* val;  // T[9][nbp]
 };
 
+// Event counters, spread over kCtrSlots cache-line-sized slots so that the
+// per-workgroup atomics do not contend on one address; the host sums slots.
+constexpr int kCtrSlots = 64;
+constexpr int kCtrStride = 32;  // ints per slot (128 B)
+enum CounterField { kNewBroken = 0, kTotalBroken, kNearThreshold, kChiZero, kDegenerate, kNumCounters };
 struct Counters {
-  int new_broken, total_broken, near_threshold, chi_zero, degenerate, pad[3];
+  int v[kCtrSlots * kCtrStride];
 };
 
 struct ElemConst {
@@ -83,19 +91,22 @@ void launch_row(hipStream_t s, int n, int G, MatView A, const int32_t* diag_blk,
                 const uint8_t* dflag, const d4* dvel, RowConst c, T* val_mut, d4* b,
                 d4* X64, T* binv, d4* f_out, double* part_bb);
 
+// Ga: workgroups (kVecThreads each) of the vector kernels; Gb: workgroups
+// (kSpmvThreads each) of the SpMV.  Both multiples of 8.  rel2: squared relative
+// reduction of |r| the solve must reach (threshold = rel2 |r_0|^2).
 template <typename T>
-void launch_pcg_init(hipStream_t s, int n, int G, const d4* src, const T* binv, v4<T>* r,
-                     v4<T>* z, v4<T>* p0, v4<T>* x, double* part_rz0);
+void launch_pcg_init(hipStream_t s, int n, int Ga, const d4* src, const T* binv, v4<T>* r, v4<T>* z,
+                     v4<T>* p0, v4<T>* x, double* part_rz);
 
 template <typename T>
-void launch_pcg_spmv(hipStream_t s, int k, int Gs, int Gv, MatView A, const v4<T>* z,
-                     const v4<T>* p_old, v4<T>* p_new, v4<T>* q, PcgCtl* ctl,
-                     const double* part_rz, double* part_pq, double thr2);
+void launch_pcg_spmv(hipStream_t s, int k, int Gb, int Ga, MatView A, const v4<T>* z, const v4<T>* p_old,
+                     v4<T>* p_new, v4<T>* q, PcgCtl* ctl, const double* part_rz, double* part_pq,
+                     double rel2);
 
 template <typename T>
-void launch_pcg_update(hipStream_t s, int k, int n, int Gv, int Gs, const v4<T>* p,
-                       const v4<T>* q, v4<T>* x, v4<T>* r, v4<T>* z, const T* binv, PcgCtl* ctl,
-                       const double* part_pq, double* part_rz);
+void launch_pcg_update(hipStream_t s, int k, int n, int Ga, int Gb, const v4<T>* p, const v4<T>* q,
+                       v4<T>* x, v4<T>* r, v4<T>* z, const T* binv, PcgCtl* ctl, const double* part_pq,
+                       double* part_rz);
 
 template <typename T>
 void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, d4* R64,
