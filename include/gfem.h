@@ -159,6 +159,43 @@ gf_status gf_set_timing(gf_mesh* m, int32_t on);
  * mean duration in microseconds and the algorithmic bytes per launch. */
 gf_status gf_bench_spmv(gf_mesh* m, int32_t reps, double* us_per_launch, double* bytes_per_launch);
 
+/* ---------------------------------------------------------------------------
+ * Learned block preconditioner (an addition to the paper, whose solver is plain
+ * conjugate gradients).  A message-passing network on the mesh graph maps edge
+ * features (rest length, current length, damage label) to a lower-triangular
+ * L_i per node; the preconditioner block is B_i = L_i A_ii^-1 L_i^T, which is
+ * block-Jacobi for L = I.  Inference and training run on the GPU in BF16 with
+ * FP32 accumulation.  A learned solve is accepted only at the same FP64 residual;
+ * otherwise the step is re-solved with block-Jacobi (gf_step_stats.used_fallback).
+ * Only the split precision mode supports the learned preconditioner.
+ * ------------------------------------------------------------------------- */
+typedef struct gf_net gf_net; /* opaque, owned by the library from create to destroy */
+
+/* Create a network on the current device: He-initialised layers, zero head
+ * (so it starts as block-Jacobi).  Deterministic in seed. */
+gf_status gf_net_create(uint64_t seed, gf_net** out);
+gf_status gf_net_destroy(gf_net* net);
+/* Number of FP32 parameters (same for every network). */
+gf_status gf_net_num_params(int32_t* n);
+/* FP32 master weights in this order: W0 (64x8), b0 (64), then for each of 3
+ * layers W (64x128, columns 0-63 act on h, 64-127 on the neighbour mean), b (64),
+ * then Wh (6x64), bh (6); matrices row-major [out][in]. */
+gf_status gf_net_get_weights(const gf_net* net, float* w_out);
+gf_status gf_net_set_weights(gf_net* net, const float* w); /* also resets the optimiser */
+/* Attach (borrowed: must outlive its use) or detach (NULL) the network used by
+ * GF_PC_LEARNED steps, and select the preconditioner of the following steps. */
+gf_status gf_set_precond_net(gf_mesh* m, gf_net* net);
+gf_status gf_set_precond(gf_mesh* m, int32_t precond);
+/* One training step on the system of the mesh's next timestep at its current
+ * state (assembled and solved with block-Jacobi to tolerance, not committed):
+ * loss = sum over free nodes |B_i b_i - dv_i|^2 / sum |dv_i|^2, gradient by the
+ * network's backward pass, one Adam step (lr).  loss_out may be NULL. */
+gf_status gf_net_train_step(gf_net* net, gf_mesh* m, double lr, double* loss_out);
+/* Same system, no update: loss, the preconditioner blocks (n_nodes*6 floats,
+ * caller node order, entries 00 11 22 01 02 12) and the weight gradient
+ * (gf_net_num_params floats).  Outputs may be NULL.  Test hook. */
+gf_status gf_net_eval(gf_net* net, gf_mesh* m, double* loss_out, float* blocks_out, float* grad_out);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char* gf_last_error(void);
 

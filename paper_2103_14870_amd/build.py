@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgfem.so")
-SOURCES = ["gfem.hip", "kernels.hip", "topo.cpp"]
+SOURCES = ["gfem.hip", "kernels.hip", "net.hip", "topo.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

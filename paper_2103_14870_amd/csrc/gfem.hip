@@ -11,11 +11,13 @@
 #include <exception>
 #include <memory>
 #include <new>
+#include <random>
 #include <string>
 #include <vector>
 
 #include "../../include/gfem.h"
 #include "kernels.hpp"
+#include "net.hpp"
 #include "topo.hpp"
 
 using gfem::d4;
@@ -85,6 +87,14 @@ int round_up8(int x) { return (x + 7) / 8 * 8; }
 
 }  // namespace
 
+struct gf_net {
+  int dev = 0;
+  Alloc al;
+  gfem::NetParamsDev P;
+  std::vector<float> host;  // master weights (host copy, kept in sync)
+  int adam_t = 0;
+};
+
 struct gf_mesh {
   gfem::Topology topo;
   gf_params p{};
@@ -136,6 +146,13 @@ struct gf_mesh {
   size_t ev_used = 0;
   std::vector<TimeRec> recs;
   std::vector<int> solve_iters;
+  // learned preconditioner
+  gf_net* net = nullptr;
+  int precond = GF_PC_BLOCK_JACOBI;
+  bool netw_ready = false, net_cached = false;
+  int net_age = 0;
+  double inv_mean_len = 1.0;
+  gfem::NetWork netw;
 
   ~gf_mesh() {
     if (stream) (void)hipStreamSynchronize(stream);
@@ -273,7 +290,7 @@ struct SolveResult {
 // vectors, FP64 dot products, device-side scalars and early exit, launched in
 // chunks so the host only synchronises once per chunk.
 template <typename T>
-SolveResult solve(gf_mesh* M) {
+SolveResult solve(gf_mesh* M, const void* precond_blocks) {
   hipStream_t s = M->stream;
   const double tol = M->p.cg_rel_tol;
   SolveResult res{false, 0, 0, 0.0};
@@ -287,7 +304,7 @@ SolveResult solve(gf_mesh* M) {
   v4<T>* q = static_cast<v4<T>*>(M->vq);
   v4<T>* x = static_cast<v4<T>*>(M->vx);
   v4<T>* pb[2] = {static_cast<v4<T>*>(M->vp[0]), static_cast<v4<T>*>(M->vp[1])};
-  const T* binv = static_cast<const T*>(M->binv);
+  const T* binv = static_cast<const T*>(precond_blocks);
   for (int outer = 0;; ++outer) {
     if (outer > 0) {
       res.rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
@@ -361,16 +378,85 @@ SolveResult solve(gf_mesh* M) {
   return res;
 }
 
+void ensure_netw(gf_mesh* M) {
+  if (M->netw_ready) return;
+  gfem::NetWork& w = M->netw;
+  w.n = M->n;
+  w.npad = (M->n + gfem::kNetRows - 1) / gfem::kNetRows * gfem::kNetRows;
+  w.nwg_dw = 256;
+  const size_t np = w.npad;
+  w.a = M->al.get<gfem::bf16>(np * gfem::kNetInPad);
+  w.inv_wdeg = M->al.get<float>(np);
+  for (auto& h : w.h) h = M->al.get<gfem::bf16>(np * gfem::kHid);
+  for (auto& m : w.m) m = M->al.get<gfem::bf16>(np * gfem::kHid);
+  for (auto& z : w.z) z = M->al.get<gfem::bf16>(np * gfem::kHid);
+  w.o = M->al.get<float>(np * 8);
+  w.B = M->al.get<float>(6 * (size_t)M->n);
+  w.gh = M->al.get<float>(np * gfem::kHid);
+  w.gz = M->al.get<gfem::bf16>(np * gfem::kHid);
+  w.gi = M->al.get<float>(np * 2 * gfem::kHid);
+  w.go = M->al.get<float>(np * 8);
+  w.part = M->al.get<float>((size_t)w.nwg_dw * (gfem::kHid * 2 * gfem::kHid + gfem::kHid));
+  w.grad = M->al.get<float>(gfem::kNetParams);
+  w.lossp = M->al.get<double>(np / 256 + 2);
+  double sum = 0;
+  for (int e = 0; e < M->ne; ++e) sum += std::sqrt(M->topo.edge_S[e]);
+  M->inv_mean_len = M->ne > 0 ? M->ne / sum : 1.0;
+  M->netw_ready = true;
+}
+
+gfem::NetInputs net_inputs(gf_mesh* M, const uint8_t* zeta) {
+  return gfem::NetInputs{M->n,        M->mat(),  M->diag_blk, M->blk_edge, M->X, M->U, zeta, M->inv_mean_len,
+                         static_cast<const float*>(M->binv), M->dflag};
+}
+
+// Preconditioner blocks of the learned path for the assembled step: the
+// network runs every net_every_n_steps steps; in between the cached head
+// outputs are combined with the current A_ii^-1.
+void learned_precond(gf_mesh* M) {
+  ensure_netw(M);
+  const gfem::NetInputs in = net_inputs(M, M->zeta[1 - M->zcur]);
+  const int every = std::max(1, (int)M->p.net_every_n_steps);
+  M->timed(3, -1, 0, [&] {
+    if (!M->net_cached || M->net_age >= every) {
+      gfem::net_forward(M->stream, M->net->P, M->netw, in);
+      M->net_cached = true;
+      M->net_age = 0;
+    } else {
+      gfem::net_apply_cached(M->stream, M->net->P, M->netw, in);
+    }
+  });
+  ++M->net_age;
+  M->check_launch();
+}
+
 template <typename T>
 gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
   for (int i = 0; i < n_steps; ++i) {
     assemble<T>(M, true, nullptr);
     hchk(hipMemcpyAsync(M->h_ctr, M->ctr, sizeof(gfem::Counters), hipMemcpyDeviceToHost, M->stream), "D2H");
-    SolveResult r = solve<T>(M);
+    SolveResult r;
+    int fallback = 0;
+    if (M->precond == GF_PC_LEARNED) {
+      // network blocks B_i = L_i A_ii^-1 L_i^T; block-Jacobi re-solve if not accepted
+      learned_precond(M);
+      r = solve<T>(M, M->netw.B);
+      if (!r.ok) {
+        fallback = 1;
+        hchk(hipMemsetAsync(M->X64, 0, sizeof(d4) * M->n, M->stream), "hipMemsetAsync");
+        const int prev_inner = r.inner, prev_outer = r.outer;
+        r = solve<T>(M, M->binv);
+        r.inner += prev_inner;
+        r.outer += prev_outer;
+      }
+    } else {
+      r = solve<T>(M, M->binv);
+    }
     int cnt[gfem::kNumCounters] = {0, 0, 0, 0, 0};
     for (int sl = 0; sl < gfem::kCtrSlots; ++sl)
       for (int c = 0; c < gfem::kNumCounters; ++c) cnt[c] += M->h_ctr->v[sl * gfem::kCtrStride + c];
     if (st) {
+      st->used_fallback += fallback;
       st->inner_iters += r.inner;
       st->outer_iters += r.outer;
       st->rel_residual = r.rel;
@@ -431,7 +517,8 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
       !(p.cg_rel_tol > 0) || p.cg_max_iter <= 0 || (p.precision != GF_PREC_FP64 && p.precision != GF_PREC_SPLIT) ||
       (p.precond != GF_PC_BLOCK_JACOBI && p.precond != GF_PC_LEARNED) || !std::isfinite(p.damage_strain))
     return fail(GF_EINVAL, "gf_mesh_create: invalid parameters");
-  if (p.precond == GF_PC_LEARNED) return fail(GF_ESTATE, "gf_mesh_create: learned preconditioner needs weights");
+  if (p.precond == GF_PC_LEARNED && p.precision != GF_PREC_SPLIT)
+    return fail(GF_EINVAL, "gf_mesh_create: the learned preconditioner needs the split precision mode");
   std::unique_ptr<gf_mesh> holder;
   GF_TRY({
     // Host-side validation and topology first: errors in the input are
@@ -454,6 +541,7 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     M->p = p;
     M->split = p.precision == GF_PREC_SPLIT;
     M->plastic = p.yield_strain > 0;
+    M->precond = p.precond;
     M->topo = std::move(*topo);
     const gfem::Topology& T = M->topo;
     M->n = T.n;
@@ -607,6 +695,8 @@ gf_status gf_step(gf_mesh* m, int32_t n_steps, gf_step_stats* stats) {
   if (gf_status s = guard(m, "gf_step")) return s;
   if (n_steps < 0) return fail(GF_EINVAL, "gf_step: negative step count");
   if (stats) std::memset(stats, 0, sizeof *stats);
+  if (m->precond == GF_PC_LEARNED && !m->net)
+    return fail(GF_ESTATE, "gf_step: learned preconditioner selected but no network attached");
   GF_TRY({
     return m->split ? step_impl<float>(m, n_steps, stats) : step_impl<double>(m, n_steps, stats);
   })
@@ -842,6 +932,163 @@ gf_status gf_bench_spmv(gf_mesh* m, int32_t reps, double* us_per_launch, double*
     *us_per_launch = 1000.0 * ms / reps;
     return GF_OK;
   })
+}
+
+// ---------------------------------------------------------------- learned preconditioner
+
+gf_status gf_net_num_params(int32_t* n) {
+  if (!n) return fail(GF_EINVAL, "gf_net_num_params: null output");
+  *n = gfem::kNetParams;
+  return GF_OK;
+}
+
+gf_status gf_net_create(uint64_t seed, gf_net** out) {
+  if (!out) return fail(GF_EINVAL, "gf_net_create: null output");
+  *out = nullptr;
+  std::unique_ptr<gf_net> holder;
+  GF_TRY({
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(GF_EDEVICE, "no HIP device");
+    holder.reset(new gf_net());
+    gf_net* net = holder.get();
+    hchk(hipGetDevice(&net->dev), "hipGetDevice");
+    gfem::NetParamsDev& P = net->P;
+    P.master = net->al.get<float>(gfem::kNetParams);
+    P.adam_m = net->al.get<float>(gfem::kNetParams);
+    P.adam_v = net->al.get<float>(gfem::kNetParams);
+    P.W0 = net->al.get<gfem::bf16>(gfem::kHid * gfem::kNetInPad);
+    for (int l = 0; l < gfem::kNetLayers; ++l) {
+      P.Wl[l] = net->al.get<gfem::bf16>(gfem::kHid * 2 * gfem::kHid);
+      P.WlT[l] = net->al.get<gfem::bf16>(gfem::kHid * 2 * gfem::kHid);
+    }
+    // He-style initial layers, zero biases and zero head (block-Jacobi at start)
+    net->host.assign(gfem::kNetParams, 0.f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (int i = 0; i < gfem::kHid * gfem::kNetIn; ++i)
+      net->host[gfem::kOffW0 + i] = (float)(nd(rng) * std::sqrt(2.0 / gfem::kNetIn));
+    for (int l = 0; l < gfem::kNetLayers; ++l)
+      for (int i = 0; i < gfem::kHid * 2 * gfem::kHid; ++i)
+        net->host[gfem::kOffL0 + l * gfem::kLayerSize + i] = (float)(nd(rng) * std::sqrt(2.0 / (2 * gfem::kHid)));
+    hchk(hipMemcpy(P.master, net->host.data(), sizeof(float) * gfem::kNetParams, hipMemcpyHostToDevice), "H2D");
+    gfem::net_pack(nullptr, P);
+    hchk(hipGetLastError(), "kernel launch");
+    hchk(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    *out = holder.release();
+    return GF_OK;
+  })
+}
+
+gf_status gf_net_destroy(gf_net* net) {
+  if (net) {
+    (void)hipDeviceSynchronize();
+    delete net;
+  }
+  return GF_OK;
+}
+
+gf_status gf_net_get_weights(const gf_net* net, float* w_out) {
+  if (!net || !w_out) return fail(GF_EINVAL, "gf_net_get_weights: null argument");
+  std::memcpy(w_out, net->host.data(), sizeof(float) * gfem::kNetParams);
+  return GF_OK;
+}
+
+gf_status gf_net_set_weights(gf_net* net, const float* w) {
+  if (!net || !w) return fail(GF_EINVAL, "gf_net_set_weights: null argument");
+  for (int i = 0; i < gfem::kNetParams; ++i)
+    if (!std::isfinite(w[i])) return fail(GF_EINVAL, "gf_net_set_weights: non-finite weight");
+  GF_TRY({
+    hchk(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    net->host.assign(w, w + gfem::kNetParams);
+    hchk(hipMemcpy(net->P.master, w, sizeof(float) * gfem::kNetParams, hipMemcpyHostToDevice), "H2D");
+    hchk(hipMemset(net->P.adam_m, 0, sizeof(float) * gfem::kNetParams), "hipMemset");
+    hchk(hipMemset(net->P.adam_v, 0, sizeof(float) * gfem::kNetParams), "hipMemset");
+    net->adam_t = 0;
+    gfem::net_pack(nullptr, net->P);
+    hchk(hipGetLastError(), "kernel launch");
+    hchk(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    return GF_OK;
+  })
+}
+
+gf_status gf_set_precond_net(gf_mesh* m, gf_net* net) {
+  if (gf_status s = guard(m, "gf_set_precond_net")) return s;
+  if (net && !m->split) return fail(GF_EINVAL, "gf_set_precond_net: needs the split precision mode");
+  if (net && net->dev != m->dev) return fail(GF_EINVAL, "gf_set_precond_net: network on another device");
+  m->net = net;
+  m->net_cached = false;
+  return GF_OK;
+}
+
+gf_status gf_set_precond(gf_mesh* m, int32_t precond) {
+  if (gf_status s = guard(m, "gf_set_precond")) return s;
+  if (precond != GF_PC_BLOCK_JACOBI && precond != GF_PC_LEARNED) return fail(GF_EINVAL, "gf_set_precond: bad value");
+  if (precond == GF_PC_LEARNED && !m->split) return fail(GF_EINVAL, "gf_set_precond: needs the split precision mode");
+  m->precond = precond;
+  m->net_cached = false;
+  return GF_OK;
+}
+
+static gf_status net_train_eval(gf_net* net, gf_mesh* m, bool train, double lr, double* loss_out, float* blocks_out,
+                                float* grad_out, const char* who) {
+  if (!net || !m) return fail(GF_EINVAL, std::string(who) + ": null argument");
+  if (!m->split) return fail(GF_EINVAL, std::string(who) + ": needs the split precision mode");
+  if (net->dev != m->dev) return fail(GF_EINVAL, std::string(who) + ": network on another device");
+  if (train && !(lr > 0.0 && std::isfinite(lr))) return fail(GF_EINVAL, std::string(who) + ": bad learning rate");
+  GF_TRY({
+    hipStream_t s = m->stream;
+    ensure_netw(m);
+    assemble<float>(m, true, nullptr);
+    const SolveResult r = solve<float>(m, m->binv);
+    m->recs.clear();
+    m->ev_used = 0;
+    m->solve_iters.clear();
+    if (!r.ok) return fail(GF_ENOTCONVERGED, std::string(who) + ": block-Jacobi solve of the training system failed");
+    const gfem::NetInputs in = net_inputs(m, m->zeta[1 - m->zcur]);
+    gfem::net_forward(s, net->P, m->netw, in);
+    const int nd = gfem::net_dv_norm(s, m->n, m->X64, m->dflag, m->netw.lossp);
+    const double D = read_partials(m, m->netw.lossp, nd);
+    double loss = 0.0;
+    if (D > 0.0) {
+      const int nl = gfem::net_backward(s, net->P, m->netw, in, m->b, m->X64, 1.0 / D);
+      m->check_launch();
+      loss = read_partials(m, m->netw.lossp, nl);
+      if (train) {
+        ++net->adam_t;
+        gfem::net_adam(s, net->P, m->netw.grad, net->adam_t, (float)lr);
+        m->check_launch();
+        hchk(hipMemcpyAsync(net->host.data(), net->P.master, sizeof(float) * gfem::kNetParams, hipMemcpyDeviceToHost,
+                            s),
+             "D2H");
+      }
+    } else {
+      hchk(hipMemsetAsync(m->netw.grad, 0, sizeof(float) * gfem::kNetParams, s), "hipMemsetAsync");
+    }
+    if (grad_out)
+      hchk(hipMemcpyAsync(grad_out, m->netw.grad, sizeof(float) * gfem::kNetParams, hipMemcpyDeviceToHost, s), "D2H");
+    std::vector<float> hb;
+    if (blocks_out) {
+      hb.resize(6 * (size_t)m->n);
+      hchk(hipMemcpyAsync(hb.data(), m->netw.B, sizeof(float) * hb.size(), hipMemcpyDeviceToHost, s), "D2H");
+    }
+    m->sync();
+    if (blocks_out)
+      for (int c = 0; c < m->n; ++c) {
+        const int i = m->topo.perm_new[c];
+        for (int q = 0; q < 6; ++q) blocks_out[6 * (size_t)c + q] = hb[(size_t)q * m->n + i];
+      }
+    if (loss_out) *loss_out = loss;
+    m->net_cached = false;
+    return GF_OK;
+  })
+}
+
+gf_status gf_net_train_step(gf_net* net, gf_mesh* m, double lr, double* loss_out) {
+  return net_train_eval(net, m, true, lr, loss_out, nullptr, nullptr, "gf_net_train_step");
+}
+
+gf_status gf_net_eval(gf_net* net, gf_mesh* m, double* loss_out, float* blocks_out, float* grad_out) {
+  return net_train_eval(net, m, false, 0.0, loss_out, blocks_out, grad_out, "gf_net_eval");
 }
 
 }  // extern "C"

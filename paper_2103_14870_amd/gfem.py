@@ -71,6 +71,15 @@ _SIGS = {
     "gf_set_timing": ([C.c_void_p, C.c_int32], C.c_int),
     "gf_bench_spmv": ([C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_double)], C.c_int),
     "gf_last_error": ([], C.c_char_p),
+    "gf_net_create": ([C.c_uint64, _P(C.c_void_p)], C.c_int),
+    "gf_net_destroy": ([C.c_void_p], C.c_int),
+    "gf_net_num_params": ([_P(C.c_int32)], C.c_int),
+    "gf_net_get_weights": ([C.c_void_p, _P(C.c_float)], C.c_int),
+    "gf_net_set_weights": ([C.c_void_p, _P(C.c_float)], C.c_int),
+    "gf_set_precond_net": ([C.c_void_p, C.c_void_p], C.c_int),
+    "gf_set_precond": ([C.c_void_p, C.c_int32], C.c_int),
+    "gf_net_train_step": ([C.c_void_p, C.c_void_p, C.c_double, _P(C.c_double)], C.c_int),
+    "gf_net_eval": ([C.c_void_p, C.c_void_p, _P(C.c_double), _P(C.c_float), _P(C.c_float)], C.c_int),
 }
 
 
@@ -248,6 +257,63 @@ class Mesh:
         us, by = C.c_double(), C.c_double()
         _check(self._lib.gf_bench_spmv(self._h, int(reps), C.byref(us), C.byref(by)))
         return us.value, by.value
+
+
+class Net:
+    """Learned block preconditioner network (lives on the current HIP device)."""
+
+    def __init__(self, seed: int = 0):
+        self._lib = load()
+        self._h = C.c_void_p()
+        _check(self._lib.gf_net_create(C.c_uint64(seed), C.byref(self._h)))
+        n = C.c_int32()
+        _check(self._lib.gf_net_num_params(C.byref(n)))
+        self.n_params = n.value
+
+    def close(self):
+        if self._h:
+            self._lib.gf_net_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_weights(self) -> np.ndarray:
+        w = np.zeros(self.n_params, np.float32)
+        _check(self._lib.gf_net_get_weights(self._h, w.ctypes.data_as(_P(C.c_float))))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.size != self.n_params:
+            raise ValueError("wrong number of weights")
+        _check(self._lib.gf_net_set_weights(self._h, w.ctypes.data_as(_P(C.c_float))))
+
+    def train_step(self, mesh: "Mesh", lr: float) -> float:
+        loss = C.c_double()
+        _check(self._lib.gf_net_train_step(self._h, mesh._h, float(lr), C.byref(loss)))
+        return loss.value
+
+    def eval(self, mesh: "Mesh"):
+        """(loss, blocks (n,6) [00 11 22 01 02 12], weight gradient)."""
+        loss = C.c_double()
+        blocks = np.zeros((mesh.n_nodes, 6), np.float32)
+        grad = np.zeros(self.n_params, np.float32)
+        _check(self._lib.gf_net_eval(self._h, mesh._h, C.byref(loss), blocks.ctypes.data_as(_P(C.c_float)),
+                                     grad.ctypes.data_as(_P(C.c_float))))
+        return loss.value, blocks, grad
+
+
+def attach_net(mesh: "Mesh", net: "Net | None", use: bool = True):
+    _check(load().gf_set_precond_net(mesh._h, net._h if net is not None else None))
+    _check(load().gf_set_precond(mesh._h, PRECOND["learned"] if (use and net is not None) else 0))
+
+
+def set_precond(mesh: "Mesh", name: str):
+    _check(load().gf_set_precond(mesh._h, PRECOND[name]))
 
 
 def mesh_from_problem(prob) -> Mesh:
