@@ -16,7 +16,12 @@ Architecture (all sizes fixed):
               h <- h + relu(Wl [h; m] + bl)                 (128 -> 64)
   head:       o = Wh h + bh                                 (64 -> 6)
   L = [[e^o0, 0, 0], [o3, e^o1, 0], [o4, o5, e^o2]]
-Loss for one system A dv* = b: sum over free nodes |B_i b_i - dv*_i|^2 / sum |dv*_i|^2.
+Two losses for one system A dv* = b:
+  "solution": sum over free nodes |B_i b_i - dv*_i|^2 / sum |dv*_i|^2;
+  "cg_step" (scale-invariant): log of the A-norm error left by one optimal
+      preconditioned conjugate-gradient step from zero,
+      log(u^T A u) - 2 log(b^T u) + log(b^T dv*) with u = B b
+      (B on prescribed nodes fixed to A_ii^-1).
 
 The backward pass is written out by hand; tests pin it to finite differences.
 """
@@ -144,20 +149,33 @@ def precond_blocks(o: np.ndarray, Aii: np.ndarray) -> np.ndarray:
 
 
 def loss_and_grad(w: np.ndarray, a: np.ndarray, P, PT, Aii: np.ndarray, b: np.ndarray, dv: np.ndarray,
-                  free: np.ndarray):
-    """Loss of one system and its gradient with respect to the flat weights."""
+                  free: np.ndarray, A=None, kind: str = "solution"):
+    """Loss of one system and its gradient with respect to the flat weights.
+    kind "cg_step" needs the assembled matrix A (3n x 3n)."""
     p = unflatten(w)
     c = forward(w, a, P)
     o = c["o"]
     L = lower_factor(o)
     C = np.linalg.inv(Aii)
     B = L @ C @ np.transpose(L, (0, 2, 1))
-    r = np.einsum("nij,nj->ni", B, b) - dv
-    r = r * free[:, None]
-    D = float(np.sum((dv * free[:, None]) ** 2))
-    loss = float(np.sum(r * r)) / D
-    # dloss/dB = 2 r b^T / D ; dloss/dL = (G + G^T) L C
-    G = 2.0 * np.einsum("ni,nj->nij", r, b) / D
+    if kind == "solution":
+        r = np.einsum("nij,nj->ni", B, b) - dv
+        r = r * free[:, None]
+        D = float(np.sum((dv * free[:, None]) ** 2))
+        loss = float(np.sum(r * r)) / D
+        # dloss/dB = 2 r b^T / D
+        G = 2.0 * np.einsum("ni,nj->nij", r, b) / D
+    else:
+        Bf = np.where(free[:, None, None] > 0, B, C)
+        u = np.einsum("nij,nj->ni", Bf, b)
+        wv = (A @ u.ravel()).reshape(-1, 3)
+        s_ = float(np.sum(b * u))
+        q_ = float(np.sum(u * wv))
+        loss = np.log(q_) - 2.0 * np.log(s_) + np.log(float(np.sum(b * dv)))
+        # dloss/dB_i = (2/q) w_i b_i^T - (2/s) b_i b_i^T on free nodes
+        G = (2.0 / q_) * np.einsum("ni,nj->nij", wv, b) - (2.0 / s_) * np.einsum("ni,nj->nij", b, b)
+        G = G * free[:, None, None]
+    # dloss/dL = (G + G^T) L C
     GL = np.einsum("nij,njk,nkl->nil", G + np.transpose(G, (0, 2, 1)), L, C)
     go = np.zeros_like(o)
     go[:, 0] = GL[:, 0, 0] * L[:, 0, 0]

@@ -24,6 +24,7 @@ def small_system(seed=0):
     f = N.edge_features(prob.X, st.x, mesh.edges, zeta)
     a = N.node_inputs(prob.n_nodes, mesh.edges, f)
     P, PT = N.mean_operator(prob.n_nodes, mesh.edges, zeta)
+    small_system.A = sysm.A
     return a, P, PT, Aii, b, d, free, mesh, zeta
 
 
@@ -49,10 +50,13 @@ def test_identity_head_is_block_jacobi():
     np.testing.assert_allclose(B, np.linalg.inv(Aii), rtol=1e-12, atol=1e-14)
 
 
-def test_backward_matches_finite_differences():
+@pytest.mark.parametrize("kind", ["solution", "cg_step"])
+def test_backward_matches_finite_differences(kind):
     a, P, PT, Aii, b, d, free, *_ = small_system(4)
+    A = small_system.A
     w = N.init_weights(5, head_scale=0.05)
-    loss, g, _ = N.loss_and_grad(w, a, P, PT, Aii, b, d, free)
+    lg = lambda ww: N.loss_and_grad(ww, a, P, PT, Aii, b, d, free, A=A, kind=kind)
+    loss, g, _ = lg(w)
     rng = np.random.default_rng(6)
     idx = rng.choice(N.N_PARAMS, 40, replace=False)
     names = np.concatenate([[nm] * int(np.prod(s)) for nm, s in N.SHAPES])
@@ -62,7 +66,7 @@ def test_backward_matches_finite_differences():
         wp, wm = w.copy(), w.copy()
         wp[i] += h
         wm[i] -= h
-        fd = (N.loss_and_grad(wp, a, P, PT, Aii, b, d, free)[0] - N.loss_and_grad(wm, a, P, PT, Aii, b, d, free)[0]) / (2 * h)
+        fd = (lg(wp)[0] - lg(wm)[0]) / (2 * h)
         assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-9 * max(1.0, abs(loss))), (i, names[i])
 
 
@@ -80,3 +84,20 @@ def test_loss_is_zero_for_the_exact_inverse_on_a_decoupled_system():
     P, PT = N.mean_operator(n, edges, zeta)
     loss, g, _ = N.loss_and_grad(N.init_weights(1), a, P, PT, Aii, b, dv, np.ones(n))
     assert loss < 1e-25
+
+
+def test_cg_step_loss_is_the_one_step_energy_error():
+    # log of |dv* - x1|_A^2 / |dv*|_A^2 for the optimal first step x1 = t B b
+    a, P, PT, Aii, b, d, free, *_ = small_system(8)
+    A = small_system.A
+    w = N.init_weights(9, head_scale=0.05)
+    loss, _, B = N.loss_and_grad(w, a, P, PT, Aii, b, d, free, A=A, kind="cg_step")
+    Bf = np.where(free[:, None, None] > 0, B, np.linalg.inv(Aii))
+    u = np.einsum("nij,nj->ni", Bf, b).ravel()
+    x = d.ravel()
+    t = (b.ravel() @ u) / (u @ (A @ u))
+    e = x - t * u
+    ratio = (e @ (A @ e)) / (x @ (A @ x))
+    # one-step error energy = 1 - exp(-loss)... loss = log(q) - 2 log(s) + log(b.x) = -log(1 - ratio)
+    assert loss == pytest.approx(-np.log(1 - ratio), rel=1e-10)
+    assert 0 <= ratio < 1
