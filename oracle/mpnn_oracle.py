@@ -1,12 +1,20 @@
-"""FP64 CPU oracle of the learned block preconditioner (message-passing network).
+"""FP64 CPU oracle of the learned preconditioner (message-passing network).
 
 TEST INFRASTRUCTURE ONLY (see gfem_oracle.py).  Not part of the paper: the
-paper solves with plain conjugate gradients.  This network predicts, per mesh
-node i, a lower-triangular 3x3 factor L_i (exponentiated diagonal) and the
-preconditioner block B_i = L_i A_ii^-1 L_i^T, so L = I is exactly 3x3
-block-Jacobi and every B_i is symmetric positive definite.
+paper solves with plain conjugate gradients.
 
-Architecture (all sizes fixed):
+Preconditioner family (factorised sparse approximate inverse): B = G^T G with
+G block lower triangular on the lower block pattern of A (3x3 blocks, node
+order):
+    G_ii = L_i C_i,        C_i = inverse of the lower Cholesky factor of A_ii,
+    G_ij = -L_i C_i W_ij A_ij A_jj^-1      for every stored block j < i,
+L_i lower triangular with exponentiated diagonal and W_ij a 3x3 block, both
+predicted by the network.  L = I, W = 0 gives B = blockdiag(A_ii^-1), i.e.
+3x3 block-Jacobi; W = w I is a damped first-order (Neumann) approximation of
+the inverse Cholesky factor.  Prescribed nodes keep G_ii = I (their rows and
+columns of A are the identity).
+
+Network (all sizes fixed):
   edge features (per edge i-j): f = (rest length / mean rest length,
       current length / rest length - 1, zeta)
   node input a_i (8): 1, and means over the incident edges of
@@ -14,31 +22,42 @@ Architecture (all sizes fixed):
   embedding:  h0 = relu(W0 a + b0)                         (8 -> 64)
   3 layers:   m = P h  (mean over unbroken incident edges, P_ij = w_ij / sum_j w_ij, w = 1 - zeta)
               h <- h + relu(Wl [h; m] + bl)                 (128 -> 64)
-  head:       o = Wh h + bh                                 (64 -> 6)
-  L = [[e^o0, 0, 0], [o3, e^o1, 0], [o4, o5, e^o2]]
-Two losses for one system A dv* = b:
-  "solution": sum over free nodes |B_i b_i - dv*_i|^2 / sum |dv*_i|^2;
-  "cg_step" (scale-invariant): log of the A-norm error left by one optimal
-      preconditioned conjugate-gradient step from zero,
-      log(u^T A u) - 2 log(b^T u) + log(b^T dv*) with u = B b
-      (B on prescribed nodes fixed to A_ii^-1).
+  node head:  o = Wh h + bh                                 (64 -> 24)
+      o[0:6]   -> L = [[e^o0, 0, 0], [o3, e^o1, 0], [o4, o5, e^o2]]
+      o[6:15]  -> s_i,  o[15:24] -> t_i
+  edge term:  W_ij = s_i + t_j + We f_ij + be  (9 values, row-major 3x3)
+The edge term is linear in (h_i, h_j, f_ij), so it costs one node GEMM and a
+gather per block.
 
-The backward pass is written out by hand; tests pin it to finite differences.
+Training objective (one system, one probe vector v with entries +-1):
+Kaporin's condition number of G A G^T, K = (tr(GAG^T)/N)^N / det(GAG^T),
+estimated with the probe (E[v^T X v] = tr X):
+    loss = log(v^T G A G^T v / N) - (2/N) log det G     (N = 3n)
+which is log K / N up to the constant log det A / N.  Its exact minimiser over
+all G with this block pattern is the classical factorised sparse approximate
+inverse (Kolotilina-Yeremin), so the network learns an approximation of that
+preconditioner from local features.  The backward pass is written out by
+hand; tests pin it to finite differences.
 """
 from __future__ import annotations
 
+from dataclasses import dataclass
+
 import numpy as np
+import scipy.sparse as sp
 
 HIDDEN = 64
 N_IN = 8
 N_LAYERS = 3
-N_OUT = 6
+N_HEAD = 24
+N_EDGE_F = 3
 
-# parameter order (flat vector): W0 (64x8), b0 (64), [Wl (64x128), bl (64)] x 3, Wh (6x64), bh (6)
+# parameter order (flat vector): W0 (64x8), b0 (64), [Wl (64x128), bl (64)] x 3,
+# Wh (24x64), bh (24), We (9x3), be (9)
 SHAPES = [("W0", (HIDDEN, N_IN)), ("b0", (HIDDEN,))]
 for _l in range(N_LAYERS):
     SHAPES += [(f"W{_l + 1}", (HIDDEN, 2 * HIDDEN)), (f"b{_l + 1}", (HIDDEN,))]
-SHAPES += [("Wh", (N_OUT, HIDDEN)), ("bh", (N_OUT,))]
+SHAPES += [("Wh", (N_HEAD, HIDDEN)), ("bh", (N_HEAD,)), ("We", (9, N_EDGE_F)), ("be", (9,))]
 N_PARAMS = int(sum(np.prod(s) for _, s in SHAPES))
 
 
@@ -55,15 +74,25 @@ def flatten(p: dict) -> np.ndarray:
     return np.concatenate([p[name].ravel() for name, _ in SHAPES])
 
 
+def offset(name: str) -> int:
+    o = 0
+    for nm, shp in SHAPES:
+        if nm == name:
+            return o
+        o += int(np.prod(shp))
+    raise KeyError(name)
+
+
 def init_weights(seed: int, head_scale: float = 0.0) -> np.ndarray:
-    """He-style initial weights; the head starts at head_scale (0 = block-Jacobi)."""
+    """He-style hidden layers; head and edge term drawn with std head_scale
+    (0 = block-Jacobi)."""
     rng = np.random.default_rng(seed)
     p = {}
     for name, shp in SHAPES:
-        if name.startswith("W") and name != "Wh":
-            p[name] = rng.normal(size=shp) * np.sqrt(2.0 / shp[1])
-        elif name == "Wh":
+        if name in ("Wh", "We"):
             p[name] = rng.normal(size=shp) * head_scale
+        elif name.startswith("W"):
+            p[name] = rng.normal(size=shp) * np.sqrt(2.0 / shp[1])
         else:
             p[name] = np.zeros(shp)
     return flatten(p)
@@ -141,50 +170,115 @@ def forward(w: np.ndarray, a: np.ndarray, P) -> dict:
     return cache
 
 
-def precond_blocks(o: np.ndarray, Aii: np.ndarray) -> np.ndarray:
-    """B_i = L_i A_ii^-1 L_i^T."""
-    L = lower_factor(o)
-    C = np.linalg.inv(Aii)
-    return L @ C @ np.transpose(L, (0, 2, 1))
+@dataclass
+class Factor:
+    """Lower block pattern of an assembled system and the fixed pieces of G."""
+    n: int
+    rows: np.ndarray     # (nb,) block row i of each stored block j < i
+    cols: np.ndarray     # (nb,) block column j
+    Ablk: np.ndarray     # (nb, 3, 3) A_ij
+    K: np.ndarray        # (nb, 3, 3) A_ij A_jj^-1
+    C: np.ndarray        # (n, 3, 3) inverse lower Cholesky factor of A_ii
+    fb: np.ndarray       # (nb, 3) features of the block's edge
+    free: np.ndarray     # (n,) 1 for free nodes, 0 for prescribed
 
 
-def loss_and_grad(w: np.ndarray, a: np.ndarray, P, PT, Aii: np.ndarray, b: np.ndarray, dv: np.ndarray,
-                  free: np.ndarray, A=None, kind: str = "solution"):
-    """Loss of one system and its gradient with respect to the flat weights.
-    kind "cg_step" needs the assembled matrix A (3n x 3n)."""
+def diagonal_blocks(A: sp.csr_matrix) -> np.ndarray:
+    n = A.shape[0] // 3
+    D = np.zeros((n, 3, 3))
+    for r in range(3):
+        for c in range(3):
+            D[:, r, c] = A.diagonal(c - r)[np.arange(n) * 3 + min(r, c)]
+    return D
+
+
+def make_factor(A: sp.csr_matrix, edges: np.ndarray, f: np.ndarray, free: np.ndarray) -> Factor:
+    """Stored lower blocks of A: every mesh edge (i, j), i < j, is block (j, i)."""
+    n = A.shape[0] // 3
+    D = diagonal_blocks(A)
+    rows = edges[:, 1].astype(np.int64)
+    cols = edges[:, 0].astype(np.int64)
+    Ad = A.toarray() if n <= 3000 else None
+    Ablk = np.zeros((len(rows), 3, 3))
+    Acsr = A.tocsr()
+    for k, (i, j) in enumerate(zip(rows, cols)):
+        Ablk[k] = Ad[3 * i:3 * i + 3, 3 * j:3 * j + 3] if Ad is not None else \
+            Acsr[3 * i:3 * i + 3, 3 * j:3 * j + 3].toarray()
+    K = Ablk @ np.linalg.inv(D)[cols]
+    C = np.linalg.inv(np.linalg.cholesky(D))
+    return Factor(n, rows, cols, Ablk, K, C, f, free.astype(float))
+
+
+def factor_blocks(o: np.ndarray, w: np.ndarray, fac: Factor):
+    """(Gd (n,3,3), Gl (nb,3,3), W (nb,3,3)) for head outputs o (n,24)."""
+    p = unflatten(w)
+    L = lower_factor(o[:, :6])
+    L[fac.free == 0] = np.eye(3)
+    M = L @ fac.C
+    Wv = o[fac.rows, 6:15] + o[fac.cols, 15:24] + fac.fb @ p["We"].T + p["be"]
+    W = Wv.reshape(-1, 3, 3)
+    Gl = -np.einsum("bij,bjk,bkl->bil", M[fac.rows], W, fac.K)
+    return M, Gl, W
+
+
+def G_matrix(fac: Factor, Gd: np.ndarray, Gl: np.ndarray) -> sp.csr_matrix:
+    """Assemble G as a sparse (3n x 3n) matrix."""
+    rows = np.concatenate([np.arange(fac.n), fac.rows])
+    cols = np.concatenate([np.arange(fac.n), fac.cols])
+    blocks = np.concatenate([Gd, Gl])
+    r = (3 * rows[:, None, None] + np.arange(3)[None, :, None]).repeat(3, 2).ravel()
+    c = (3 * cols[:, None, None] + np.arange(3)[None, None, :]).repeat(3, 1).ravel()
+    return sp.csr_matrix((blocks.ravel(), (r, c)), shape=(3 * fac.n, 3 * fac.n))
+
+
+def apply(fac: Factor, Gd: np.ndarray, Gl: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """z = G^T G r (r and z of shape (n, 3))."""
+    y = np.einsum("nij,nj->ni", Gd, r)
+    np.add.at(y, fac.rows, np.einsum("bij,bj->bi", Gl, r[fac.cols]))
+    z = np.einsum("nji,nj->ni", Gd, y)
+    np.add.at(z, fac.cols, np.einsum("bji,bj->bi", Gl, y[fac.rows]))
+    return z
+
+
+def loss_and_grad(w: np.ndarray, a: np.ndarray, P, PT, fac: Factor, A: sp.csr_matrix, v: np.ndarray):
+    """Kaporin probe loss of one system and its gradient w.r.t. the flat weights.
+    v: (n, 3) probe.  Returns (loss, grad, (Gd, Gl))."""
     p = unflatten(w)
     c = forward(w, a, P)
     o = c["o"]
-    L = lower_factor(o)
-    C = np.linalg.inv(Aii)
-    B = L @ C @ np.transpose(L, (0, 2, 1))
-    if kind == "solution":
-        r = np.einsum("nij,nj->ni", B, b) - dv
-        r = r * free[:, None]
-        D = float(np.sum((dv * free[:, None]) ** 2))
-        loss = float(np.sum(r * r)) / D
-        # dloss/dB = 2 r b^T / D
-        G = 2.0 * np.einsum("ni,nj->nij", r, b) / D
-    else:
-        Bf = np.where(free[:, None, None] > 0, B, C)
-        u = np.einsum("nij,nj->ni", Bf, b)
-        wv = (A @ u.ravel()).reshape(-1, 3)
-        s_ = float(np.sum(b * u))
-        q_ = float(np.sum(u * wv))
-        loss = np.log(q_) - 2.0 * np.log(s_) + np.log(float(np.sum(b * dv)))
-        # dloss/dB_i = (2/q) w_i b_i^T - (2/s) b_i b_i^T on free nodes
-        G = (2.0 / q_) * np.einsum("ni,nj->nij", wv, b) - (2.0 / s_) * np.einsum("ni,nj->nij", b, b)
-        G = G * free[:, None, None]
-    # dloss/dL = (G + G^T) L C
-    GL = np.einsum("nij,njk,nkl->nil", G + np.transpose(G, (0, 2, 1)), L, C)
+    Gd, Gl, W = factor_blocks(o, w, fac)
+    N = 3 * fac.n
+    # u = G^T v, w = A u, t = u.w
+    u = np.einsum("nji,nj->ni", Gd, v)
+    np.add.at(u, fac.cols, np.einsum("bji,bj->bi", Gl, v[fac.rows]))
+    wv = (A @ u.ravel()).reshape(-1, 3)
+    t = float(np.sum(u * wv))
+    L = lower_factor(o[:, :6])
+    logdet = float(np.sum(np.log(np.abs(np.linalg.det(Gd)))))
+    loss = np.log(t / N) - 2.0 / N * logdet
+    # dloss/dW_b = -(2/t) (M_i^T v_i)(K_b w_j)^T
+    m = np.einsum("nji,nj->ni", Gd, v)                       # M_i^T v_i
+    k = np.einsum("bij,bj->bi", fac.K, wv[fac.cols])         # K_b w_j
+    dW = -(2.0 / t) * np.einsum("bi,bj->bij", m[fac.rows], k)
+    # dloss/dL_i = (2/t) v_i rho_i^T - (2/N) L_i^-T, rho_i = C_i (w_i - sum_b W_b k_b)
+    s = wv.copy()
+    np.add.at(s, fac.rows, -np.einsum("bij,bj->bi", W, k))
+    rho = np.einsum("nij,nj->ni", fac.C, s)
+    dL = (2.0 / t) * np.einsum("ni,nj->nij", v, rho) - (2.0 / N) * np.transpose(np.linalg.inv(L), (0, 2, 1))
     go = np.zeros_like(o)
-    go[:, 0] = GL[:, 0, 0] * L[:, 0, 0]
-    go[:, 1] = GL[:, 1, 1] * L[:, 1, 1]
-    go[:, 2] = GL[:, 2, 2] * L[:, 2, 2]
-    go[:, 3] = GL[:, 1, 0]
-    go[:, 4] = GL[:, 2, 0]
-    go[:, 5] = GL[:, 2, 1]
-    g = {k: np.zeros_like(v) for k, v in p.items()}
+    go[:, 0] = dL[:, 0, 0] * L[:, 0, 0]
+    go[:, 1] = dL[:, 1, 1] * L[:, 1, 1]
+    go[:, 2] = dL[:, 2, 2] * L[:, 2, 2]
+    go[:, 3] = dL[:, 1, 0]
+    go[:, 4] = dL[:, 2, 0]
+    go[:, 5] = dL[:, 2, 1]
+    go[fac.free == 0, :6] = 0.0
+    dWv = dW.reshape(-1, 9)
+    np.add.at(go[:, 6:15], fac.rows, dWv)
+    np.add.at(go[:, 15:24], fac.cols, dWv)
+    g = {kk: np.zeros_like(vv) for kk, vv in p.items()}
+    g["We"] = dWv.T @ fac.fb
+    g["be"] = dWv.sum(0)
     h = c["h"]
     g["Wh"] = go.T @ h[-1]
     g["bh"] = go.sum(0)
@@ -199,18 +293,16 @@ def loss_and_grad(w: np.ndarray, a: np.ndarray, P, PT, Aii: np.ndarray, b: np.nd
     gz0 = gh * (c["z0"] > 0)
     g["W0"] = gz0.T @ c["a"]
     g["b0"] = gz0.sum(0)
-    return loss, flatten(g), B
+    return loss, flatten(g), (Gd, Gl)
 
 
-def system_data(mesh, state, sysm, dv: np.ndarray, dir_nodes):
-    """Per-node diagonal blocks, right-hand side, solution and free mask of an
-    assembled oracle system (gfem_oracle.System)."""
+def system_inputs(mesh, x: np.ndarray, zeta: np.ndarray, A: sp.csr_matrix, dir_nodes):
+    """Network inputs and the factor pattern of an assembled oracle system."""
     n = mesh.X.shape[0]
-    A = sysm.A
-    Aii = np.zeros((n, 3, 3))
-    for r in range(3):
-        for cc in range(3):
-            Aii[:, r, cc] = A.diagonal(cc - r)[np.arange(n) * 3 + min(r, cc)]
     free = np.ones(n)
     free[np.asarray(dir_nodes, dtype=int)] = 0.0
-    return Aii, sysm.b.reshape(-1, 3), dv.reshape(-1, 3), free
+    f = edge_features(mesh.X, x, mesh.edges, zeta)
+    a = node_inputs(n, mesh.edges, f)
+    P, PT = mean_operator(n, mesh.edges, zeta)
+    fac = make_factor(A, mesh.edges, f, free)
+    return a, P, PT, fac

@@ -1,16 +1,19 @@
-"""Pins of the network oracle: its hand-written backward pass against central
-finite differences of its own loss (FP64), the identity head against block
-Jacobi, and the mean operator's transpose against a dense matrix."""
+"""Pins of the network oracle: the factor G against a direct dense
+construction, its log-determinant against a dense one, the zero network
+against block-Jacobi, the Kaporin loss at the exact inverse, the hand-written
+backward pass against central finite differences (FP64), and the mean
+operator's transpose against a dense matrix."""
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 from oracle import gfem_oracle as O
 from oracle import mpnn_oracle as N
 from paper_2103_14870_amd import meshgen as mg
 
 
-def small_system(seed=0):
-    prob = mg.tiny_cube(2, h=0.1, jitter_frac=0.05, seed=seed, top_speed=0.4, damage_strain=0.05)
+def small_system(seed=0, n=2):
+    prob = mg.tiny_cube(n, h=0.1, jitter_frac=0.05, seed=seed, top_speed=0.4, damage_strain=0.05)
     mesh = O.setup(prob.X, prob.tets, prob.params)
     st = O.initial_state(mesh)
     rng = np.random.default_rng(seed + 1)
@@ -19,21 +22,16 @@ def small_system(seed=0):
     st.zeta = rng.random(mesh.edges.shape[0]) < 0.2
     zeta, _ = O.damage_update(mesh, st.x, st.zeta)
     sysm = O.build_system(mesh, st, prob.dir_nodes, prob.dir_vel, zeta, st.Ep)
-    dv = np.linalg.solve(sysm.A.toarray(), sysm.b)
-    Aii, b, d, free = N.system_data(mesh, st, sysm, dv, prob.dir_nodes)
-    f = N.edge_features(prob.X, st.x, mesh.edges, zeta)
-    a = N.node_inputs(prob.n_nodes, mesh.edges, f)
-    P, PT = N.mean_operator(prob.n_nodes, mesh.edges, zeta)
-    small_system.A = sysm.A
-    return a, P, PT, Aii, b, d, free, mesh, zeta
+    a, P, PT, fac = N.system_inputs(mesh, st.x, zeta, sysm.A, prob.dir_nodes)
+    return a, P, PT, fac, sysm.A.tocsr(), sysm.b, mesh
 
 
 def test_parameter_count():
-    assert N.N_PARAMS == 64 * 8 + 64 + 3 * (64 * 128 + 64) + 6 * 64 + 6
+    assert N.N_PARAMS == 64 * 8 + 64 + 3 * (64 * 128 + 64) + 24 * 64 + 24 + 9 * 3 + 9
 
 
 def test_mean_operator_transpose_is_dense_transpose():
-    a, P, PT, *_ , mesh, zeta = small_system(1)
+    a, P, PT, fac, *_ = small_system(1)
     n = a.shape[0]
     Pd = np.stack([P(np.eye(n)[:, [i]])[:, 0] for i in range(n)], 1)
     rng = np.random.default_rng(2)
@@ -43,24 +41,81 @@ def test_mean_operator_transpose_is_dense_transpose():
     assert np.all((np.abs(rows - 1) < 1e-12) | (rows == 0))
 
 
-def test_identity_head_is_block_jacobi():
-    a, P, PT, Aii, b, d, free, *_ = small_system(3)
+def test_zero_network_is_block_jacobi():
+    a, P, PT, fac, A, b, _ = small_system(3)
     w = N.init_weights(0, head_scale=0.0)
-    B = N.precond_blocks(N.forward(w, a, P)["o"], Aii)
-    np.testing.assert_allclose(B, np.linalg.inv(Aii), rtol=1e-12, atol=1e-14)
+    Gd, Gl, _ = N.factor_blocks(N.forward(w, a, P)["o"], w, fac)
+    r = np.random.default_rng(4).normal(size=(fac.n, 3))
+    Dinv = np.linalg.inv(N.diagonal_blocks(A))
+    np.testing.assert_allclose(N.apply(fac, Gd, Gl, r), np.einsum("nij,nj->ni", Dinv, r), rtol=1e-11, atol=1e-13)
 
 
-@pytest.mark.parametrize("kind", ["solution", "cg_step"])
-def test_backward_matches_finite_differences(kind):
-    a, P, PT, Aii, b, d, free, *_ = small_system(4)
-    A = small_system.A
+def test_constant_damping_matches_dense_construction():
+    # W_ij = w I, L = I: G = blockdiag(C) (I - w E_L blockdiag(D^-1)), E_L the strictly block-lower part of A
+    a, P, PT, fac, A, b, _ = small_system(5)
+    wgt = N.init_weights(0, head_scale=0.0)
+    om = 0.7
+    wgt[N.offset("be"):N.offset("be") + 9] = om * np.eye(3).ravel()
+    Gd, Gl, _ = N.factor_blocks(N.forward(wgt, a, P)["o"], wgt, fac)
+    G = N.G_matrix(fac, Gd, Gl).toarray()
+    Ad = A.toarray()
+    n3 = Ad.shape[0]
+    blk = np.arange(n3) // 3
+    EL = np.where(blk[:, None] > blk[None, :], Ad, 0.0)
+    Dd = np.where(blk[:, None] == blk[None, :], Ad, 0.0)
+    Lc = np.linalg.cholesky(Dd)
+    Gref = np.linalg.inv(Lc) @ (np.eye(n3) - om * EL @ np.linalg.inv(Dd))
+    np.testing.assert_allclose(G, Gref, rtol=1e-10, atol=1e-12)
+    assert np.allclose(np.triu(G, 1)[blk[:, None] != blk[None, :]], 0.0)
+
+
+def test_factor_is_lower_triangular_and_B_is_spd():
+    a, P, PT, fac, A, b, _ = small_system(6)
+    w = N.init_weights(7, head_scale=0.1)
+    Gd, Gl, _ = N.factor_blocks(N.forward(w, a, P)["o"], w, fac)
+    G = N.G_matrix(fac, Gd, Gl).toarray()
+    blk = np.arange(G.shape[0]) // 3
+    assert np.all(G[blk[:, None] < blk[None, :]] == 0.0)
+    B = G.T @ G
+    assert np.linalg.eigvalsh(B).min() > 0
+    r = np.random.default_rng(8).normal(size=(fac.n, 3))
+    np.testing.assert_allclose(N.apply(fac, Gd, Gl, r).ravel(), B @ r.ravel(), rtol=1e-10, atol=1e-12)
+    # log det G from the diagonal blocks equals the dense log-determinant
+    sign, ld = np.linalg.slogdet(G)
+    assert ld == pytest.approx(np.sum(np.log(np.abs(np.linalg.det(Gd)))), rel=1e-10)
+
+
+def test_kaporin_loss_at_the_exact_inverse():
+    # block-diagonal A: G = blockdiag(C) is an exact inverse factor, G A G^T = I,
+    # so K = 1 and loss = log K / N + log det A / N = log det A / N for any probe of +-1 entries
+    rng = np.random.default_rng(9)
+    n = 5
+    Mx = rng.normal(size=(n, 3, 3))
+    D = Mx @ np.transpose(Mx, (0, 2, 1)) + 3 * np.eye(3)
+    A = sp.block_diag(list(D), format="csr")
+    edges = np.array([[0, 1], [1, 2], [2, 3], [3, 4]])
+    f = np.zeros((4, 3))
+    a = N.node_inputs(n, edges, f)
+    P, PT = N.mean_operator(n, edges, np.zeros(4, bool))
+    fac = N.make_factor(A, edges, f, np.ones(n))
+    v = rng.choice([-1.0, 1.0], size=(n, 3))
+    w = N.init_weights(1, head_scale=0.0)
+    w[N.offset("be"):N.offset("be") + 9] = rng.normal(size=9)  # W is irrelevant: A_ij = 0
+    loss, _, _ = N.loss_and_grad(w, a, P, PT, fac, A, v)
+    assert loss == pytest.approx(np.linalg.slogdet(A.toarray())[1] / (3 * n), rel=1e-12)
+
+
+def test_backward_matches_finite_differences():
+    a, P, PT, fac, A, b, _ = small_system(4)
     w = N.init_weights(5, head_scale=0.05)
-    lg = lambda ww: N.loss_and_grad(ww, a, P, PT, Aii, b, d, free, A=A, kind=kind)
+    v = np.random.default_rng(6).choice([-1.0, 1.0], size=(fac.n, 3))
+    lg = lambda ww: N.loss_and_grad(ww, a, P, PT, fac, A, v)
     loss, g, _ = lg(w)
     rng = np.random.default_rng(6)
     idx = rng.choice(N.N_PARAMS, 40, replace=False)
     names = np.concatenate([[nm] * int(np.prod(s)) for nm, s in N.SHAPES])
-    idx = np.unique(np.concatenate([idx, [np.nonzero(names == nm)[0][0] for nm, _ in N.SHAPES]]))
+    idx = np.unique(np.concatenate([idx, [np.nonzero(names == nm)[0][0] for nm, _ in N.SHAPES],
+                                    N.offset("Wh") + np.arange(0, 24 * 64, 64) + 3]))
     h = 1e-6
     for i in idx:
         wp, wm = w.copy(), w.copy()
@@ -70,34 +125,22 @@ def test_backward_matches_finite_differences(kind):
         assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-9 * max(1.0, abs(loss))), (i, names[i])
 
 
-def test_loss_is_zero_for_the_exact_inverse_on_a_decoupled_system():
-    # block-diagonal A: block Jacobi is the exact inverse, so the identity head has zero loss
-    rng = np.random.default_rng(7)
-    n = 5
-    M = rng.normal(size=(n, 3, 3))
-    Aii = M @ np.transpose(M, (0, 2, 1)) + 3 * np.eye(3)
-    dv = rng.normal(size=(n, 3))
-    b = np.einsum("nij,nj->ni", Aii, dv)
-    edges = np.array([[0, 1], [1, 2], [2, 3], [3, 4]])
-    zeta = np.zeros(4, bool)
-    a = N.node_inputs(n, edges, np.zeros((4, 3)))
-    P, PT = N.mean_operator(n, edges, zeta)
-    loss, g, _ = N.loss_and_grad(N.init_weights(1), a, P, PT, Aii, b, dv, np.ones(n))
-    assert loss < 1e-25
-
-
-def test_cg_step_loss_is_the_one_step_energy_error():
-    # log of |dv* - x1|_A^2 / |dv*|_A^2 for the optimal first step x1 = t B b
-    a, P, PT, Aii, b, d, free, *_ = small_system(8)
-    A = small_system.A
-    w = N.init_weights(9, head_scale=0.05)
-    loss, _, B = N.loss_and_grad(w, a, P, PT, Aii, b, d, free, A=A, kind="cg_step")
-    Bf = np.where(free[:, None, None] > 0, B, np.linalg.inv(Aii))
-    u = np.einsum("nij,nj->ni", Bf, b).ravel()
-    x = d.ravel()
-    t = (b.ravel() @ u) / (u @ (A @ u))
-    e = x - t * u
-    ratio = (e @ (A @ e)) / (x @ (A @ x))
-    # one-step error energy = 1 - exp(-loss)... loss = log(q) - 2 log(s) + log(b.x) = -log(1 - ratio)
-    assert loss == pytest.approx(-np.log(1 - ratio), rel=1e-10)
-    assert 0 <= ratio < 1
+def test_damped_factor_reduces_cg_iterations():
+    # the family's constant member W = 0.75 I already needs far fewer PCG
+    # iterations than block-Jacobi on a three-point-bending beam
+    prob = mg.notched_beam(16, 4, 4, h=0.01, notch_cells=1)
+    mesh = O.setup(prob.X, prob.tets, prob.params)
+    st = O.initial_state(mesh)
+    O.break_pairs(mesh, st, prob.broken_pairs)
+    zeta, _ = O.damage_update(mesh, st.x, st.zeta)
+    sysm = O.build_system(mesh, st, prob.dir_nodes, prob.dir_vel, zeta, st.Ep)
+    a, P, PT, fac = N.system_inputs(mesh, st.x, zeta, sysm.A, prob.dir_nodes)
+    w = N.init_weights(0)
+    w[N.offset("be"):N.offset("be") + 9] = 0.75 * np.eye(3).ravel()
+    Gd, Gl, _ = N.factor_blocks(N.forward(w, a, P)["o"], w, fac)
+    G = N.G_matrix(fac, Gd, Gl)
+    B = (G.T @ G).tocsr()
+    _, it_f, _, ok_f = O.pcg(sysm.A, sysm.b, B, 1e-6, 5000)
+    _, it_j, _, ok_j = O.pcg(sysm.A, sysm.b, O.block_jacobi(sysm.A), 1e-6, 5000)
+    assert ok_f and ok_j
+    assert it_f < 0.7 * it_j, (it_f, it_j)
