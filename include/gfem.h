@@ -81,12 +81,14 @@ typedef struct {
   int32_t near_threshold;   /* edge evaluations with |strain - threshold| < 1e-6 */
   int32_t chi_zero_tets;    /* tets with chi = 0 (disconnected) in the last step */
   int32_t degenerate_tets;  /* tets with |J| < 0.05 in the last step */
-  int32_t n_launch[8];      /* kernel launches per timing category (timing on) */
+  int32_t n_launch[9];      /* kernel launches per timing category (timing on) */
   double rel_residual;      /* final FP64 |b - A dv| / |b| of the last step */
-  double kernel_us[8];      /* device time per category (timing on), microseconds:
+  double kernel_us[9];      /* device time per category (timing on), microseconds:
                                0 damage, 1 element (+plasticity), 2 assembly (edge + row),
-                               3 preconditioner, 4 SpMV (PCG), 5 PCG vector updates,
-                               6 FP64 residual / refinement, 7 integrate */
+                               3 preconditioner set-up (network, factor), 4 SpMV (PCG),
+                               5 PCG vector updates (with the G pass of the factorised
+                               preconditioner), 6 FP64 residual / refinement, 7 integrate,
+                               8 G^T pass of the factorised preconditioner */
 } gf_step_stats;
 
 /* Create a mesh.  rest_xyz: n_nodes*3 doubles (caller order); tets:
@@ -160,26 +162,34 @@ gf_status gf_set_timing(gf_mesh* m, int32_t on);
 gf_status gf_bench_spmv(gf_mesh* m, int32_t reps, double* us_per_launch, double* bytes_per_launch);
 
 /* ---------------------------------------------------------------------------
- * Learned block preconditioner (an addition to the paper, whose solver is plain
+ * Learned preconditioner (an addition to the paper, whose solver is plain
  * conjugate gradients).  A message-passing network on the mesh graph maps edge
- * features (rest length, current length, damage label) to a lower-triangular
- * L_i per node; the preconditioner block is B_i = L_i A_ii^-1 L_i^T, which is
- * block-Jacobi for L = I.  Inference and training run on the GPU in BF16 with
- * FP32 accumulation.  A learned solve is accepted only at the same FP64 residual;
- * otherwise the step is re-solved with block-Jacobi (gf_step_stats.used_fallback).
- * Only the split precision mode supports the learned preconditioner.
+ * features (rest length, current length, damage label) to the 3x3 blocks of a
+ * factorised sparse approximate inverse B = G^T G, with G block lower
+ * triangular on the lower block pattern of A in node order:
+ *   G_ii = L_i C_i,   G_ij = -L_i C_i W_ij A_ij A_jj^-1   (j < i, i-j an edge),
+ * C_i the inverse lower Cholesky factor of A_ii, L_i lower triangular with
+ * exponentiated diagonal (per node) and W_ij a 3x3 block (per edge).  B is
+ * symmetric positive definite by construction; the zero network gives 3x3
+ * block-Jacobi.  Inference and training run on the GPU in BF16 with FP32
+ * accumulation; the solve stores G in BF16.  A learned solve is accepted only
+ * at the same FP64 residual; otherwise the step is re-solved with block-Jacobi
+ * (gf_step_stats.used_fallback).  Only the split precision mode supports it.
  * ------------------------------------------------------------------------- */
 typedef struct gf_net gf_net; /* opaque, owned by the library from create to destroy */
 
-/* Create a network on the current device: He-initialised layers, zero head
- * (so it starts as block-Jacobi).  Deterministic in seed. */
+/* Create a network on the current device: He-initialised hidden layers, zero
+ * head and edge term (so it starts as block-Jacobi).  Deterministic in seed,
+ * which also seeds the training probes. */
 gf_status gf_net_create(uint64_t seed, gf_net** out);
 gf_status gf_net_destroy(gf_net* net);
 /* Number of FP32 parameters (same for every network). */
 gf_status gf_net_num_params(int32_t* n);
 /* FP32 master weights in this order: W0 (64x8), b0 (64), then for each of 3
  * layers W (64x128, columns 0-63 act on h, 64-127 on the neighbour mean), b (64),
- * then Wh (6x64), bh (6); matrices row-major [out][in]. */
+ * then the node head Wh (24x64), bh (24) (outputs 0-5: L_i, 6-14: s_i,
+ * 15-23: t_i) and the edge term We (9x3), be (9), with
+ * W_ij = s_i + t_j + We f_ij + be (row-major 3x3); matrices row-major [out][in]. */
 gf_status gf_net_get_weights(const gf_net* net, float* w_out);
 gf_status gf_net_set_weights(gf_net* net, const float* w); /* also resets the optimiser */
 /* Attach (borrowed: must outlive its use) or detach (NULL) the network used by
@@ -187,14 +197,20 @@ gf_status gf_net_set_weights(gf_net* net, const float* w); /* also resets the op
 gf_status gf_set_precond_net(gf_mesh* m, gf_net* net);
 gf_status gf_set_precond(gf_mesh* m, int32_t precond);
 /* One training step on the system of the mesh's next timestep at its current
- * state (assembled and solved with block-Jacobi to tolerance, not committed):
- * loss = sum over free nodes |B_i b_i - dv_i|^2 / sum |dv_i|^2, gradient by the
+ * state (assembled, not solved, not committed).  Loss: Kaporin's condition
+ * number of G A G^T estimated with a +-1 probe v (drawn from a counter-based
+ * generator seeded by the network's seed and step count),
+ *   loss = log(v^T G A G^T v / N) - (2/N) log det G,   N = 3 n_nodes,
+ * which is log K / N up to the constant log det A / N; gradient by the
  * network's backward pass, one Adam step (lr).  loss_out may be NULL. */
 gf_status gf_net_train_step(gf_net* net, gf_mesh* m, double lr, double* loss_out);
-/* Same system, no update: loss, the preconditioner blocks (n_nodes*6 floats,
- * caller node order, entries 00 11 22 01 02 12) and the weight gradient
- * (gf_net_num_params floats).  Outputs may be NULL.  Test hook. */
-gf_status gf_net_eval(gf_net* net, gf_mesh* m, double* loss_out, float* blocks_out, float* grad_out);
+/* Same system, no update.  probe: n_nodes*3 doubles in caller order (NULL: the
+ * generator's next probe).  Outputs (each may be NULL): the loss; the diagonal
+ * factor blocks G_ii (n_nodes*9 floats, caller order, row-major); the lower
+ * blocks G_ji of every edge (i, j), i < j (n_edges*9 floats, canonical edge
+ * order, row-major); the weight gradient (gf_net_num_params floats).  Test hook. */
+gf_status gf_net_eval(gf_net* net, gf_mesh* m, const double* probe, double* loss_out, float* gdiag_out,
+                      float* glower_out, float* grad_out);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char* gf_last_error(void);

@@ -13,6 +13,7 @@
 #include <new>
 #include <random>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/gfem.h"
@@ -93,6 +94,7 @@ struct gf_net {
   gfem::NetParamsDev P;
   std::vector<float> host;  // master weights (host copy, kept in sync)
   int adam_t = 0;
+  uint64_t seed = 0;
 };
 
 struct gf_mesh {
@@ -130,6 +132,7 @@ struct gf_mesh {
   void* binv = nullptr;
   // PCG
   void *vr = nullptr, *vz = nullptr, *vp[2] = {nullptr, nullptr}, *vq = nullptr, *vx = nullptr;
+  void *vr2 = nullptr, *vy = nullptr;  // second residual buffer and G r (factorised preconditioner)
   double *part_a = nullptr, *part_rz = nullptr, *part_pq = nullptr;
   gfem::PcgCtl* ctl = nullptr;
   gfem::Counters* ctr = nullptr;
@@ -149,7 +152,7 @@ struct gf_mesh {
   // learned preconditioner
   gf_net* net = nullptr;
   int precond = GF_PC_BLOCK_JACOBI;
-  bool netw_ready = false, net_cached = false;
+  bool netw_ready = false, net_train_ready = false, net_cached = false;
   int net_age = 0;
   double inv_mean_len = 1.0;
   gfem::NetWork netw;
@@ -234,6 +237,8 @@ void alloc_precision(gf_mesh* M) {
   M->vp[1] = M->al.get<v4<T>>(n);
   M->vq = M->al.get<v4<T>>(n);
   M->vx = M->al.get<v4<T>>(n);
+  M->vr2 = M->al.get<v4<T>>(n);
+  M->vy = M->al.get<v4<T>>(n);
 }
 
 // Damage (into the spare label buffer), element pass (+ plastic flow into the
@@ -272,10 +277,13 @@ void assemble(gf_mesh* M, bool flow, d4* f_out) {
 }
 
 double read_partials(gf_mesh* M, const double* dpart, int count) {
-  hchk(hipMemcpyAsync(M->h_part, dpart, sizeof(double) * count, hipMemcpyDeviceToHost, M->stream), "D2H");
-  M->sync();
   double s = 0;
-  for (int i = 0; i < count; ++i) s += M->h_part[i];
+  for (int c0 = 0; c0 < count; c0 += kMaxPart) {
+    const int c = std::min(kMaxPart, count - c0);
+    hchk(hipMemcpyAsync(M->h_part, dpart + c0, sizeof(double) * c, hipMemcpyDeviceToHost, M->stream), "D2H");
+    M->sync();
+    for (int i = 0; i < c; ++i) s += M->h_part[i];
+  }
   return s;
 }
 
@@ -290,7 +298,7 @@ struct SolveResult {
 // vectors, FP64 dot products, device-side scalars and early exit, launched in
 // chunks so the host only synchronises once per chunk.
 template <typename T>
-SolveResult solve(gf_mesh* M, const void* precond_blocks) {
+SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* F = nullptr) {
   hipStream_t s = M->stream;
   const double tol = M->p.cg_rel_tol;
   SolveResult res{false, 0, 0, 0.0};
@@ -304,7 +312,14 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks) {
   v4<T>* q = static_cast<v4<T>*>(M->vq);
   v4<T>* x = static_cast<v4<T>*>(M->vx);
   v4<T>* pb[2] = {static_cast<v4<T>*>(M->vp[0]), static_cast<v4<T>*>(M->vp[1])};
+  v4<T>* rb[2] = {r, static_cast<v4<T>*>(M->vr2)};
+  v4<T>* y = static_cast<v4<T>*>(M->vy);
   const T* binv = static_cast<const T*>(precond_blocks);
+  // factorised preconditioner (split precision only): the G pass replaces the
+  // vector update and writes Gb partials, which the SpMV then reduces
+  constexpr bool kFloat = std::is_same<T, float>::value;
+  const bool fact = kFloat && F != nullptr;
+  const int nrz = fact ? M->Gb : M->Ga;
   for (int outer = 0;; ++outer) {
     if (outer > 0) {
       res.rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
@@ -317,7 +332,15 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks) {
     const double rel_in = outer == 0 ? std::max(0.5 * tol, floor_rel) : std::max(0.5 * tol * std::sqrt(bb / rr), floor_rel);
     const int solve_id = (int)M->solve_iters.size();
     hchk(hipMemsetAsync(M->ctl, 0, sizeof(gfem::PcgCtl), s), "hipMemsetAsync");
-    M->timed(5, -1, 0, [&] { gfem::launch_pcg_init<T>(s, M->n, M->Ga, src, binv, r, z, pb[0], x, M->part_rz); });
+    M->timed(5, -1, 0, [&] {
+      if constexpr (kFloat) {
+        if (fact) {
+          gfem::launch_pcg_fact_init<float>(s, M->Gb, *F, src, rb[0], x, y, z, pb[0], M->part_rz);
+          return;
+        }
+      }
+      gfem::launch_pcg_init<T>(s, M->n, M->Ga, src, binv, r, z, pb[0], x, M->part_rz);
+    });
     const int left = budget - res.inner;
     int k = 0;
     // the first chunk covers the iteration count of the previous step's first solve (+10 %)
@@ -329,9 +352,19 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks) {
       const int kend = std::min(k + chunk, left);
       for (; k < kend; ++k) {
         M->timed(4, solve_id, k, [&] {
-          gfem::launch_pcg_spmv<T>(s, k, M->Gb, M->Ga, A, z, pb[(k + 1) & 1], pb[k & 1], q, M->ctl, M->part_rz,
+          gfem::launch_pcg_spmv<T>(s, k, M->Gb, nrz, A, z, pb[(k + 1) & 1], pb[k & 1], q, M->ctl, M->part_rz,
                                    M->part_pq, rel_in * rel_in);
         });
+        if constexpr (kFloat) {
+          if (fact) {
+            M->timed(5, solve_id, k, [&] {
+              gfem::launch_pcg_gpass<float>(s, k, M->Gb, *F, rb[k & 1], rb[(k + 1) & 1], q, pb[k & 1], x, y, M->ctl,
+                                            M->part_pq, M->part_rz);
+            });
+            M->timed(8, solve_id, k, [&] { gfem::launch_pcg_gtpass<float>(s, M->Gb, *F, y, z, M->ctl); });
+            continue;
+          }
+        }
         M->timed(5, solve_id, k, [&] {
           gfem::launch_pcg_update<T>(s, k, M->n, M->Ga, M->Gb, pb[k & 1], q, x, r, z, binv, M->ctl, M->part_pq,
                                      M->part_rz);
@@ -390,41 +423,58 @@ void ensure_netw(gf_mesh* M) {
   for (auto& h : w.h) h = M->al.get<gfem::bf16>(np * gfem::kHid);
   for (auto& m : w.m) m = M->al.get<gfem::bf16>(np * gfem::kHid);
   for (auto& z : w.z) z = M->al.get<gfem::bf16>(np * gfem::kHid);
-  w.o = M->al.get<float>(np * 8);
-  w.B = M->al.get<float>(6 * (size_t)M->n);
-  w.gh = M->al.get<float>(np * gfem::kHid);
-  w.gz = M->al.get<gfem::bf16>(np * gfem::kHid);
-  w.gi = M->al.get<float>(np * 2 * gfem::kHid);
-  w.go = M->al.get<float>(np * 8);
-  w.part = M->al.get<float>((size_t)w.nwg_dw * (gfem::kHid * 2 * gfem::kHid + gfem::kHid));
-  w.grad = M->al.get<float>(gfem::kNetParams);
-  w.lossp = M->al.get<double>(np / 256 + 2);
+  w.o = M->al.get<float>(np * gfem::kNetHead);
+  w.g = M->al.get<gfem::bf16>((size_t)9 * M->nbp);
   double sum = 0;
   for (int e = 0; e < M->ne; ++e) sum += std::sqrt(M->topo.edge_S[e]);
   M->inv_mean_len = M->ne > 0 ? M->ne / sum : 1.0;
   M->netw_ready = true;
 }
 
-gfem::NetInputs net_inputs(gf_mesh* M, const uint8_t* zeta) {
-  return gfem::NetInputs{M->n,        M->mat(),  M->diag_blk, M->blk_edge, M->X, M->U, zeta, M->inv_mean_len,
-                         static_cast<const float*>(M->binv), M->dflag};
+// Buffers used only by training and the evaluation hook.
+void ensure_net_train(gf_mesh* M) {
+  ensure_netw(M);
+  if (M->net_train_ready) return;
+  gfem::NetWork& w = M->netw;
+  const size_t np = w.npad;
+  w.gh = M->al.get<float>(np * gfem::kHid);
+  w.gz = M->al.get<gfem::bf16>(np * gfem::kHid);
+  w.gi = M->al.get<float>(np * 2 * gfem::kHid);
+  w.go = M->al.get<float>(np * gfem::kNetHead);
+  w.part = M->al.get<float>((size_t)w.nwg_dw * (gfem::kHid * 2 * gfem::kHid + gfem::kHid));
+  w.grad = M->al.get<float>(gfem::kNetParams);
+  w.g32 = M->al.get<float>((size_t)9 * M->nbp);
+  w.probe = M->al.get<d4>(M->n);
+  w.u = M->al.get<d4>(M->n);
+  w.wneg = M->al.get<d4>(M->n);
+  w.zero = M->al.get<d4>(M->n);  // zero-filled by the allocator
+  w.mv = M->al.get<v4<float>>(M->n);
+  w.sv = M->al.get<v4<float>>(M->n);
+  w.dpart = M->al.get<double>(2 * kMaxPart);
+  w.epart = M->al.get<float>((size_t)kMaxPart * gfem::kEdgeGrad);
+  M->net_train_ready = true;
 }
 
-// Preconditioner blocks of the learned path for the assembled step: the
-// network runs every net_every_n_steps steps; in between the cached head
-// outputs are combined with the current A_ii^-1.
+gfem::NetInputs net_inputs(gf_mesh* M, const uint8_t* zeta) {
+  return gfem::NetInputs{M->n,      M->mat(), M->diag_blk,      M->blk_edge,
+                         M->blk_ij, M->blk_ji, M->X,             M->U,
+                         zeta,      M->inv_mean_len, static_cast<const float*>(M->binv), M->dflag};
+}
+
+// Factor of the learned path for the assembled step: the network runs every
+// net_every_n_steps steps; in between its cached head outputs are combined
+// with the current system.
 void learned_precond(gf_mesh* M) {
   ensure_netw(M);
   const gfem::NetInputs in = net_inputs(M, M->zeta[1 - M->zcur]);
   const int every = std::max(1, (int)M->p.net_every_n_steps);
   M->timed(3, -1, 0, [&] {
     if (!M->net_cached || M->net_age >= every) {
-      gfem::net_forward(M->stream, M->net->P, M->netw, in);
+      gfem::net_forward(M->stream, M->net->P, M->netw, in, M->Gb);
       M->net_cached = true;
       M->net_age = 0;
-    } else {
-      gfem::net_apply_cached(M->stream, M->net->P, M->netw, in);
     }
+    gfem::net_build_factor(M->stream, M->net->P, M->netw, in, M->Gb, false);
   });
   ++M->net_age;
   M->check_launch();
@@ -438,9 +488,10 @@ gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
     SolveResult r;
     int fallback = 0;
     if (M->precond == GF_PC_LEARNED) {
-      // network blocks B_i = L_i A_ii^-1 L_i^T; block-Jacobi re-solve if not accepted
+      // network factor B = G^T G; block-Jacobi re-solve if not accepted
       learned_precond(M);
-      r = solve<T>(M, M->netw.B);
+      const gfem::FactView F = gfem::net_factor_view(M->netw, net_inputs(M, M->zeta[1 - M->zcur]));
+      r = solve<T>(M, M->binv, &F);
       if (!r.ok) {
         fallback = 1;
         hchk(hipMemsetAsync(M->X64, 0, sizeof(d4) * M->n, M->stream), "hipMemsetAsync");
@@ -951,6 +1002,7 @@ gf_status gf_net_create(uint64_t seed, gf_net** out) {
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(GF_EDEVICE, "no HIP device");
     holder.reset(new gf_net());
     gf_net* net = holder.get();
+    net->seed = seed;
     hchk(hipGetDevice(&net->dev), "hipGetDevice");
     gfem::NetParamsDev& P = net->P;
     P.master = net->al.get<float>(gfem::kNetParams);
@@ -1029,53 +1081,74 @@ gf_status gf_set_precond(gf_mesh* m, int32_t precond) {
   return GF_OK;
 }
 
-static gf_status net_train_eval(gf_net* net, gf_mesh* m, bool train, double lr, double* loss_out, float* blocks_out,
-                                float* grad_out, const char* who) {
+static gf_status net_train_eval(gf_net* net, gf_mesh* m, bool train, double lr, const double* probe,
+                                double* loss_out, float* gdiag_out, float* glower_out, float* grad_out,
+                                const char* who) {
   if (!net || !m) return fail(GF_EINVAL, std::string(who) + ": null argument");
   if (!m->split) return fail(GF_EINVAL, std::string(who) + ": needs the split precision mode");
   if (net->dev != m->dev) return fail(GF_EINVAL, std::string(who) + ": network on another device");
   if (train && !(lr > 0.0 && std::isfinite(lr))) return fail(GF_EINVAL, std::string(who) + ": bad learning rate");
+  if ((size_t)m->n > (size_t)256 * kMaxPart) return fail(GF_EINVAL, std::string(who) + ": mesh too large");
+  if (probe)
+    for (size_t i = 0; i < 3 * (size_t)m->n; ++i)
+      if (!std::isfinite(probe[i])) return fail(GF_EINVAL, std::string(who) + ": non-finite probe");
   GF_TRY({
     hipStream_t s = m->stream;
-    ensure_netw(m);
+    ensure_net_train(m);
     assemble<float>(m, true, nullptr);
-    const SolveResult r = solve<float>(m, m->binv);
     m->recs.clear();
     m->ev_used = 0;
     m->solve_iters.clear();
-    if (!r.ok) return fail(GF_ENOTCONVERGED, std::string(who) + ": block-Jacobi solve of the training system failed");
     const gfem::NetInputs in = net_inputs(m, m->zeta[1 - m->zcur]);
-    gfem::net_forward(s, net->P, m->netw, in);
-    const int nd = gfem::net_dv_norm(s, m->n, m->X64, m->dflag, m->netw.lossp);
-    const double D = read_partials(m, m->netw.lossp, nd);
-    double loss = 0.0;
-    if (D > 0.0) {
-      const int nl = gfem::net_backward(s, net->P, m->netw, in, m->b, m->X64, 1.0 / D);
-      m->check_launch();
-      loss = read_partials(m, m->netw.lossp, nl);
-      if (train) {
-        ++net->adam_t;
-        gfem::net_adam(s, net->P, m->netw.grad, net->adam_t, (float)lr);
-        m->check_launch();
-        hchk(hipMemcpyAsync(net->host.data(), net->P.master, sizeof(float) * gfem::kNetParams, hipMemcpyDeviceToHost,
-                            s),
-             "D2H");
-      }
+    gfem::NetWork& w = m->netw;
+    gfem::net_forward(s, net->P, w, in, m->Gb);
+    gfem::net_build_factor(s, net->P, w, in, m->Gb, true);
+    std::vector<d4> hv;
+    if (probe) {
+      hv.resize(m->n);
+      for (int c = 0; c < m->n; ++c)
+        hv[m->topo.perm_new[c]] = d4{probe[3 * (size_t)c], probe[3 * (size_t)c + 1], probe[3 * (size_t)c + 2], 0.0};
+      hchk(hipMemcpyAsync(w.probe, hv.data(), sizeof(d4) * m->n, hipMemcpyHostToDevice, s), "H2D");
     } else {
-      hchk(hipMemsetAsync(m->netw.grad, 0, sizeof(float) * gfem::kNetParams, s), "hipMemsetAsync");
+      gfem::net_probe(s, w, net->seed * 0x9E3779B97F4A7C15ull + (uint64_t)net->adam_t + 1);
+    }
+    gfem::net_kaporin_u(s, w, in, m->Gb);
+    gfem::launch_resid<float>(s, m->Gs, m->mat(), w.zero, w.u, w.wneg, m->part_a);
+    const int G = gfem::net_kaporin_dots(s, net->P, w, in);
+    m->check_launch();
+    const double t = read_partials(m, w.dpart, G);
+    const double ld = read_partials(m, w.dpart + kMaxPart, G);
+    const double N = 3.0 * m->n;
+    if (!(t > 0.0) || !std::isfinite(t) || !std::isfinite(ld))
+      return fail(GF_ESTATE, std::string(who) + ": probe energy of the factor is not positive and finite");
+    const double loss = std::log(t / N) - 2.0 * ld / N;
+    gfem::net_kaporin_backward(s, net->P, w, in, m->Gb, t);
+    m->check_launch();
+    if (train) {
+      ++net->adam_t;
+      gfem::net_adam(s, net->P, w.grad, net->adam_t, (float)lr);
+      m->check_launch();
+      hchk(hipMemcpyAsync(net->host.data(), net->P.master, sizeof(float) * gfem::kNetParams, hipMemcpyDeviceToHost,
+                          s),
+           "D2H");
     }
     if (grad_out)
-      hchk(hipMemcpyAsync(grad_out, m->netw.grad, sizeof(float) * gfem::kNetParams, hipMemcpyDeviceToHost, s), "D2H");
-    std::vector<float> hb;
-    if (blocks_out) {
-      hb.resize(6 * (size_t)m->n);
-      hchk(hipMemcpyAsync(hb.data(), m->netw.B, sizeof(float) * hb.size(), hipMemcpyDeviceToHost, s), "D2H");
+      hchk(hipMemcpyAsync(grad_out, w.grad, sizeof(float) * gfem::kNetParams, hipMemcpyDeviceToHost, s), "D2H");
+    std::vector<float> hg;
+    if (gdiag_out || glower_out) {
+      hg.resize((size_t)9 * m->nbp);
+      hchk(hipMemcpyAsync(hg.data(), w.g32, sizeof(float) * hg.size(), hipMemcpyDeviceToHost, s), "D2H");
     }
     m->sync();
-    if (blocks_out)
+    if (gdiag_out)
       for (int c = 0; c < m->n; ++c) {
-        const int i = m->topo.perm_new[c];
-        for (int q = 0; q < 6; ++q) blocks_out[6 * (size_t)c + q] = hb[(size_t)q * m->n + i];
+        const int b = m->topo.diag_blk[m->topo.perm_new[c]];
+        for (int q = 0; q < 9; ++q) gdiag_out[9 * (size_t)c + q] = hg[(size_t)q * m->nbp + b];
+      }
+    if (glower_out)
+      for (int c = 0; c < m->ne; ++c) {
+        const int b = m->topo.blk_ji[m->topo.edge_internal[c]];
+        for (int q = 0; q < 9; ++q) glower_out[9 * (size_t)c + q] = hg[(size_t)q * m->nbp + b];
       }
     if (loss_out) *loss_out = loss;
     m->net_cached = false;
@@ -1084,11 +1157,12 @@ static gf_status net_train_eval(gf_net* net, gf_mesh* m, bool train, double lr, 
 }
 
 gf_status gf_net_train_step(gf_net* net, gf_mesh* m, double lr, double* loss_out) {
-  return net_train_eval(net, m, true, lr, loss_out, nullptr, nullptr, "gf_net_train_step");
+  return net_train_eval(net, m, true, lr, nullptr, loss_out, nullptr, nullptr, nullptr, "gf_net_train_step");
 }
 
-gf_status gf_net_eval(gf_net* net, gf_mesh* m, double* loss_out, float* blocks_out, float* grad_out) {
-  return net_train_eval(net, m, false, 0.0, loss_out, blocks_out, grad_out, "gf_net_eval");
+gf_status gf_net_eval(gf_net* net, gf_mesh* m, const double* probe, double* loss_out, float* gdiag_out,
+                      float* glower_out, float* grad_out) {
+  return net_train_eval(net, m, false, 0.0, probe, loss_out, gdiag_out, glower_out, grad_out, "gf_net_eval");
 }
 
 }  // extern "C"

@@ -963,6 +963,161 @@ __global__ __launch_bounds__(NT) void k_pcg_update(int k, int n, int Gb, const v
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->iters = k + 1;
 }
 
+// ---------------------------------------------------------------- factorised preconditioner
+
+// y += G_b x for the BF16 block in slot b (row-major 3x3).
+template <typename T>
+__device__ __forceinline__ void gblk_fma(const __bf16* __restrict__ g, int nbp, int b, const v4<T>& x, T& ax, T& ay,
+                                         T& az) {
+  T a[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) a[c] = (T)(float)g[(size_t)c * nbp + b];
+  ax = fmadd(a[0], x.x, fmadd(a[1], x.y, fmadd(a[2], x.z, ax)));
+  ay = fmadd(a[3], x.x, fmadd(a[4], x.y, fmadd(a[5], x.z, ay)));
+  az = fmadd(a[6], x.x, fmadd(a[7], x.y, fmadd(a[8], x.z, az)));
+}
+
+// y += G_b^T x.
+template <typename T>
+__device__ __forceinline__ void gblk_fma_t(const __bf16* __restrict__ g, int nbp, int b, const v4<T>& x, T& ax,
+                                           T& ay, T& az) {
+  T a[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) a[c] = (T)(float)g[(size_t)c * nbp + b];
+  ax = fmadd(a[0], x.x, fmadd(a[3], x.y, fmadd(a[6], x.z, ax)));
+  ay = fmadd(a[1], x.x, fmadd(a[4], x.y, fmadd(a[7], x.z, ay)));
+  az = fmadd(a[2], x.x, fmadd(a[5], x.y, fmadd(a[8], x.z, az)));
+}
+
+template <typename T>
+__device__ __forceinline__ T half_row_sum(T v) {
+#pragma unroll
+  for (int o = kHalfLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kHalfLanes);
+  return v;
+}
+
+// G pass.  INIT: r = src rounded to T (written to r_new), x = 0, partials into
+// parity 0.  Otherwise iteration k: alpha from the SpMV's p.q partials and
+// this grid's r.z partials of parity k; every neighbour's r_new entry is
+// formed on the fly with the same fused operation its owner uses (r_old and
+// r_new are distinct buffers, so no row reads a value another workgroup is
+// overwriting).  kHalfLanes lanes per row walk the row's lower slots.
+template <typename T, bool INIT, int NT>
+__global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* __restrict__ src,
+                                                  const v4<T>* __restrict__ r_old, v4<T>* __restrict__ r_new,
+                                                  const v4<T>* __restrict__ q, const v4<T>* __restrict__ p,
+                                                  v4<T>* __restrict__ x, v4<T>* __restrict__ y, PcgCtl* ctl,
+                                                  const double* __restrict__ part_pq,
+                                                  double* __restrict__ part_rz) {
+  __shared__ double sh[3 * (NT / 64)];
+  if (!INIT && ctl->done) return;
+  const int n = F.n;
+  const int G = gridDim.x;
+  const int L = xcd_logical(blockIdx.x, G);
+  const int chunk = (n + G - 1) / G;
+  const int r0 = min(n, L * chunk), r1 = min(n, r0 + chunk);
+  const int lane = threadIdx.x & (kHalfLanes - 1);
+  const int grp = threadIdx.x / kHalfLanes;
+  constexpr int NG = NT / kHalfLanes;
+  T al = T(0);
+  if (!INIT) {
+    const double* cur = part_rz + (size_t)(k & 1) * 2 * kMaxPart;
+    double pq = 0, rz = 0, unused = 0;
+    for (int t = threadIdx.x; t < G; t += NT) {
+      pq += part_pq[t];
+      rz += cur[t];
+    }
+    block_sum3n<NT>(pq, rz, unused, sh);
+    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->fail = 1;
+        ctl->done = 1;
+      }
+      return;
+    }
+    al = (T)(rz / pq);
+  }
+  double yy = 0, rr = 0;
+  for (int i = r0 + grp; i < r1; i += NG) {
+    const int s = F.row_ptr[i], d = F.diag_blk[i];
+    T ax = 0, ay = 0, az = 0;
+    for (int b = s + lane; b < d; b += kHalfLanes) {
+      const int j = F.col[b];
+      v4<T> rj;
+      if (INIT) {
+        const d4 sj = src[j];
+        rj = v4<T>{(T)sj.x, (T)sj.y, (T)sj.z, T(0)};
+      } else {
+        const v4<T> ro = r_old[j], qj = q[j];
+        rj = v4<T>{fmadd(-al, qj.x, ro.x), fmadd(-al, qj.y, ro.y), fmadd(-al, qj.z, ro.z), T(0)};
+      }
+      gblk_fma(F.g, F.nbp, b, rj, ax, ay, az);
+    }
+    ax = half_row_sum(ax);
+    ay = half_row_sum(ay);
+    az = half_row_sum(az);
+    if (lane == 0) {
+      v4<T> ri;
+      if (INIT) {
+        const d4 si = src[i];
+        ri = v4<T>{(T)si.x, (T)si.y, (T)si.z, T(0)};
+        x[i] = v4<T>{T(0), T(0), T(0), T(0)};
+      } else {
+        const v4<T> ro = r_old[i], qi = q[i], pi = p[i];
+        ri = v4<T>{fmadd(-al, qi.x, ro.x), fmadd(-al, qi.y, ro.y), fmadd(-al, qi.z, ro.z), T(0)};
+        v4<T> xi = x[i];
+        xi.x = fmadd(al, pi.x, xi.x);
+        xi.y = fmadd(al, pi.y, xi.y);
+        xi.z = fmadd(al, pi.z, xi.z);
+        x[i] = xi;
+      }
+      r_new[i] = ri;
+      gblk_fma(F.g, F.nbp, d, ri, ax, ay, az);
+      y[i] = v4<T>{ax, ay, az, T(0)};
+      yy += (double)ax * ax + (double)ay * ay + (double)az * az;
+      rr += (double)ri.x * ri.x + (double)ri.y * ri.y + (double)ri.z * ri.z;
+    }
+  }
+  double unused = 0;
+  block_sum3n<NT>(yy, rr, unused, sh);
+  double* nxt = part_rz + (size_t)(INIT ? 0 : ((k + 1) & 1)) * 2 * kMaxPart;
+  if (threadIdx.x == 0) {
+    nxt[L] = yy;
+    nxt[kMaxPart + L] = rr;
+  }
+  if (!INIT && blockIdx.x == 0 && threadIdx.x == 0) ctl->iters = k + 1;
+}
+
+// G^T pass: z_i = G_ii^T y_i + sum over the upper slots (i, j) of G_ji^T y_j;
+// INIT also writes p_0 = z.
+template <typename T, bool INIT, int NT>
+__global__ __launch_bounds__(NT) void k_pcg_gtpass(FactView F, const v4<T>* __restrict__ y, v4<T>* __restrict__ z,
+                                                   v4<T>* __restrict__ p0, PcgCtl* ctl) {
+  if (!INIT && ctl->done) return;
+  const int n = F.n;
+  const int G = gridDim.x;
+  const int L = xcd_logical(blockIdx.x, G);
+  const int chunk = (n + G - 1) / G;
+  const int r0 = min(n, L * chunk), r1 = min(n, r0 + chunk);
+  const int lane = threadIdx.x & (kHalfLanes - 1);
+  const int grp = threadIdx.x / kHalfLanes;
+  constexpr int NG = NT / kHalfLanes;
+  for (int i = r0 + grp; i < r1; i += NG) {
+    const int d = F.diag_blk[i], e = F.row_ptr[i + 1];
+    T ax = 0, ay = 0, az = 0;
+    for (int b = d + 1 + lane; b < e; b += kHalfLanes) gblk_fma(F.g, F.nbp, b, y[F.col[b]], ax, ay, az);
+    ax = half_row_sum(ax);
+    ay = half_row_sum(ay);
+    az = half_row_sum(az);
+    if (lane == 0) {
+      gblk_fma_t(F.g, F.nbp, d, y[i], ax, ay, az);
+      const v4<T> zi{ax, ay, az, T(0)};
+      z[i] = zi;
+      if (INIT) p0[i] = zi;
+    }
+  }
+}
+
 // FP64 residual of the outer (iterative refinement) loop: R = b - A X64 with
 // the stored (FP32 or FP64) block values promoted to FP64; partial |R|^2.
 template <typename T>
@@ -1108,6 +1263,33 @@ void launch_pcg_update(hipStream_t s, int k, int n, int Ga, int Gb, const v4<T>*
                        v4<T>* r, v4<T>* z, const T* binv, PcgCtl* ctl, const double* part_pq, double* part_rz) {
   k_pcg_update<T, kVecThreads><<<Ga, kVecThreads, 0, s>>>(k, n, Gb, p, q, x, r, z, binv, ctl, part_pq, part_rz);
 }
+
+template <typename T>
+void launch_pcg_fact_init(hipStream_t s, int Gb, FactView F, const d4* src, v4<T>* r0, v4<T>* x, v4<T>* y,
+                          v4<T>* z, v4<T>* p0, double* part_rz) {
+  k_pcg_gpass<T, true, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(0, F, src, nullptr, r0, nullptr, nullptr, x, y,
+                                                                nullptr, nullptr, part_rz);
+  k_pcg_gtpass<T, true, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(F, y, z, p0, nullptr);
+}
+
+template <typename T>
+void launch_pcg_gpass(hipStream_t s, int k, int Gb, FactView F, const v4<T>* r_old, v4<T>* r_new, const v4<T>* q,
+                      const v4<T>* p, v4<T>* x, v4<T>* y, PcgCtl* ctl, const double* part_pq, double* part_rz) {
+  k_pcg_gpass<T, false, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(k, F, nullptr, r_old, r_new, q, p, x, y, ctl,
+                                                                 part_pq, part_rz);
+}
+
+template <typename T>
+void launch_pcg_gtpass(hipStream_t s, int Gb, FactView F, const v4<T>* y, v4<T>* z, PcgCtl* ctl) {
+  k_pcg_gtpass<T, false, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(F, y, z, nullptr, ctl);
+}
+
+template void launch_pcg_fact_init<float>(hipStream_t, int, FactView, const d4*, v4<float>*, v4<float>*,
+                                          v4<float>*, v4<float>*, v4<float>*, double*);
+template void launch_pcg_gpass<float>(hipStream_t, int, int, FactView, const v4<float>*, v4<float>*,
+                                      const v4<float>*, const v4<float>*, v4<float>*, v4<float>*, PcgCtl*,
+                                      const double*, double*);
+template void launch_pcg_gtpass<float>(hipStream_t, int, FactView, const v4<float>*, v4<float>*, PcgCtl*);
 
 template <typename T>
 void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, d4* R64, double* part_rr) {

@@ -108,6 +108,38 @@ void launch_pcg_update(hipStream_t s, int k, int n, int Ga, int Gb, const v4<T>*
                        v4<T>* x, v4<T>* r, v4<T>* z, const T* binv, PcgCtl* ctl, const double* part_pq,
                        double* part_rz);
 
+// Factorised sparse approximate inverse preconditioner z = G^T G r, G block
+// lower triangular on the lower block pattern of A (node order).  BF16 block
+// values on the full symmetric pattern of A, SoA [9][nbp]: the lower slot
+// (i, j < i) holds G_ij, its mirror upper slot (j, i) holds G_ij^T and the
+// diagonal slot holds G_ii (lower triangular), so G r reads the lower slots
+// of a row and G^T y the upper ones.
+struct FactView {
+  int n, nbp;
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const int32_t* diag_blk;
+  const __bf16* g;
+};
+constexpr int kHalfLanes = 8;  // lanes cooperating on one half row in the G and G^T passes
+
+// Start of a solve with the factorised preconditioner: r_0 = src (rounded to
+// T), x = 0, y = G r_0, z = G^T y, p_0 = z; partials of r.z (= y.y) and r.r.
+// Gb workgroups (kSpmvThreads each), the same grid as the SpMV, so the SpMV
+// reduces Gb partials.
+template <typename T>
+void launch_pcg_fact_init(hipStream_t s, int Gb, FactView F, const d4* src, v4<T>* r0, v4<T>* x, v4<T>* y,
+                          v4<T>* z, v4<T>* p0, double* part_rz);
+// Iteration k after the SpMV: alpha = r.z / p.q; x += alpha p; r_new = r_old -
+// alpha q; y = G r_new; partials y.y and r.r for iteration k + 1.
+template <typename T>
+void launch_pcg_gpass(hipStream_t s, int k, int Gb, FactView F, const v4<T>* r_old, v4<T>* r_new,
+                      const v4<T>* q, const v4<T>* p, v4<T>* x, v4<T>* y, PcgCtl* ctl, const double* part_pq,
+                      double* part_rz);
+// z = G^T y.
+template <typename T>
+void launch_pcg_gtpass(hipStream_t s, int Gb, FactView F, const v4<T>* y, v4<T>* z, PcgCtl* ctl);
+
 template <typename T>
 void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, d4* R64,
                   double* part_rr);

@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_net_mean_bwd(NetInputs in, int npad, co
   gz[(size_t)node * kHid + f] = (bf16)((float)zprev[(size_t)node * kHid + f] > 0.f ? g : 0.f);
 }
 
-// ---------------------------------------------------------------- head
+// ---------------------------------------------------------------- head and factor
 
 __device__ __forceinline__ void lower_from_o(const float* o, float L[3][3]) {
   L[0][0] = expf(o[0]);
@@ -178,6 +178,12 @@ __device__ __forceinline__ void lower_from_o(const float* o, float L[3][3]) {
   L[0][1] = L[0][2] = L[1][2] = 0.f;
 }
 
+// Row-major 3x3 block of slot b.
+__device__ __forceinline__ void load_blk9(const float* __restrict__ val, int nbp, int b, float a[9]) {
+#pragma unroll
+  for (int c = 0; c < 9; ++c) a[c] = val[(size_t)c * nbp + b];
+}
+
 __device__ __forceinline__ void sym_from_binv(const float* binv, int n, int i, float C[3][3]) {
   C[0][0] = binv[i];
   C[1][1] = binv[(size_t)n + i];
@@ -187,133 +193,392 @@ __device__ __forceinline__ void sym_from_binv(const float* binv, int n, int i, f
   C[1][2] = C[2][1] = binv[5 * (size_t)n + i];
 }
 
-// B = L C L^T (symmetrised) stored as [6][n] (00, 11, 22, 01, 02, 12).
-__device__ __forceinline__ void store_block(float* Bout, int n, int i, const float L[3][3], const float C[3][3]) {
-  float LC[3][3], B[3][3];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) LC[r][c] = L[r][0] * C[0][c] + L[r][1] * C[1][c] + L[r][2] * C[2][c];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) B[r][c] = LC[r][0] * L[c][0] + LC[r][1] * L[c][1] + LC[r][2] * L[c][2];
-  Bout[i] = B[0][0];
-  Bout[(size_t)n + i] = B[1][1];
-  Bout[2 * (size_t)n + i] = B[2][2];
-  Bout[3 * (size_t)n + i] = 0.5f * (B[0][1] + B[1][0]);
-  Bout[4 * (size_t)n + i] = 0.5f * (B[0][2] + B[2][0]);
-  Bout[5 * (size_t)n + i] = 0.5f * (B[1][2] + B[2][1]);
+// C = inverse of the lower Cholesky factor of the SPD block a (FP64 inside),
+// and log det C.
+__device__ __forceinline__ float inv_chol(const float a[9], float C[3][3]) {
+  const double l00 = sqrt((double)a[0]);
+  const double l10 = a[3] / l00, l20 = a[6] / l00;
+  const double l11 = sqrt((double)a[4] - l10 * l10);
+  const double l21 = (a[7] - l20 * l10) / l11;
+  const double l22 = sqrt((double)a[8] - l20 * l20 - l21 * l21);
+  const double c00 = 1.0 / l00, c11 = 1.0 / l11, c22 = 1.0 / l22;
+  const double c10 = -l10 * c00 / l11;
+  const double c21 = -l21 * c11 / l22;
+  const double c20 = -(l20 * c00 + l21 * c10) / l22;
+  C[0][0] = (float)c00;
+  C[1][1] = (float)c11;
+  C[2][2] = (float)c22;
+  C[1][0] = (float)c10;
+  C[2][1] = (float)c21;
+  C[2][0] = (float)c20;
+  C[0][1] = C[0][2] = C[1][2] = 0.f;
+  return (float)(log(c00) + log(c11) + log(c22));
 }
 
-// One thread per node: o = Wh h3 + bh, L(o), B = L A_ii^-1 L^T (prescribed
-// nodes keep A_ii^-1).  TRAIN: residual r = B b - dv over free nodes, loss
-// partial, go = dloss/do, gh3 = Wh^T go and gz3 = gh3 * (z3 > 0).
-template <bool TRAIN>
-__global__ __launch_bounds__(256) void k_net_head(NetInputs in, int npad, const float* __restrict__ master,
-                                                  const bf16* __restrict__ h3, float* __restrict__ o_out,
-                                                  float* __restrict__ Bout, const d4* __restrict__ bvec,
-                                                  const d4* __restrict__ dv, double inv_norm,
-                                                  const bf16* __restrict__ z3, float* __restrict__ gh,
-                                                  bf16* __restrict__ gz, float* __restrict__ go_out,
-                                                  double* __restrict__ lossp) {
-  __shared__ float Wh[kNetOut * kHid + kNetOut];
-  __shared__ double sh[4];
-  for (int t = threadIdx.x; t < kNetOut * kHid + kNetOut; t += 256) Wh[t] = master[kOffWh + t];
+__device__ __forceinline__ void mat3_mul(const float A[3][3], const float B[3][3], float Cm[3][3]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Cm[r][c] = A[r][0] * B[0][c] + A[r][1] * B[1][c] + A[r][2] * B[2][c];
+}
+
+// Edge features of the edge between nodes i and j (label of edge e).
+__device__ __forceinline__ void edge_feat(const NetInputs& in, int i, int j, int e, float f[3]) {
+  const d4 Xi = in.X[i], Xj = in.X[j], Ui = in.U[i], Uj = in.U[j];
+  const double dx = Xj.x - Xi.x, dy = Xj.y - Xi.y, dz = Xj.z - Xi.z;
+  const double cx = dx + (Uj.x - Ui.x), cy = dy + (Uj.y - Ui.y), cz = dz + (Uj.z - Ui.z);
+  const double L0 = sqrt(dx * dx + dy * dy + dz * dz), L = sqrt(cx * cx + cy * cy + cz * cz);
+  f[0] = (float)(L0 * in.inv_mean_len);
+  f[1] = (float)(L / L0 - 1.0);
+  f[2] = in.zeta[e] ? 1.f : 0.f;
+}
+
+// M_i = L_i C_i (prescribed nodes: L = I), and log det M_i.
+__device__ __forceinline__ float node_factor(const NetInputs& in, const float* __restrict__ o, int i,
+                                             float M[3][3], float L[3][3], float C[3][3]) {
+  float a[9];
+  load_blk9(static_cast<const float*>(in.A.val), in.A.nbp, in.diag_blk[i], a);
+  const float ldc = inv_chol(a, C);
+  if (in.dflag[i]) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) L[r][c] = r == c ? 1.f : 0.f;
+  } else {
+    lower_from_o(o + (size_t)i * kNetHead, L);
+  }
+  mat3_mul(L, C, M);
+  return in.dflag[i] ? ldc : ldc + o[(size_t)i * kNetHead] + o[(size_t)i * kNetHead + 1] +
+                                 o[(size_t)i * kNetHead + 2];
+}
+
+// W_b = s_i + t_j + We f + be (row-major 3x3).
+__device__ __forceinline__ void edge_w(const float* __restrict__ o, int i, int j, const float f[3],
+                                       const float* __restrict__ We, float W[3][3]) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+    W[q / 3][q % 3] = o[(size_t)i * kNetHead + 6 + q] + o[(size_t)j * kNetHead + 15 + q] + We[3 * q] * f[0] +
+                      We[3 * q + 1] * f[1] + We[3 * q + 2] * f[2] + We[27 + q];
+}
+
+// o = Wh h3 + bh for every padded row, one thread per node.
+__global__ __launch_bounds__(256) void k_net_head_fwd(int npad, const float* __restrict__ master,
+                                                      const bf16* __restrict__ h3, float* __restrict__ o_out) {
+  __shared__ float Wh[kNetHead * kHid + kNetHead];
+  for (int t = threadIdx.x; t < kNetHead * kHid + kNetHead; t += 256) Wh[t] = master[kOffWh + t];
   __syncthreads();
   const int i = blockIdx.x * 256 + threadIdx.x;
-  const int n = in.n;
-  double lsum = 0.0;
-  if (i < npad) {
-    float h[kHid];
+  if (i >= npad) return;
+  float h[kHid];
 #pragma unroll
-    for (int c = 0; c < kHid / 8; ++c) {
-      const bf16x8 v = *reinterpret_cast<const bf16x8*>(h3 + (size_t)i * kHid + 8 * c);
+  for (int c = 0; c < kHid / 8; ++c) {
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(h3 + (size_t)i * kHid + 8 * c);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) h[8 * c + q] = (float)v[q];
-    }
-    float o[kNetOut];
-#pragma unroll
-    for (int k = 0; k < kNetOut; ++k) {
-      float acc = Wh[kNetOut * kHid + k];
-#pragma unroll
-      for (int f = 0; f < kHid; ++f) acc += Wh[k * kHid + f] * h[f];
-      o[k] = acc;
-    }
-#pragma unroll
-    for (int k = 0; k < kNetOut; ++k) o_out[(size_t)i * 8 + k] = o[k];
-    float go[kNetOut] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (i < n) {
-      float L[3][3], C[3][3];
-      lower_from_o(o, L);
-      sym_from_binv(in.binv, n, i, C);
-      const bool fixed = in.dflag[i] != 0;
-      if (fixed) {
-        float I3[3][3] = {{1.f, 0.f, 0.f}, {0.f, 1.f, 0.f}, {0.f, 0.f, 1.f}};
-        store_block(Bout, n, i, I3, C);
-      } else {
-        store_block(Bout, n, i, L, C);
-      }
-      if (TRAIN && !fixed) {
-        float LC[3][3], B[3][3];
-        for (int r = 0; r < 3; ++r)
-          for (int c = 0; c < 3; ++c) LC[r][c] = L[r][0] * C[0][c] + L[r][1] * C[1][c] + L[r][2] * C[2][c];
-        for (int r = 0; r < 3; ++r)
-          for (int c = 0; c < 3; ++c) B[r][c] = LC[r][0] * L[c][0] + LC[r][1] * L[c][1] + LC[r][2] * L[c][2];
-        const d4 bi = bvec[i], di = dv[i];
-        const float bb[3] = {(float)bi.x, (float)bi.y, (float)bi.z};
-        float r3[3];
-        for (int r = 0; r < 3; ++r)
-          r3[r] = B[r][0] * bb[0] + B[r][1] * bb[1] + B[r][2] * bb[2] - (float)(r == 0 ? di.x : (r == 1 ? di.y : di.z));
-        lsum = (double)r3[0] * r3[0] + (double)r3[1] * r3[1] + (double)r3[2] * r3[2];
-        // dloss/dB = 2 r b^T / D; dloss/dL = (G + G^T) L C
-        const float s2 = (float)(2.0 * inv_norm);
-        float S[3][3], SL[3][3], GL[3][3];
-        for (int r = 0; r < 3; ++r)
-          for (int c = 0; c < 3; ++c) S[r][c] = s2 * (r3[r] * bb[c] + r3[c] * bb[r]);
-        for (int r = 0; r < 3; ++r)
-          for (int c = 0; c < 3; ++c) SL[r][c] = S[r][0] * L[0][c] + S[r][1] * L[1][c] + S[r][2] * L[2][c];
-        for (int r = 0; r < 3; ++r)
-          for (int c = 0; c < 3; ++c) GL[r][c] = SL[r][0] * C[0][c] + SL[r][1] * C[1][c] + SL[r][2] * C[2][c];
-        go[0] = GL[0][0] * L[0][0];
-        go[1] = GL[1][1] * L[1][1];
-        go[2] = GL[2][2] * L[2][2];
-        go[3] = GL[1][0];
-        go[4] = GL[2][0];
-        go[5] = GL[2][1];
-      }
-    }
-    if (TRAIN) {
-#pragma unroll
-      for (int k = 0; k < kNetOut; ++k) go_out[(size_t)i * 8 + k] = go[k];
-#pragma unroll
-      for (int f = 0; f < kHid; ++f) {
-        float g = 0.f;
-#pragma unroll
-        for (int k = 0; k < kNetOut; ++k) g += Wh[k * kHid + f] * go[k];
-        gh[(size_t)i * kHid + f] = g;
-        gz[(size_t)i * kHid + f] = (bf16)((float)z3[(size_t)i * kHid + f] > 0.f ? g : 0.f);
-      }
-    }
+    for (int q = 0; q < 8; ++q) h[8 * c + q] = (float)v[q];
   }
-  if (TRAIN) {
-    lsum = wsum(lsum);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = lsum;
-    __syncthreads();
-    if (threadIdx.x == 0) lossp[blockIdx.x] = ((sh[0] + sh[1]) + (sh[2] + sh[3])) * inv_norm;
+  for (int k = 0; k < kNetHead; ++k) {
+    float acc = Wh[kNetHead * kHid + k];
+#pragma unroll
+    for (int f = 0; f < kHid; ++f) acc += Wh[k * kHid + f] * h[f];
+    o_out[(size_t)i * kNetHead + k] = acc;
   }
 }
 
-// B from cached head outputs and the current A_ii^-1.
-__global__ __launch_bounds__(256) void k_net_apply(NetInputs in, const float* __restrict__ o_in,
-                                                   float* __restrict__ Bout) {
+// Factor values: kHalfLanes lanes per block row; lane 0 writes the diagonal
+// slot (M_i), the lanes walk the lower slots (i, j) and write G_ij there and
+// G_ij^T into the mirror slot (j, i).
+template <typename OutT>
+__global__ __launch_bounds__(256) void k_fact_build(NetInputs in, const float* __restrict__ o,
+                                                    const float* __restrict__ master, OutT* __restrict__ g) {
+  __shared__ float We[kEdgeGrad];
+  for (int t = threadIdx.x; t < kEdgeGrad; t += 256) We[t] = master[kOffWe + t];
+  __syncthreads();
+  const int n = in.n, nbp = in.A.nbp;
+  const int lane = threadIdx.x & (kHalfLanes - 1);
+  const float* __restrict__ val = static_cast<const float*>(in.A.val);
+  for (int i = blockIdx.x * (256 / kHalfLanes) + threadIdx.x / kHalfLanes; i < n;
+       i += gridDim.x * (256 / kHalfLanes)) {
+    float M[3][3], L[3][3], C[3][3];
+    node_factor(in, o, i, M, L, C);
+    const int d = in.diag_blk[i];
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < 9; ++q) g[(size_t)q * nbp + d] = (OutT)M[q / 3][q % 3];
+    for (int b = in.A.row_ptr[i] + lane; b < d; b += kHalfLanes) {
+      const int j = in.A.col[b], e = in.blk_edge[b];
+      const int mir = in.blk_ij[e] == b ? in.blk_ji[e] : in.blk_ij[e];
+      float f[3], W[3][3], a[9], Dj[3][3], K[3][3], T[3][3], Gb[3][3];
+      edge_feat(in, i, j, e, f);
+      edge_w(o, i, j, f, We, W);
+      load_blk9(val, nbp, b, a);
+      sym_from_binv(in.binv, n, j, Dj);
+      const float Am[3][3] = {{a[0], a[1], a[2]}, {a[3], a[4], a[5]}, {a[6], a[7], a[8]}};
+      mat3_mul(Am, Dj, K);
+      mat3_mul(W, K, T);
+      mat3_mul(M, T, Gb);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        g[(size_t)q * nbp + b] = (OutT)(-Gb[q / 3][q % 3]);
+        g[(size_t)q * nbp + mir] = (OutT)(-Gb[q % 3][q / 3]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- training (Kaporin probe loss)
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_net_probe_gen(int n, uint64_t seed, d4* __restrict__ v) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= in.n) return;
-  float o[kNetOut], L[3][3], C[3][3];
-  for (int k = 0; k < kNetOut; ++k) o[k] = o_in[(size_t)i * 8 + k];
-  lower_from_o(o, L);
-  sym_from_binv(in.binv, in.n, i, C);
-  if (in.dflag[i]) {
-    float I3[3][3] = {{1.f, 0.f, 0.f}, {0.f, 1.f, 0.f}, {0.f, 0.f, 1.f}};
-    store_block(Bout, in.n, i, I3, C);
-  } else {
-    store_block(Bout, in.n, i, L, C);
+  if (i >= n) return;
+  const uint64_t base = splitmix64(seed) ^ (3ull * (uint64_t)i);
+  d4 r;
+  r.x = (splitmix64(base) >> 63) ? -1.0 : 1.0;
+  r.y = (splitmix64(base + 1) >> 63) ? -1.0 : 1.0;
+  r.z = (splitmix64(base + 2) >> 63) ? -1.0 : 1.0;
+  r.w = 0.0;
+  v[i] = r;
+}
+
+// u = G^T v from the FP32 factor, FP64 accumulation (kHalfLanes lanes per row).
+__global__ __launch_bounds__(256) void k_kap_u(NetInputs in, const float* __restrict__ g, const d4* __restrict__ v,
+                                               d4* __restrict__ u) {
+  const int n = in.n, nbp = in.A.nbp;
+  const int lane = threadIdx.x & (kHalfLanes - 1);
+  for (int i = blockIdx.x * (256 / kHalfLanes) + threadIdx.x / kHalfLanes; i < n;
+       i += gridDim.x * (256 / kHalfLanes)) {
+    const int d = in.diag_blk[i], e = in.A.row_ptr[i + 1];
+    double ax = 0, ay = 0, az = 0;
+    for (int b = d + 1 + lane; b < e; b += kHalfLanes) {
+      const d4 vj = v[in.A.col[b]];
+      float a[9];
+      load_blk9(g, nbp, b, a);
+      ax += a[0] * vj.x + a[1] * vj.y + a[2] * vj.z;
+      ay += a[3] * vj.x + a[4] * vj.y + a[5] * vj.z;
+      az += a[6] * vj.x + a[7] * vj.y + a[8] * vj.z;
+    }
+#pragma unroll
+    for (int s = kHalfLanes / 2; s > 0; s >>= 1) {
+      ax += __shfl_xor(ax, s, kHalfLanes);
+      ay += __shfl_xor(ay, s, kHalfLanes);
+      az += __shfl_xor(az, s, kHalfLanes);
+    }
+    if (lane == 0) {
+      const d4 vi = v[i];
+      float a[9];
+      load_blk9(g, nbp, d, a);
+      ax += a[0] * vi.x + a[3] * vi.y + a[6] * vi.z;
+      ay += a[1] * vi.x + a[4] * vi.y + a[7] * vi.z;
+      az += a[2] * vi.x + a[5] * vi.y + a[8] * vi.z;
+      u[i] = d4{ax, ay, az, 0.0};
+    }
+  }
+}
+
+// Per node: partials of t = u.w (w = -wneg) and of log det M_i; m_i = M_i^T v_i
+// and s_i = A_ii^-1 w_i for the gradient kernel.
+__global__ __launch_bounds__(256) void k_kap_node(NetInputs in, const float* __restrict__ o, const d4* __restrict__ v,
+                                                  const d4* __restrict__ u, const d4* __restrict__ wneg,
+                                                  v4<float>* __restrict__ mv, v4<float>* __restrict__ sv,
+                                                  double* __restrict__ dpart) {
+  __shared__ double sh[8];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double t = 0.0, ld = 0.0;
+  if (i < in.n) {
+    float M[3][3], L[3][3], C[3][3], D[3][3];
+    ld = node_factor(in, o, i, M, L, C);
+    const d4 vi = v[i], ui = u[i], wi = wneg[i];
+    t = -(ui.x * wi.x + ui.y * wi.y + ui.z * wi.z);
+    const float v3[3] = {(float)vi.x, (float)vi.y, (float)vi.z};
+    const float w3[3] = {(float)-wi.x, (float)-wi.y, (float)-wi.z};
+    float m3[3], s3[3];
+    sym_from_binv(in.binv, in.n, i, D);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      m3[c] = M[0][c] * v3[0] + M[1][c] * v3[1] + M[2][c] * v3[2];
+      s3[c] = D[c][0] * w3[0] + D[c][1] * w3[1] + D[c][2] * w3[2];
+    }
+    mv[i] = v4<float>{m3[0], m3[1], m3[2], 0.f};
+    sv[i] = v4<float>{s3[0], s3[1], s3[2], 0.f};
+  }
+  t = wsum(t);
+  ld = wsum(ld);
+  if ((threadIdx.x & 63) == 0) {
+    sh[threadIdx.x >> 6] = t;
+    sh[4 + (threadIdx.x >> 6)] = ld;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    dpart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    dpart[kMaxPart + blockIdx.x] = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+  }
+}
+
+__device__ __forceinline__ float wsumf(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Head-output gradient go (24 per row, zero on padding rows) and per-workgroup
+// partials of the edge-term gradient (We, be).  With k_b = A_ij s_j:
+//   dloss/dW_b = -(2/t) m_i k_b^T,
+//   go[6:15]_i  = sum over lower slots of row i of dloss/dW_b,
+//   go[15:24]_j = sum over lower blocks (i, j) of dloss/dW_b (row j's upper slots),
+//   dloss/dL_i  = (2/t) v_i rho_i^T - (2/N) L_i^-T, rho_i = C_i (w_i - sum_b W_b k_b).
+__global__ __launch_bounds__(256) void k_kap_grad(NetInputs in, int npad, const float* __restrict__ o,
+                                                  const float* __restrict__ master, const d4* __restrict__ v,
+                                                  const d4* __restrict__ wneg, const v4<float>* __restrict__ mv,
+                                                  const v4<float>* __restrict__ sv, float c2t, float c2n,
+                                                  float* __restrict__ go, float* __restrict__ epart) {
+  __shared__ float We[kEdgeGrad];
+  __shared__ float red[4][kEdgeGrad];
+  for (int t = threadIdx.x; t < kEdgeGrad; t += 256) We[t] = master[kOffWe + t];
+  __syncthreads();
+  const int n = in.n, nbp = in.A.nbp;
+  const int lane = threadIdx.x & (kHalfLanes - 1);
+  const float* __restrict__ val = static_cast<const float*>(in.A.val);
+  float eg[kEdgeGrad];
+#pragma unroll
+  for (int q = 0; q < kEdgeGrad; ++q) eg[q] = 0.f;
+  const int rows_per = 256 / kHalfLanes;
+  const int nrow_iter = (npad + gridDim.x * rows_per - 1) / (gridDim.x * rows_per);
+  for (int it = 0; it < nrow_iter; ++it) {
+    const int i = (it * gridDim.x + blockIdx.x) * rows_per + threadIdx.x / kHalfLanes;
+    if (i >= npad) continue;
+    if (i >= n) {
+      if (lane == 0)
+        for (int q = 0; q < kNetHead; ++q) go[(size_t)i * kNetHead + q] = 0.f;
+      continue;
+    }
+    const v4<float> mi = mv[i], si = sv[i];
+    float a3[3] = {0.f, 0.f, 0.f}, rho3[3] = {0.f, 0.f, 0.f}, gt[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) gt[q] = 0.f;
+    const int s = in.A.row_ptr[i], d = in.diag_blk[i], e = in.A.row_ptr[i + 1];
+    for (int b = s + lane; b < e; b += kHalfLanes) {
+      if (b == d) continue;
+      const int j = in.A.col[b];
+      float a[9];
+      load_blk9(val, nbp, b, a);
+      if (b < d) {
+        const v4<float> sj = sv[j];
+        const float k3[3] = {a[0] * sj.x + a[1] * sj.y + a[2] * sj.z, a[3] * sj.x + a[4] * sj.y + a[5] * sj.z,
+                             a[6] * sj.x + a[7] * sj.y + a[8] * sj.z};
+        float f[3], W[3][3];
+        edge_feat(in, i, j, in.blk_edge[b], f);
+        edge_w(o, i, j, f, We, W);
+        const float m3[3] = {mi.x, mi.y, mi.z};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          a3[r] += k3[r];
+          rho3[r] += W[r][0] * k3[0] + W[r][1] * k3[1] + W[r][2] * k3[2];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float dw = -c2t * m3[r] * k3[c];
+            const int q = 3 * r + c;
+            eg[3 * q] += dw * f[0];
+            eg[3 * q + 1] += dw * f[1];
+            eg[3 * q + 2] += dw * f[2];
+            eg[27 + q] += dw;
+          }
+        }
+      } else {
+        // upper slot (i, k): lower block (k, i) with k_b = A_ki s_i = A_ik^T s_i
+        const v4<float> mk = mv[j];
+        const float k3[3] = {a[0] * si.x + a[3] * si.y + a[6] * si.z, a[1] * si.x + a[4] * si.y + a[7] * si.z,
+                             a[2] * si.x + a[5] * si.y + a[8] * si.z};
+        const float m3[3] = {mk.x, mk.y, mk.z};
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) gt[3 * r + c] -= c2t * m3[r] * k3[c];
+      }
+    }
+#pragma unroll
+    for (int sft = kHalfLanes / 2; sft > 0; sft >>= 1) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        a3[r] += __shfl_xor(a3[r], sft, kHalfLanes);
+        rho3[r] += __shfl_xor(rho3[r], sft, kHalfLanes);
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) gt[q] += __shfl_xor(gt[q], sft, kHalfLanes);
+    }
+    if (lane == 0) {
+      float* gout = go + (size_t)i * kNetHead;
+      const float m3[3] = {mi.x, mi.y, mi.z};
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          gout[6 + 3 * r + c] = -c2t * m3[r] * a3[c];
+          gout[15 + 3 * r + c] = gt[3 * r + c];
+        }
+      if (in.dflag[i]) {
+        for (int q = 0; q < 6; ++q) gout[q] = 0.f;
+      } else {
+        float M[3][3], L[3][3], C[3][3];
+        node_factor(in, o, i, M, L, C);
+        const d4 vi = v[i], wi = wneg[i];
+        const float w3[3] = {(float)-wi.x - rho3[0], (float)-wi.y - rho3[1], (float)-wi.z - rho3[2]};
+        float rho[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) rho[r] = C[r][0] * w3[0] + C[r][1] * w3[1] + C[r][2] * w3[2];
+        const float v3[3] = {(float)vi.x, (float)vi.y, (float)vi.z};
+        gout[0] = c2t * v3[0] * rho[0] * L[0][0] - c2n;
+        gout[1] = c2t * v3[1] * rho[1] * L[1][1] - c2n;
+        gout[2] = c2t * v3[2] * rho[2] * L[2][2] - c2n;
+        gout[3] = c2t * v3[1] * rho[0];
+        gout[4] = c2t * v3[2] * rho[0];
+        gout[5] = c2t * v3[2] * rho[1];
+      }
+    }
+  }
+  // workgroup partials of the edge-term gradient, fixed order
+#pragma unroll
+  for (int q = 0; q < kEdgeGrad; ++q) {
+    const float r = wsumf(eg[q]);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = r;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < kEdgeGrad; q += 256)
+    epart[(size_t)blockIdx.x * kEdgeGrad + q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+}
+
+__global__ __launch_bounds__(64) void k_kap_edge_reduce(int nwg, const float* __restrict__ epart,
+                                                        float* __restrict__ grad) {
+  const int q = threadIdx.x;
+  if (q >= kEdgeGrad) return;
+  float s = 0.f;
+  for (int w = 0; w < nwg; ++w) s += epart[(size_t)w * kEdgeGrad + q];
+  grad[kOffWe + q] = s;
+}
+
+// gh3 = Wh^T go and gz3 = gh3 * (z3 > 0), one thread per padded row.
+__global__ __launch_bounds__(256) void k_net_head_bwd(int npad, const float* __restrict__ master,
+                                                      const float* __restrict__ go, const bf16* __restrict__ z3,
+                                                      float* __restrict__ gh, bf16* __restrict__ gz) {
+  __shared__ float Wh[kNetHead * kHid];
+  for (int t = threadIdx.x; t < kNetHead * kHid; t += 256) Wh[t] = master[kOffWh + t];
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= npad) return;
+  float g[kNetHead];
+#pragma unroll
+  for (int k = 0; k < kNetHead; ++k) g[k] = go[(size_t)i * kNetHead + k];
+  for (int f = 0; f < kHid; ++f) {
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < kNetHead; ++k) acc += Wh[k * kHid + f] * g[k];
+    gh[(size_t)i * kHid + f] = acc;
+    gz[(size_t)i * kHid + f] = (bf16)((float)z3[(size_t)i * kHid + f] > 0.f ? acc : 0.f);
   }
 }
 
@@ -394,29 +659,30 @@ __global__ __launch_bounds__(256) void k_net_dw_reduce(int nwg, int K, int Kreal
 }
 
 // dWh[k][f] = sum go[k] h3[f], dbh[k] = sum go[k]: per workgroup a node range,
-// one output per thread; partials [workgroup][390].
+// outputs strided over the threads; partials [workgroup][24*64 + 24].
+constexpr int kHeadGrad = kNetHead * kHid + kNetHead;
+
 __global__ __launch_bounds__(512) void k_net_dhead(int npad, const float* __restrict__ go, const bf16* __restrict__ h3,
                                                    float* __restrict__ part) {
-  constexpr int NO = kNetOut * kHid + kNetOut;
-  const int t = threadIdx.x;
   const int G = gridDim.x;
   const int per = (npad + G - 1) / G;
   const int c0 = min(npad, blockIdx.x * per), c1 = min(npad, c0 + per);
-  if (t >= NO) return;
-  const int k = t < kNetOut * kHid ? t / kHid : t - kNetOut * kHid;
-  const int f = t < kNetOut * kHid ? t % kHid : -1;
-  float s = 0.f;
-  for (int i = c0; i < c1; ++i) s += go[(size_t)i * 8 + k] * (f >= 0 ? (float)h3[(size_t)i * kHid + f] : 1.f);
-  part[(size_t)blockIdx.x * NO + t] = s;
+  for (int t = threadIdx.x; t < kHeadGrad; t += 512) {
+    const int k = t < kNetHead * kHid ? t / kHid : t - kNetHead * kHid;
+    const int f = t < kNetHead * kHid ? t % kHid : -1;
+    float s = 0.f;
+    for (int i = c0; i < c1; ++i)
+      s += go[(size_t)i * kNetHead + k] * (f >= 0 ? (float)h3[(size_t)i * kHid + f] : 1.f);
+    part[(size_t)blockIdx.x * kHeadGrad + t] = s;
+  }
 }
 
-__global__ __launch_bounds__(512) void k_net_dhead_reduce(int nwg, const float* __restrict__ part,
+__global__ __launch_bounds__(256) void k_net_dhead_reduce(int nwg, const float* __restrict__ part,
                                                           float* __restrict__ grad) {
-  constexpr int NO = kNetOut * kHid + kNetOut;
-  const int t = threadIdx.x;
-  if (t >= NO) return;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= kHeadGrad) return;
   float s = 0.f;
-  for (int w = 0; w < nwg; ++w) s += part[(size_t)w * NO + t];
+  for (int w = 0; w < nwg; ++w) s += part[(size_t)w * kHeadGrad + t];
   grad[kOffWh + t] = s;
 }
 
@@ -456,26 +722,11 @@ __global__ __launch_bounds__(256) void k_net_pack(const float* __restrict__ w, b
   }
 }
 
-__global__ __launch_bounds__(256) void k_net_dvnorm(int n, const d4* __restrict__ dv, const uint8_t* __restrict__ dflag,
-                                                    double* __restrict__ part) {
-  __shared__ double sh[4];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  double s = 0.0;
-  if (i < n && !dflag[i]) {
-    const d4 d = dv[i];
-    s = d.x * d.x + d.y * d.y + d.z * d.z;
-  }
-  s = wsum(s);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-}
-
 inline int nb256(int n) { return (n + 255) / 256; }
 
 }  // namespace
 
-void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in) {
+void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int) {
   const int np = w.npad;
   k_net_inputs<<<nb256(np), 256, 0, s>>>(in, np, w.a, w.inv_wdeg);
   k_net_gemm<kNetInPad, 0, kHid, 0><<<np / kNetRows, 256, 0, s>>>(w.a, nullptr, P.W0, P.master + kOffB0, nullptr,
@@ -486,22 +737,40 @@ void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInpu
         w.h[l], w.m[l], P.Wl[l], P.master + kOffL0 + l * kLayerSize + kHid * 2 * kHid, w.h[l], w.z[l + 1],
         w.h[l + 1], nullptr);
   }
-  k_net_head<false><<<nb256(np), 256, 0, s>>>(in, np, P.master, w.h[kNetLayers], w.o, w.B, nullptr, nullptr, 0.0,
-                                              nullptr, nullptr, nullptr, nullptr, nullptr);
+  k_net_head_fwd<<<nb256(np), 256, 0, s>>>(np, P.master, w.h[kNetLayers], w.o);
 }
 
-void net_apply_cached(hipStream_t s, const NetParamsDev&, NetWork& w, const NetInputs& in) {
-  k_net_apply<<<nb256(in.n), 256, 0, s>>>(in, w.o, w.B);
+void net_build_factor(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int Gb, bool fp32) {
+  if (fp32)
+    k_fact_build<float><<<Gb, 256, 0, s>>>(in, w.o, P.master, w.g32);
+  else
+    k_fact_build<bf16><<<Gb, 256, 0, s>>>(in, w.o, P.master, w.g);
 }
 
-int net_backward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, const d4* b, const d4* dv,
-                 double inv_norm) {
+FactView net_factor_view(const NetWork& w, const NetInputs& in) {
+  return FactView{in.n, in.A.nbp, in.A.row_ptr, in.A.col, in.diag_blk, w.g};
+}
+
+void net_probe(hipStream_t s, NetWork& w, uint64_t seed) { k_net_probe_gen<<<nb256(w.n), 256, 0, s>>>(w.n, seed, w.probe); }
+
+void net_kaporin_u(hipStream_t s, NetWork& w, const NetInputs& in, int Gb) {
+  k_kap_u<<<Gb, 256, 0, s>>>(in, w.g32, w.probe, w.u);
+}
+
+int net_kaporin_dots(hipStream_t s, const NetParamsDev&, NetWork& w, const NetInputs& in) {
+  k_kap_node<<<nb256(in.n), 256, 0, s>>>(in, w.o, w.probe, w.u, w.wneg, w.mv, w.sv, w.dpart);
+  return nb256(in.n);
+}
+
+void net_kaporin_backward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int Gb, double t) {
   const int np = w.npad;
-  const int nh = nb256(np);
-  k_net_head<true><<<nh, 256, 0, s>>>(in, np, P.master, w.h[kNetLayers], w.o, w.B, b, dv, inv_norm, w.z[kNetLayers],
-                                      w.gh, w.gz, w.go, w.lossp);
+  const double N = 3.0 * in.n;
+  k_kap_grad<<<Gb, 256, 0, s>>>(in, np, w.o, P.master, w.probe, w.wneg, w.mv, w.sv, (float)(2.0 / t),
+                                (float)(2.0 / N), w.go, w.epart);
+  k_kap_edge_reduce<<<1, 64, 0, s>>>(Gb, w.epart, w.grad);
   k_net_dhead<<<kDwWorkgroups, 512, 0, s>>>(np, w.go, w.h[kNetLayers], w.part);
-  k_net_dhead_reduce<<<1, 512, 0, s>>>(kDwWorkgroups, w.part, w.grad);
+  k_net_dhead_reduce<<<nb256(kHeadGrad), 256, 0, s>>>(kDwWorkgroups, w.part, w.grad);
+  k_net_head_bwd<<<nb256(np), 256, 0, s>>>(np, P.master, w.go, w.z[kNetLayers], w.gh, w.gz);
   for (int l = kNetLayers - 1; l >= 0; --l) {
     // gz holds dloss/dz_{l+1}
     k_net_dw<kHid, kHid><<<kDwWorkgroups, 256, 0, s>>>(np, w.gz, w.h[l], w.m[l], w.part);
@@ -515,7 +784,6 @@ int net_backward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInpu
   k_net_dw<kNetInPad, 0><<<kDwWorkgroups, 256, 0, s>>>(np, w.gz, w.a, nullptr, w.part);
   k_net_dw_reduce<<<nb256(kHid * kNetIn + kHid), 256, 0, s>>>(kDwWorkgroups, kNetInPad, kNetIn, w.part, w.grad,
                                                               kOffW0, kOffB0);
-  return nh;
 }
 
 void net_adam(hipStream_t s, NetParamsDev& P, const float* grad, int t, float lr) {
@@ -528,11 +796,6 @@ void net_adam(hipStream_t s, NetParamsDev& P, const float* grad, int t, float lr
 void net_pack(hipStream_t s, NetParamsDev& P) {
   k_net_pack<<<nb256(kHid * 2 * kHid), 256, 0, s>>>(P.master, P.W0, P.Wl[0], P.Wl[1], P.Wl[2], P.WlT[0], P.WlT[1],
                                                      P.WlT[2]);
-}
-
-int net_dv_norm(hipStream_t s, int n, const d4* dv, const uint8_t* dflag, double* part) {
-  k_net_dvnorm<<<nb256(n), 256, 0, s>>>(n, dv, dflag, part);
-  return nb256(n);
 }
 
 }  // namespace gfem

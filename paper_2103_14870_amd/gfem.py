@@ -19,7 +19,8 @@ STATUS_NAMES = {0: "GF_OK", -1: "GF_EINVAL", -2: "GF_EDEGENERATE", -3: "GF_ENOME
                 -5: "GF_ENOTCONVERGED", -6: "GF_ESTATE"}
 PREC = {"fp64": 0, "split": 1}
 PRECOND = {"block_jacobi": 0, "learned": 1}
-KERNEL_CATEGORIES = ("damage", "element", "assembly", "precond", "spmv", "pcg_vector", "residual", "integrate")
+KERNEL_CATEGORIES = ("damage", "element", "assembly", "precond", "spmv", "pcg_vector", "residual", "integrate",
+                     "precond_gt")
 
 
 class GfParams(C.Structure):
@@ -34,7 +35,7 @@ class GfStepStats(C.Structure):
     _fields_ = [("steps_done", C.c_int32), ("inner_iters", C.c_int32), ("outer_iters", C.c_int32),
                 ("used_fallback", C.c_int32), ("new_broken", C.c_int32), ("total_broken", C.c_int32),
                 ("near_threshold", C.c_int32), ("chi_zero_tets", C.c_int32), ("degenerate_tets", C.c_int32),
-                ("n_launch", C.c_int32 * 8), ("rel_residual", C.c_double), ("kernel_us", C.c_double * 8)]
+                ("n_launch", C.c_int32 * 9), ("rel_residual", C.c_double), ("kernel_us", C.c_double * 9)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("n_launch", "kernel_us")}
@@ -79,7 +80,8 @@ _SIGS = {
     "gf_set_precond_net": ([C.c_void_p, C.c_void_p], C.c_int),
     "gf_set_precond": ([C.c_void_p, C.c_int32], C.c_int),
     "gf_net_train_step": ([C.c_void_p, C.c_void_p, C.c_double, _P(C.c_double)], C.c_int),
-    "gf_net_eval": ([C.c_void_p, C.c_void_p, _P(C.c_double), _P(C.c_float), _P(C.c_float)], C.c_int),
+    "gf_net_eval": ([C.c_void_p, C.c_void_p, _P(C.c_double), _P(C.c_double), _P(C.c_float), _P(C.c_float),
+                     _P(C.c_float)], C.c_int),
 }
 
 
@@ -297,14 +299,21 @@ class Net:
         _check(self._lib.gf_net_train_step(self._h, mesh._h, float(lr), C.byref(loss)))
         return loss.value
 
-    def eval(self, mesh: "Mesh"):
-        """(loss, blocks (n,6) [00 11 22 01 02 12], weight gradient)."""
+    def eval(self, mesh: "Mesh", probe=None):
+        """(loss, diagonal factor blocks (n,3,3), lower blocks G_ji of the
+        canonical edges (ne,3,3), weight gradient) on the mesh's next system.
+        probe: (n,3) array of +-1 (caller order) or None for the generator's."""
         loss = C.c_double()
-        blocks = np.zeros((mesh.n_nodes, 6), np.float32)
+        gd = np.zeros((mesh.n_nodes, 3, 3), np.float32)
+        gl = np.zeros((mesh.n_edges, 3, 3), np.float32)
         grad = np.zeros(self.n_params, np.float32)
-        _check(self._lib.gf_net_eval(self._h, mesh._h, C.byref(loss), blocks.ctypes.data_as(_P(C.c_float)),
-                                     grad.ctypes.data_as(_P(C.c_float))))
-        return loss.value, blocks, grad
+        pv = None
+        if probe is not None:
+            pv = np.ascontiguousarray(probe, dtype=np.float64).reshape(mesh.n_nodes, 3)
+        _check(self._lib.gf_net_eval(self._h, mesh._h, pv.ctypes.data_as(_P(C.c_double)) if pv is not None else None,
+                                     C.byref(loss), gd.ctypes.data_as(_P(C.c_float)),
+                                     gl.ctypes.data_as(_P(C.c_float)), grad.ctypes.data_as(_P(C.c_float))))
+        return loss.value, gd, gl, grad
 
 
 def attach_net(mesh: "Mesh", net: "Net | None", use: bool = True):
