@@ -128,6 +128,7 @@ struct gf_mesh {
   void* edge_w = nullptr;
   // block matrix
   int32_t *row_ptr = nullptr, *col = nullptr, *diag_blk = nullptr, *blk_edge = nullptr;
+  int32_t *lptr = nullptr, *lcol = nullptr, *uptr = nullptr, *ucol = nullptr, *upos = nullptr;
   void* val = nullptr;
   void* binv = nullptr;
   // PCG
@@ -424,7 +425,9 @@ void ensure_netw(gf_mesh* M) {
   for (auto& m : w.m) m = M->al.get<gfem::bf16>(np * gfem::kHid);
   for (auto& z : w.z) z = M->al.get<gfem::bf16>(np * gfem::kHid);
   w.o = M->al.get<float>(np * gfem::kNetHead);
-  w.g = M->al.get<gfem::bf16>((size_t)9 * M->nbp);
+  w.gl = M->al.get<gfem::bf16>((size_t)9 * M->ne);
+  w.gu = M->al.get<gfem::bf16>((size_t)9 * M->ne);
+  w.gd = M->al.get<gfem::bf16>((size_t)6 * M->n);
   double sum = 0;
   for (int e = 0; e < M->ne; ++e) sum += std::sqrt(M->topo.edge_S[e]);
   M->inv_mean_len = M->ne > 0 ? M->ne / sum : 1.0;
@@ -443,7 +446,9 @@ void ensure_net_train(gf_mesh* M) {
   w.go = M->al.get<float>(np * gfem::kNetHead);
   w.part = M->al.get<float>((size_t)w.nwg_dw * (gfem::kHid * 2 * gfem::kHid + gfem::kHid));
   w.grad = M->al.get<float>(gfem::kNetParams);
-  w.g32 = M->al.get<float>((size_t)9 * M->nbp);
+  w.gl32 = M->al.get<float>((size_t)9 * M->ne);
+  w.gu32 = M->al.get<float>((size_t)9 * M->ne);
+  w.gd32 = M->al.get<float>((size_t)6 * M->n);
   w.probe = M->al.get<d4>(M->n);
   w.u = M->al.get<d4>(M->n);
   w.wneg = M->al.get<d4>(M->n);
@@ -456,9 +461,9 @@ void ensure_net_train(gf_mesh* M) {
 }
 
 gfem::NetInputs net_inputs(gf_mesh* M, const uint8_t* zeta) {
-  return gfem::NetInputs{M->n,      M->mat(), M->diag_blk,      M->blk_edge,
-                         M->blk_ij, M->blk_ji, M->X,             M->U,
-                         zeta,      M->inv_mean_len, static_cast<const float*>(M->binv), M->dflag};
+  return gfem::NetInputs{M->n,    M->mat(), M->diag_blk, M->blk_edge, M->ne,           M->lptr,
+                         M->uptr, M->lcol,  M->ucol,     M->upos,     M->X,            M->U,
+                         zeta,    M->inv_mean_len, static_cast<const float*>(M->binv), M->dflag};
 }
 
 // Factor of the learned path for the assembled step: the network runs every
@@ -647,6 +652,11 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     M->col = upload(M, T.col);
     M->diag_blk = upload(M, T.diag_blk);
     M->blk_edge = upload(M, T.blk_edge);
+    M->lptr = upload(M, T.lptr);
+    M->lcol = upload(M, T.lcol);
+    M->uptr = upload(M, T.uptr);
+    M->ucol = upload(M, T.ucol);
+    M->upos = upload(M, T.upos);
     if (M->split)
       alloc_precision<float>(M);
     else
@@ -1134,21 +1144,33 @@ static gf_status net_train_eval(gf_net* net, gf_mesh* m, bool train, double lr, 
     }
     if (grad_out)
       hchk(hipMemcpyAsync(grad_out, w.grad, sizeof(float) * gfem::kNetParams, hipMemcpyDeviceToHost, s), "D2H");
-    std::vector<float> hg;
-    if (gdiag_out || glower_out) {
-      hg.resize((size_t)9 * m->nbp);
-      hchk(hipMemcpyAsync(hg.data(), w.g32, sizeof(float) * hg.size(), hipMemcpyDeviceToHost, s), "D2H");
+    std::vector<float> hd, hl;
+    if (gdiag_out) {
+      hd.resize((size_t)6 * m->n);
+      hchk(hipMemcpyAsync(hd.data(), w.gd32, sizeof(float) * hd.size(), hipMemcpyDeviceToHost, s), "D2H");
+    }
+    if (glower_out) {
+      hl.resize((size_t)9 * m->ne);
+      hchk(hipMemcpyAsync(hl.data(), w.gl32, sizeof(float) * hl.size(), hipMemcpyDeviceToHost, s), "D2H");
     }
     m->sync();
     if (gdiag_out)
       for (int c = 0; c < m->n; ++c) {
-        const int b = m->topo.diag_blk[m->topo.perm_new[c]];
-        for (int q = 0; q < 9; ++q) gdiag_out[9 * (size_t)c + q] = hg[(size_t)q * m->nbp + b];
+        const size_t i = m->topo.perm_new[c];
+        const size_t nn = m->n;
+        float* o = gdiag_out + 9 * (size_t)c;
+        o[0] = hd[i];
+        o[1] = o[2] = o[5] = 0.f;
+        o[3] = hd[nn + i];
+        o[4] = hd[2 * nn + i];
+        o[6] = hd[3 * nn + i];
+        o[7] = hd[4 * nn + i];
+        o[8] = hd[5 * nn + i];
       }
     if (glower_out)
       for (int c = 0; c < m->ne; ++c) {
-        const int b = m->topo.blk_ji[m->topo.edge_internal[c]];
-        for (int q = 0; q < 9; ++q) glower_out[9 * (size_t)c + q] = hg[(size_t)q * m->nbp + b];
+        const int li = m->topo.lpos[m->topo.edge_internal[c]];
+        for (int q = 0; q < 9; ++q) glower_out[9 * (size_t)c + q] = hl[(size_t)q * m->ne + li];
       }
     if (loss_out) *loss_out = loss;
     m->net_cached = false;

@@ -965,28 +965,23 @@ __global__ __launch_bounds__(NT) void k_pcg_update(int k, int n, int Gb, const v
 
 // ---------------------------------------------------------------- factorised preconditioner
 
-// y += G_b x for the BF16 block in slot b (row-major 3x3).
+// y += G x for the BF16 block at index b of a [9][stride] array (row-major 3x3).
 template <typename T>
-__device__ __forceinline__ void gblk_fma(const __bf16* __restrict__ g, int nbp, int b, const v4<T>& x, T& ax, T& ay,
-                                         T& az) {
+__device__ __forceinline__ void gblk_fma(const __bf16* __restrict__ g, int stride, int b, const v4<T>& x, T& ax,
+                                         T& ay, T& az) {
   T a[9];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) a[c] = (T)(float)g[(size_t)c * nbp + b];
+  for (int c = 0; c < 9; ++c) a[c] = (T)(float)g[(size_t)c * stride + b];
   ax = fmadd(a[0], x.x, fmadd(a[1], x.y, fmadd(a[2], x.z, ax)));
   ay = fmadd(a[3], x.x, fmadd(a[4], x.y, fmadd(a[5], x.z, ay)));
   az = fmadd(a[6], x.x, fmadd(a[7], x.y, fmadd(a[8], x.z, az)));
 }
 
-// y += G_b^T x.
+// Lower-triangular diagonal block (00, 10, 11, 20, 21, 22) of node i.
 template <typename T>
-__device__ __forceinline__ void gblk_fma_t(const __bf16* __restrict__ g, int nbp, int b, const v4<T>& x, T& ax,
-                                           T& ay, T& az) {
-  T a[9];
+__device__ __forceinline__ void gdiag_load(const __bf16* __restrict__ gd, int n, int i, T d[6]) {
 #pragma unroll
-  for (int c = 0; c < 9; ++c) a[c] = (T)(float)g[(size_t)c * nbp + b];
-  ax = fmadd(a[0], x.x, fmadd(a[3], x.y, fmadd(a[6], x.z, ax)));
-  ay = fmadd(a[1], x.x, fmadd(a[4], x.y, fmadd(a[7], x.z, ay)));
-  az = fmadd(a[2], x.x, fmadd(a[5], x.y, fmadd(a[8], x.z, az)));
+  for (int c = 0; c < 6; ++c) d[c] = (T)(float)gd[(size_t)c * n + i];
 }
 
 template <typename T>
@@ -1039,10 +1034,10 @@ __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* _
   }
   double yy = 0, rr = 0;
   for (int i = r0 + grp; i < r1; i += NG) {
-    const int s = F.row_ptr[i], d = F.diag_blk[i];
+    const int s = F.lptr[i], d = F.lptr[i + 1];
     T ax = 0, ay = 0, az = 0;
     for (int b = s + lane; b < d; b += kHalfLanes) {
-      const int j = F.col[b];
+      const int j = F.lcol[b];
       v4<T> rj;
       if (INIT) {
         const d4 sj = src[j];
@@ -1051,7 +1046,7 @@ __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* _
         const v4<T> ro = r_old[j], qj = q[j];
         rj = v4<T>{fmadd(-al, qj.x, ro.x), fmadd(-al, qj.y, ro.y), fmadd(-al, qj.z, ro.z), T(0)};
       }
-      gblk_fma(F.g, F.nbp, b, rj, ax, ay, az);
+      gblk_fma(F.gl, F.ne, b, rj, ax, ay, az);
     }
     ax = half_row_sum(ax);
     ay = half_row_sum(ay);
@@ -1072,7 +1067,11 @@ __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* _
         x[i] = xi;
       }
       r_new[i] = ri;
-      gblk_fma(F.g, F.nbp, d, ri, ax, ay, az);
+      T g6[6];
+      gdiag_load(F.gd, n, i, g6);
+      ax = fmadd(g6[0], ri.x, ax);
+      ay = fmadd(g6[1], ri.x, fmadd(g6[2], ri.y, ay));
+      az = fmadd(g6[3], ri.x, fmadd(g6[4], ri.y, fmadd(g6[5], ri.z, az)));
       y[i] = v4<T>{ax, ay, az, T(0)};
       yy += (double)ax * ax + (double)ay * ay + (double)az * az;
       rr += (double)ri.x * ri.x + (double)ri.y * ri.y + (double)ri.z * ri.z;
@@ -1088,7 +1087,7 @@ __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* _
   if (!INIT && blockIdx.x == 0 && threadIdx.x == 0) ctl->iters = k + 1;
 }
 
-// G^T pass: z_i = G_ii^T y_i + sum over the upper slots (i, j) of G_ji^T y_j;
+// G^T pass: z_i = G_ii^T y_i + sum over the upper blocks (i, j) of G_ji^T y_j;
 // INIT also writes p_0 = z.
 template <typename T, bool INIT, int NT>
 __global__ __launch_bounds__(NT) void k_pcg_gtpass(FactView F, const v4<T>* __restrict__ y, v4<T>* __restrict__ z,
@@ -1103,14 +1102,19 @@ __global__ __launch_bounds__(NT) void k_pcg_gtpass(FactView F, const v4<T>* __re
   const int grp = threadIdx.x / kHalfLanes;
   constexpr int NG = NT / kHalfLanes;
   for (int i = r0 + grp; i < r1; i += NG) {
-    const int d = F.diag_blk[i], e = F.row_ptr[i + 1];
+    const int s = F.uptr[i], e = F.uptr[i + 1];
     T ax = 0, ay = 0, az = 0;
-    for (int b = d + 1 + lane; b < e; b += kHalfLanes) gblk_fma(F.g, F.nbp, b, y[F.col[b]], ax, ay, az);
+    for (int b = s + lane; b < e; b += kHalfLanes) gblk_fma(F.gu, F.ne, b, y[F.ucol[b]], ax, ay, az);
     ax = half_row_sum(ax);
     ay = half_row_sum(ay);
     az = half_row_sum(az);
     if (lane == 0) {
-      gblk_fma_t(F.g, F.nbp, d, y[i], ax, ay, az);
+      const v4<T> yi = y[i];
+      T g6[6];
+      gdiag_load(F.gd, n, i, g6);
+      ax = fmadd(g6[0], yi.x, fmadd(g6[1], yi.y, fmadd(g6[3], yi.z, ax)));
+      ay = fmadd(g6[2], yi.y, fmadd(g6[4], yi.z, ay));
+      az = fmadd(g6[5], yi.z, az);
       const v4<T> zi{ax, ay, az, T(0)};
       z[i] = zi;
       if (INIT) p0[i] = zi;

@@ -110,16 +110,21 @@ void launch_pcg_update(hipStream_t s, int k, int n, int Ga, int Gb, const v4<T>*
 
 // Factorised sparse approximate inverse preconditioner z = G^T G r, G block
 // lower triangular on the lower block pattern of A (node order).  BF16 block
-// values on the full symmetric pattern of A, SoA [9][nbp]: the lower slot
-// (i, j < i) holds G_ij, its mirror upper slot (j, i) holds G_ij^T and the
-// diagonal slot holds G_ii (lower triangular), so G r reads the lower slots
-// of a row and G^T y the upper ones.
+// values in compact half-pattern arrays, SoA with unit stride across blocks:
+// gl [9][ne] holds G_ij of the strictly lower blocks in the order of lcol
+// (row i: lptr[i] .. lptr[i+1]), gu [9][ne] holds G_ji^T at the mirror
+// positions in the order of ucol, and gd [6][n] the lower-triangular diagonal
+// blocks G_ii (entries 00, 10, 11, 20, 21, 22).  G r streams gl and G^T y
+// streams gu, each once, with no interleaved bytes of the other half.
 struct FactView {
-  int n, nbp;
-  const int32_t* row_ptr;
-  const int32_t* col;
-  const int32_t* diag_blk;
-  const __bf16* g;
+  int n, ne;
+  const int32_t* lptr;
+  const int32_t* lcol;
+  const int32_t* uptr;
+  const int32_t* ucol;
+  const __bf16* gl;
+  const __bf16* gu;
+  const __bf16* gd;
 };
 constexpr int kHalfLanes = 8;  // lanes cooperating on one half row in the G and G^T passes
 

@@ -124,46 +124,60 @@ __global__ __launch_bounds__(256) void k_net_gemm(const bf16* __restrict__ XA, c
 // ---------------------------------------------------------------- neighbour mean
 
 // m_i = (1 / number of unbroken incident edges) sum over unbroken edges of h_j.
-// One wave per node, lane = feature.
+// Eight lanes per node, eight features (one 16-byte load) per lane.
 __global__ __launch_bounds__(256) void k_net_mean(NetInputs in, int npad, const float* __restrict__ inv_wdeg,
                                                   const bf16* __restrict__ h, bf16* __restrict__ m) {
-  const int node = blockIdx.x * 4 + (threadIdx.x >> 6), f = threadIdx.x & 63;
+  const int node = blockIdx.x * 32 + (threadIdx.x >> 3), f8 = (threadIdx.x & 7) * 8;
   if (node >= npad) return;
-  float acc = 0.f;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (node < in.n) {
     const int s = in.A.row_ptr[node], e = in.A.row_ptr[node + 1], db = in.diag_blk[node];
     for (int b = s; b < e; ++b) {
       if (b == db) continue;
       if (in.zeta[in.blk_edge[b]]) continue;
-      acc += (float)h[(size_t)in.A.col[b] * kHid + f];
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(h + (size_t)in.A.col[b] * kHid + f8);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += (float)v[q];
     }
-    acc *= inv_wdeg[node];
+    const float iw = inv_wdeg[node];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] *= iw;
   }
-  m[(size_t)node * kHid + f] = (bf16)acc;
+  bf16x8 out;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) out[q] = (bf16)acc[q];
+  *reinterpret_cast<bf16x8*>(m + (size_t)node * kHid + f8) = out;
 }
 
 // Backward through h_l = h_{l-1} + relu(W [h_{l-1}; m]) with m = P h_{l-1}:
 // gh <- gh + gi[:, :64] + P^T gi[:, 64:], (P^T g)_j = sum_i w_ij g_i / wdeg_i over
 // unbroken edges (a gather over the same symmetric pattern), then
-// gz = gh * (zprev > 0) for the layer below.
+// gz = gh * (zprev > 0) for the layer below.  Eight lanes per node, eight
+// features per lane.
 __global__ __launch_bounds__(256) void k_net_mean_bwd(NetInputs in, int npad, const float* __restrict__ inv_wdeg,
                                                       const float* __restrict__ gi, float* __restrict__ gh,
                                                       const bf16* __restrict__ zprev, bf16* __restrict__ gz) {
-  const int node = blockIdx.x * 4 + (threadIdx.x >> 6), f = threadIdx.x & 63;
+  typedef float f32x8 __attribute__((ext_vector_type(8)));
+  const int node = blockIdx.x * 32 + (threadIdx.x >> 3), f8 = (threadIdx.x & 7) * 8;
   if (node >= npad) return;
-  float g = 0.f;
+  f32x8 g = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (node < in.n) {
-    g = gh[(size_t)node * kHid + f] + gi[(size_t)node * 2 * kHid + f];
+    g = *reinterpret_cast<const f32x8*>(gh + (size_t)node * kHid + f8) +
+        *reinterpret_cast<const f32x8*>(gi + (size_t)node * 2 * kHid + f8);
     const int s = in.A.row_ptr[node], e = in.A.row_ptr[node + 1], db = in.diag_blk[node];
     for (int b = s; b < e; ++b) {
       if (b == db) continue;
       if (in.zeta[in.blk_edge[b]]) continue;
       const int j = in.A.col[b];
-      g += inv_wdeg[j] * gi[(size_t)j * 2 * kHid + kHid + f];
+      g += inv_wdeg[j] * *reinterpret_cast<const f32x8*>(gi + (size_t)j * 2 * kHid + kHid + f8);
     }
   }
-  gh[(size_t)node * kHid + f] = g;
-  gz[(size_t)node * kHid + f] = (bf16)((float)zprev[(size_t)node * kHid + f] > 0.f ? g : 0.f);
+  *reinterpret_cast<f32x8*>(gh + (size_t)node * kHid + f8) = g;
+  const bf16x8 zp = *reinterpret_cast<const bf16x8*>(zprev + (size_t)node * kHid + f8);
+  bf16x8 out;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) out[q] = (bf16)((float)zp[q] > 0.f ? g[q] : 0.f);
+  *reinterpret_cast<bf16x8*>(gz + (size_t)node * kHid + f8) = out;
 }
 
 // ---------------------------------------------------------------- head and factor
@@ -285,28 +299,34 @@ __global__ __launch_bounds__(256) void k_net_head_fwd(int npad, const float* __r
 }
 
 // Factor values: kHalfLanes lanes per block row; lane 0 writes the diagonal
-// slot (M_i), the lanes walk the lower slots (i, j) and write G_ij there and
-// G_ij^T into the mirror slot (j, i).
+// block M_i, the lanes walk the row's strictly lower blocks (i, j) and write
+// G_ij into gl and G_ij^T into gu at the mirror position.
 template <typename OutT>
 __global__ __launch_bounds__(256) void k_fact_build(NetInputs in, const float* __restrict__ o,
-                                                    const float* __restrict__ master, OutT* __restrict__ g) {
+                                                    const float* __restrict__ master, OutT* __restrict__ gl,
+                                                    OutT* __restrict__ gu, OutT* __restrict__ gd) {
   __shared__ float We[kEdgeGrad];
   for (int t = threadIdx.x; t < kEdgeGrad; t += 256) We[t] = master[kOffWe + t];
   __syncthreads();
-  const int n = in.n, nbp = in.A.nbp;
+  const int n = in.n, nbp = in.A.nbp, ne = in.ne;
   const int lane = threadIdx.x & (kHalfLanes - 1);
   const float* __restrict__ val = static_cast<const float*>(in.A.val);
   for (int i = blockIdx.x * (256 / kHalfLanes) + threadIdx.x / kHalfLanes; i < n;
        i += gridDim.x * (256 / kHalfLanes)) {
     float M[3][3], L[3][3], C[3][3];
     node_factor(in, o, i, M, L, C);
-    const int d = in.diag_blk[i];
-    if (lane == 0)
-#pragma unroll
-      for (int q = 0; q < 9; ++q) g[(size_t)q * nbp + d] = (OutT)M[q / 3][q % 3];
-    for (int b = in.A.row_ptr[i] + lane; b < d; b += kHalfLanes) {
+    if (lane == 0) {
+      gd[i] = (OutT)M[0][0];
+      gd[(size_t)n + i] = (OutT)M[1][0];
+      gd[2 * (size_t)n + i] = (OutT)M[1][1];
+      gd[3 * (size_t)n + i] = (OutT)M[2][0];
+      gd[4 * (size_t)n + i] = (OutT)M[2][1];
+      gd[5 * (size_t)n + i] = (OutT)M[2][2];
+    }
+    const int s = in.A.row_ptr[i], d = in.diag_blk[i], l0 = in.lptr[i];
+    for (int b = s + lane; b < d; b += kHalfLanes) {
       const int j = in.A.col[b], e = in.blk_edge[b];
-      const int mir = in.blk_ij[e] == b ? in.blk_ji[e] : in.blk_ij[e];
+      const int li = l0 + (b - s), ui = in.upos[e];
       float f[3], W[3][3], a[9], Dj[3][3], K[3][3], T[3][3], Gb[3][3];
       edge_feat(in, i, j, e, f);
       edge_w(o, i, j, f, We, W);
@@ -318,8 +338,8 @@ __global__ __launch_bounds__(256) void k_fact_build(NetInputs in, const float* _
       mat3_mul(M, T, Gb);
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
-        g[(size_t)q * nbp + b] = (OutT)(-Gb[q / 3][q % 3]);
-        g[(size_t)q * nbp + mir] = (OutT)(-Gb[q % 3][q / 3]);
+        gl[(size_t)q * ne + li] = (OutT)(-Gb[q / 3][q % 3]);
+        gu[(size_t)q * ne + ui] = (OutT)(-Gb[q % 3][q / 3]);
       }
     }
   }
@@ -347,18 +367,18 @@ __global__ __launch_bounds__(256) void k_net_probe_gen(int n, uint64_t seed, d4*
 }
 
 // u = G^T v from the FP32 factor, FP64 accumulation (kHalfLanes lanes per row).
-__global__ __launch_bounds__(256) void k_kap_u(NetInputs in, const float* __restrict__ g, const d4* __restrict__ v,
+__global__ __launch_bounds__(256) void k_kap_u(NetInputs in, const float* __restrict__ gu,
+                                               const float* __restrict__ gd, const d4* __restrict__ v,
                                                d4* __restrict__ u) {
-  const int n = in.n, nbp = in.A.nbp;
+  const int n = in.n, ne = in.ne;
   const int lane = threadIdx.x & (kHalfLanes - 1);
   for (int i = blockIdx.x * (256 / kHalfLanes) + threadIdx.x / kHalfLanes; i < n;
        i += gridDim.x * (256 / kHalfLanes)) {
-    const int d = in.diag_blk[i], e = in.A.row_ptr[i + 1];
     double ax = 0, ay = 0, az = 0;
-    for (int b = d + 1 + lane; b < e; b += kHalfLanes) {
-      const d4 vj = v[in.A.col[b]];
+    for (int b = in.uptr[i] + lane; b < in.uptr[i + 1]; b += kHalfLanes) {
+      const d4 vj = v[in.ucol[b]];
       float a[9];
-      load_blk9(g, nbp, b, a);
+      load_blk9(gu, ne, b, a);
       ax += a[0] * vj.x + a[1] * vj.y + a[2] * vj.z;
       ay += a[3] * vj.x + a[4] * vj.y + a[5] * vj.z;
       az += a[6] * vj.x + a[7] * vj.y + a[8] * vj.z;
@@ -371,11 +391,11 @@ __global__ __launch_bounds__(256) void k_kap_u(NetInputs in, const float* __rest
     }
     if (lane == 0) {
       const d4 vi = v[i];
-      float a[9];
-      load_blk9(g, nbp, d, a);
-      ax += a[0] * vi.x + a[3] * vi.y + a[6] * vi.z;
-      ay += a[1] * vi.x + a[4] * vi.y + a[7] * vi.z;
-      az += a[2] * vi.x + a[5] * vi.y + a[8] * vi.z;
+      const double g00 = gd[i], g10 = gd[(size_t)n + i], g11 = gd[2 * (size_t)n + i];
+      const double g20 = gd[3 * (size_t)n + i], g21 = gd[4 * (size_t)n + i], g22 = gd[5 * (size_t)n + i];
+      ax += g00 * vi.x + g10 * vi.y + g20 * vi.z;
+      ay += g11 * vi.y + g21 * vi.z;
+      az += g22 * vi.z;
       u[i] = d4{ax, ay, az, 0.0};
     }
   }
@@ -732,7 +752,7 @@ void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInpu
   k_net_gemm<kNetInPad, 0, kHid, 0><<<np / kNetRows, 256, 0, s>>>(w.a, nullptr, P.W0, P.master + kOffB0, nullptr,
                                                                   w.z[0], w.h[0], nullptr);
   for (int l = 0; l < kNetLayers; ++l) {
-    k_net_mean<<<np / 4, 256, 0, s>>>(in, np, w.inv_wdeg, w.h[l], w.m[l]);
+    k_net_mean<<<np / 32, 256, 0, s>>>(in, np, w.inv_wdeg, w.h[l], w.m[l]);
     k_net_gemm<kHid, kHid, kHid, 1><<<np / kNetRows, 256, 0, s>>>(
         w.h[l], w.m[l], P.Wl[l], P.master + kOffL0 + l * kLayerSize + kHid * 2 * kHid, w.h[l], w.z[l + 1],
         w.h[l + 1], nullptr);
@@ -742,19 +762,19 @@ void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInpu
 
 void net_build_factor(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int Gb, bool fp32) {
   if (fp32)
-    k_fact_build<float><<<Gb, 256, 0, s>>>(in, w.o, P.master, w.g32);
+    k_fact_build<float><<<Gb, 256, 0, s>>>(in, w.o, P.master, w.gl32, w.gu32, w.gd32);
   else
-    k_fact_build<bf16><<<Gb, 256, 0, s>>>(in, w.o, P.master, w.g);
+    k_fact_build<bf16><<<Gb, 256, 0, s>>>(in, w.o, P.master, w.gl, w.gu, w.gd);
 }
 
 FactView net_factor_view(const NetWork& w, const NetInputs& in) {
-  return FactView{in.n, in.A.nbp, in.A.row_ptr, in.A.col, in.diag_blk, w.g};
+  return FactView{in.n, in.ne, in.lptr, in.lcol, in.uptr, in.ucol, w.gl, w.gu, w.gd};
 }
 
 void net_probe(hipStream_t s, NetWork& w, uint64_t seed) { k_net_probe_gen<<<nb256(w.n), 256, 0, s>>>(w.n, seed, w.probe); }
 
 void net_kaporin_u(hipStream_t s, NetWork& w, const NetInputs& in, int Gb) {
-  k_kap_u<<<Gb, 256, 0, s>>>(in, w.g32, w.probe, w.u);
+  k_kap_u<<<Gb, 256, 0, s>>>(in, w.gu32, w.gd32, w.probe, w.u);
 }
 
 int net_kaporin_dots(hipStream_t s, const NetParamsDev&, NetWork& w, const NetInputs& in) {
@@ -779,7 +799,7 @@ void net_kaporin_backward(hipStream_t s, const NetParamsDev& P, NetWork& w, cons
                                                                   kOffL0 + l * kLayerSize + kHid * 2 * kHid);
     k_net_gemm<kHid, 0, 2 * kHid, 2><<<np / kNetRows, 256, 0, s>>>(w.gz, nullptr, P.WlT[l], nullptr, nullptr,
                                                                    nullptr, nullptr, w.gi);
-    k_net_mean_bwd<<<np / 4, 256, 0, s>>>(in, np, w.inv_wdeg, w.gi, w.gh, w.z[l], w.gz);
+    k_net_mean_bwd<<<np / 32, 256, 0, s>>>(in, np, w.inv_wdeg, w.gi, w.gh, w.z[l], w.gz);
   }
   k_net_dw<kNetInPad, 0><<<kDwWorkgroups, 256, 0, s>>>(np, w.gz, w.a, nullptr, w.part);
   k_net_dw_reduce<<<nb256(kHid * kNetIn + kHid), 256, 0, s>>>(kDwWorkgroups, kNetInPad, kNetIn, w.part, w.grad,

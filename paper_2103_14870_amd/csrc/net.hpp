@@ -73,9 +73,10 @@ struct NetWork {
   float* go = nullptr;                  // [npad][24]
   float* part = nullptr;                // weight-gradient partials [nwg_dw][64*128 + 64]
   float* grad = nullptr;                // [kNetParams]
-  // factor values: BF16 for the solve, FP32 for training ([9][nbp] each)
-  bf16* g = nullptr;
-  float* g32 = nullptr;
+  // factor values in the compact half-pattern layout of FactView: BF16 for
+  // the solve, FP32 for training (gl, gu [9][ne], gd [6][n])
+  bf16 *gl = nullptr, *gu = nullptr, *gd = nullptr;
+  float *gl32 = nullptr, *gu32 = nullptr, *gd32 = nullptr;
   // training scratch
   d4* probe = nullptr;                  // [n] +-1 probe v
   d4* u = nullptr;                      // [n] G^T v
@@ -92,8 +93,12 @@ struct NetInputs {
   MatView A;                    // block pattern and (FP32) values of the system
   const int32_t* diag_blk;
   const int32_t* blk_edge;
-  const int32_t* blk_ij;        // edge -> slot (i, j) and slot (j, i), i < j
-  const int32_t* blk_ji;
+  int ne;
+  const int32_t* lptr;          // compact strictly lower / upper halves (FactView)
+  const int32_t* uptr;
+  const int32_t* lcol;
+  const int32_t* ucol;
+  const int32_t* upos;          // edge -> compact upper index of its block (i, j), i < j
   const d4* X;
   const d4* U;
   const uint8_t* zeta;          // labels of the system being solved
@@ -105,7 +110,7 @@ struct NetInputs {
 // Forward pass: node inputs, embedding, three layers, head -> w.o.
 void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int Gb);
 // Factor values from the head outputs w.o and the current system: BF16 into
-// w.g (fp32 = false) or FP32 into w.g32.
+// w.gl/gu/gd (fp32 = false) or FP32 into w.gl32/gu32/gd32.
 void net_build_factor(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int Gb, bool fp32);
 // View of the BF16 factor for the solve.
 FactView net_factor_view(const NetWork& w, const NetInputs& in);

@@ -168,6 +168,30 @@ std::string build_topology(const double* xyz, int n, const int32_t* tets_in, int
     }
   }
 
+  // Compact strictly lower / upper halves of the pattern.
+  T.lptr.assign(n + 1, 0);
+  T.uptr.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    T.lptr[i + 1] = T.lptr[i] + (T.diag_blk[i] - T.row_ptr[i]);
+    T.uptr[i + 1] = T.uptr[i] + (T.row_ptr[i + 1] - T.diag_blk[i] - 1);
+  }
+  T.lcol.resize(T.ne);
+  T.ucol.resize(T.ne);
+  T.lpos.resize(T.ne);
+  T.upos.resize(T.ne);
+  for (int i = 0; i < n; ++i) {
+    for (int b = T.row_ptr[i]; b < T.diag_blk[i]; ++b) {
+      const int li = T.lptr[i] + (b - T.row_ptr[i]);
+      T.lcol[li] = T.col[b];
+      T.lpos[T.blk_edge[b]] = li;
+    }
+    for (int b = T.diag_blk[i] + 1; b < T.row_ptr[i + 1]; ++b) {
+      const int ui = T.uptr[i] + (b - T.diag_blk[i] - 1);
+      T.ucol[ui] = T.col[b];
+      T.upos[T.blk_edge[b]] = ui;
+    }
+  }
+
   // Rest squared edge lengths and the consistent mass (Eq. 5):
   // m_ab = rho V (1 + delta_ab) / 20 per tet; off-diagonal per edge, row sums per node.
   T.edge_S.resize(T.ne);

@@ -35,6 +35,11 @@ struct Topology {
   std::vector<int32_t> blk_ij;    // ne: block (i,j) of edge e, i < j
   std::vector<int32_t> blk_ji;    // ne: block (j,i)
   std::vector<int32_t> blk_edge;  // nb: edge of an off-diagonal block, -1 on the diagonal
+  // Strictly lower / strictly upper halves of the pattern as compact CSR (same
+  // column order as the full pattern): row i's lower blocks are entries
+  // lptr[i] .. lptr[i+1] of lcol, its upper blocks uptr[i] .. uptr[i+1] of ucol.
+  std::vector<int32_t> lptr, lcol, uptr, ucol;  // n+1, ne, n+1, ne
+  std::vector<int32_t> lpos, upos;  // ne: compact lower / upper index of edge e's blocks (j,i) / (i,j)
   std::vector<double> edge_S;     // ne: rest squared length
   std::vector<double> edge_mass;  // ne: consistent off-diagonal mass, sum rho V / 20
   std::vector<double> lumped;     // n: row sum of the consistent mass, sum rho V / 4
