@@ -5,12 +5,16 @@ Workload: the ductile ellipsoid of 619,830 tets (111,912 nodes, 748,579
 edges), split precision (FP32 element pass and SpMV, FP64 dot products,
 residual and refinement), one backward-Euler step per timestep accepted at
 FP64 |b - A dv| <= 1e-6 |b|.  A "step" is one whole timestep: damage update,
-element pass with plasticity, assembly, preconditioner, PCG with iterative
-refinement, integration.  All inputs are resident in HBM before timing.
+element pass with plasticity, assembly, preconditioner (network inference
+every 4 steps, factor build every step), PCG with iterative refinement,
+integration.  All inputs are resident in HBM before timing.
 
-Prints one JSON line (rank 0).  Extra legs: the dominant kernel's roofline
-(SpMV, HIP events on the library's stream) and the FP64 CPU oracle timed on a
-one-step sample of the same workload.
+`value` is the learned-preconditioner leg (trained weights shipped in
+paper_2103_14870_amd/weights); the same K steps from the same start state
+are timed again with block-Jacobi PCG and reported beside it.  Prints one
+JSON line.  Extra legs: the dominant kernel's roofline (SpMV, HIP events on
+the library's stream) and the FP64 CPU oracle timed on a one-step sample of
+the same workload.
 """
 from __future__ import annotations
 
@@ -44,49 +48,31 @@ def cpu_baseline(prob, n_threads=1):
                        f"(FP64 NumPy/SciPy oracle, {h['iters']} PCG iterations, {dt:.1f} s)")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--dt", type=float, default=1e-2)
-    ap.add_argument("--precond", default="block_jacobi", choices=["block_jacobi"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--roofline-steps", type=int, default=5)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)
-        sys.exit(2)
-
+def timed_steps(m, steps, warmup):
     import torch
 
-    from paper_2103_14870_amd import gfem, meshgen
-
-    prob = meshgen.make_config(3, dt=args.dt)
-    prob.params["precond"] = args.precond
-    stream = torch.cuda.Stream()
-    m = gfem.mesh_from_problem(prob)
-    m.set_stream(stream.cuda_stream)
-
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         m.step(1)
     torch.cuda.synchronize()
-    iters, outer = [], []
+    iters, outer, fb = [], [], 0
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         s = m.step(1)
         iters.append(s["inner_iters"])
         outer.append(s["outer_iters"])
+        fb += s["used_fallback"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    value = args.steps / elapsed
+    return dict(value=steps / elapsed, elapsed=elapsed, iters=sum(iters) / len(iters),
+                outer=sum(outer) / len(outer), fallback=fb)
 
-    # Roofline leg: per-kernel HIP events on the library's stream over further steps.
+
+def kernel_times(m, steps):
+    import torch
+
     m.set_timing(True)
-    kus = {}
-    kn = {}
-    for _ in range(args.roofline_steps):
+    kus, kn = {}, {}
+    for _ in range(steps):
         s = m.step(1)
         for k, v in s["kernel_us"].items():
             kus[k] = kus.get(k, 0.0) + v
@@ -94,33 +80,93 @@ def main():
             kn[k] = kn.get(k, 0) + v
     torch.cuda.synchronize()
     m.set_timing(False)
+    return kus, kn
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--dt", type=float, default=1e-2)
+    ap.add_argument("--precond", default="learned", choices=["learned", "block_jacobi"])
+    ap.add_argument("--net-every", type=int, default=4, help="network inference every N steps (factor every step)")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2103_14870_amd", "weights", "precond_net.npy"))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--roofline-steps", type=int, default=5)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before the legs, one device-to-device copy of this many MiB (calibrates HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2103_14870_amd import gfem, meshgen
+
+    if args.calib_copy_mb > 0:
+        nel = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    prob = meshgen.make_config(3, dt=args.dt)
+    prob.params["net_every_n_steps"] = args.net_every
+    stream = torch.cuda.Stream()
+    net = None
+    if args.precond == "learned":
+        net = gfem.Net(seed=0)
+        net.set_weights(np.load(args.weights))
+
+    def make_mesh(learned):
+        m = gfem.mesh_from_problem(prob)
+        m.set_stream(stream.cuda_stream)
+        if learned:
+            gfem.attach_net(m, net)
+        return m
+
+    m = make_mesh(net is not None)
+    main_leg = timed_steps(m, args.steps, args.warmup)
+    kus, kn = kernel_times(m, args.roofline_steps)
     _, spmv_bytes = m.bench_spmv(10)
     spmv_us = kus["spmv"] / max(kn["spmv"], 1)
     achieved = spmv_bytes / (spmv_us * 1e-6) / 1e9
-    stats = m.step(0)
-    del stats
+    n_edges, n_blocks = m.n_edges, m.n_blocks
+    m.close()
+    jac = None
+    if net is not None:
+        mj = make_mesh(False)
+        jac = timed_steps(mj, args.steps, args.warmup)
+        mj.close()
 
     out = {
         "metric": "timesteps/s @620k tets: learned-PCG vs Jacobi-PCG at 1e-6 rel. residual",
-        "value": value,
+        "value": main_leg["value"],
         "unit": "timesteps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "ms_per_step": 1000.0 * main_leg["elapsed"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32+f64 (bf16 network and factor)" if net is not None else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": f"ellipsoid {prob.n_tets} tets / {prob.n_nodes} nodes, ductile (yield 0.05, damage 0.3), "
                         f"end caps pulled 1 cm/step, dt={args.dt:g}, PCG to 1e-6 FP64 rel. residual",
-            "tets": prob.n_tets, "nodes": prob.n_nodes, "edges": m.n_edges, "blocks": m.n_blocks,
-            "precond": args.precond, "dt": args.dt, "parallelism": "single GPU",
+            "tets": prob.n_tets, "nodes": prob.n_nodes, "edges": n_edges, "blocks": n_blocks,
+            "precond": args.precond, "net_every_n_steps": args.net_every if net is not None else None,
+            "dt": args.dt, "parallelism": "single GPU",
         },
-        "pcg_iters_per_step": sum(iters) / len(iters),
-        "outer_iters_per_step": sum(outer) / len(outer),
+        "pcg_iters_per_step": main_leg["iters"],
+        "outer_iters_per_step": main_leg["outer"],
+        "fallback_steps": main_leg["fallback"],
         "kernel_us_per_step": {k: v / args.roofline_steps for k, v in kus.items()},
         "roofline": {
             "kernel": "k_pcg_spmv (BSR 3x3 FP32 SpMV fused with the direction update and p.q)",
@@ -129,10 +175,13 @@ def main():
             "avg_launch_us": spmv_us, "launches": kn["spmv"], "bytes_per_launch": spmv_bytes,
         },
     }
+    if jac is not None:
+        out["block_jacobi"] = {"value": jac["value"], "pcg_iters_per_step": jac["iters"],
+                               "ms_per_step": 1000.0 * jac["elapsed"] / args.steps}
+        out["speedup_vs_block_jacobi"] = main_leg["value"] / jac["value"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
         out["cpu_baseline"]["host_cpus"] = os.cpu_count()
-    m.close()
     print(json.dumps(out), flush=True)
 
 

@@ -16,18 +16,21 @@ columns of A are the identity).
 
 Network (all sizes fixed):
   edge features (per edge i-j): f = (rest length / mean rest length,
-      current length / rest length - 1, zeta)
+      tanh(current length / rest length - 1), zeta)
   node input a_i (8): 1, and means over the incident edges of
       f0, f1, f2, f1^2, |f1|, (1 - zeta) f1, plus degree / 16
   embedding:  h0 = relu(W0 a + b0)                         (8 -> 64)
   3 layers:   m = P h  (mean over unbroken incident edges, P_ij = w_ij / sum_j w_ij, w = 1 - zeta)
               h <- h + relu(Wl [h; m] + bl)                 (128 -> 64)
   node head:  o = Wh h + bh                                 (64 -> 24)
-      o[0:6]   -> L = [[e^o0, 0, 0], [o3, e^o1, 0], [o4, o5, e^o2]]
+      o[0:6]   -> L = [[e^b(o0), 0, 0], [b(o3), e^b(o1), 0], [b(o4), b(o5), e^b(o2)]]
       o[6:15]  -> s_i,  o[15:24] -> t_i
-  edge term:  W_ij = s_i + t_j + We f_ij + be  (9 values, row-major 3x3)
-The edge term is linear in (h_i, h_j, f_ij), so it costs one node GEMM and a
-gather per block.
+  edge term:  W_ij = b(s_i + t_j + We f_ij + be)  (9 values, row-major 3x3)
+with the bounded map b(x) = 2 tanh(x / 2) (slope 1 at 0, range (-2, 2)), so
+that no input drives the factor to overflow: the diagonal of L stays within
+(e^-2, e^2) and every W entry within (-2, 2).  The pre-activation of the edge
+term is linear in (h_i, h_j, f_ij), so it costs one node GEMM and a gather per
+block.
 
 Training objective (one system, one probe vector v with entries +-1):
 Kaporin's condition number of G A G^T, K = (tr(GAG^T)/N)^N / det(GAG^T),
@@ -99,10 +102,20 @@ def init_weights(seed: int, head_scale: float = 0.0) -> np.ndarray:
 
 
 def edge_features(X: np.ndarray, x: np.ndarray, edges: np.ndarray, zeta: np.ndarray) -> np.ndarray:
-    """(ne, 3): rest length / mean rest length, stretch - 1, zeta."""
+    """(ne, 3): rest length / mean rest length, tanh(stretch - 1), zeta."""
     L0 = np.linalg.norm(X[edges[:, 1]] - X[edges[:, 0]], axis=1)
     L = np.linalg.norm(x[edges[:, 1]] - x[edges[:, 0]], axis=1)
-    return np.stack([L0 / L0.mean(), L / L0 - 1.0, zeta.astype(float)], axis=1)
+    return np.stack([L0 / L0.mean(), np.tanh(L / L0 - 1.0), zeta.astype(float)], axis=1)
+
+
+def bound(x: np.ndarray) -> np.ndarray:
+    """b(x) = 2 tanh(x / 2)."""
+    return 2.0 * np.tanh(0.5 * x)
+
+
+def bound_slope(x: np.ndarray) -> np.ndarray:
+    """b'(x) = 1 - tanh(x / 2)^2."""
+    return 1.0 - np.tanh(0.5 * x) ** 2
 
 
 def node_inputs(n: int, edges: np.ndarray, f: np.ndarray) -> np.ndarray:
@@ -142,13 +155,14 @@ def mean_operator(n: int, edges: np.ndarray, zeta: np.ndarray):
 
 
 def lower_factor(o: np.ndarray) -> np.ndarray:
+    bo = bound(o)
     L = np.zeros((o.shape[0], 3, 3))
-    L[:, 0, 0] = np.exp(o[:, 0])
-    L[:, 1, 1] = np.exp(o[:, 1])
-    L[:, 2, 2] = np.exp(o[:, 2])
-    L[:, 1, 0] = o[:, 3]
-    L[:, 2, 0] = o[:, 4]
-    L[:, 2, 1] = o[:, 5]
+    L[:, 0, 0] = np.exp(bo[:, 0])
+    L[:, 1, 1] = np.exp(bo[:, 1])
+    L[:, 2, 2] = np.exp(bo[:, 2])
+    L[:, 1, 0] = bo[:, 3]
+    L[:, 2, 0] = bo[:, 4]
+    L[:, 2, 1] = bo[:, 5]
     return L
 
 
@@ -209,14 +223,18 @@ def make_factor(A: sp.csr_matrix, edges: np.ndarray, f: np.ndarray, free: np.nda
     return Factor(n, rows, cols, Ablk, K, C, f, free.astype(float))
 
 
+def edge_preactivation(o: np.ndarray, w: np.ndarray, fac: Factor) -> np.ndarray:
+    """(nb, 9): s_i + t_j + We f_ij + be for every stored lower block (i, j)."""
+    p = unflatten(w)
+    return o[fac.rows, 6:15] + o[fac.cols, 15:24] + fac.fb @ p["We"].T + p["be"]
+
+
 def factor_blocks(o: np.ndarray, w: np.ndarray, fac: Factor):
     """(Gd (n,3,3), Gl (nb,3,3), W (nb,3,3)) for head outputs o (n,24)."""
-    p = unflatten(w)
     L = lower_factor(o[:, :6])
     L[fac.free == 0] = np.eye(3)
     M = L @ fac.C
-    Wv = o[fac.rows, 6:15] + o[fac.cols, 15:24] + fac.fb @ p["We"].T + p["be"]
-    W = Wv.reshape(-1, 3, 3)
+    W = bound(edge_preactivation(o, w, fac)).reshape(-1, 3, 3)
     Gl = -np.einsum("bij,bjk,bkl->bil", M[fac.rows], W, fac.K)
     return M, Gl, W
 
@@ -255,6 +273,8 @@ def loss_and_grad(w: np.ndarray, a: np.ndarray, P, PT, fac: Factor, A: sp.csr_ma
     t = float(np.sum(u * wv))
     L = lower_factor(o[:, :6])
     logdet = float(np.sum(np.log(np.abs(np.linalg.det(Gd)))))
+    slope_o = bound_slope(o[:, :6])
+    slope_w = bound_slope(edge_preactivation(o, w, fac))
     loss = np.log(t / N) - 2.0 / N * logdet
     # dloss/dW_b = -(2/t) (M_i^T v_i)(K_b w_j)^T
     m = np.einsum("nji,nj->ni", Gd, v)                       # M_i^T v_i
@@ -272,8 +292,9 @@ def loss_and_grad(w: np.ndarray, a: np.ndarray, P, PT, fac: Factor, A: sp.csr_ma
     go[:, 3] = dL[:, 1, 0]
     go[:, 4] = dL[:, 2, 0]
     go[:, 5] = dL[:, 2, 1]
+    go[:, :6] *= slope_o
     go[fac.free == 0, :6] = 0.0
-    dWv = dW.reshape(-1, 9)
+    dWv = dW.reshape(-1, 9) * slope_w
     np.add.at(go[:, 6:15], fac.rows, dWv)
     np.add.at(go[:, 15:24], fac.cols, dWv)
     g = {kk: np.zeros_like(vv) for kk, vv in p.items()}

@@ -145,6 +145,7 @@ struct gf_mesh {
   std::vector<d4> h_dvel;
   int step_index = 0;
   int last_first_solve = 0;
+  int last_learned_iters = 0;  // inner iterations of the last accepted learned solve
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
@@ -299,7 +300,7 @@ struct SolveResult {
 // vectors, FP64 dot products, device-side scalars and early exit, launched in
 // chunks so the host only synchronises once per chunk.
 template <typename T>
-SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* F = nullptr) {
+SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* F = nullptr, int max_inner = 0) {
   hipStream_t s = M->stream;
   const double tol = M->p.cg_rel_tol;
   SolveResult res{false, 0, 0, 0.0};
@@ -307,6 +308,7 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
   double bb = -1.0, rr = -1.0;  // |b|^2 is read back with the first chunk
   const d4* src = M->b;
   int budget = std::max(1, (int)M->p.cg_max_iter);
+  if (max_inner > 0) budget = std::min(budget, max_inner);
   const gfem::MatView A = M->mat();
   v4<T>* r = static_cast<v4<T>*>(M->vr);
   v4<T>* z = static_cast<v4<T>*>(M->vz);
@@ -425,9 +427,11 @@ void ensure_netw(gf_mesh* M) {
   for (auto& m : w.m) m = M->al.get<gfem::bf16>(np * gfem::kHid);
   for (auto& z : w.z) z = M->al.get<gfem::bf16>(np * gfem::kHid);
   w.o = M->al.get<float>(np * gfem::kNetHead);
-  w.gl = M->al.get<gfem::bf16>((size_t)9 * M->ne);
-  w.gu = M->al.get<gfem::bf16>((size_t)9 * M->ne);
-  w.gd = M->al.get<gfem::bf16>((size_t)6 * M->n);
+  w.glv = M->al.get<uint4>(M->ne);
+  w.guv = M->al.get<uint4>(M->ne);
+  w.gl8 = M->al.get<gfem::bf16>(M->ne);
+  w.gu8 = M->al.get<gfem::bf16>(M->ne);
+  w.gdv = M->al.get<uint4>(M->n);
   double sum = 0;
   for (int e = 0; e < M->ne; ++e) sum += std::sqrt(M->topo.edge_S[e]);
   M->inv_mean_len = M->ne > 0 ? M->ne / sum : 1.0;
@@ -493,10 +497,14 @@ gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
     SolveResult r;
     int fallback = 0;
     if (M->precond == GF_PC_LEARNED) {
-      // network factor B = G^T G; block-Jacobi re-solve if not accepted
+      // network factor B = G^T G; block-Jacobi re-solve if not accepted.  The
+      // learned attempt may spend at most 3x (+100) the iterations of the last
+      // accepted learned solve, so a poor factor costs a bounded detour.
       learned_precond(M);
       const gfem::FactView F = gfem::net_factor_view(M->netw, net_inputs(M, M->zeta[1 - M->zcur]));
-      r = solve<T>(M, M->binv, &F);
+      const int cap = M->last_learned_iters > 0 ? 3 * M->last_learned_iters + 100 : 0;
+      r = solve<T>(M, M->binv, &F, cap);
+      if (r.ok) M->last_learned_iters = r.inner;
       if (!r.ok) {
         fallback = 1;
         hchk(hipMemsetAsync(M->X64, 0, sizeof(d4) * M->n, M->stream), "hipMemsetAsync");

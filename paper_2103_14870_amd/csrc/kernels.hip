@@ -965,38 +965,79 @@ __global__ __launch_bounds__(NT) void k_pcg_update(int k, int n, int Gb, const v
 
 // ---------------------------------------------------------------- factorised preconditioner
 
-// y += G x for the BF16 block at index b of a [9][stride] array (row-major 3x3).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// One strictly lower (G pass) or upper (G^T pass) block in flight: its 3x3
+// values and the gathered operand(s) of its column.
 template <typename T>
-__device__ __forceinline__ void gblk_fma(const __bf16* __restrict__ g, int stride, int b, const v4<T>& x, T& ax,
-                                         T& ay, T& az) {
-  T a[9];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) a[c] = (T)(float)g[(size_t)c * stride + b];
-  ax = fmadd(a[0], x.x, fmadd(a[1], x.y, fmadd(a[2], x.z, ax)));
-  ay = fmadd(a[3], x.x, fmadd(a[4], x.y, fmadd(a[5], x.z, ay)));
-  az = fmadd(a[6], x.x, fmadd(a[7], x.y, fmadd(a[8], x.z, az)));
+struct FSlot {
+  bool on;
+  uint4 g;     // entries 0-7
+  __bf16 g8;   // entry 8
+  v4<T> a, b;  // gathered operands
+};
+
+// MODE 0: G pass of an iteration (a = r_old[j], b = q[j]); 1: G pass at the
+// start of a solve (a = src[j] rounded to T); 2: G^T pass (a = y[j]).
+template <typename T, int MODE>
+__device__ __forceinline__ FSlot<T> fslot_load(const int32_t* __restrict__ colv, const uint4* __restrict__ gv,
+                                               const __bf16* __restrict__ g8, int idx, bool on,
+                                               const d4* __restrict__ src, const v4<T>* __restrict__ va,
+                                               const v4<T>* __restrict__ vb) {
+  FSlot<T> s;
+  s.on = on;
+  if (on) {
+    const int j = colv[idx];
+    s.g = gv[idx];
+    s.g8 = g8[idx];
+    if (MODE == 1) {
+      const d4 sj = src[j];
+      s.a = v4<T>{(T)sj.x, (T)sj.y, (T)sj.z, T(0)};
+    } else {
+      s.a = va[j];
+      if (MODE == 0) s.b = vb[j];
+    }
+  }
+  return s;
 }
 
-// Lower-triangular diagonal block (00, 10, 11, 20, 21, 22) of node i.
-template <typename T>
-__device__ __forceinline__ void gdiag_load(const __bf16* __restrict__ gd, int n, int i, T d[6]) {
-#pragma unroll
-  for (int c = 0; c < 6; ++c) d[c] = (T)(float)gd[(size_t)c * n + i];
+template <typename T, int MODE>
+__device__ __forceinline__ void fslot_apply(const FSlot<T>& s, T al, T& ax, T& ay, T& az) {
+  if (!s.on) return;
+  v4<T> x = s.a;
+  if (MODE == 0) {
+    x.x = fmadd(-al, s.b.x, x.x);
+    x.y = fmadd(-al, s.b.y, x.y);
+    x.z = fmadd(-al, s.b.z, x.z);
+  }
+  const bf16x8_t g = __builtin_bit_cast(bf16x8_t, s.g);
+  ax = fmadd((T)(float)g[0], x.x, fmadd((T)(float)g[1], x.y, fmadd((T)(float)g[2], x.z, ax)));
+  ay = fmadd((T)(float)g[3], x.x, fmadd((T)(float)g[4], x.y, fmadd((T)(float)g[5], x.z, ay)));
+  az = fmadd((T)(float)g[6], x.x, fmadd((T)(float)g[7], x.y, fmadd((T)(float)s.g8, x.z, az)));
 }
 
 template <typename T>
-__device__ __forceinline__ T half_row_sum(T v) {
+__device__ __forceinline__ T fact_row_sum(T v) {
 #pragma unroll
-  for (int o = kHalfLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kHalfLanes);
+  for (int o = kFactLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kFactLanes);
   return v;
 }
+
+// Row-local operands of the G pass (owner lane only).
+template <typename T>
+struct GOwn {
+  v4<T> r, q, p, x;
+  uint4 d;
+};
 
 // G pass.  INIT: r = src rounded to T (written to r_new), x = 0, partials into
 // parity 0.  Otherwise iteration k: alpha from the SpMV's p.q partials and
 // this grid's r.z partials of parity k; every neighbour's r_new entry is
 // formed on the fly with the same fused operation its owner uses (r_old and
 // r_new are distinct buffers, so no row reads a value another workgroup is
-// overwriting).  kHalfLanes lanes per row walk the row's lower slots.
+// overwriting).  kFactLanes lanes per row, two blocks per lane in flight; the
+// first row's loads are issued before the scalar reduction so that the two
+// latencies overlap.
 template <typename T, bool INIT, int NT>
 __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* __restrict__ src,
                                                   const v4<T>* __restrict__ r_old, v4<T>* __restrict__ r_new,
@@ -1004,6 +1045,7 @@ __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* _
                                                   v4<T>* __restrict__ x, v4<T>* __restrict__ y, PcgCtl* ctl,
                                                   const double* __restrict__ part_pq,
                                                   double* __restrict__ part_rz) {
+  constexpr int MODE = INIT ? 1 : 0;
   __shared__ double sh[3 * (NT / 64)];
   if (!INIT && ctl->done) return;
   const int n = F.n;
@@ -1011,9 +1053,34 @@ __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* _
   const int L = xcd_logical(blockIdx.x, G);
   const int chunk = (n + G - 1) / G;
   const int r0 = min(n, L * chunk), r1 = min(n, r0 + chunk);
-  const int lane = threadIdx.x & (kHalfLanes - 1);
-  const int grp = threadIdx.x / kHalfLanes;
-  constexpr int NG = NT / kHalfLanes;
+  const int lane = threadIdx.x & (kFactLanes - 1);
+  const int grp = threadIdx.x / kFactLanes;
+  constexpr int NG = NT / kFactLanes;
+  int i = r0 + grp;
+  int s = 0, e = 0;
+  if (i < r1) {
+    s = F.lptr[i];
+    e = F.lptr[i + 1];
+  }
+  FSlot<T> fa = fslot_load<T, MODE>(F.lcol, F.glv, F.gl8, s + lane, s + lane < e, src, r_old, q);
+  FSlot<T> fb = fslot_load<T, MODE>(F.lcol, F.glv, F.gl8, s + lane + kFactLanes, s + lane + kFactLanes < e, src,
+                                    r_old, q);
+  GOwn<T> own{};
+  auto load_own = [&](int row) {
+    if (lane == 0 && row < r1) {
+      if (INIT) {
+        const d4 si = src[row];
+        own.r = v4<T>{(T)si.x, (T)si.y, (T)si.z, T(0)};
+      } else {
+        own.r = r_old[row];
+        own.q = q[row];
+        own.p = p[row];
+        own.x = x[row];
+      }
+      own.d = F.gdv[row];
+    }
+  };
+  load_own(i);
   T al = T(0);
   if (!INIT) {
     const double* cur = part_rz + (size_t)(k & 1) * 2 * kMaxPart;
@@ -1033,45 +1100,46 @@ __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* _
     al = (T)(rz / pq);
   }
   double yy = 0, rr = 0;
-  for (int i = r0 + grp; i < r1; i += NG) {
-    const int s = F.lptr[i], d = F.lptr[i + 1];
-    T ax = 0, ay = 0, az = 0;
-    for (int b = s + lane; b < d; b += kHalfLanes) {
-      const int j = F.lcol[b];
-      v4<T> rj;
-      if (INIT) {
-        const d4 sj = src[j];
-        rj = v4<T>{(T)sj.x, (T)sj.y, (T)sj.z, T(0)};
-      } else {
-        const v4<T> ro = r_old[j], qj = q[j];
-        rj = v4<T>{fmadd(-al, qj.x, ro.x), fmadd(-al, qj.y, ro.y), fmadd(-al, qj.z, ro.z), T(0)};
-      }
-      gblk_fma(F.gl, F.ne, b, rj, ax, ay, az);
+  bool first = true;
+  for (; i < r1; i += NG) {
+    if (!first) {
+      s = F.lptr[i];
+      e = F.lptr[i + 1];
+      fa = fslot_load<T, MODE>(F.lcol, F.glv, F.gl8, s + lane, s + lane < e, src, r_old, q);
+      fb = fslot_load<T, MODE>(F.lcol, F.glv, F.gl8, s + lane + kFactLanes, s + lane + kFactLanes < e, src, r_old,
+                               q);
+      load_own(i);
     }
-    ax = half_row_sum(ax);
-    ay = half_row_sum(ay);
-    az = half_row_sum(az);
+    first = false;
+    T ax = 0, ay = 0, az = 0;
+    fslot_apply<T, MODE>(fa, al, ax, ay, az);
+    fslot_apply<T, MODE>(fb, al, ax, ay, az);
+    for (int b = s + lane + 2 * kFactLanes; b < e; b += kFactLanes) {
+      const FSlot<T> t = fslot_load<T, MODE>(F.lcol, F.glv, F.gl8, b, true, src, r_old, q);
+      fslot_apply<T, MODE>(t, al, ax, ay, az);
+    }
+    ax = fact_row_sum(ax);
+    ay = fact_row_sum(ay);
+    az = fact_row_sum(az);
     if (lane == 0) {
-      v4<T> ri;
-      if (INIT) {
-        const d4 si = src[i];
-        ri = v4<T>{(T)si.x, (T)si.y, (T)si.z, T(0)};
-        x[i] = v4<T>{T(0), T(0), T(0), T(0)};
-      } else {
-        const v4<T> ro = r_old[i], qi = q[i], pi = p[i];
-        ri = v4<T>{fmadd(-al, qi.x, ro.x), fmadd(-al, qi.y, ro.y), fmadd(-al, qi.z, ro.z), T(0)};
-        v4<T> xi = x[i];
-        xi.x = fmadd(al, pi.x, xi.x);
-        xi.y = fmadd(al, pi.y, xi.y);
-        xi.z = fmadd(al, pi.z, xi.z);
+      v4<T> ri = own.r;
+      if (!INIT) {
+        ri.x = fmadd(-al, own.q.x, ri.x);
+        ri.y = fmadd(-al, own.q.y, ri.y);
+        ri.z = fmadd(-al, own.q.z, ri.z);
+        v4<T> xi = own.x;
+        xi.x = fmadd(al, own.p.x, xi.x);
+        xi.y = fmadd(al, own.p.y, xi.y);
+        xi.z = fmadd(al, own.p.z, xi.z);
         x[i] = xi;
+      } else {
+        x[i] = v4<T>{T(0), T(0), T(0), T(0)};
       }
       r_new[i] = ri;
-      T g6[6];
-      gdiag_load(F.gd, n, i, g6);
-      ax = fmadd(g6[0], ri.x, ax);
-      ay = fmadd(g6[1], ri.x, fmadd(g6[2], ri.y, ay));
-      az = fmadd(g6[3], ri.x, fmadd(g6[4], ri.y, fmadd(g6[5], ri.z, az)));
+      const bf16x8_t d = __builtin_bit_cast(bf16x8_t, own.d);
+      ax = fmadd((T)(float)d[0], ri.x, ax);
+      ay = fmadd((T)(float)d[1], ri.x, fmadd((T)(float)d[2], ri.y, ay));
+      az = fmadd((T)(float)d[3], ri.x, fmadd((T)(float)d[4], ri.y, fmadd((T)(float)d[5], ri.z, az)));
       y[i] = v4<T>{ax, ay, az, T(0)};
       yy += (double)ax * ax + (double)ay * ay + (double)az * az;
       rr += (double)ri.x * ri.x + (double)ri.y * ri.y + (double)ri.z * ri.z;
@@ -1098,23 +1166,35 @@ __global__ __launch_bounds__(NT) void k_pcg_gtpass(FactView F, const v4<T>* __re
   const int L = xcd_logical(blockIdx.x, G);
   const int chunk = (n + G - 1) / G;
   const int r0 = min(n, L * chunk), r1 = min(n, r0 + chunk);
-  const int lane = threadIdx.x & (kHalfLanes - 1);
-  const int grp = threadIdx.x / kHalfLanes;
-  constexpr int NG = NT / kHalfLanes;
+  const int lane = threadIdx.x & (kFactLanes - 1);
+  const int grp = threadIdx.x / kFactLanes;
+  constexpr int NG = NT / kFactLanes;
   for (int i = r0 + grp; i < r1; i += NG) {
     const int s = F.uptr[i], e = F.uptr[i + 1];
-    T ax = 0, ay = 0, az = 0;
-    for (int b = s + lane; b < e; b += kHalfLanes) gblk_fma(F.gu, F.ne, b, y[F.ucol[b]], ax, ay, az);
-    ax = half_row_sum(ax);
-    ay = half_row_sum(ay);
-    az = half_row_sum(az);
+    const FSlot<T> fa = fslot_load<T, 2>(F.ucol, F.guv, F.gu8, s + lane, s + lane < e, nullptr, y, nullptr);
+    const FSlot<T> fb =
+        fslot_load<T, 2>(F.ucol, F.guv, F.gu8, s + lane + kFactLanes, s + lane + kFactLanes < e, nullptr, y, nullptr);
+    v4<T> yi{};
+    uint4 dv{};
     if (lane == 0) {
-      const v4<T> yi = y[i];
-      T g6[6];
-      gdiag_load(F.gd, n, i, g6);
-      ax = fmadd(g6[0], yi.x, fmadd(g6[1], yi.y, fmadd(g6[3], yi.z, ax)));
-      ay = fmadd(g6[2], yi.y, fmadd(g6[4], yi.z, ay));
-      az = fmadd(g6[5], yi.z, az);
+      yi = y[i];
+      dv = F.gdv[i];
+    }
+    T ax = 0, ay = 0, az = 0;
+    fslot_apply<T, 2>(fa, T(0), ax, ay, az);
+    fslot_apply<T, 2>(fb, T(0), ax, ay, az);
+    for (int b = s + lane + 2 * kFactLanes; b < e; b += kFactLanes) {
+      const FSlot<T> t = fslot_load<T, 2>(F.ucol, F.guv, F.gu8, b, true, nullptr, y, nullptr);
+      fslot_apply<T, 2>(t, T(0), ax, ay, az);
+    }
+    ax = fact_row_sum(ax);
+    ay = fact_row_sum(ay);
+    az = fact_row_sum(az);
+    if (lane == 0) {
+      const bf16x8_t d = __builtin_bit_cast(bf16x8_t, dv);
+      ax = fmadd((T)(float)d[0], yi.x, fmadd((T)(float)d[1], yi.y, fmadd((T)(float)d[3], yi.z, ax)));
+      ay = fmadd((T)(float)d[2], yi.y, fmadd((T)(float)d[4], yi.z, ay));
+      az = fmadd((T)(float)d[5], yi.z, az);
       const v4<T> zi{ax, ay, az, T(0)};
       z[i] = zi;
       if (INIT) p0[i] = zi;

@@ -110,23 +110,26 @@ void launch_pcg_update(hipStream_t s, int k, int n, int Ga, int Gb, const v4<T>*
 
 // Factorised sparse approximate inverse preconditioner z = G^T G r, G block
 // lower triangular on the lower block pattern of A (node order).  BF16 block
-// values in compact half-pattern arrays, SoA with unit stride across blocks:
-// gl [9][ne] holds G_ij of the strictly lower blocks in the order of lcol
-// (row i: lptr[i] .. lptr[i+1]), gu [9][ne] holds G_ji^T at the mirror
-// positions in the order of ucol, and gd [6][n] the lower-triangular diagonal
-// blocks G_ii (entries 00, 10, 11, 20, 21, 22).  G r streams gl and G^T y
-// streams gu, each once, with no interleaved bytes of the other half.
+// values in compact half-pattern arrays, one 16-byte record (entries 0-7,
+// row-major 3x3) plus one BF16 (entry 8) per block, unit stride across blocks:
+// glv/gl8 [ne] hold G_ij of the strictly lower blocks in the order of lcol
+// (row i: lptr[i] .. lptr[i+1]), guv/gu8 [ne] hold G_ji^T at the mirror
+// positions in the order of ucol, and gdv [n] the lower-triangular diagonal
+// blocks G_ii (entries 00, 10, 11, 20, 21, 22, then two zero pads).  G r
+// streams the lower arrays and G^T y the upper ones, each once.
 struct FactView {
   int n, ne;
   const int32_t* lptr;
   const int32_t* lcol;
   const int32_t* uptr;
   const int32_t* ucol;
-  const __bf16* gl;
-  const __bf16* gu;
-  const __bf16* gd;
+  const uint4* glv;
+  const __bf16* gl8;
+  const uint4* guv;
+  const __bf16* gu8;
+  const uint4* gdv;
 };
-constexpr int kHalfLanes = 8;  // lanes cooperating on one half row in the G and G^T passes
+constexpr int kFactLanes = 4;  // lanes cooperating on one half row in the G and G^T passes
 
 // Start of a solve with the factorised preconditioner: r_0 = src (rounded to
 // T), x = 0, y = G r_0, z = G^T y, p_0 = z; partials of r.z (= y.y) and r.r.

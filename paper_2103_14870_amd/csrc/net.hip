@@ -14,6 +14,7 @@ typedef bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kDwWorkgroups = 256;
+constexpr int kBuildLanes = 8;  // lanes per block row in the factor and training kernels
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -25,7 +26,7 @@ __device__ __forceinline__ double wsum(double v) {
 
 // Node input a_i = [1, mean f0, mean f1, mean f2, mean f1^2, mean |f1|,
 // mean (1 - f2) f1, degree / 16] over the incident edges, with edge features
-// f0 = rest length / mean rest length, f1 = current / rest length - 1,
+// f0 = rest length / mean rest length, f1 = tanh(current / rest length - 1),
 // f2 = damage label; zero-padded to 32.  Also 1 / (number of unbroken
 // incident edges) for the neighbour mean.
 __global__ __launch_bounds__(256) void k_net_inputs(NetInputs in, int npad, bf16* __restrict__ a,
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void k_net_inputs(NetInputs in, int npad, bf16
       const double dx = Xj.x - Xi.x, dy = Xj.y - Xi.y, dz = Xj.z - Xi.z;
       const double cx = dx + (Uj.x - Ui.x), cy = dy + (Uj.y - Ui.y), cz = dz + (Uj.z - Ui.z);
       const double L0 = sqrt(dx * dx + dy * dy + dz * dz), L = sqrt(cx * cx + cy * cy + cz * cz);
-      const float f0 = (float)(L0 * in.inv_mean_len), f1 = (float)(L / L0 - 1.0);
+      const float f0 = (float)(L0 * in.inv_mean_len), f1 = (float)tanh(L / L0 - 1.0);
       const float f2 = in.zeta[ed] ? 1.f : 0.f;
       acc[0] += f0;
       acc[1] += f1;
@@ -182,13 +183,21 @@ __global__ __launch_bounds__(256) void k_net_mean_bwd(NetInputs in, int npad, co
 
 // ---------------------------------------------------------------- head and factor
 
+// Bounded map b(x) = 2 tanh(x / 2) of the network outputs and its slope.
+__device__ __forceinline__ float bnd(float x) { return 2.f * tanhf(0.5f * x); }
+__device__ __forceinline__ float bnd_slope(float x) {
+  const float t = tanhf(0.5f * x);
+  return 1.f - t * t;
+}
+
+// L = [[e^b(o0), 0, 0], [b(o3), e^b(o1), 0], [b(o4), b(o5), e^b(o2)]].
 __device__ __forceinline__ void lower_from_o(const float* o, float L[3][3]) {
-  L[0][0] = expf(o[0]);
-  L[1][1] = expf(o[1]);
-  L[2][2] = expf(o[2]);
-  L[1][0] = o[3];
-  L[2][0] = o[4];
-  L[2][1] = o[5];
+  L[0][0] = expf(bnd(o[0]));
+  L[1][1] = expf(bnd(o[1]));
+  L[2][2] = expf(bnd(o[2]));
+  L[1][0] = bnd(o[3]);
+  L[2][0] = bnd(o[4]);
+  L[2][1] = bnd(o[5]);
   L[0][1] = L[0][2] = L[1][2] = 0.f;
 }
 
@@ -243,7 +252,7 @@ __device__ __forceinline__ void edge_feat(const NetInputs& in, int i, int j, int
   const double cx = dx + (Uj.x - Ui.x), cy = dy + (Uj.y - Ui.y), cz = dz + (Uj.z - Ui.z);
   const double L0 = sqrt(dx * dx + dy * dy + dz * dz), L = sqrt(cx * cx + cy * cy + cz * cz);
   f[0] = (float)(L0 * in.inv_mean_len);
-  f[1] = (float)(L / L0 - 1.0);
+  f[1] = (float)tanh(L / L0 - 1.0);
   f[2] = in.zeta[e] ? 1.f : 0.f;
 }
 
@@ -262,17 +271,21 @@ __device__ __forceinline__ float node_factor(const NetInputs& in, const float* _
     lower_from_o(o + (size_t)i * kNetHead, L);
   }
   mat3_mul(L, C, M);
-  return in.dflag[i] ? ldc : ldc + o[(size_t)i * kNetHead] + o[(size_t)i * kNetHead + 1] +
-                                 o[(size_t)i * kNetHead + 2];
+  return in.dflag[i] ? ldc : ldc + bnd(o[(size_t)i * kNetHead]) + bnd(o[(size_t)i * kNetHead + 1]) +
+                                 bnd(o[(size_t)i * kNetHead + 2]);
 }
 
-// W_b = s_i + t_j + We f + be (row-major 3x3).
+// W_b = b(s_i + t_j + We f + be) (row-major 3x3); slope (if given) = b' at the
+// pre-activation.
 __device__ __forceinline__ void edge_w(const float* __restrict__ o, int i, int j, const float f[3],
-                                       const float* __restrict__ We, float W[3][3]) {
+                                       const float* __restrict__ We, float W[3][3], float* slope = nullptr) {
 #pragma unroll
-  for (int q = 0; q < 9; ++q)
-    W[q / 3][q % 3] = o[(size_t)i * kNetHead + 6 + q] + o[(size_t)j * kNetHead + 15 + q] + We[3 * q] * f[0] +
+  for (int q = 0; q < 9; ++q) {
+    const float raw = o[(size_t)i * kNetHead + 6 + q] + o[(size_t)j * kNetHead + 15 + q] + We[3 * q] * f[0] +
                       We[3 * q + 1] * f[1] + We[3 * q + 2] * f[2] + We[27 + q];
+    W[q / 3][q % 3] = bnd(raw);
+    if (slope) slope[q] = bnd_slope(raw);
+  }
 }
 
 // o = Wh h3 + bh for every padded row, one thread per node.
@@ -298,36 +311,63 @@ __global__ __launch_bounds__(256) void k_net_head_fwd(int npad, const float* __r
   }
 }
 
-// Factor values: kHalfLanes lanes per block row; lane 0 writes the diagonal
+// Factor values: kBuildLanes lanes per block row; lane 0 writes the diagonal
 // block M_i, the lanes walk the row's strictly lower blocks (i, j) and write
-// G_ij into gl and G_ij^T into gu at the mirror position.
-template <typename OutT>
+// G_ij into the lower arrays and G_ij^T into the upper ones at the mirror
+// position.  FP32 (training): SoA gl, gu [9][ne], gd [6][n].  BF16 (solve):
+// the packed records of FactView.
+struct FactOut {
+  float *gl32, *gu32, *gd32;
+  uint4 *glv, *guv, *gdv;
+  bf16 *gl8, *gu8;
+};
+
+template <bool FP32>
+__device__ __forceinline__ void store_gblock(const FactOut& out, int ne, int idx, bool lower, const float B[3][3]) {
+  if (FP32) {
+    float* g = lower ? out.gl32 : out.gu32;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) g[(size_t)q * ne + idx] = B[q / 3][q % 3];
+  } else {
+    bf16x8 v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = (bf16)B[q / 3][q % 3];
+    (lower ? out.glv : out.guv)[idx] = __builtin_bit_cast(uint4, v);
+    (lower ? out.gl8 : out.gu8)[idx] = (bf16)B[2][2];
+  }
+}
+
+template <bool FP32>
 __global__ __launch_bounds__(256) void k_fact_build(NetInputs in, const float* __restrict__ o,
-                                                    const float* __restrict__ master, OutT* __restrict__ gl,
-                                                    OutT* __restrict__ gu, OutT* __restrict__ gd) {
+                                                    const float* __restrict__ master, FactOut out) {
   __shared__ float We[kEdgeGrad];
   for (int t = threadIdx.x; t < kEdgeGrad; t += 256) We[t] = master[kOffWe + t];
   __syncthreads();
   const int n = in.n, nbp = in.A.nbp, ne = in.ne;
-  const int lane = threadIdx.x & (kHalfLanes - 1);
+  const int lane = threadIdx.x & (kBuildLanes - 1);
   const float* __restrict__ val = static_cast<const float*>(in.A.val);
-  for (int i = blockIdx.x * (256 / kHalfLanes) + threadIdx.x / kHalfLanes; i < n;
-       i += gridDim.x * (256 / kHalfLanes)) {
+  for (int i = blockIdx.x * (256 / kBuildLanes) + threadIdx.x / kBuildLanes; i < n;
+       i += gridDim.x * (256 / kBuildLanes)) {
     float M[3][3], L[3][3], C[3][3];
     node_factor(in, o, i, M, L, C);
     if (lane == 0) {
-      gd[i] = (OutT)M[0][0];
-      gd[(size_t)n + i] = (OutT)M[1][0];
-      gd[2 * (size_t)n + i] = (OutT)M[1][1];
-      gd[3 * (size_t)n + i] = (OutT)M[2][0];
-      gd[4 * (size_t)n + i] = (OutT)M[2][1];
-      gd[5 * (size_t)n + i] = (OutT)M[2][2];
+      const float d6[6] = {M[0][0], M[1][0], M[1][1], M[2][0], M[2][1], M[2][2]};
+      if (FP32) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) out.gd32[(size_t)q * n + i] = d6[q];
+      } else {
+        bf16x8 v;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[q] = (bf16)d6[q];
+        v[6] = v[7] = (bf16)0.f;
+        out.gdv[i] = __builtin_bit_cast(uint4, v);
+      }
     }
     const int s = in.A.row_ptr[i], d = in.diag_blk[i], l0 = in.lptr[i];
-    for (int b = s + lane; b < d; b += kHalfLanes) {
+    for (int b = s + lane; b < d; b += kBuildLanes) {
       const int j = in.A.col[b], e = in.blk_edge[b];
       const int li = l0 + (b - s), ui = in.upos[e];
-      float f[3], W[3][3], a[9], Dj[3][3], K[3][3], T[3][3], Gb[3][3];
+      float f[3], W[3][3], a[9], Dj[3][3], K[3][3], T[3][3], Gb[3][3], Gt[3][3];
       edge_feat(in, i, j, e, f);
       edge_w(o, i, j, f, We, W);
       load_blk9(val, nbp, b, a);
@@ -337,10 +377,14 @@ __global__ __launch_bounds__(256) void k_fact_build(NetInputs in, const float* _
       mat3_mul(W, K, T);
       mat3_mul(M, T, Gb);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        gl[(size_t)q * ne + li] = (OutT)(-Gb[q / 3][q % 3]);
-        gu[(size_t)q * ne + ui] = (OutT)(-Gb[q % 3][q / 3]);
-      }
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          Gb[r][c] = -Gb[r][c];
+          Gt[c][r] = Gb[r][c];
+        }
+      store_gblock<FP32>(out, ne, li, true, Gb);
+      store_gblock<FP32>(out, ne, ui, false, Gt);
     }
   }
 }
@@ -366,16 +410,16 @@ __global__ __launch_bounds__(256) void k_net_probe_gen(int n, uint64_t seed, d4*
   v[i] = r;
 }
 
-// u = G^T v from the FP32 factor, FP64 accumulation (kHalfLanes lanes per row).
+// u = G^T v from the FP32 factor, FP64 accumulation (kBuildLanes lanes per row).
 __global__ __launch_bounds__(256) void k_kap_u(NetInputs in, const float* __restrict__ gu,
                                                const float* __restrict__ gd, const d4* __restrict__ v,
                                                d4* __restrict__ u) {
   const int n = in.n, ne = in.ne;
-  const int lane = threadIdx.x & (kHalfLanes - 1);
-  for (int i = blockIdx.x * (256 / kHalfLanes) + threadIdx.x / kHalfLanes; i < n;
-       i += gridDim.x * (256 / kHalfLanes)) {
+  const int lane = threadIdx.x & (kBuildLanes - 1);
+  for (int i = blockIdx.x * (256 / kBuildLanes) + threadIdx.x / kBuildLanes; i < n;
+       i += gridDim.x * (256 / kBuildLanes)) {
     double ax = 0, ay = 0, az = 0;
-    for (int b = in.uptr[i] + lane; b < in.uptr[i + 1]; b += kHalfLanes) {
+    for (int b = in.uptr[i] + lane; b < in.uptr[i + 1]; b += kBuildLanes) {
       const d4 vj = v[in.ucol[b]];
       float a[9];
       load_blk9(gu, ne, b, a);
@@ -384,10 +428,10 @@ __global__ __launch_bounds__(256) void k_kap_u(NetInputs in, const float* __rest
       az += a[6] * vj.x + a[7] * vj.y + a[8] * vj.z;
     }
 #pragma unroll
-    for (int s = kHalfLanes / 2; s > 0; s >>= 1) {
-      ax += __shfl_xor(ax, s, kHalfLanes);
-      ay += __shfl_xor(ay, s, kHalfLanes);
-      az += __shfl_xor(az, s, kHalfLanes);
+    for (int s = kBuildLanes / 2; s > 0; s >>= 1) {
+      ax += __shfl_xor(ax, s, kBuildLanes);
+      ay += __shfl_xor(ay, s, kBuildLanes);
+      az += __shfl_xor(az, s, kBuildLanes);
     }
     if (lane == 0) {
       const d4 vi = v[i];
@@ -447,11 +491,13 @@ __device__ __forceinline__ float wsumf(float v) {
 }
 
 // Head-output gradient go (24 per row, zero on padding rows) and per-workgroup
-// partials of the edge-term gradient (We, be).  With k_b = A_ij s_j:
-//   dloss/dW_b = -(2/t) m_i k_b^T,
-//   go[6:15]_i  = sum over lower slots of row i of dloss/dW_b,
-//   go[15:24]_j = sum over lower blocks (i, j) of dloss/dW_b (row j's upper slots),
-//   dloss/dL_i  = (2/t) v_i rho_i^T - (2/N) L_i^-T, rho_i = C_i (w_i - sum_b W_b k_b).
+// partials of the edge-term gradient (We, be).  With k_b = A_ij s_j and r_b
+// the edge pre-activation (W_b = b(r_b)):
+//   dloss/dr_b  = -(2/t) m_i k_b^T * b'(r_b)  (elementwise),
+//   go[6:15]_i  = sum over lower slots of row i of dloss/dr_b,
+//   go[15:24]_j = sum over lower blocks (i, j) of dloss/dr_b (row j's upper slots),
+//   dloss/dL_i  = (2/t) v_i rho_i^T - (2/N) L_i^-T, rho_i = C_i (w_i - sum_b W_b k_b),
+//   and through L = L(b(o)) to o[0:6].
 __global__ __launch_bounds__(256) void k_kap_grad(NetInputs in, int npad, const float* __restrict__ o,
                                                   const float* __restrict__ master, const d4* __restrict__ v,
                                                   const d4* __restrict__ wneg, const v4<float>* __restrict__ mv,
@@ -462,15 +508,15 @@ __global__ __launch_bounds__(256) void k_kap_grad(NetInputs in, int npad, const 
   for (int t = threadIdx.x; t < kEdgeGrad; t += 256) We[t] = master[kOffWe + t];
   __syncthreads();
   const int n = in.n, nbp = in.A.nbp;
-  const int lane = threadIdx.x & (kHalfLanes - 1);
+  const int lane = threadIdx.x & (kBuildLanes - 1);
   const float* __restrict__ val = static_cast<const float*>(in.A.val);
   float eg[kEdgeGrad];
 #pragma unroll
   for (int q = 0; q < kEdgeGrad; ++q) eg[q] = 0.f;
-  const int rows_per = 256 / kHalfLanes;
+  const int rows_per = 256 / kBuildLanes;
   const int nrow_iter = (npad + gridDim.x * rows_per - 1) / (gridDim.x * rows_per);
   for (int it = 0; it < nrow_iter; ++it) {
-    const int i = (it * gridDim.x + blockIdx.x) * rows_per + threadIdx.x / kHalfLanes;
+    const int i = (it * gridDim.x + blockIdx.x) * rows_per + threadIdx.x / kBuildLanes;
     if (i >= npad) continue;
     if (i >= n) {
       if (lane == 0)
@@ -478,11 +524,11 @@ __global__ __launch_bounds__(256) void k_kap_grad(NetInputs in, int npad, const 
       continue;
     }
     const v4<float> mi = mv[i], si = sv[i];
-    float a3[3] = {0.f, 0.f, 0.f}, rho3[3] = {0.f, 0.f, 0.f}, gt[9];
+    float rho3[3] = {0.f, 0.f, 0.f}, gs[9], gt[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) gt[q] = 0.f;
+    for (int q = 0; q < 9; ++q) gs[q] = gt[q] = 0.f;
     const int s = in.A.row_ptr[i], d = in.diag_blk[i], e = in.A.row_ptr[i + 1];
-    for (int b = s + lane; b < e; b += kHalfLanes) {
+    for (int b = s + lane; b < e; b += kBuildLanes) {
       if (b == d) continue;
       const int j = in.A.col[b];
       float a[9];
@@ -491,18 +537,18 @@ __global__ __launch_bounds__(256) void k_kap_grad(NetInputs in, int npad, const 
         const v4<float> sj = sv[j];
         const float k3[3] = {a[0] * sj.x + a[1] * sj.y + a[2] * sj.z, a[3] * sj.x + a[4] * sj.y + a[5] * sj.z,
                              a[6] * sj.x + a[7] * sj.y + a[8] * sj.z};
-        float f[3], W[3][3];
+        float f[3], W[3][3], sl[9];
         edge_feat(in, i, j, in.blk_edge[b], f);
-        edge_w(o, i, j, f, We, W);
+        edge_w(o, i, j, f, We, W, sl);
         const float m3[3] = {mi.x, mi.y, mi.z};
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-          a3[r] += k3[r];
           rho3[r] += W[r][0] * k3[0] + W[r][1] * k3[1] + W[r][2] * k3[2];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const float dw = -c2t * m3[r] * k3[c];
             const int q = 3 * r + c;
+            const float dw = -c2t * m3[r] * k3[c] * sl[q];
+            gs[q] += dw;
             eg[3 * q] += dw * f[0];
             eg[3 * q + 1] += dw * f[1];
             eg[3 * q + 2] += dw * f[2];
@@ -515,32 +561,32 @@ __global__ __launch_bounds__(256) void k_kap_grad(NetInputs in, int npad, const 
         const float k3[3] = {a[0] * si.x + a[3] * si.y + a[6] * si.z, a[1] * si.x + a[4] * si.y + a[7] * si.z,
                              a[2] * si.x + a[5] * si.y + a[8] * si.z};
         const float m3[3] = {mk.x, mk.y, mk.z};
+        float f[3], W[3][3], sl[9];
+        edge_feat(in, j, i, in.blk_edge[b], f);
+        edge_w(o, j, i, f, We, W, sl);
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) gt[3 * r + c] -= c2t * m3[r] * k3[c];
+          for (int c = 0; c < 3; ++c) gt[3 * r + c] -= c2t * m3[r] * k3[c] * sl[3 * r + c];
       }
     }
 #pragma unroll
-    for (int sft = kHalfLanes / 2; sft > 0; sft >>= 1) {
+    for (int sft = kBuildLanes / 2; sft > 0; sft >>= 1) {
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        a3[r] += __shfl_xor(a3[r], sft, kHalfLanes);
-        rho3[r] += __shfl_xor(rho3[r], sft, kHalfLanes);
+      for (int r = 0; r < 3; ++r) rho3[r] += __shfl_xor(rho3[r], sft, kBuildLanes);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        gs[q] += __shfl_xor(gs[q], sft, kBuildLanes);
+        gt[q] += __shfl_xor(gt[q], sft, kBuildLanes);
       }
-#pragma unroll
-      for (int q = 0; q < 9; ++q) gt[q] += __shfl_xor(gt[q], sft, kHalfLanes);
     }
     if (lane == 0) {
       float* gout = go + (size_t)i * kNetHead;
-      const float m3[3] = {mi.x, mi.y, mi.z};
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          gout[6 + 3 * r + c] = -c2t * m3[r] * a3[c];
-          gout[15 + 3 * r + c] = gt[3 * r + c];
-        }
+      for (int q = 0; q < 9; ++q) {
+        gout[6 + q] = gs[q];
+        gout[15 + q] = gt[q];
+      }
       if (in.dflag[i]) {
         for (int q = 0; q < 6; ++q) gout[q] = 0.f;
       } else {
@@ -552,12 +598,13 @@ __global__ __launch_bounds__(256) void k_kap_grad(NetInputs in, int npad, const 
 #pragma unroll
         for (int r = 0; r < 3; ++r) rho[r] = C[r][0] * w3[0] + C[r][1] * w3[1] + C[r][2] * w3[2];
         const float v3[3] = {(float)vi.x, (float)vi.y, (float)vi.z};
-        gout[0] = c2t * v3[0] * rho[0] * L[0][0] - c2n;
-        gout[1] = c2t * v3[1] * rho[1] * L[1][1] - c2n;
-        gout[2] = c2t * v3[2] * rho[2] * L[2][2] - c2n;
-        gout[3] = c2t * v3[1] * rho[0];
-        gout[4] = c2t * v3[2] * rho[0];
-        gout[5] = c2t * v3[2] * rho[1];
+        const float* oi = o + (size_t)i * kNetHead;
+        gout[0] = (c2t * v3[0] * rho[0] * L[0][0] - c2n) * bnd_slope(oi[0]);
+        gout[1] = (c2t * v3[1] * rho[1] * L[1][1] - c2n) * bnd_slope(oi[1]);
+        gout[2] = (c2t * v3[2] * rho[2] * L[2][2] - c2n) * bnd_slope(oi[2]);
+        gout[3] = c2t * v3[1] * rho[0] * bnd_slope(oi[3]);
+        gout[4] = c2t * v3[2] * rho[0] * bnd_slope(oi[4]);
+        gout[5] = c2t * v3[2] * rho[1] * bnd_slope(oi[5]);
       }
     }
   }
@@ -761,14 +808,15 @@ void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInpu
 }
 
 void net_build_factor(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int Gb, bool fp32) {
+  const FactOut out{w.gl32, w.gu32, w.gd32, w.glv, w.guv, w.gdv, w.gl8, w.gu8};
   if (fp32)
-    k_fact_build<float><<<Gb, 256, 0, s>>>(in, w.o, P.master, w.gl32, w.gu32, w.gd32);
+    k_fact_build<true><<<Gb, 256, 0, s>>>(in, w.o, P.master, out);
   else
-    k_fact_build<bf16><<<Gb, 256, 0, s>>>(in, w.o, P.master, w.gl, w.gu, w.gd);
+    k_fact_build<false><<<Gb, 256, 0, s>>>(in, w.o, P.master, out);
 }
 
 FactView net_factor_view(const NetWork& w, const NetInputs& in) {
-  return FactView{in.n, in.ne, in.lptr, in.lcol, in.uptr, in.ucol, w.gl, w.gu, w.gd};
+  return FactView{in.n, in.ne, in.lptr, in.lcol, in.uptr, in.ucol, w.glv, w.gl8, w.guv, w.gu8, w.gdv};
 }
 
 void net_probe(hipStream_t s, NetWork& w, uint64_t seed) { k_net_probe_gen<<<nb256(w.n), 256, 0, s>>>(w.n, seed, w.probe); }

@@ -73,9 +73,10 @@ struct NetWork {
   float* go = nullptr;                  // [npad][24]
   float* part = nullptr;                // weight-gradient partials [nwg_dw][64*128 + 64]
   float* grad = nullptr;                // [kNetParams]
-  // factor values in the compact half-pattern layout of FactView: BF16 for
-  // the solve, FP32 for training (gl, gu [9][ne], gd [6][n])
-  bf16 *gl = nullptr, *gu = nullptr, *gd = nullptr;
+  // factor values: packed BF16 records of FactView for the solve, FP32 SoA
+  // for training (gl32, gu32 [9][ne], gd32 [6][n])
+  uint4 *glv = nullptr, *guv = nullptr, *gdv = nullptr;
+  bf16 *gl8 = nullptr, *gu8 = nullptr;
   float *gl32 = nullptr, *gu32 = nullptr, *gd32 = nullptr;
   // training scratch
   d4* probe = nullptr;                  // [n] +-1 probe v
@@ -109,8 +110,8 @@ struct NetInputs {
 
 // Forward pass: node inputs, embedding, three layers, head -> w.o.
 void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int Gb);
-// Factor values from the head outputs w.o and the current system: BF16 into
-// w.gl/gu/gd (fp32 = false) or FP32 into w.gl32/gu32/gd32.
+// Factor values from the head outputs w.o and the current system: packed
+// BF16 (fp32 = false) or FP32 SoA into w.gl32/gu32/gd32.
 void net_build_factor(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int Gb, bool fp32);
 // View of the BF16 factor for the solve.
 FactView net_factor_view(const NetWork& w, const NetInputs& in);

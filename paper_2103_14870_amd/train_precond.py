@@ -29,9 +29,10 @@ else:
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "precond_net.npy")
 
 
-def episode(rng: np.random.Generator):
-    """One seeded training problem (split precision)."""
-    kind = rng.choice(["beam", "cube", "ellipsoid"], p=[0.45, 0.2, 0.35])
+def episode(rng: np.random.Generator, max_steps: int):
+    """One seeded training problem (split precision) and its number of steps.
+    Ellipsoid episodes run long enough to reach heavy ductile damage."""
+    kind = rng.choice(["beam", "cube", "ellipsoid"], p=[0.4, 0.2, 0.4])
     thr_scale = rng.uniform(0.8, 1.2)
     rate = rng.uniform(0.5, 2.0)
     if kind == "beam":
@@ -40,22 +41,23 @@ def episode(rng: np.random.Generator):
         prob = meshgen.notched_beam(nx, ny, ny, h=0.01, notch_cells=max(1, ny // 4),
                                     crack_fraction=float(rng.uniform(0.0, 0.3)) * (rng.random() < 0.7),
                                     crack_seed=int(rng.integers(100, 10 ** 6)))
-        prob.params["damage_strain"] *= thr_scale
+        steps = int(rng.integers(max_steps // 4, max_steps // 2 + 1))
     elif kind == "cube":
         n = int(rng.integers(4, 9))
         prob = meshgen.cube_block(n, n, n, h=0.1, jitter_frac=0.05, seed=int(rng.integers(1000, 10 ** 6)),
                                   precision="split", cg_rel_tol=1e-6)
-        prob.params["damage_strain"] *= thr_scale
+        steps = int(rng.integers(max_steps // 4, max_steps // 2 + 1))
     else:
         h = float(rng.uniform(0.06, 0.1))
         grid = (int(math.ceil(2.1 / h)) | 1, int(math.ceil(1.1 / h)) | 1, int(math.ceil(1.1 / h)) | 1)
         prob = meshgen.ellipsoid(h=h, grid=grid, jitter_frac=0.1, seed=int(rng.integers(1000, 10 ** 6)), dt=1e-2)
-        prob.params["damage_strain"] *= thr_scale
+        steps = int(rng.integers(max_steps // 4, max_steps + 1))
+    prob.params["damage_strain"] *= thr_scale
     prob.dir_vel = prob.dir_vel * rate
-    return prob
+    return prob, steps
 
 
-def train(n_systems: int, seed: int, steps_per_episode: int, lr0: float, lr1: float, log_every: int,
+def train(n_systems: int, seed: int, max_steps: int, lr0: float, lr1: float, log_every: int,
           net: "gfem.Net | None" = None, verbose: bool = True):
     rng = np.random.default_rng(seed)
     net = net or gfem.Net(seed=seed)
@@ -63,9 +65,9 @@ def train(n_systems: int, seed: int, steps_per_episode: int, lr0: float, lr1: fl
     hist = []
     t0 = time.time()
     while done < n_systems:
-        prob = episode(rng)
+        prob, steps = episode(rng, max_steps)
         with gfem.mesh_from_problem(prob) as m:
-            for _ in range(steps_per_episode):
+            for _ in range(steps):
                 if done >= n_systems:
                     break
                 frac = done / max(1, n_systems - 1)
@@ -89,14 +91,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--systems", type=int, default=20000)
     ap.add_argument("--seed", type=int, default=2024)
-    ap.add_argument("--steps-per-episode", type=int, default=25)
+    ap.add_argument("--max-steps", type=int, default=100, help="longest episode (ellipsoids; others half)")
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--lr-final", type=float, default=1e-4)
     ap.add_argument("--log-every", type=int, default=500)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     args = ap.parse_args()
     gfem.load()
-    net, hist = train(args.systems, args.seed, args.steps_per_episode, args.lr, args.lr_final, args.log_every)
+    net, hist = train(args.systems, args.seed, args.max_steps, args.lr, args.lr_final, args.log_every)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, net.get_weights())
     k = max(1, len(hist) // 10)

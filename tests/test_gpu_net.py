@@ -53,8 +53,9 @@ def oracle_system(prob, U, V):
 
 
 def damped_weights(om=0.75, seed=0):
+    """Weights whose factor is W_ij = om I, L = I (network part zero)."""
     w = N.init_weights(seed)
-    w[N.offset("be"):N.offset("be") + 9] = om * np.eye(3).ravel()
+    w[N.offset("be"):N.offset("be") + 9] = 2.0 * np.arctanh(om / 2.0) * np.eye(3).ravel()
     return w.astype(np.float32)
 
 
@@ -62,7 +63,7 @@ def damped_weights(om=0.75, seed=0):
 def test_factor_loss_and_gradient_match_oracle(seed):
     say(f"case net parity seed={seed}")
     prob, U, V = seeded_state(seed)
-    w = N.init_weights(seed + 10, head_scale=0.05).astype(np.float32)
+    w = N.init_weights(seed + 10, head_scale=0.3).astype(np.float32)
     w[N.offset("be"):N.offset("be") + 9] += (0.5 * np.eye(3)).ravel().astype(np.float32)
     probe = np.random.default_rng(seed + 20).choice([-1.0, 1.0], size=prob.X.shape)
     net = gfem.Net(seed=0)

@@ -55,7 +55,7 @@ def test_constant_damping_matches_dense_construction():
     a, P, PT, fac, A, b, _ = small_system(5)
     wgt = N.init_weights(0, head_scale=0.0)
     om = 0.7
-    wgt[N.offset("be"):N.offset("be") + 9] = om * np.eye(3).ravel()
+    wgt[N.offset("be"):N.offset("be") + 9] = 2.0 * np.arctanh(om / 2.0) * np.eye(3).ravel()
     Gd, Gl, _ = N.factor_blocks(N.forward(wgt, a, P)["o"], wgt, fac)
     G = N.G_matrix(fac, Gd, Gl).toarray()
     Ad = A.toarray()
@@ -105,9 +105,20 @@ def test_kaporin_loss_at_the_exact_inverse():
     assert loss == pytest.approx(np.linalg.slogdet(A.toarray())[1] / (3 * n), rel=1e-12)
 
 
+def test_bounded_maps():
+    x = np.linspace(-30, 30, 601)
+    assert np.all(np.abs(N.bound(x)) < 2.0) and N.bound(np.zeros(1))[0] == 0.0
+    h = 1e-6
+    np.testing.assert_allclose(N.bound_slope(x), (N.bound(x + h) - N.bound(x - h)) / (2 * h), atol=1e-8)
+    # huge head outputs still give a finite, well-defined factor
+    o = np.full((4, 6), 1e6)
+    L = N.lower_factor(o)
+    assert np.all(np.isfinite(L)) and np.allclose(np.diagonal(L, axis1=1, axis2=2), np.exp(2.0))
+
+
 def test_backward_matches_finite_differences():
     a, P, PT, fac, A, b, _ = small_system(4)
-    w = N.init_weights(5, head_scale=0.05)
+    w = N.init_weights(5, head_scale=0.5)
     v = np.random.default_rng(6).choice([-1.0, 1.0], size=(fac.n, 3))
     lg = lambda ww: N.loss_and_grad(ww, a, P, PT, fac, A, v)
     loss, g, _ = lg(w)
@@ -136,7 +147,7 @@ def test_damped_factor_reduces_cg_iterations():
     sysm = O.build_system(mesh, st, prob.dir_nodes, prob.dir_vel, zeta, st.Ep)
     a, P, PT, fac = N.system_inputs(mesh, st.x, zeta, sysm.A, prob.dir_nodes)
     w = N.init_weights(0)
-    w[N.offset("be"):N.offset("be") + 9] = 0.75 * np.eye(3).ravel()
+    w[N.offset("be"):N.offset("be") + 9] = 2.0 * np.arctanh(0.75 / 2.0) * np.eye(3).ravel()
     Gd, Gl, _ = N.factor_blocks(N.forward(w, a, P)["o"], w, fac)
     G = N.G_matrix(fac, Gd, Gl)
     B = (G.T @ G).tocsr()
