@@ -179,3 +179,25 @@ def test_random_network_solve_meets_tolerance():
         assert s["rel_residual"] <= prob.params["cg_rel_tol"] and s["steps_done"] == 5
         say(f"  iters {s['inner_iters']} fallback {s['used_fallback']}")
     net.close()
+
+
+def test_factor_stays_finite_under_extreme_stretch():
+    # bounded features and outputs: a random network on a wildly stretched mesh
+    # still gives a finite factor and a learned solve that meets the tolerance
+    say("case learned factor under extreme stretch")
+    prob, U, V = seeded_state(6)
+    rng = np.random.default_rng(6)
+    U = 0.05 * rng.normal(size=prob.X.shape)  # 5x the cell size
+    w = N.init_weights(11, head_scale=2.0).astype(np.float32)
+    net = gfem.Net(seed=0)
+    net.set_weights(w)
+    with gfem.mesh_from_problem(prob) as m:
+        gfem.set_displacement(m, U, V)
+        loss, gd, gl, grad = net.eval(m)
+        assert np.isfinite(loss) and np.all(np.isfinite(gd)) and np.all(np.isfinite(gl))
+        assert np.all(np.isfinite(grad))
+        gfem.attach_net(m, net)
+        s = m.step(1, raise_on_error=False)
+        say(f"  loss {loss:.3f} iters {s['inner_iters']} fallback {s['used_fallback']} status {s['status']}")
+        assert s["status"] == gfem.GF_OK
+    net.close()
