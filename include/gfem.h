@@ -153,12 +153,15 @@ gf_status gf_get_state(const gf_mesh* m, void* buf, size_t* bytes);
 gf_status gf_set_state(gf_mesh* m, const void* buf, size_t bytes);
 
 /* Per-kernel device timing with HIP events on the library's stream
- * (fills gf_step_stats.kernel_us / n_launch).  Off by default. */
+ * (fills gf_step_stats.kernel_us / n_launch); the PCG kernels' events are
+ * recorded by their dispatches, so they time kernel execution only.  Off by
+ * default. */
 gf_status gf_set_timing(gf_mesh* m, int32_t on);
 
 /* Time `reps` launches of the PCG SpMV kernel alone on the current operator
- * (after at least one step or gf_get_system) with HIP events; returns the
- * mean duration in microseconds and the algorithmic bytes per launch. */
+ * (after at least one step or gf_get_system) with HIP events recorded by each
+ * dispatch (kernel execution only); returns the mean duration in microseconds
+ * and the algorithmic bytes per launch. */
 gf_status gf_bench_spmv(gf_mesh* m, int32_t reps, double* us_per_launch, double* bytes_per_launch);
 
 /* ---------------------------------------------------------------------------

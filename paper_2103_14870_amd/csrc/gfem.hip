@@ -178,6 +178,18 @@ struct gf_mesh {
     }
     return ev_pool[ev_used++];
   }
+  // Timing with events recorded by the dispatch itself (kernel execution only):
+  // launch(LaunchEvents) receives the events, or null events when timing is off.
+  template <typename F>
+  void timed_ev(int cat, int solve, int k, F&& launch) {
+    if (!timing) {
+      launch(gfem::LaunchEvents{});
+      return;
+    }
+    TimeRec r{cat, solve, k, ev(), ev()};
+    launch(gfem::LaunchEvents{r.a, r.b});
+    recs.push_back(r);
+  }
   // Records events around one launch when timing is on.
   template <typename F>
   void timed(int cat, int solve, int k, F&& launch) {
@@ -354,23 +366,25 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
     while (true) {
       const int kend = std::min(k + chunk, left);
       for (; k < kend; ++k) {
-        M->timed(4, solve_id, k, [&] {
+        M->timed_ev(4, solve_id, k, [&](gfem::LaunchEvents e) {
           gfem::launch_pcg_spmv<T>(s, k, M->Gb, nrz, A, z, pb[(k + 1) & 1], pb[k & 1], q, M->ctl, M->part_rz,
-                                   M->part_pq, rel_in * rel_in);
+                                   M->part_pq, rel_in * rel_in, e);
         });
         if constexpr (kFloat) {
           if (fact) {
-            M->timed(5, solve_id, k, [&] {
+            M->timed_ev(5, solve_id, k, [&](gfem::LaunchEvents e) {
               gfem::launch_pcg_gpass<float>(s, k, M->Gb, *F, rb[k & 1], rb[(k + 1) & 1], q, pb[k & 1], x, y, M->ctl,
-                                            M->part_pq, M->part_rz);
+                                            M->part_pq, M->part_rz, e);
             });
-            M->timed(8, solve_id, k, [&] { gfem::launch_pcg_gtpass<float>(s, M->Gb, *F, y, z, M->ctl); });
+            M->timed_ev(8, solve_id, k, [&](gfem::LaunchEvents e) {
+              gfem::launch_pcg_gtpass<float>(s, M->Gb, *F, y, z, M->ctl, e);
+            });
             continue;
           }
         }
-        M->timed(5, solve_id, k, [&] {
+        M->timed_ev(5, solve_id, k, [&](gfem::LaunchEvents e) {
           gfem::launch_pcg_update<T>(s, k, M->n, M->Ga, M->Gb, pb[k & 1], q, x, r, z, binv, M->ctl, M->part_pq,
-                                     M->part_rz);
+                                     M->part_rz, e);
         });
       }
       M->check_launch();
@@ -966,9 +980,8 @@ gf_status gf_bench_spmv(gf_mesh* m, int32_t reps, double* us_per_launch, double*
     // row_ptr per block row
     if (bytes_per_launch) *bytes_per_launch = (double)m->nb * (9 * ab + 4) + (double)m->n * (4 * vb + 4);
     hipStream_t s = m->stream;
-    hipEvent_t a, b;
-    hchk(hipEventCreate(&a), "hipEventCreate");
-    hchk(hipEventCreate(&b), "hipEventCreate");
+    std::vector<hipEvent_t> evs(2 * (size_t)reps);
+    for (auto& e : evs) hchk(hipEventCreate(&e), "hipEventCreate");
     auto run = [&](auto tag) {
       using T = decltype(tag);
       v4<T>* pb[2] = {static_cast<v4<T>*>(m->vp[0]), static_cast<v4<T>*>(m->vp[1])};
@@ -982,11 +995,9 @@ gf_status gf_bench_spmv(gf_mesh* m, int32_t reps, double* us_per_launch, double*
                                -1.0);  // negative threshold: never converges
       gfem::launch_pcg_update<T>(s, 0, m->n, m->Ga, m->Gb, pb[0], q, static_cast<v4<T>*>(m->vx),
                                  static_cast<v4<T>*>(m->vr), z, binv, m->ctl, m->part_pq, m->part_rz);
-      hchk(hipEventRecord(a, s), "hipEventRecord");
       for (int i = 0; i < reps; ++i)
         gfem::launch_pcg_spmv<T>(s, 1, m->Gb, m->Ga, m->mat(), z, pb[0], pb[1], q, m->ctl, m->part_rz, m->part_pq,
-                                 -1.0);
-      hchk(hipEventRecord(b, s), "hipEventRecord");
+                                 -1.0, gfem::LaunchEvents{evs[2 * i], evs[2 * i + 1]});
     };
     if (m->split)
       run(float{});
@@ -994,11 +1005,14 @@ gf_status gf_bench_spmv(gf_mesh* m, int32_t reps, double* us_per_launch, double*
       run(double{});
     m->check_launch();
     m->sync();
-    float ms = 0;
-    hchk(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    *us_per_launch = 1000.0 * ms / reps;
+    double total_ms = 0;
+    for (int i = 0; i < reps; ++i) {
+      float ms = 0;
+      hchk(hipEventElapsedTime(&ms, evs[2 * i], evs[2 * i + 1]), "hipEventElapsedTime");
+      total_ms += ms;
+    }
+    for (auto& e : evs) (void)hipEventDestroy(e);
+    *us_per_launch = 1000.0 * total_ms / reps;
     return GF_OK;
   })
 }

@@ -4,6 +4,8 @@
 // and Brittle Fracture".
 #include "kernels.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 namespace gfem {
@@ -1325,6 +1327,15 @@ void launch_row(hipStream_t s, int n, int G, MatView A, const int32_t* diag_blk,
                                   val_mut, b, X64, binv, f_out, part_bb);
 }
 
+// Launch with dispatch-recorded events when given.
+template <typename... P, typename... A>
+void launch_ev(void (*kernel)(P...), dim3 grid, dim3 block, hipStream_t s, const LaunchEvents& ev, A... args) {
+  if (ev.start)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, ev.start, ev.stop, 0, static_cast<P>(args)...);
+  else
+    kernel<<<grid, block, 0, s>>>(static_cast<P>(args)...);
+}
+
 template <typename T>
 void launch_pcg_init(hipStream_t s, int n, int Ga, const d4* src, const T* binv, v4<T>* r, v4<T>* z, v4<T>* p0,
                      v4<T>* x, double* part_rz) {
@@ -1333,19 +1344,22 @@ void launch_pcg_init(hipStream_t s, int n, int Ga, const d4* src, const T* binv,
 
 template <typename T>
 void launch_pcg_spmv(hipStream_t s, int k, int Gb, int Ga, MatView A, const v4<T>* z, const v4<T>* p_old,
-                     v4<T>* p_new, v4<T>* q, PcgCtl* ctl, const double* part_rz, double* part_pq, double rel2) {
+                     v4<T>* p_new, v4<T>* q, PcgCtl* ctl, const double* part_rz, double* part_pq, double rel2,
+                     LaunchEvents ev) {
   if (k == 0)
-    k_pcg_spmv<T, false, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(k, Ga, A, z, p_old, p_new, q, ctl, part_rz, part_pq,
-                                                               rel2);
+    launch_ev(k_pcg_spmv<T, false, kSpmvThreads>, Gb, kSpmvThreads, s, ev, k, Ga, A, z, p_old, p_new, q, ctl,
+              part_rz, part_pq, rel2);
   else
-    k_pcg_spmv<T, true, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(k, Ga, A, z, p_old, p_new, q, ctl, part_rz, part_pq,
-                                                              rel2);
+    launch_ev(k_pcg_spmv<T, true, kSpmvThreads>, Gb, kSpmvThreads, s, ev, k, Ga, A, z, p_old, p_new, q, ctl, part_rz,
+              part_pq, rel2);
 }
 
 template <typename T>
 void launch_pcg_update(hipStream_t s, int k, int n, int Ga, int Gb, const v4<T>* p, const v4<T>* q, v4<T>* x,
-                       v4<T>* r, v4<T>* z, const T* binv, PcgCtl* ctl, const double* part_pq, double* part_rz) {
-  k_pcg_update<T, kVecThreads><<<Ga, kVecThreads, 0, s>>>(k, n, Gb, p, q, x, r, z, binv, ctl, part_pq, part_rz);
+                       v4<T>* r, v4<T>* z, const T* binv, PcgCtl* ctl, const double* part_pq, double* part_rz,
+                       LaunchEvents ev) {
+  launch_ev(k_pcg_update<T, kVecThreads>, Ga, kVecThreads, s, ev, k, n, Gb, p, q, x, r, z, binv, ctl, part_pq,
+            part_rz);
 }
 
 template <typename T>
@@ -1358,22 +1372,24 @@ void launch_pcg_fact_init(hipStream_t s, int Gb, FactView F, const d4* src, v4<T
 
 template <typename T>
 void launch_pcg_gpass(hipStream_t s, int k, int Gb, FactView F, const v4<T>* r_old, v4<T>* r_new, const v4<T>* q,
-                      const v4<T>* p, v4<T>* x, v4<T>* y, PcgCtl* ctl, const double* part_pq, double* part_rz) {
-  k_pcg_gpass<T, false, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(k, F, nullptr, r_old, r_new, q, p, x, y, ctl,
-                                                                 part_pq, part_rz);
+                      const v4<T>* p, v4<T>* x, v4<T>* y, PcgCtl* ctl, const double* part_pq, double* part_rz,
+                      LaunchEvents ev) {
+  launch_ev(k_pcg_gpass<T, false, kSpmvThreads>, Gb, kSpmvThreads, s, ev, k, F, nullptr, r_old, r_new, q, p, x, y,
+            ctl, part_pq, part_rz);
 }
 
 template <typename T>
-void launch_pcg_gtpass(hipStream_t s, int Gb, FactView F, const v4<T>* y, v4<T>* z, PcgCtl* ctl) {
-  k_pcg_gtpass<T, false, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(F, y, z, nullptr, ctl);
+void launch_pcg_gtpass(hipStream_t s, int Gb, FactView F, const v4<T>* y, v4<T>* z, PcgCtl* ctl, LaunchEvents ev) {
+  launch_ev(k_pcg_gtpass<T, false, kSpmvThreads>, Gb, kSpmvThreads, s, ev, F, y, z, nullptr, ctl);
 }
 
 template void launch_pcg_fact_init<float>(hipStream_t, int, FactView, const d4*, v4<float>*, v4<float>*,
                                           v4<float>*, v4<float>*, v4<float>*, double*);
 template void launch_pcg_gpass<float>(hipStream_t, int, int, FactView, const v4<float>*, v4<float>*,
                                       const v4<float>*, const v4<float>*, v4<float>*, v4<float>*, PcgCtl*,
-                                      const double*, double*);
-template void launch_pcg_gtpass<float>(hipStream_t, int, FactView, const v4<float>*, v4<float>*, PcgCtl*);
+                                      const double*, double*, LaunchEvents);
+template void launch_pcg_gtpass<float>(hipStream_t, int, FactView, const v4<float>*, v4<float>*, PcgCtl*,
+                                       LaunchEvents);
 
 template <typename T>
 void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, d4* R64, double* part_rr) {
@@ -1401,9 +1417,10 @@ void launch_integrate(hipStream_t s, int n, const d4* X64, d4* V, d4* U, const u
   template void launch_pcg_init<T>(hipStream_t, int, int, const d4*, const T*, v4<T>*, v4<T>*, v4<T>*,      \
                                    v4<T>*, double*);                                                         \
   template void launch_pcg_spmv<T>(hipStream_t, int, int, int, MatView, const v4<T>*, const v4<T>*, v4<T>*, \
-                                   v4<T>*, PcgCtl*, const double*, double*, double);                        \
+                                   v4<T>*, PcgCtl*, const double*, double*, double, LaunchEvents);          \
   template void launch_pcg_update<T>(hipStream_t, int, int, int, int, const v4<T>*, const v4<T>*, v4<T>*,   \
-                                     v4<T>*, v4<T>*, const T*, PcgCtl*, const double*, double*);            \
+                                     v4<T>*, v4<T>*, const T*, PcgCtl*, const double*, double*,             \
+                                     LaunchEvents);                                                          \
   template void launch_resid<T>(hipStream_t, int, MatView, const d4*, const d4*, d4*, double*);             \
   template void launch_addcorr<T>(hipStream_t, int, int, const v4<T>*, d4*);
 

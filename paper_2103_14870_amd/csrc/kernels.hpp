@@ -91,6 +91,12 @@ void launch_row(hipStream_t s, int n, int G, MatView A, const int32_t* diag_blk,
                 const uint8_t* dflag, const d4* dvel, RowConst c, T* val_mut, d4* b,
                 d4* X64, T* binv, d4* f_out, double* part_bb);
 
+// Optional start/stop events recorded by the dispatch itself (kernel execution
+// time only, as a profiler reports it); null events: plain launch.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // Ga: workgroups (kVecThreads each) of the vector kernels; Gb: workgroups
 // (kSpmvThreads each) of the SpMV.  Both multiples of 8.  rel2: squared relative
 // reduction of |r| the solve must reach (threshold = rel2 |r_0|^2).
@@ -101,12 +107,12 @@ void launch_pcg_init(hipStream_t s, int n, int Ga, const d4* src, const T* binv,
 template <typename T>
 void launch_pcg_spmv(hipStream_t s, int k, int Gb, int Ga, MatView A, const v4<T>* z, const v4<T>* p_old,
                      v4<T>* p_new, v4<T>* q, PcgCtl* ctl, const double* part_rz, double* part_pq,
-                     double rel2);
+                     double rel2, LaunchEvents ev = {});
 
 template <typename T>
 void launch_pcg_update(hipStream_t s, int k, int n, int Ga, int Gb, const v4<T>* p, const v4<T>* q,
                        v4<T>* x, v4<T>* r, v4<T>* z, const T* binv, PcgCtl* ctl, const double* part_pq,
-                       double* part_rz);
+                       double* part_rz, LaunchEvents ev = {});
 
 // Factorised sparse approximate inverse preconditioner z = G^T G r, G block
 // lower triangular on the lower block pattern of A (node order).  BF16 block
@@ -143,10 +149,11 @@ void launch_pcg_fact_init(hipStream_t s, int Gb, FactView F, const d4* src, v4<T
 template <typename T>
 void launch_pcg_gpass(hipStream_t s, int k, int Gb, FactView F, const v4<T>* r_old, v4<T>* r_new,
                       const v4<T>* q, const v4<T>* p, v4<T>* x, v4<T>* y, PcgCtl* ctl, const double* part_pq,
-                      double* part_rz);
+                      double* part_rz, LaunchEvents ev = {});
 // z = G^T y.
 template <typename T>
-void launch_pcg_gtpass(hipStream_t s, int Gb, FactView F, const v4<T>* y, v4<T>* z, PcgCtl* ctl);
+void launch_pcg_gtpass(hipStream_t s, int Gb, FactView F, const v4<T>* y, v4<T>* z, PcgCtl* ctl,
+                       LaunchEvents ev = {});
 
 template <typename T>
 void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, d4* R64,
