@@ -350,7 +350,8 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
     M->timed(5, -1, 0, [&] {
       if constexpr (kFloat) {
         if (fact) {
-          gfem::launch_pcg_fact_init<float>(s, M->Gb, *F, src, rb[0], x, y, z, pb[0], M->part_rz);
+          gfem::launch_pcg_fact_init<float>(s, M->Gb, *F, src, rb[0], x, y, pb[0], M->ctl, M->part_rz,
+                                            rel_in * rel_in);
           return;
         }
       }
@@ -366,22 +367,25 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
     while (true) {
       const int kend = std::min(k + chunk, left);
       for (; k < kend; ++k) {
-        M->timed_ev(4, solve_id, k, [&](gfem::LaunchEvents e) {
-          gfem::launch_pcg_spmv<T>(s, k, M->Gb, nrz, A, z, pb[(k + 1) & 1], pb[k & 1], q, M->ctl, M->part_rz,
-                                   M->part_pq, rel_in * rel_in, e);
-        });
         if constexpr (kFloat) {
           if (fact) {
+            M->timed_ev(4, solve_id, k, [&](gfem::LaunchEvents e) {
+              gfem::launch_pcg_spmv_p<float>(s, M->Gb, A, pb[k & 1], q, M->ctl, M->part_pq, e);
+            });
             M->timed_ev(5, solve_id, k, [&](gfem::LaunchEvents e) {
               gfem::launch_pcg_gpass<float>(s, k, M->Gb, *F, rb[k & 1], rb[(k + 1) & 1], q, pb[k & 1], x, y, M->ctl,
                                             M->part_pq, M->part_rz, e);
             });
             M->timed_ev(8, solve_id, k, [&](gfem::LaunchEvents e) {
-              gfem::launch_pcg_gtpass<float>(s, M->Gb, *F, y, z, M->ctl, e);
+              gfem::launch_pcg_gtpass<float>(s, k, M->Gb, *F, y, pb[k & 1], pb[(k + 1) & 1], M->ctl, M->part_rz, e);
             });
             continue;
           }
         }
+        M->timed_ev(4, solve_id, k, [&](gfem::LaunchEvents e) {
+          gfem::launch_pcg_spmv<T>(s, k, M->Gb, nrz, A, z, pb[(k + 1) & 1], pb[k & 1], q, M->ctl, M->part_rz,
+                                   M->part_pq, rel_in * rel_in, e);
+        });
         M->timed_ev(5, solve_id, k, [&](gfem::LaunchEvents e) {
           gfem::launch_pcg_update<T>(s, k, M->n, M->Ga, M->Gb, pb[k & 1], q, x, r, z, binv, M->ctl, M->part_pq,
                                      M->part_rz, e);

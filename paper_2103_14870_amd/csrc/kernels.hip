@@ -1157,11 +1157,17 @@ __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* _
   if (!INIT && blockIdx.x == 0 && threadIdx.x == 0) ctl->iters = k + 1;
 }
 
-// G^T pass: z_i = G_ii^T y_i + sum over the upper blocks (i, j) of G_ji^T y_j;
-// INIT also writes p_0 = z.
+// G^T pass and direction update.  The G pass's partials (r.z = y.y and r.r
+// of parity INIT ? 0 : (k + 1) & 1) are reduced first: stop when
+// |r|^2 <= thr2 (thr2 = rel2 |r_0|^2, fixed by the INIT launch), else
+// beta = r.z / (previous r.z), z_i = G_ii^T y_i + sum over the upper blocks
+// (i, j) of G_ji^T y_j and p_new = z + beta p_old for the workgroup's own rows
+// (INIT: p_0 = z).  The SpMV then gathers p alone.
 template <typename T, bool INIT, int NT>
-__global__ __launch_bounds__(NT) void k_pcg_gtpass(FactView F, const v4<T>* __restrict__ y, v4<T>* __restrict__ z,
-                                                   v4<T>* __restrict__ p0, PcgCtl* ctl) {
+__global__ __launch_bounds__(NT) void k_pcg_gtpass(int k, FactView F, const v4<T>* __restrict__ y,
+                                                   const v4<T>* __restrict__ p_old, v4<T>* __restrict__ p_new,
+                                                   PcgCtl* ctl, const double* __restrict__ part_rz, double rel2) {
+  __shared__ double sh[3 * (NT / 64)];
   if (!INIT && ctl->done) return;
   const int n = F.n;
   const int G = gridDim.x;
@@ -1171,17 +1177,58 @@ __global__ __launch_bounds__(NT) void k_pcg_gtpass(FactView F, const v4<T>* __re
   const int lane = threadIdx.x & (kFactLanes - 1);
   const int grp = threadIdx.x / kFactLanes;
   constexpr int NG = NT / kFactLanes;
-  for (int i = r0 + grp; i < r1; i += NG) {
-    const int s = F.uptr[i], e = F.uptr[i + 1];
-    const FSlot<T> fa = fslot_load<T, 2>(F.ucol, F.guv, F.gu8, s + lane, s + lane < e, nullptr, y, nullptr);
-    const FSlot<T> fb =
-        fslot_load<T, 2>(F.ucol, F.guv, F.gu8, s + lane + kFactLanes, s + lane + kFactLanes < e, nullptr, y, nullptr);
-    v4<T> yi{};
-    uint4 dv{};
-    if (lane == 0) {
-      yi = y[i];
-      dv = F.gdv[i];
+  // first row's loads before the reduction
+  int i = r0 + grp;
+  int s = 0, e = 0;
+  if (i < r1) {
+    s = F.uptr[i];
+    e = F.uptr[i + 1];
+  }
+  FSlot<T> fa = fslot_load<T, 2>(F.ucol, F.guv, F.gu8, s + lane, s + lane < e, nullptr, y, nullptr);
+  FSlot<T> fb =
+      fslot_load<T, 2>(F.ucol, F.guv, F.gu8, s + lane + kFactLanes, s + lane + kFactLanes < e, nullptr, y, nullptr);
+  v4<T> yi{}, po{};
+  uint4 dv{};
+  auto load_own = [&](int row) {
+    if (lane == 0 && row < r1) {
+      yi = y[row];
+      dv = F.gdv[row];
+      if (!INIT) po = p_old[row];
     }
+  };
+  load_own(i);
+  const double* cur = part_rz + (size_t)(INIT ? 0 : ((k + 1) & 1)) * 2 * kMaxPart;
+  const double* prv = part_rz + (size_t)(k & 1) * 2 * kMaxPart;
+  double rz = 0, rr = 0, rzp = 0;
+  for (int t = threadIdx.x; t < G; t += NT) {
+    rz += cur[t];
+    rr += cur[kMaxPart + t];
+    if (!INIT) rzp += prv[t];
+  }
+  block_sum3n<NT>(rz, rr, rzp, sh);
+  double thr2;
+  if (INIT) {
+    thr2 = rel2 * rr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->thr2 = thr2;
+  } else {
+    thr2 = ctl->thr2;
+  }
+  if (!(rr > thr2) || rz == 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->done = 1;
+    return;
+  }
+  const T beta = INIT ? T(0) : (T)(rz / rzp);
+  bool first = true;
+  for (; i < r1; i += NG) {
+    if (!first) {
+      s = F.uptr[i];
+      e = F.uptr[i + 1];
+      fa = fslot_load<T, 2>(F.ucol, F.guv, F.gu8, s + lane, s + lane < e, nullptr, y, nullptr);
+      fb = fslot_load<T, 2>(F.ucol, F.guv, F.gu8, s + lane + kFactLanes, s + lane + kFactLanes < e, nullptr, y,
+                            nullptr);
+      load_own(i);
+    }
+    first = false;
     T ax = 0, ay = 0, az = 0;
     fslot_apply<T, 2>(fa, T(0), ax, ay, az);
     fslot_apply<T, 2>(fb, T(0), ax, ay, az);
@@ -1198,10 +1245,69 @@ __global__ __launch_bounds__(NT) void k_pcg_gtpass(FactView F, const v4<T>* __re
       ay = fmadd((T)(float)d[2], yi.y, fmadd((T)(float)d[4], yi.z, ay));
       az = fmadd((T)(float)d[5], yi.z, az);
       const v4<T> zi{ax, ay, az, T(0)};
-      z[i] = zi;
-      if (INIT) p0[i] = zi;
+      p_new[i] = INIT ? zi : dir_comb(zi, beta, po);
     }
   }
+}
+
+// SpMV of the factorised path: q = A p (p formed by the G^T pass), partial
+// p.q.  kRowLanes lanes per block row, two rows in flight per lane group, no
+// scalar prologue.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_pcg_spmv_p(MatView Am, const v4<T>* __restrict__ p, v4<T>* __restrict__ q,
+                                                   PcgCtl* ctl, double* __restrict__ part_pq) {
+  __shared__ double sh[3 * (NT / 64)];
+  if (ctl->done) return;
+  const int n = Am.n;
+  const int G = gridDim.x;
+  const int L = xcd_logical(blockIdx.x, G);
+  const int chunk = (n + G - 1) / G;
+  const int r0 = min(n, L * chunk), r1 = min(n, r0 + chunk);
+  const int lane = threadIdx.x & (kRowLanes - 1);
+  const int grp = threadIdx.x / kRowLanes;
+  constexpr int NG = NT / kRowLanes;
+  const T* __restrict__ val = static_cast<const T*>(Am.val);
+  double dot = 0;
+  for (int ra = r0 + grp; ra < r1; ra += 2 * NG) {
+    const int rb = ra + NG;
+    const bool hb = rb < r1;
+    const int sa = Am.row_ptr[ra], ea = Am.row_ptr[ra + 1];
+    const int sb = hb ? Am.row_ptr[rb] : 0, eb = hb ? Am.row_ptr[rb + 1] : 0;
+    SpmvSlot<T, false> fa = spmv_load<T, false>(Am, val, sa + lane, lane < ea - sa, nullptr, nullptr, p);
+    SpmvSlot<T, false> fb = spmv_load<T, false>(Am, val, sb + lane, lane < eb - sb, nullptr, nullptr, p);
+    T ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
+    if (fa.on) blk_fma(fa.k, fa.p, ax, ay, az);
+    if (fb.on) blk_fma(fb.k, fb.p, bx, by, bz);
+    const int len = max(ea - sa, eb - sb);
+    for (int o = lane + kRowLanes; o < len; o += kRowLanes) {
+      const SpmvSlot<T, false> ta = spmv_load<T, false>(Am, val, sa + o, o < ea - sa, nullptr, nullptr, p);
+      const SpmvSlot<T, false> tb = spmv_load<T, false>(Am, val, sb + o, o < eb - sb, nullptr, nullptr, p);
+      if (ta.on) blk_fma(ta.k, ta.p, ax, ay, az);
+      if (tb.on) blk_fma(tb.k, tb.p, bx, by, bz);
+    }
+#pragma unroll
+    for (int o = kRowLanes / 2; o > 0; o >>= 1) {
+      ax += __shfl_xor(ax, o, kRowLanes);
+      ay += __shfl_xor(ay, o, kRowLanes);
+      az += __shfl_xor(az, o, kRowLanes);
+      bx += __shfl_xor(bx, o, kRowLanes);
+      by += __shfl_xor(by, o, kRowLanes);
+      bz += __shfl_xor(bz, o, kRowLanes);
+    }
+    if (lane == 0) {
+      const v4<T> pa = p[ra];
+      q[ra] = v4<T>{ax, ay, az, T(0)};
+      dot += (double)pa.x * ax + (double)pa.y * ay + (double)pa.z * az;
+      if (hb) {
+        const v4<T> pb = p[rb];
+        q[rb] = v4<T>{bx, by, bz, T(0)};
+        dot += (double)pb.x * bx + (double)pb.y * by + (double)pb.z * bz;
+      }
+    }
+  }
+  double u1 = 0, u2 = 0;
+  block_sum3n<NT>(dot, u1, u2, sh);
+  if (threadIdx.x == 0) part_pq[L] = dot;
 }
 
 // FP64 residual of the outer (iterative refinement) loop: R = b - A X64 with
@@ -1364,10 +1470,16 @@ void launch_pcg_update(hipStream_t s, int k, int n, int Ga, int Gb, const v4<T>*
 
 template <typename T>
 void launch_pcg_fact_init(hipStream_t s, int Gb, FactView F, const d4* src, v4<T>* r0, v4<T>* x, v4<T>* y,
-                          v4<T>* z, v4<T>* p0, double* part_rz) {
+                          v4<T>* p0, PcgCtl* ctl, double* part_rz, double rel2) {
   k_pcg_gpass<T, true, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(0, F, src, nullptr, r0, nullptr, nullptr, x, y,
                                                                 nullptr, nullptr, part_rz);
-  k_pcg_gtpass<T, true, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(F, y, z, p0, nullptr);
+  k_pcg_gtpass<T, true, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(0, F, y, nullptr, p0, ctl, part_rz, rel2);
+}
+
+template <typename T>
+void launch_pcg_spmv_p(hipStream_t s, int Gb, MatView A, const v4<T>* p, v4<T>* q, PcgCtl* ctl, double* part_pq,
+                       LaunchEvents ev) {
+  launch_ev(k_pcg_spmv_p<T, kSpmvThreads>, Gb, kSpmvThreads, s, ev, A, p, q, ctl, part_pq);
 }
 
 template <typename T>
@@ -1379,17 +1491,20 @@ void launch_pcg_gpass(hipStream_t s, int k, int Gb, FactView F, const v4<T>* r_o
 }
 
 template <typename T>
-void launch_pcg_gtpass(hipStream_t s, int Gb, FactView F, const v4<T>* y, v4<T>* z, PcgCtl* ctl, LaunchEvents ev) {
-  launch_ev(k_pcg_gtpass<T, false, kSpmvThreads>, Gb, kSpmvThreads, s, ev, F, y, z, nullptr, ctl);
+void launch_pcg_gtpass(hipStream_t s, int k, int Gb, FactView F, const v4<T>* y, const v4<T>* p_old, v4<T>* p_new,
+                       PcgCtl* ctl, const double* part_rz, LaunchEvents ev) {
+  launch_ev(k_pcg_gtpass<T, false, kSpmvThreads>, Gb, kSpmvThreads, s, ev, k, F, y, p_old, p_new, ctl, part_rz, 0.0);
 }
 
 template void launch_pcg_fact_init<float>(hipStream_t, int, FactView, const d4*, v4<float>*, v4<float>*,
-                                          v4<float>*, v4<float>*, v4<float>*, double*);
+                                          v4<float>*, v4<float>*, PcgCtl*, double*, double);
+template void launch_pcg_spmv_p<float>(hipStream_t, int, MatView, const v4<float>*, v4<float>*, PcgCtl*, double*,
+                                       LaunchEvents);
 template void launch_pcg_gpass<float>(hipStream_t, int, int, FactView, const v4<float>*, v4<float>*,
                                       const v4<float>*, const v4<float>*, v4<float>*, v4<float>*, PcgCtl*,
                                       const double*, double*, LaunchEvents);
-template void launch_pcg_gtpass<float>(hipStream_t, int, FactView, const v4<float>*, v4<float>*, PcgCtl*,
-                                       LaunchEvents);
+template void launch_pcg_gtpass<float>(hipStream_t, int, int, FactView, const v4<float>*, const v4<float>*,
+                                       v4<float>*, PcgCtl*, const double*, LaunchEvents);
 
 template <typename T>
 void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, d4* R64, double* part_rr) {

@@ -137,23 +137,28 @@ struct FactView {
 };
 constexpr int kFactLanes = 4;  // lanes cooperating on one half row in the G and G^T passes
 
-// Start of a solve with the factorised preconditioner: r_0 = src (rounded to
-// T), x = 0, y = G r_0, z = G^T y, p_0 = z; partials of r.z (= y.y) and r.r.
-// Gb workgroups (kSpmvThreads each), the same grid as the SpMV, so the SpMV
-// reduces Gb partials.
+// Factorised-preconditioner PCG, three kernels per iteration (Gb workgroups
+// of kSpmvThreads each, the same grid for all three):
+//   start:  r_0 = src (rounded to T), x = 0, y = G r_0, partials y.y (= r.z)
+//           and r.r; then threshold thr2 = rel2 |r_0|^2, p_0 = G^T y.
+//   k:      SpMV q = A p_k, partial p.q;
+//           G pass: alpha = r.z / p.q, x += alpha p_k, r_{k+1} = r_k - alpha q,
+//           y = G r_{k+1}, partials for k + 1;
+//           G^T pass: stop if |r_{k+1}|^2 <= thr2, else
+//           p_{k+1} = G^T y + beta p_k.
 template <typename T>
 void launch_pcg_fact_init(hipStream_t s, int Gb, FactView F, const d4* src, v4<T>* r0, v4<T>* x, v4<T>* y,
-                          v4<T>* z, v4<T>* p0, double* part_rz);
-// Iteration k after the SpMV: alpha = r.z / p.q; x += alpha p; r_new = r_old -
-// alpha q; y = G r_new; partials y.y and r.r for iteration k + 1.
+                          v4<T>* p0, PcgCtl* ctl, double* part_rz, double rel2);
+template <typename T>
+void launch_pcg_spmv_p(hipStream_t s, int Gb, MatView A, const v4<T>* p, v4<T>* q, PcgCtl* ctl, double* part_pq,
+                       LaunchEvents ev = {});
 template <typename T>
 void launch_pcg_gpass(hipStream_t s, int k, int Gb, FactView F, const v4<T>* r_old, v4<T>* r_new,
                       const v4<T>* q, const v4<T>* p, v4<T>* x, v4<T>* y, PcgCtl* ctl, const double* part_pq,
                       double* part_rz, LaunchEvents ev = {});
-// z = G^T y.
 template <typename T>
-void launch_pcg_gtpass(hipStream_t s, int Gb, FactView F, const v4<T>* y, v4<T>* z, PcgCtl* ctl,
-                       LaunchEvents ev = {});
+void launch_pcg_gtpass(hipStream_t s, int k, int Gb, FactView F, const v4<T>* y, const v4<T>* p_old,
+                       v4<T>* p_new, PcgCtl* ctl, const double* part_rz, LaunchEvents ev = {});
 
 template <typename T>
 void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, d4* R64,
