@@ -204,6 +204,7 @@ def main():
         "outer_iters_per_step": main_leg["outer"],
         "fallback_steps": main_leg["fallback"],
         "kernel_us_per_step": {k: v / args.roofline_steps for k, v in kus.items()},
+        "kernel_avg_us_per_launch": {k: kus[k] / kn[k] for k in kus if kn.get(k)},
         "roofline": {
             "kernel": spmv_name,
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -104,7 +104,7 @@ struct gf_mesh {
   bool plastic = false;
   int dev = 0;
   hipStream_t own = nullptr, stream = nullptr;
-  int n = 0, m = 0, ne = 0, nb = 0, nbp = 0, Gv = 8, Gs = 8, Ga = 8, Gb = 8;
+  int n = 0, m = 0, ne = 0, nb = 0, nbp = 0, Gv = 8, Gs = 8, Ga = 8, Gb = 8, Gp = 8;
   double mu = 0, lam = 0, alpha_m1 = 0;
   Alloc al;
   // node data
@@ -134,17 +134,17 @@ struct gf_mesh {
   // PCG
   void *vr = nullptr, *vz = nullptr, *vp[2] = {nullptr, nullptr}, *vq = nullptr, *vx = nullptr;
   void *vr2 = nullptr, *vy = nullptr;  // second residual buffer and G r (factorised preconditioner)
-  double *part_a = nullptr, *part_rz = nullptr, *part_pq = nullptr;
+  double *part_a = nullptr, *part_rz = nullptr, *part_pq = nullptr, *part_r = nullptr;
   gfem::PcgCtl* ctl = nullptr;
   gfem::Counters* ctr = nullptr;
   // host side
-  double* h_part = nullptr;          // pinned
+  double* h_part = nullptr;          // pinned, 2 x kMaxPart
   gfem::PcgCtl* h_ctl = nullptr;     // pinned
   gfem::Counters* h_ctr = nullptr;   // pinned
   std::vector<uint8_t> h_dflag;
   std::vector<d4> h_dvel;
   int step_index = 0;
-  int last_first_solve = 0;
+  int last_solve_iters[4] = {0, 0, 0, 0};  // inner iterations of each outer solve of the last step
   int last_learned_iters = 0;  // inner iterations of the last accepted learned solve
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -346,7 +346,7 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
     }
     const double rel_in = outer == 0 ? std::max(0.5 * tol, floor_rel) : std::max(0.5 * tol * std::sqrt(bb / rr), floor_rel);
     const int solve_id = (int)M->solve_iters.size();
-    hchk(hipMemsetAsync(M->ctl, 0, sizeof(gfem::PcgCtl), s), "hipMemsetAsync");
+    // (the control block is reset by the solve's first kernel)
     M->timed(5, -1, 0, [&] {
       if constexpr (kFloat) {
         if (fact) {
@@ -355,26 +355,31 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
           return;
         }
       }
-      gfem::launch_pcg_init<T>(s, M->n, M->Ga, src, binv, r, z, pb[0], x, M->part_rz);
+      gfem::launch_pcg_init<T>(s, M->n, M->Ga, src, binv, r, z, pb[0], x, M->part_rz, M->ctl);
     });
     const int left = budget - res.inner;
     int k = 0;
-    // the first chunk covers the iteration count of the previous step's first solve (+10 %)
-    int chunk = (outer == 0 && M->last_first_solve > 0) ? M->last_first_solve + M->last_first_solve / 10 + 1 : 16;
+    // The first chunk covers the iteration count of the same outer solve in the
+    // previous step; further chunks are short.  A launch after convergence
+    // exits at entry but still costs the dispatch latency (~9 us per kernel on
+    // MI355X, ~30 us per iteration), about as much as one extra host
+    // synchronisation, so the prediction carries no margin.
+    const int slot = std::min(outer, 3);
+    int chunk = M->last_solve_iters[slot] > 0 ? M->last_solve_iters[slot] : (outer == 0 ? 16 : 8);
     chunk = std::max(1, std::min(chunk, left));
     int iters = 0;
-    bool failed = false;
+    bool failed = false, converged_flag = false;
     while (true) {
       const int kend = std::min(k + chunk, left);
       for (; k < kend; ++k) {
         if constexpr (kFloat) {
           if (fact) {
             M->timed_ev(4, solve_id, k, [&](gfem::LaunchEvents e) {
-              gfem::launch_pcg_spmv_p<float>(s, M->Gb, A, pb[k & 1], q, M->ctl, M->part_pq, e);
+              gfem::launch_pcg_spmv_p<float>(s, M->Gp, A, pb[k & 1], q, M->ctl, M->part_pq, e);
             });
             M->timed_ev(5, solve_id, k, [&](gfem::LaunchEvents e) {
-              gfem::launch_pcg_gpass<float>(s, k, M->Gb, *F, rb[k & 1], rb[(k + 1) & 1], q, pb[k & 1], x, y, M->ctl,
-                                            M->part_pq, M->part_rz, e);
+              gfem::launch_pcg_gpass<float>(s, k, M->Gb, M->Gp, *F, rb[k & 1], rb[(k + 1) & 1], q, pb[k & 1], x, y,
+                                            M->ctl, M->part_pq, M->part_rz, e);
             });
             M->timed_ev(8, solve_id, k, [&](gfem::LaunchEvents e) {
               gfem::launch_pcg_gtpass<float>(s, k, M->Gb, *F, y, pb[k & 1], pb[(k + 1) & 1], M->ctl, M->part_rz, e);
@@ -391,10 +396,17 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
                                      M->part_rz, e);
         });
       }
+      // queued behind the chunk, effective only once the solve has converged:
+      // the FP64 correction dv += x and the FP64 residual, read back with the
+      // control block by the same synchronisation
+      M->timed(6, -1, 0, [&] { gfem::launch_addcorr<T>(s, M->n, M->Gv, x, M->X64, M->ctl); });
+      M->timed(6, -1, 0, [&] { gfem::launch_resid<T>(s, M->Gs, A, M->b, M->X64, M->R64, M->part_r, M->ctl); });
       M->check_launch();
       hchk(hipMemcpyAsync(M->h_ctl, M->ctl, sizeof(gfem::PcgCtl), hipMemcpyDeviceToHost, s), "D2H");
       if (bb < 0.0)
         hchk(hipMemcpyAsync(M->h_part, M->part_a, sizeof(double) * M->Gs, hipMemcpyDeviceToHost, s), "D2H");
+      hchk(hipMemcpyAsync(M->h_part + kMaxPart, M->part_r, sizeof(double) * M->Gs, hipMemcpyDeviceToHost, s),
+           "D2H");
       M->sync();
       if (bb < 0.0) {
         bb = 0.0;
@@ -403,11 +415,12 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
       }
       iters = M->h_ctl->iters;
       failed = M->h_ctl->fail != 0;
-      if (M->h_ctl->done || k >= left || bb == 0.0) break;
-      chunk = 8;
+      converged_flag = M->h_ctl->done != 0;
+      if (converged_flag || k >= left || bb == 0.0) break;
+      chunk = 3;
     }
     M->solve_iters.push_back(iters);
-    if (outer == 0) M->last_first_solve = iters;
+    M->last_solve_iters[slot] = iters;
     res.inner += iters;
     res.outer = outer + 1;
     if (bb == 0.0) {  // b = 0: dv = 0 (X64 was zeroed by the row pass)
@@ -415,12 +428,17 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
       res.rel = 0.0;
       break;
     }
-    if (iters > 0) {
-      M->timed(6, -1, 0, [&] { gfem::launch_addcorr<T>(s, M->n, M->Gv, x, M->X64); });
+    if (converged_flag) {
+      // correction and residual were applied behind the last chunk
+      rr = 0;
+      for (int i = 0; i < M->Gs; ++i) rr += M->h_part[kMaxPart + i];
+    } else {
+      // iteration budget exhausted without the flag: apply what was reached
+      if (iters > 0) M->timed(6, -1, 0, [&] { gfem::launch_addcorr<T>(s, M->n, M->Gv, x, M->X64); });
+      M->timed(6, -1, 0, [&] { gfem::launch_resid<T>(s, M->Gs, A, M->b, M->X64, M->R64, M->part_r); });
+      M->check_launch();
+      rr = read_partials(M, M->part_r, M->Gs);
     }
-    M->timed(6, -1, 0, [&] { gfem::launch_resid<T>(s, M->Gs, A, M->b, M->X64, M->R64, M->part_a); });
-    M->check_launch();
-    rr = read_partials(M, M->part_a, M->Gs);
     src = M->R64;
     if (failed && iters == 0) {
       res.rel = std::sqrt(rr / bb);
@@ -637,6 +655,9 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     // workgroups (four resident per CU) so the update kernel reduces few partials.
     M->Gb = std::min(1024, std::max(8, round_up8((T.n * gfem::kRowLanes + gfem::kSpmvThreads - 1) / gfem::kSpmvThreads)));
     M->Ga = std::min(kMaxPart, std::max(8, round_up8((T.n + gfem::kVecThreads - 1) / gfem::kVecThreads)));
+    // SpMV of the factorised path: the same cap (its partials are reduced by
+    // every workgroup of the G pass, so more of them cost more than they save)
+    M->Gp = M->Gb;
     const double E = p.youngs, nu = p.poisson;
     const double mu0 = E / (2 * (1 + nu)), lam0 = E * nu / ((1 + nu) * (1 - 2 * nu));
     M->mu = 4.0 * mu0 / 3.0;             // Smith et al. reparametrisation of Eq. 35
@@ -690,9 +711,10 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     M->part_a = M->al.get<double>(kMaxPart);
     M->part_rz = M->al.get<double>(4 * kMaxPart);
     M->part_pq = M->al.get<double>(kMaxPart);
+    M->part_r = M->al.get<double>(kMaxPart);
     M->ctl = M->al.get<gfem::PcgCtl>(1);
     M->ctr = M->al.get<gfem::Counters>(1);
-    hchk(hipHostMalloc((void**)&M->h_part, sizeof(double) * kMaxPart, hipHostMallocDefault), "hipHostMalloc");
+    hchk(hipHostMalloc((void**)&M->h_part, sizeof(double) * 2 * kMaxPart, hipHostMallocDefault), "hipHostMalloc");
     hchk(hipHostMalloc((void**)&M->h_ctl, sizeof(gfem::PcgCtl), hipHostMallocDefault), "hipHostMalloc");
     hchk(hipHostMalloc((void**)&M->h_ctr, sizeof(gfem::Counters), hipHostMallocDefault), "hipHostMalloc");
     M->h_dflag.assign(T.n, 0);
@@ -994,7 +1016,7 @@ gf_status gf_bench_spmv(gf_mesh* m, int32_t reps, double* us_per_launch, double*
       const T* binv = static_cast<const T*>(m->binv);
       hchk(hipMemsetAsync(m->ctl, 0, sizeof(gfem::PcgCtl), s), "hipMemsetAsync");
       gfem::launch_pcg_init<T>(s, m->n, m->Ga, m->b, binv, static_cast<v4<T>*>(m->vr), z, pb[0],
-                               static_cast<v4<T>*>(m->vx), m->part_rz);
+                               static_cast<v4<T>*>(m->vx), m->part_rz, m->ctl);
       gfem::launch_pcg_spmv<T>(s, 0, m->Gb, m->Ga, m->mat(), z, pb[1], pb[0], q, m->ctl, m->part_rz, m->part_pq,
                                -1.0);  // negative threshold: never converges
       gfem::launch_pcg_update<T>(s, 0, m->n, m->Ga, m->Gb, pb[0], q, static_cast<v4<T>*>(m->vx),

@@ -729,13 +729,15 @@ __device__ __forceinline__ void blk_fma(const Blk<T>& k, const v4<T>& x, T& ax, 
   az = fmadd(k.a[6], x.x, fmadd(k.a[7], x.y, fmadd(k.a[8], x.z, az)));
 }
 
-// r = src (rounded to T), z = B r, p_0 = z, x = 0; partials of r.z and r.r.
+// r = src (rounded to T), z = B r, p_0 = z, x = 0; partials of r.z and r.r;
+// resets the control block for the solve.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_pcg_init(int n, const d4* __restrict__ src, const T* __restrict__ binv,
                                                  v4<T>* __restrict__ r, v4<T>* __restrict__ z,
                                                  v4<T>* __restrict__ p0, v4<T>* __restrict__ x,
-                                                 double* __restrict__ part_rz) {
+                                                 double* __restrict__ part_rz, PcgCtl* ctl) {
   __shared__ double sh[3 * (NT / 64)];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ctl = PcgCtl{0, 0, 0, 0, 0.0};
   const int G = gridDim.x;
   const int L = xcd_logical(blockIdx.x, G);
   const int chunk = (n + G - 1) / G;
@@ -1041,7 +1043,7 @@ struct GOwn {
 // first row's loads are issued before the scalar reduction so that the two
 // latencies overlap.
 template <typename T, bool INIT, int NT>
-__global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* __restrict__ src,
+__global__ __launch_bounds__(NT) void k_pcg_gpass(int k, int npq, FactView F, const d4* __restrict__ src,
                                                   const v4<T>* __restrict__ r_old, v4<T>* __restrict__ r_new,
                                                   const v4<T>* __restrict__ q, const v4<T>* __restrict__ p,
                                                   v4<T>* __restrict__ x, v4<T>* __restrict__ y, PcgCtl* ctl,
@@ -1049,6 +1051,7 @@ __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* _
                                                   double* __restrict__ part_rz) {
   constexpr int MODE = INIT ? 1 : 0;
   __shared__ double sh[3 * (NT / 64)];
+  if (INIT && blockIdx.x == 0 && threadIdx.x == 0) *ctl = PcgCtl{0, 0, 0, 0, 0.0};
   if (!INIT && ctl->done) return;
   const int n = F.n;
   const int G = gridDim.x;
@@ -1087,10 +1090,8 @@ __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, FactView F, const d4* _
   if (!INIT) {
     const double* cur = part_rz + (size_t)(k & 1) * 2 * kMaxPart;
     double pq = 0, rz = 0, unused = 0;
-    for (int t = threadIdx.x; t < G; t += NT) {
-      pq += part_pq[t];
-      rz += cur[t];
-    }
+    for (int t = threadIdx.x; t < npq; t += NT) pq += part_pq[t];
+    for (int t = threadIdx.x; t < G; t += NT) rz += cur[t];
     block_sum3n<NT>(pq, rz, unused, sh);
     if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1251,8 +1252,8 @@ __global__ __launch_bounds__(NT) void k_pcg_gtpass(int k, FactView F, const v4<T
 }
 
 // SpMV of the factorised path: q = A p (p formed by the G^T pass), partial
-// p.q.  kRowLanes lanes per block row, two rows in flight per lane group, no
-// scalar prologue.
+// p.q.  kRowLanes lanes per block row, one row per lane group at a time, no
+// scalar prologue; launched on its own (larger) grid.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_pcg_spmv_p(MatView Am, const v4<T>* __restrict__ p, v4<T>* __restrict__ q,
                                                    PcgCtl* ctl, double* __restrict__ part_pq) {
@@ -1268,41 +1269,23 @@ __global__ __launch_bounds__(NT) void k_pcg_spmv_p(MatView Am, const v4<T>* __re
   constexpr int NG = NT / kRowLanes;
   const T* __restrict__ val = static_cast<const T*>(Am.val);
   double dot = 0;
-  for (int ra = r0 + grp; ra < r1; ra += 2 * NG) {
-    const int rb = ra + NG;
-    const bool hb = rb < r1;
+  for (int ra = r0 + grp; ra < r1; ra += NG) {
     const int sa = Am.row_ptr[ra], ea = Am.row_ptr[ra + 1];
-    const int sb = hb ? Am.row_ptr[rb] : 0, eb = hb ? Am.row_ptr[rb + 1] : 0;
-    SpmvSlot<T, false> fa = spmv_load<T, false>(Am, val, sa + lane, lane < ea - sa, nullptr, nullptr, p);
-    SpmvSlot<T, false> fb = spmv_load<T, false>(Am, val, sb + lane, lane < eb - sb, nullptr, nullptr, p);
-    T ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
-    if (fa.on) blk_fma(fa.k, fa.p, ax, ay, az);
-    if (fb.on) blk_fma(fb.k, fb.p, bx, by, bz);
-    const int len = max(ea - sa, eb - sb);
-    for (int o = lane + kRowLanes; o < len; o += kRowLanes) {
-      const SpmvSlot<T, false> ta = spmv_load<T, false>(Am, val, sa + o, o < ea - sa, nullptr, nullptr, p);
-      const SpmvSlot<T, false> tb = spmv_load<T, false>(Am, val, sb + o, o < eb - sb, nullptr, nullptr, p);
-      if (ta.on) blk_fma(ta.k, ta.p, ax, ay, az);
-      if (tb.on) blk_fma(tb.k, tb.p, bx, by, bz);
+    T ax = 0, ay = 0, az = 0;
+    for (int o = lane; o < ea - sa; o += kRowLanes) {
+      const SpmvSlot<T, false> t = spmv_load<T, false>(Am, val, sa + o, true, nullptr, nullptr, p);
+      blk_fma(t.k, t.p, ax, ay, az);
     }
 #pragma unroll
     for (int o = kRowLanes / 2; o > 0; o >>= 1) {
       ax += __shfl_xor(ax, o, kRowLanes);
       ay += __shfl_xor(ay, o, kRowLanes);
       az += __shfl_xor(az, o, kRowLanes);
-      bx += __shfl_xor(bx, o, kRowLanes);
-      by += __shfl_xor(by, o, kRowLanes);
-      bz += __shfl_xor(bz, o, kRowLanes);
     }
     if (lane == 0) {
       const v4<T> pa = p[ra];
       q[ra] = v4<T>{ax, ay, az, T(0)};
       dot += (double)pa.x * ax + (double)pa.y * ay + (double)pa.z * az;
-      if (hb) {
-        const v4<T> pb = p[rb];
-        q[rb] = v4<T>{bx, by, bz, T(0)};
-        dot += (double)pb.x * bx + (double)pb.y * by + (double)pb.z * bz;
-      }
     }
   }
   double u1 = 0, u2 = 0;
@@ -1315,8 +1298,9 @@ __global__ __launch_bounds__(NT) void k_pcg_spmv_p(MatView Am, const v4<T>* __re
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_resid(MatView Am, const d4* __restrict__ bvec,
                                                     const d4* __restrict__ X64, d4* __restrict__ R64,
-                                                    double* __restrict__ part_rr) {
+                                                    double* __restrict__ part_rr, const PcgCtl* ctl) {
   __shared__ double sh[16];
+  if (ctl && !ctl->done) return;
   const int n = Am.n, nbp = Am.nbp;
   const int G = gridDim.x;
   const int L = xcd_logical(blockIdx.x, G);
@@ -1357,7 +1341,9 @@ __global__ __launch_bounds__(kThreads) void k_resid(MatView Am, const d4* __rest
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_addcorr(int n, const v4<T>* __restrict__ x, d4* __restrict__ X64) {
+__global__ __launch_bounds__(kThreads) void k_addcorr(int n, const v4<T>* __restrict__ x, d4* __restrict__ X64,
+                                                      const PcgCtl* ctl) {
+  if (ctl && !ctl->done) return;
   int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
   const v4<T> xi = x[i];
@@ -1444,8 +1430,8 @@ void launch_ev(void (*kernel)(P...), dim3 grid, dim3 block, hipStream_t s, const
 
 template <typename T>
 void launch_pcg_init(hipStream_t s, int n, int Ga, const d4* src, const T* binv, v4<T>* r, v4<T>* z, v4<T>* p0,
-                     v4<T>* x, double* part_rz) {
-  k_pcg_init<T, kVecThreads><<<Ga, kVecThreads, 0, s>>>(n, src, binv, r, z, p0, x, part_rz);
+                     v4<T>* x, double* part_rz, PcgCtl* ctl) {
+  k_pcg_init<T, kVecThreads><<<Ga, kVecThreads, 0, s>>>(n, src, binv, r, z, p0, x, part_rz, ctl);
 }
 
 template <typename T>
@@ -1471,23 +1457,23 @@ void launch_pcg_update(hipStream_t s, int k, int n, int Ga, int Gb, const v4<T>*
 template <typename T>
 void launch_pcg_fact_init(hipStream_t s, int Gb, FactView F, const d4* src, v4<T>* r0, v4<T>* x, v4<T>* y,
                           v4<T>* p0, PcgCtl* ctl, double* part_rz, double rel2) {
-  k_pcg_gpass<T, true, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(0, F, src, nullptr, r0, nullptr, nullptr, x, y,
-                                                                nullptr, nullptr, part_rz);
+  k_pcg_gpass<T, true, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(0, 0, F, src, nullptr, r0, nullptr, nullptr, x, y,
+                                                                ctl, nullptr, part_rz);
   k_pcg_gtpass<T, true, kSpmvThreads><<<Gb, kSpmvThreads, 0, s>>>(0, F, y, nullptr, p0, ctl, part_rz, rel2);
 }
 
 template <typename T>
-void launch_pcg_spmv_p(hipStream_t s, int Gb, MatView A, const v4<T>* p, v4<T>* q, PcgCtl* ctl, double* part_pq,
+void launch_pcg_spmv_p(hipStream_t s, int Gp, MatView A, const v4<T>* p, v4<T>* q, PcgCtl* ctl, double* part_pq,
                        LaunchEvents ev) {
-  launch_ev(k_pcg_spmv_p<T, kSpmvThreads>, Gb, kSpmvThreads, s, ev, A, p, q, ctl, part_pq);
+  launch_ev(k_pcg_spmv_p<T, kSpmvThreads>, Gp, kSpmvThreads, s, ev, A, p, q, ctl, part_pq);
 }
 
 template <typename T>
-void launch_pcg_gpass(hipStream_t s, int k, int Gb, FactView F, const v4<T>* r_old, v4<T>* r_new, const v4<T>* q,
-                      const v4<T>* p, v4<T>* x, v4<T>* y, PcgCtl* ctl, const double* part_pq, double* part_rz,
-                      LaunchEvents ev) {
-  launch_ev(k_pcg_gpass<T, false, kSpmvThreads>, Gb, kSpmvThreads, s, ev, k, F, nullptr, r_old, r_new, q, p, x, y,
-            ctl, part_pq, part_rz);
+void launch_pcg_gpass(hipStream_t s, int k, int Gb, int npq, FactView F, const v4<T>* r_old, v4<T>* r_new,
+                      const v4<T>* q, const v4<T>* p, v4<T>* x, v4<T>* y, PcgCtl* ctl, const double* part_pq,
+                      double* part_rz, LaunchEvents ev) {
+  launch_ev(k_pcg_gpass<T, false, kSpmvThreads>, Gb, kSpmvThreads, s, ev, k, npq, F, nullptr, r_old, r_new, q, p, x,
+            y, ctl, part_pq, part_rz);
 }
 
 template <typename T>
@@ -1500,20 +1486,21 @@ template void launch_pcg_fact_init<float>(hipStream_t, int, FactView, const d4*,
                                           v4<float>*, v4<float>*, PcgCtl*, double*, double);
 template void launch_pcg_spmv_p<float>(hipStream_t, int, MatView, const v4<float>*, v4<float>*, PcgCtl*, double*,
                                        LaunchEvents);
-template void launch_pcg_gpass<float>(hipStream_t, int, int, FactView, const v4<float>*, v4<float>*,
+template void launch_pcg_gpass<float>(hipStream_t, int, int, int, FactView, const v4<float>*, v4<float>*,
                                       const v4<float>*, const v4<float>*, v4<float>*, v4<float>*, PcgCtl*,
                                       const double*, double*, LaunchEvents);
 template void launch_pcg_gtpass<float>(hipStream_t, int, int, FactView, const v4<float>*, const v4<float>*,
                                        v4<float>*, PcgCtl*, const double*, LaunchEvents);
 
 template <typename T>
-void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, d4* R64, double* part_rr) {
-  k_resid<T><<<Gs, kThreads, 0, s>>>(A, b, X64, R64, part_rr);
+void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, d4* R64, double* part_rr,
+                  const PcgCtl* only_if_done) {
+  k_resid<T><<<Gs, kThreads, 0, s>>>(A, b, X64, R64, part_rr, only_if_done);
 }
 
 template <typename T>
-void launch_addcorr(hipStream_t s, int n, int, const v4<T>* x, d4* X64) {
-  k_addcorr<T><<<blocks_for(n), kThreads, 0, s>>>(n, x, X64);
+void launch_addcorr(hipStream_t s, int n, int, const v4<T>* x, d4* X64, const PcgCtl* only_if_done) {
+  k_addcorr<T><<<blocks_for(n), kThreads, 0, s>>>(n, x, X64, only_if_done);
 }
 
 void launch_integrate(hipStream_t s, int n, const d4* X64, d4* V, d4* U, const uint8_t* dflag, const d4* dvel,
@@ -1530,14 +1517,15 @@ void launch_integrate(hipStream_t s, int n, const d4* X64, d4* V, d4* U, const u
                               const T*, const double*, const d4*, const d4*, const d4*, const uint8_t*,      \
                               const d4*, RowConst, T*, d4*, d4*, T*, d4*, double*);                          \
   template void launch_pcg_init<T>(hipStream_t, int, int, const d4*, const T*, v4<T>*, v4<T>*, v4<T>*,      \
-                                   v4<T>*, double*);                                                         \
+                                   v4<T>*, double*, PcgCtl*);                                                \
   template void launch_pcg_spmv<T>(hipStream_t, int, int, int, MatView, const v4<T>*, const v4<T>*, v4<T>*, \
                                    v4<T>*, PcgCtl*, const double*, double*, double, LaunchEvents);          \
   template void launch_pcg_update<T>(hipStream_t, int, int, int, int, const v4<T>*, const v4<T>*, v4<T>*,   \
                                      v4<T>*, v4<T>*, const T*, PcgCtl*, const double*, double*,             \
                                      LaunchEvents);                                                          \
-  template void launch_resid<T>(hipStream_t, int, MatView, const d4*, const d4*, d4*, double*);             \
-  template void launch_addcorr<T>(hipStream_t, int, int, const v4<T>*, d4*);
+  template void launch_resid<T>(hipStream_t, int, MatView, const d4*, const d4*, d4*, double*,             \
+                                const PcgCtl*);                                                              \
+  template void launch_addcorr<T>(hipStream_t, int, int, const v4<T>*, d4*, const PcgCtl*);
 
 GFEM_INST(float)
 GFEM_INST(double)

@@ -102,7 +102,7 @@ struct LaunchEvents {
 // reduction of |r| the solve must reach (threshold = rel2 |r_0|^2).
 template <typename T>
 void launch_pcg_init(hipStream_t s, int n, int Ga, const d4* src, const T* binv, v4<T>* r, v4<T>* z,
-                     v4<T>* p0, v4<T>* x, double* part_rz);
+                     v4<T>* p0, v4<T>* x, double* part_rz, PcgCtl* ctl);
 
 template <typename T>
 void launch_pcg_spmv(hipStream_t s, int k, int Gb, int Ga, MatView A, const v4<T>* z, const v4<T>* p_old,
@@ -137,10 +137,12 @@ struct FactView {
 };
 constexpr int kFactLanes = 4;  // lanes cooperating on one half row in the G and G^T passes
 
-// Factorised-preconditioner PCG, three kernels per iteration (Gb workgroups
-// of kSpmvThreads each, the same grid for all three):
-//   start:  r_0 = src (rounded to T), x = 0, y = G r_0, partials y.y (= r.z)
-//           and r.r; then threshold thr2 = rel2 |r_0|^2, p_0 = G^T y.
+// Factorised-preconditioner PCG, three kernels per iteration (G and G^T
+// passes on Gb workgroups of kSpmvThreads, the SpMV on its own grid of Gp,
+// whose p.q partials the G pass reduces):
+//   start:  control block reset, r_0 = src (rounded to T), x = 0, y = G r_0,
+//           partials y.y (= r.z) and r.r; then threshold thr2 = rel2 |r_0|^2,
+//           p_0 = G^T y.
 //   k:      SpMV q = A p_k, partial p.q;
 //           G pass: alpha = r.z / p.q, x += alpha p_k, r_{k+1} = r_k - alpha q,
 //           y = G r_{k+1}, partials for k + 1;
@@ -150,22 +152,24 @@ template <typename T>
 void launch_pcg_fact_init(hipStream_t s, int Gb, FactView F, const d4* src, v4<T>* r0, v4<T>* x, v4<T>* y,
                           v4<T>* p0, PcgCtl* ctl, double* part_rz, double rel2);
 template <typename T>
-void launch_pcg_spmv_p(hipStream_t s, int Gb, MatView A, const v4<T>* p, v4<T>* q, PcgCtl* ctl, double* part_pq,
+void launch_pcg_spmv_p(hipStream_t s, int Gp, MatView A, const v4<T>* p, v4<T>* q, PcgCtl* ctl, double* part_pq,
                        LaunchEvents ev = {});
 template <typename T>
-void launch_pcg_gpass(hipStream_t s, int k, int Gb, FactView F, const v4<T>* r_old, v4<T>* r_new,
+void launch_pcg_gpass(hipStream_t s, int k, int Gb, int npq, FactView F, const v4<T>* r_old, v4<T>* r_new,
                       const v4<T>* q, const v4<T>* p, v4<T>* x, v4<T>* y, PcgCtl* ctl, const double* part_pq,
                       double* part_rz, LaunchEvents ev = {});
 template <typename T>
 void launch_pcg_gtpass(hipStream_t s, int k, int Gb, FactView F, const v4<T>* y, const v4<T>* p_old,
                        v4<T>* p_new, PcgCtl* ctl, const double* part_rz, LaunchEvents ev = {});
 
+// only_if_done (nullable): the kernel does nothing unless that PCG control
+// block reports convergence, so it can be queued behind a launch chunk.
 template <typename T>
 void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, d4* R64,
-                  double* part_rr);
+                  double* part_rr, const PcgCtl* only_if_done = nullptr);
 
 template <typename T>
-void launch_addcorr(hipStream_t s, int n, int G, const v4<T>* x, d4* X64);
+void launch_addcorr(hipStream_t s, int n, int G, const v4<T>* x, d4* X64, const PcgCtl* only_if_done = nullptr);
 
 void launch_integrate(hipStream_t s, int n, const d4* X64, d4* V, d4* U, const uint8_t* dflag,
                       const d4* dvel, double dt);

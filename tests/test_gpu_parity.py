@@ -233,3 +233,43 @@ def test_spmv_bench_hook():
         us, by = m.bench_spmv(20)
         say(f"  spmv {us:.2f} us, {by / us / 1e3:.1f} GB/s")
         assert us > 0 and by > 0
+
+
+def test_config3_full_size_jacobi_and_learned():
+    """Full 619,830-tet ductile ellipsoid in the launch configuration the
+    benchmark times (split precision; block-Jacobi, and the learned factor with
+    the shipped weights and the network every 4 steps): a 2-step slice against
+    the oracle.  Labels of the learned run equal those of the block-Jacobi run;
+    labels of the block-Jacobi run equal the oracle's away from the threshold."""
+    import os
+
+    say("case config3 full size 2 steps, block-Jacobi and learned")
+    prob = meshgen.make_config(3)
+    prob.params["net_every_n_steps"] = 4
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    net = gfem.Net(seed=0)
+    net.set_weights(np.load(os.path.join(root, "paper_2103_14870_amd", "weights", "precond_net.npy")))
+    mj = gfem.mesh_from_problem(prob)
+    ml = gfem.mesh_from_problem(prob)
+    gfem.attach_net(ml, net)
+    mesh = O.setup(prob.X, prob.tets, prob.params)
+    st = O.initial_state(mesh)
+    for i in range(2):
+        sj = mj.step(1)
+        sl = ml.step(1)
+        zj = mj.edge_damage().astype(bool)
+        eps = O.edge_strain(mesh, st.x)
+        near = np.nonzero(np.abs(eps - prob.params["damage_strain"]) < 1e-6)[0]
+        st, h = O.step(mesh, st, prob.dir_nodes, prob.dir_vel, override={int(e): bool(zj[e]) for e in near})
+        assert h["converged"]
+        assert sj["rel_residual"] <= 1e-6 and sl["rel_residual"] <= 1e-6 and sl["used_fallback"] == 0
+        assert np.array_equal(zj, st.zeta)
+        assert np.array_equal(ml.edge_damage().astype(bool), zj)
+        say(f"  step {i}: iters block-Jacobi {sj['inner_iters']} learned {sl['inner_iters']} oracle {h['iters']}")
+    dj = rel(mj.positions() - prob.X, st.x - prob.X)
+    dl = rel(ml.positions() - prob.X, st.x - prob.X)
+    say(f"  disp rel block-Jacobi {dj:.3e} learned {dl:.3e}")
+    assert dj <= 1e-4 and dl <= 1e-4
+    mj.close()
+    ml.close()
+    net.close()
