@@ -75,12 +75,16 @@ typedef struct {
   int32_t steps_done;       /* committed steps */
   int32_t inner_iters;      /* PCG iterations */
   int32_t outer_iters;      /* FP64 residual recomputations (iterative refinement) */
-  int32_t used_fallback;    /* learned -> block-Jacobi fallbacks */
+  int32_t used_fallback;    /* learned preconditioner selected but the step solved with
+                               block-Jacobi: a rejected learned solve (re-solved), or one of
+                               the following back-off steps (4, doubling to 64 per rejection) */
   int32_t new_broken;       /* edges newly labelled broken */
   int32_t total_broken;     /* broken edges after the last step */
   int32_t near_threshold;   /* edge evaluations with |strain - threshold| < 1e-6 */
   int32_t chi_zero_tets;    /* tets with chi = 0 (disconnected) in the last step */
   int32_t degenerate_tets;  /* tets with |J| < 0.05 in the last step */
+  int32_t fp64_steps;       /* split precision only: steps whose FP32 operator could not be
+                               solved and that were re-run in FP64 (element pass, blocks, PCG) */
   int32_t n_launch[9];      /* kernel launches per timing category (timing on) */
   double rel_residual;      /* final FP64 |b - A dv| / |b| of the last step */
   double kernel_us[9];      /* device time per category (timing on), microseconds:

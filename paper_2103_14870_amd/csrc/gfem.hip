@@ -134,6 +134,18 @@ struct gf_mesh {
   // PCG
   void *vr = nullptr, *vz = nullptr, *vp[2] = {nullptr, nullptr}, *vq = nullptr, *vx = nullptr;
   void *vr2 = nullptr, *vy = nullptr;  // second residual buffer and G r (factorised preconditioner)
+  // FP64 copies of the precision-typed buffers of a split-precision mesh, for
+  // steps re-run in FP64 (allocated on first use; swapped in for that step)
+  struct PrecBufs {
+    void *val, *contrib, *edge_w, *binv, *pl[2], *vr, *vz, *vp[2], *vq, *vx, *vr2, *vy;
+  };
+  bool esc_ready = false;
+  PrecBufs esc{};
+  PrecBufs cur() const { return PrecBufs{val, contrib, edge_w, binv, {pl[0], pl[1]}, vr, vz, {vp[0], vp[1]}, vq, vx, vr2, vy}; }
+  void use(const PrecBufs& b) {
+    val = b.val; contrib = b.contrib; edge_w = b.edge_w; binv = b.binv; pl[0] = b.pl[0]; pl[1] = b.pl[1];
+    vr = b.vr; vz = b.vz; vp[0] = b.vp[0]; vp[1] = b.vp[1]; vq = b.vq; vx = b.vx; vr2 = b.vr2; vy = b.vy;
+  }
   double *part_a = nullptr, *part_rz = nullptr, *part_pq = nullptr, *part_r = nullptr;
   gfem::PcgCtl* ctl = nullptr;
   gfem::Counters* ctr = nullptr;
@@ -144,8 +156,12 @@ struct gf_mesh {
   std::vector<uint8_t> h_dflag;
   std::vector<d4> h_dvel;
   int step_index = 0;
-  int last_solve_iters[4] = {0, 0, 0, 0};  // inner iterations of each outer solve of the last step
+  // inner iterations of each outer solve of the last step, per solve kind
+  // (0 working precision block-Jacobi, 1 learned factor, 2 FP64 re-run)
+  int last_solve_iters[3][4] = {};
   int last_learned_iters = 0;  // inner iterations of the last accepted learned solve
+  int learned_skip = 0;        // steps left that use block-Jacobi directly after a rejected learned solve
+  int learned_backoff = 4;     // length of the next such pause (doubles per rejection, up to 64)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
@@ -312,12 +328,14 @@ struct SolveResult {
 // vectors, FP64 dot products, device-side scalars and early exit, launched in
 // chunks so the host only synchronises once per chunk.
 template <typename T>
-SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* F = nullptr, int max_inner = 0) {
+SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* F = nullptr, int max_inner = 0,
+                  int kind = 0) {
   hipStream_t s = M->stream;
   const double tol = M->p.cg_rel_tol;
   SolveResult res{false, 0, 0, 0.0};
   const double floor_rel = M->split ? 1e-7 : 0.0;
   double bb = -1.0, rr = -1.0;  // |b|^2 is read back with the first chunk
+  double rr_prev = 0.0;
   const d4* src = M->b;
   int budget = std::max(1, (int)M->p.cg_max_iter);
   if (max_inner > 0) budget = std::min(budget, max_inner);
@@ -365,7 +383,8 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
     // MI355X, ~30 us per iteration), about as much as one extra host
     // synchronisation, so the prediction carries no margin.
     const int slot = std::min(outer, 3);
-    int chunk = M->last_solve_iters[slot] > 0 ? M->last_solve_iters[slot] : (outer == 0 ? 16 : 8);
+    int* hist = M->last_solve_iters[kind];
+    int chunk = hist[slot] > 0 ? hist[slot] : (outer == 0 ? 16 : 8);
     chunk = std::max(1, std::min(chunk, left));
     int iters = 0;
     bool failed = false, converged_flag = false;
@@ -420,7 +439,7 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
       chunk = 3;
     }
     M->solve_iters.push_back(iters);
-    M->last_solve_iters[slot] = iters;
+    hist[slot] = iters;
     res.inner += iters;
     res.outer = outer + 1;
     if (bb == 0.0) {  // b = 0: dv = 0 (X64 was zeroed by the row pass)
@@ -440,6 +459,10 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
       rr = read_partials(M, M->part_r, M->Gs);
     }
     src = M->R64;
+    // an outer correction that grows the FP64 residual means the inner solve
+    // broke down on the working-precision operator: give up on this solve
+    if (rr > 100.0 * (outer == 0 ? bb : rr_prev)) break;
+    rr_prev = rr;
     if (failed && iters == 0) {
       res.rel = std::sqrt(rr / bb);
       res.ok = res.rel <= tol;
@@ -525,6 +548,59 @@ void learned_precond(gf_mesh* M) {
   M->check_launch();
 }
 
+// FP64 copies of the precision-typed buffers of a split-precision mesh.
+void ensure_esc(gf_mesh* M) {
+  if (M->esc_ready) return;
+  const size_t n = M->n, m = M->m;
+  gf_mesh::PrecBufs& b = M->esc;
+  b.val = M->al.get<double>(9 * (size_t)M->nbp);
+  b.contrib = M->al.get<double>(60 * m);
+  b.edge_w = M->al.get<double>(M->ne);
+  b.binv = M->al.get<double>(6 * n);
+  b.pl[0] = M->plastic ? M->al.get<double>(6 * m) : nullptr;
+  b.pl[1] = M->plastic ? M->al.get<double>(6 * m) : nullptr;
+  b.vr = M->al.get<d4>(n);
+  b.vz = M->al.get<d4>(n);
+  b.vp[0] = M->al.get<d4>(n);
+  b.vp[1] = M->al.get<d4>(n);
+  b.vq = M->al.get<d4>(n);
+  b.vx = M->al.get<d4>(n);
+  b.vr2 = M->al.get<d4>(n);
+  b.vy = M->al.get<d4>(n);
+  M->esc_ready = true;
+}
+
+// Re-run the assembled step of a split-precision mesh in FP64 (element pass,
+// block values and block-Jacobi PCG): used when the FP32 operator cannot be
+// solved, which happens once near-flat tets make the rounding of their
+// stiffness exceed the mass term.  Nothing is committed here.
+SolveResult fp64_rerun(gf_mesh* M) {
+  ensure_esc(M);
+  const gf_mesh::PrecBufs keep = M->cur();
+  const size_t np = 6 * (size_t)M->m;
+  if (M->plastic)
+    gfem::launch_convert(M->stream, static_cast<const float*>(keep.pl[M->plcur]),
+                         static_cast<double*>(M->esc.pl[M->plcur]), np);
+  M->use(M->esc);
+  M->split = false;
+  SolveResult r{false, 0, 0, 0.0};
+  try {
+    assemble<double>(M, true, nullptr);
+    r = solve<double>(M, M->binv, nullptr, 0, 2);
+  } catch (...) {
+    M->use(keep);
+    M->split = true;
+    throw;
+  }
+  M->use(keep);
+  M->split = true;
+  if (r.ok && M->plastic)
+    gfem::launch_convert(M->stream, static_cast<const double*>(M->esc.pl[1 - M->plcur]),
+                         static_cast<float*>(keep.pl[1 - M->plcur]), np);
+  M->check_launch();
+  return r;
+}
+
 template <typename T>
 gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
   for (int i = 0; i < n_steps; ++i) {
@@ -532,17 +608,22 @@ gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
     hchk(hipMemcpyAsync(M->h_ctr, M->ctr, sizeof(gfem::Counters), hipMemcpyDeviceToHost, M->stream), "D2H");
     SolveResult r;
     int fallback = 0;
-    if (M->precond == GF_PC_LEARNED) {
+    if (M->precond == GF_PC_LEARNED && M->learned_skip == 0) {
       // network factor B = G^T G; block-Jacobi re-solve if not accepted.  The
       // learned attempt may spend at most 3x (+100) the iterations of the last
-      // accepted learned solve, so a poor factor costs a bounded detour.
+      // accepted learned solve, so a poor factor costs a bounded detour; after
+      // a rejection the next steps use block-Jacobi directly (back-off).
       learned_precond(M);
       const gfem::FactView F = gfem::net_factor_view(M->netw, net_inputs(M, M->zeta[1 - M->zcur]));
       const int cap = M->last_learned_iters > 0 ? 3 * M->last_learned_iters + 100 : 0;
-      r = solve<T>(M, M->binv, &F, cap);
-      if (r.ok) M->last_learned_iters = r.inner;
-      if (!r.ok) {
+      r = solve<T>(M, M->binv, &F, cap, 1);
+      if (r.ok) {
+        M->last_learned_iters = r.inner;
+        M->learned_backoff = 4;
+      } else {
         fallback = 1;
+        M->learned_skip = M->learned_backoff;
+        M->learned_backoff = std::min(2 * M->learned_backoff, 64);
         hchk(hipMemsetAsync(M->X64, 0, sizeof(d4) * M->n, M->stream), "hipMemsetAsync");
         const int prev_inner = r.inner, prev_outer = r.outer;
         r = solve<T>(M, M->binv);
@@ -550,13 +631,28 @@ gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
         r.outer += prev_outer;
       }
     } else {
+      if (M->precond == GF_PC_LEARNED) {
+        fallback = 1;
+        --M->learned_skip;
+      }
       r = solve<T>(M, M->binv);
+    }
+    int escalated = 0;
+    if constexpr (std::is_same<T, float>::value) {
+      if (!r.ok) {
+        escalated = 1;
+        const int prev_inner = r.inner, prev_outer = r.outer;
+        r = fp64_rerun(M);
+        r.inner += prev_inner;
+        r.outer += prev_outer;
+      }
     }
     int cnt[gfem::kNumCounters] = {0, 0, 0, 0, 0};
     for (int sl = 0; sl < gfem::kCtrSlots; ++sl)
       for (int c = 0; c < gfem::kNumCounters; ++c) cnt[c] += M->h_ctr->v[sl * gfem::kCtrStride + c];
     if (st) {
       st->used_fallback += fallback;
+      st->fp64_steps += escalated;
       st->inner_iters += r.inner;
       st->outer_iters += r.outer;
       st->rel_residual = r.rel;

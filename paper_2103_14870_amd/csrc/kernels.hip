@@ -484,12 +484,17 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
       Kab[1][1] -= lap;
       Kab[2][2] -= lap;
       const bool tr = (fl >> k) & 1;
-      T* rec = contrib + ((size_t)k * m + t) * 10;
+      // one 10-value record written as five aligned pairs
+      typedef T T2 __attribute__((ext_vector_type(2)));
+      T v[10];
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) rec[3 * r + c] = tr ? Kab[c][r] : Kab[r][c];
-      rec[9] = T(2) * Vc * g[k];
+        for (int c = 0; c < 3; ++c) v[3 * r + c] = tr ? Kab[c][r] : Kab[r][c];
+      v[9] = T(2) * Vc * g[k];
+      T2* rec = reinterpret_cast<T2*>(contrib + ((size_t)k * m + t) * 10);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) rec[c] = T2{v[2 * c], v[2 * c + 1]};
     }
   }
 }
@@ -513,10 +518,17 @@ __global__ __launch_bounds__(kThreads) void k_edge(int ne, int m6, const int32_t
 #pragma unroll
   for (int c = 0; c < 10; ++c) acc[c] = 0;
   const int s0 = edge_ptr[e], s1 = edge_ptr[e + 1];
+  // records are 10 values at a 10-value stride: 8-byte (FP32) or 16-byte
+  // (FP64) aligned, read as five pairs
+  typedef T T2 __attribute__((ext_vector_type(2)));
   for (int s = s0; s < s1; ++s) {
-    const T* rec = contrib + (size_t)edge_slot[s] * 10;
+    const T2* rec = reinterpret_cast<const T2*>(contrib + (size_t)edge_slot[s] * 10);
 #pragma unroll
-    for (int c = 0; c < 10; ++c) acc[c] += rec[c];
+    for (int c = 0; c < 5; ++c) {
+      const T2 v = rec[c];
+      acc[2 * c] += v.x;
+      acc[2 * c + 1] += v.y;
+    }
   }
   const double md = edge_mass[e] * mass_fac;
   const int bij = blk_ij[e], bji = blk_ji[e];
@@ -547,6 +559,10 @@ __device__ __forceinline__ double seg_sum(double v) {
 //   b_i  = dt (m_i g + f_i) - dt alpha (M v)_i - sum_j (A_ij - m_ij (1 + dt alpha) I)(v_j - v_i)
 // then Dirichlet elimination (b_f -= A_fc dv_c; rows/columns of c -> identity),
 // the block-Jacobi inverse of A_ii, X64 = 0 and the partial |b|^2.
+// Lanes per block row in the row pass (22 FP64 partial sums per row are
+// reduced across them; 8 lanes cover the ~14 blocks of a row in two rounds).
+constexpr int kRowPassLanes = 8;
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32_t* __restrict__ diag_blk,
                                                   const int32_t* __restrict__ blk_edge,
@@ -564,10 +580,10 @@ __global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32
   const int chunk = (n + G - 1) / G;
   const int r0 = L * chunk, r1 = min(n, r0 + chunk);
   const int nbp = Am.nbp;
-  const int lane = threadIdx.x & (kRowLanes - 1);
-  const int grp = threadIdx.x / kRowLanes;
+  const int lane = threadIdx.x & (kRowPassLanes - 1);
+  const int grp = threadIdx.x / kRowPassLanes;
   double bb = 0;
-  for (int i = r0 + grp; i < r1; i += kThreads / kRowLanes) {
+  for (int i = r0 + grp; i < r1; i += kThreads / kRowPassLanes) {
     const int s = Am.row_ptr[i], e = Am.row_ptr[i + 1], db = diag_blk[i];
     const d4 Xi = X[i], Ui = U[i], vi = V[i];
     const bool ci = dflag[i] != 0;
@@ -575,7 +591,7 @@ __global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32
     double acc[22];
 #pragma unroll
     for (int c = 0; c < 22; ++c) acc[c] = 0.0;
-    for (int b = s + lane; b < e; b += kRowLanes) {
+    for (int b = s + lane; b < e; b += kRowPassLanes) {
       if (b == db) continue;
       const int j = Am.col[b];
       const int ed = blk_edge[b];
@@ -617,7 +633,7 @@ __global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32
       }
     }
 #pragma unroll
-    for (int c = 0; c < 22; ++c) acc[c] = seg_sum<kRowLanes>(acc[c]);
+    for (int c = 0; c < 22; ++c) acc[c] = seg_sum<kRowPassLanes>(acc[c]);
     if (lane == 0) {
       const double mi = lumped[i];
       const double mii = mi - acc[21];
@@ -1501,6 +1517,20 @@ void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, 
 template <typename T>
 void launch_addcorr(hipStream_t s, int n, int, const v4<T>* x, d4* X64, const PcgCtl* only_if_done) {
   k_addcorr<T><<<blocks_for(n), kThreads, 0, s>>>(n, x, X64, only_if_done);
+}
+
+template <typename A, typename B>
+__global__ __launch_bounds__(kThreads) void k_convert(const A* __restrict__ in, B* __restrict__ out, size_t count) {
+  const size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < count) out[i] = (B)in[i];
+}
+
+void launch_convert(hipStream_t s, const float* in, double* out, size_t count) {
+  if (count) k_convert<float, double><<<(unsigned)((count + kThreads - 1) / kThreads), kThreads, 0, s>>>(in, out, count);
+}
+
+void launch_convert(hipStream_t s, const double* in, float* out, size_t count) {
+  if (count) k_convert<double, float><<<(unsigned)((count + kThreads - 1) / kThreads), kThreads, 0, s>>>(in, out, count);
 }
 
 void launch_integrate(hipStream_t s, int n, const d4* X64, d4* V, d4* U, const uint8_t* dflag, const d4* dvel,

@@ -171,6 +171,10 @@ void launch_resid(hipStream_t s, int Gs, MatView A, const d4* b, const d4* X64, 
 template <typename T>
 void launch_addcorr(hipStream_t s, int n, int G, const v4<T>* x, d4* X64, const PcgCtl* only_if_done = nullptr);
 
+// Elementwise precision conversion of count values.
+void launch_convert(hipStream_t s, const float* in, double* out, size_t count);
+void launch_convert(hipStream_t s, const double* in, float* out, size_t count);
+
 void launch_integrate(hipStream_t s, int n, const d4* X64, d4* V, d4* U, const uint8_t* dflag,
                       const d4* dvel, double dt);
 

@@ -35,6 +35,7 @@ class GfStepStats(C.Structure):
     _fields_ = [("steps_done", C.c_int32), ("inner_iters", C.c_int32), ("outer_iters", C.c_int32),
                 ("used_fallback", C.c_int32), ("new_broken", C.c_int32), ("total_broken", C.c_int32),
                 ("near_threshold", C.c_int32), ("chi_zero_tets", C.c_int32), ("degenerate_tets", C.c_int32),
+                ("fp64_steps", C.c_int32),
                 ("n_launch", C.c_int32 * 9), ("rel_residual", C.c_double), ("kernel_us", C.c_double * 9)]
 
     def as_dict(self) -> dict:
