@@ -152,7 +152,10 @@ gf_status gf_get_system(gf_mesh* m, int32_t* bi_out, int32_t* bj_out, double* va
                         double* rhs_out);
 
 /* Checkpoint: the step is Markov in (displacement, velocity, damage, plastic
- * state, step index).  gf_get_state with buf == NULL reports the size. */
+ * state, step index).  gf_get_state with buf == NULL reports the size.
+ * gf_set_state also clears the solver history (the network's cached outputs,
+ * the learned back-off and attempt cap, the launch chunk predictions), so a
+ * restored state is solved as from a fresh mesh. */
 gf_status gf_get_state(const gf_mesh* m, void* buf, size_t* bytes);
 gf_status gf_set_state(gf_mesh* m, const void* buf, size_t bytes);
 
@@ -205,11 +208,16 @@ gf_status gf_set_precond_net(gf_mesh* m, gf_net* net);
 gf_status gf_set_precond(gf_mesh* m, int32_t precond);
 /* One training step on the system of the mesh's next timestep at its current
  * state (assembled, not solved, not committed).  Loss: Kaporin's condition
- * number of G A G^T estimated with a +-1 probe v (drawn from a counter-based
- * generator seeded by the network's seed and step count),
- *   loss = log(v^T G A G^T v / N) - (2/N) log det G,   N = 3 n_nodes,
+ * number of X = G A G^T estimated with a +-1 probe v (drawn from a
+ * counter-based generator seeded by the network's seed and step count),
+ *   loss = log(v^T X v / N) - (2/N) log det G,   N = 3 n_nodes,
  * which is log K / N up to the constant log det A / N; gradient by the
- * network's backward pass, one Adam step (lr).  loss_out may be NULL. */
+ * network's backward pass, one Adam step (lr).  loss_out may be NULL.
+ * With k power steps (gf_net_set_power_steps) the probe is first replaced by
+ * X^k v rescaled to |v|^2 = N, so the first term is the Rayleigh quotient of
+ * X^k v: k = 0 weighs the spectrum by its mean (Kaporin), large k by its
+ * largest eigenvalue.  The gradient treats the power-stepped probe as fixed. */
+gf_status gf_net_set_power_steps(gf_net* net, int32_t k); /* 0 <= k <= 64; default 0 */
 gf_status gf_net_train_step(gf_net* net, gf_mesh* m, double lr, double* loss_out);
 /* Same system, no update.  probe: n_nodes*3 doubles in caller order (NULL: the
  * generator's next probe).  Outputs (each may be NULL): the loss; the diagonal

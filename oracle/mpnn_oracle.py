@@ -41,6 +41,14 @@ all G with this block pattern is the classical factorised sparse approximate
 inverse (Kolotilina-Yeremin), so the network learns an approximation of that
 preconditioner from local features.  The backward pass is written out by
 hand; tests pin it to finite differences.
+
+Power-weighted variant: the probe is first replaced by X^k v (X = G A G^T),
+rescaled to |v|^2 = N, so that the first term is the Rayleigh quotient of
+X^k v.  Over the eigen-decomposition of X it weighs eigenvalue lambda by
+lambda^(2k) times the probe's component: k = 0 is the mean (Kaporin), and as
+k grows it tends to the largest eigenvalue, the end of the spectrum that
+conjugate gradients pays for and the mean hardly sees.  The gradient holds
+the stepped probe fixed (loss_and_grad with that probe).
 """
 from __future__ import annotations
 
@@ -256,6 +264,25 @@ def apply(fac: Factor, Gd: np.ndarray, Gl: np.ndarray, r: np.ndarray) -> np.ndar
     z = np.einsum("nji,nj->ni", Gd, y)
     np.add.at(z, fac.cols, np.einsum("bji,bj->bi", Gl, y[fac.rows]))
     return z
+
+
+def power_probe(fac: Factor, Gd: np.ndarray, Gl: np.ndarray, A: sp.csr_matrix, v: np.ndarray, k: int) -> np.ndarray:
+    """The probe after k power steps on X = G A G^T: v <- X v, rescaled to
+    |v|^2 = N (N = 3n) after every step.  k = 0 returns v."""
+    G = G_matrix(fac, Gd, Gl)
+    N = 3 * fac.n
+    x = np.array(v, dtype=float).ravel()
+    for _ in range(k):
+        y = G @ (A @ (G.T @ x))
+        x = y * np.sqrt(N / (y @ y))
+    return x.reshape(-1, 3)
+
+
+def loss_and_grad_power(w: np.ndarray, a: np.ndarray, P, PT, fac: Factor, A: sp.csr_matrix, v: np.ndarray, k: int):
+    """Power-weighted loss: loss_and_grad with the probe after k power steps
+    on this network's X (held fixed in the gradient)."""
+    Gd, Gl, _ = factor_blocks(forward(w, a, P)["o"], w, fac)
+    return loss_and_grad(w, a, P, PT, fac, A, power_probe(fac, Gd, Gl, A, v, k))
 
 
 def loss_and_grad(w: np.ndarray, a: np.ndarray, P, PT, fac: Factor, A: sp.csr_matrix, v: np.ndarray):

@@ -95,6 +95,7 @@ struct gf_net {
   std::vector<float> host;  // master weights (host copy, kept in sync)
   int adam_t = 0;
   uint64_t seed = 0;
+  int power_steps = 0;  // power steps on X = G A G^T applied to the training probe
 };
 
 struct gf_mesh {
@@ -241,6 +242,7 @@ struct gf_mesh {
 namespace {
 
 using gfem::kMaxPart;
+constexpr int kMaxPowerSteps = 64;
 
 // Upload host vector to a fresh device buffer.
 template <typename P>
@@ -1082,6 +1084,14 @@ gf_status gf_set_state(gf_mesh* m, const void* buf, size_t bytes) {
       }
     }
     m->step_index = h.step;
+    // a restored state starts a fresh solver history: the network runs on the
+    // next learned step, and the learned back-off, attempt cap and launch
+    // chunk predictions are cleared
+    m->net_cached = false;
+    m->last_learned_iters = 0;
+    m->learned_skip = 0;
+    m->learned_backoff = 4;
+    std::memset(m->last_solve_iters, 0, sizeof m->last_solve_iters);
     return GF_OK;
   })
 }
@@ -1266,6 +1276,19 @@ static gf_status net_train_eval(gf_net* net, gf_mesh* m, bool train, double lr, 
     } else {
       gfem::net_probe(s, w, net->seed * 0x9E3779B97F4A7C15ull + (uint64_t)net->adam_t + 1);
     }
+    // power-weighted probe: v <- X v rescaled to |v|^2 = N, X = G A G^T, so
+    // that t / N below is the Rayleigh quotient of X^k v
+    const double Nd = 3.0 * m->n;
+    for (int k = 0; k < net->power_steps; ++k) {
+      gfem::net_kaporin_u(s, w, in, m->Gb);
+      gfem::launch_resid<float>(s, m->Gs, m->mat(), w.zero, w.u, w.wneg, m->part_a);
+      const int G = gfem::net_power_apply(s, w, in, m->Gb);
+      m->check_launch();
+      const double yy = read_partials(m, w.dpart, G);
+      if (!(yy > 0.0) || !std::isfinite(yy))
+        return fail(GF_ESTATE, std::string(who) + ": power step of the probe is not positive and finite");
+      gfem::net_scale_probe(s, w, std::sqrt(Nd / yy));
+    }
     gfem::net_kaporin_u(s, w, in, m->Gb);
     gfem::launch_resid<float>(s, m->Gs, m->mat(), w.zero, w.u, w.wneg, m->part_a);
     const int G = gfem::net_kaporin_dots(s, net->P, w, in);
@@ -1320,6 +1343,13 @@ static gf_status net_train_eval(gf_net* net, gf_mesh* m, bool train, double lr, 
     m->net_cached = false;
     return GF_OK;
   })
+}
+
+gf_status gf_net_set_power_steps(gf_net* net, int32_t k) {
+  if (!net) return fail(GF_EINVAL, "gf_net_set_power_steps: null network");
+  if (k < 0 || k > kMaxPowerSteps) return fail(GF_EINVAL, "gf_net_set_power_steps: k outside [0, 64]");
+  net->power_steps = k;
+  return GF_OK;
 }
 
 gf_status gf_net_train_step(gf_net* net, gf_mesh* m, double lr, double* loss_out) {

@@ -484,6 +484,57 @@ __global__ __launch_bounds__(256) void k_kap_node(NetInputs in, const float* __r
   }
 }
 
+// One power step on X = G A G^T: y = G x with x = -wneg (the caller's residual
+// kernel leaves -A G^T v there), FP32 factor, FP64 accumulation
+// (kBuildLanes lanes per row), and per-workgroup partials of |y|^2.
+__global__ __launch_bounds__(256) void k_kap_gx(NetInputs in, const float* __restrict__ gl,
+                                                const float* __restrict__ gd, const d4* __restrict__ wneg,
+                                                d4* __restrict__ y, double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int n = in.n, ne = in.ne;
+  const int lane = threadIdx.x & (kBuildLanes - 1);
+  double acc = 0.0;
+  for (int i = blockIdx.x * (256 / kBuildLanes) + threadIdx.x / kBuildLanes; i < n;
+       i += gridDim.x * (256 / kBuildLanes)) {
+    double ax = 0, ay = 0, az = 0;
+    for (int b = in.lptr[i] + lane; b < in.lptr[i + 1]; b += kBuildLanes) {
+      const d4 xj = wneg[in.lcol[b]];
+      float a[9];
+      load_blk9(gl, ne, b, a);
+      ax -= a[0] * xj.x + a[1] * xj.y + a[2] * xj.z;
+      ay -= a[3] * xj.x + a[4] * xj.y + a[5] * xj.z;
+      az -= a[6] * xj.x + a[7] * xj.y + a[8] * xj.z;
+    }
+#pragma unroll
+    for (int s = kBuildLanes / 2; s > 0; s >>= 1) {
+      ax += __shfl_xor(ax, s, kBuildLanes);
+      ay += __shfl_xor(ay, s, kBuildLanes);
+      az += __shfl_xor(az, s, kBuildLanes);
+    }
+    if (lane == 0) {
+      const d4 xi = wneg[i];
+      const double g00 = gd[i], g10 = gd[(size_t)n + i], g11 = gd[2 * (size_t)n + i];
+      const double g20 = gd[3 * (size_t)n + i], g21 = gd[4 * (size_t)n + i], g22 = gd[5 * (size_t)n + i];
+      ax -= g00 * xi.x;
+      ay -= g10 * xi.x + g11 * xi.y;
+      az -= g20 * xi.x + g21 * xi.y + g22 * xi.z;
+      y[i] = d4{ax, ay, az, 0.0};
+      acc += ax * ax + ay * ay + az * az;
+    }
+  }
+  acc = wsum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ __launch_bounds__(256) void k_scale_d4(int n, double f, d4* __restrict__ v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const d4 a = v[i];
+  v[i] = d4{a.x * f, a.y * f, a.z * f, 0.0};
+}
+
 __device__ __forceinline__ float wsumf(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -824,6 +875,13 @@ void net_probe(hipStream_t s, NetWork& w, uint64_t seed) { k_net_probe_gen<<<nb2
 void net_kaporin_u(hipStream_t s, NetWork& w, const NetInputs& in, int Gb) {
   k_kap_u<<<Gb, 256, 0, s>>>(in, w.gu32, w.gd32, w.probe, w.u);
 }
+
+int net_power_apply(hipStream_t s, NetWork& w, const NetInputs& in, int Gb) {
+  k_kap_gx<<<Gb, 256, 0, s>>>(in, w.gl32, w.gd32, w.wneg, w.probe, w.dpart);
+  return Gb;
+}
+
+void net_scale_probe(hipStream_t s, NetWork& w, double f) { k_scale_d4<<<nb256(w.n), 256, 0, s>>>(w.n, f, w.probe); }
 
 int net_kaporin_dots(hipStream_t s, const NetParamsDev&, NetWork& w, const NetInputs& in) {
   k_kap_node<<<nb256(in.n), 256, 0, s>>>(in, w.o, w.probe, w.u, w.wneg, w.mv, w.sv, w.dpart);

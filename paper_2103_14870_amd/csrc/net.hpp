@@ -121,6 +121,11 @@ void net_probe(hipStream_t s, NetWork& w, uint64_t seed);
 // factor: u = G^T v (needs -A u in w.wneg afterwards, from the caller's
 // residual kernel).
 void net_kaporin_u(hipStream_t s, NetWork& w, const NetInputs& in, int Gb);
+// After net_kaporin_u and w.wneg = -A u: w.probe = G A G^T v (one power step
+// on X) and partials of |w.probe|^2 in dpart[0..G); returns G (<= kMaxPart).
+int net_power_apply(hipStream_t s, NetWork& w, const NetInputs& in, int Gb);
+// w.probe *= f.
+void net_scale_probe(hipStream_t s, NetWork& w, double f);
 // After w.wneg = -A u: partials of t = u.A u in dpart[0..G) and of log det G
 // in dpart[kMaxPart..kMaxPart+G); returns G.
 int net_kaporin_dots(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in);

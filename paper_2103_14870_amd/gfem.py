@@ -81,6 +81,7 @@ _SIGS = {
     "gf_set_precond_net": ([C.c_void_p, C.c_void_p], C.c_int),
     "gf_set_precond": ([C.c_void_p, C.c_int32], C.c_int),
     "gf_net_train_step": ([C.c_void_p, C.c_void_p, C.c_double, _P(C.c_double)], C.c_int),
+    "gf_net_set_power_steps": ([C.c_void_p, C.c_int32], C.c_int),
     "gf_net_eval": ([C.c_void_p, C.c_void_p, _P(C.c_double), _P(C.c_double), _P(C.c_float), _P(C.c_float),
                      _P(C.c_float)], C.c_int),
 }
@@ -294,6 +295,10 @@ class Net:
         if w.size != self.n_params:
             raise ValueError("wrong number of weights")
         _check(self._lib.gf_net_set_weights(self._h, w.ctypes.data_as(_P(C.c_float))))
+
+    def set_power_steps(self, k: int):
+        """Power steps on G A G^T applied to the training probe (0: Kaporin)."""
+        _check(self._lib.gf_net_set_power_steps(self._h, int(k)))
 
     def train_step(self, mesh: "Mesh", lr: float) -> float:
         loss = C.c_double()

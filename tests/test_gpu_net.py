@@ -84,6 +84,32 @@ def test_factor_loss_and_gradient_match_oracle(seed):
     net.close()
 
 
+@pytest.mark.parametrize("k", [1, 4])
+def test_power_weighted_loss_and_gradient_match_oracle(k):
+    # the probe after k power steps on G A G^T (GPU: FP32 factor, FP64 vectors)
+    say(f"case net power-weighted parity k={k}")
+    prob, U, V = seeded_state(4)
+    w = N.init_weights(14, head_scale=0.3).astype(np.float32)
+    w[N.offset("be"):N.offset("be") + 9] += (0.5 * np.eye(3)).ravel().astype(np.float32)
+    probe = np.random.default_rng(24).choice([-1.0, 1.0], size=prob.X.shape)
+    net = gfem.Net(seed=0)
+    net.set_weights(w)
+    net.set_power_steps(k)
+    with gfem.mesh_from_problem(prob) as m:
+        gfem.set_displacement(m, U, V)
+        loss_g, _, _, grad_g = net.eval(m, probe)
+    a, P, PT, fac, sysm = oracle_system(prob, U, V)
+    loss_o, grad_o, _ = N.loss_and_grad_power(w.astype(np.float64), a, P, PT, fac, sysm.A, probe, k)
+    loss_0, _, _ = N.loss_and_grad(w.astype(np.float64), a, P, PT, fac, sysm.A, probe)
+    eloss = abs(loss_g - loss_o) / max(1.0, abs(loss_o))
+    cos = float(grad_g @ grad_o / (np.linalg.norm(grad_g) * np.linalg.norm(grad_o)))
+    eg = rel(grad_g, grad_o)
+    say(f"  loss {loss_g:.6f} vs {loss_o:.6f} (k=0: {loss_0:.6f}) grad cos {cos:.5f} rel {eg:.2e}")
+    assert loss_o > loss_0  # the power steps raise the Rayleigh quotient
+    assert eloss <= 2e-2 and cos >= 0.999 and eg <= 3e-2
+    net.close()
+
+
 def test_zero_network_factor_is_block_jacobi():
     say("case net zero network = block Jacobi factor")
     prob, U, V = seeded_state(3)

@@ -155,3 +155,39 @@ def test_damped_factor_reduces_cg_iterations():
     _, it_j, _, ok_j = O.pcg(sysm.A, sysm.b, O.block_jacobi(sysm.A), 1e-6, 5000)
     assert ok_f and ok_j
     assert it_f < 0.7 * it_j, (it_f, it_j)
+
+
+def test_power_probe_is_the_normalised_matrix_power():
+    # k power steps equal the dense X^k v, X = G A G^T, scaled to |v|^2 = N
+    a, P, PT, fac, A, b, _ = small_system(7)
+    w = N.init_weights(8, head_scale=0.2)
+    Gd, Gl, _ = N.factor_blocks(N.forward(w, a, P)["o"], w, fac)
+    G = N.G_matrix(fac, Gd, Gl).toarray()
+    X = G @ A.toarray() @ G.T
+    v = np.random.default_rng(9).choice([-1.0, 1.0], size=(fac.n, 3))
+    for k in (0, 1, 3):
+        ref = np.linalg.matrix_power(X, k) @ v.ravel()
+        ref *= np.sqrt(3 * fac.n / (ref @ ref))
+        np.testing.assert_allclose(N.power_probe(fac, Gd, Gl, A, v, k).ravel(), ref, rtol=1e-10, atol=1e-12)
+
+
+def test_power_loss_rises_to_the_largest_eigenvalue():
+    # loss + (2/N) log det G = log of the Rayleigh quotient of X^k v: it never
+    # decreases with k, never exceeds log lambda_max(X), and reaches it
+    a, P, PT, fac, A, b, _ = small_system(8)
+    w = N.init_weights(10, head_scale=0.2)
+    Gd, Gl, _ = N.factor_blocks(N.forward(w, a, P)["o"], w, fac)
+    G = N.G_matrix(fac, Gd, Gl).toarray()
+    lmax = np.linalg.eigvalsh(G @ A.toarray() @ G.T).max()
+    Nn = 3 * fac.n
+    ld = np.sum(np.log(np.abs(np.linalg.det(Gd))))
+    v = np.random.default_rng(11).choice([-1.0, 1.0], size=(fac.n, 3))
+    rq = []
+    for k in (0, 1, 2, 4, 8, 16, 64, 400):
+        loss, _, _ = N.loss_and_grad_power(w, a, P, PT, fac, A, v, k)
+        rq.append(loss + 2.0 / Nn * ld)
+    assert np.all(np.diff(rq) >= -1e-12)
+    assert rq[-1] <= np.log(lmax) + 1e-12
+    assert rq[-1] == pytest.approx(np.log(lmax), abs=1e-6)
+    # k = 0 is the plain Kaporin probe loss
+    assert N.loss_and_grad_power(w, a, P, PT, fac, A, v, 0)[0] == N.loss_and_grad(w, a, P, PT, fac, A, v)[0]
