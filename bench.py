@@ -13,7 +13,7 @@ integration.  All inputs are resident in HBM before timing.
 paper_2103_14870_amd/weights); the same K steps from the same start state
 are timed again with block-Jacobi PCG and reported beside it.  Prints one
 JSON line.  Extra legs: the dominant kernel's roofline (SpMV, HIP events on
-the library's stream) and the FP64 CPU oracle timed on a one-step sample of
+the library's stream) and the FP64 CPU oracle timed on a two-step sample of
 the same workload.
 """
 from __future__ import annotations
@@ -51,8 +51,70 @@ def measured_traffic():
         return None
 
 
+def kernel_short_name(name):
+    import re
+
+    m = re.search(r"(k_[a-z0-9_]+)(<[^>(]*>)?", name)
+    return (m.group(1) + (m.group(2) or "")) if m else name.split("(")[0][-60:]
+
+
+def write_counter_summary(fetch_csv, write_csv, calib_mb, command_f, command_w):
+    """Per-kernel HBM traffic from two rocprofv3 counter runs of
+    `bench.py --calib-copy-mb calib_mb` (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch), each scaled by what the same counter reads for the cache-cold
+    calibration sum (reads calib_mb MiB) and copy (writes calib_mb MiB) that
+    the bench runs first.  Writes the summary that measured_traffic() reads."""
+    import collections
+    import csv
+    import hashlib
+
+    def per_kernel(path, counter):
+        agg = collections.defaultdict(list)
+        full = []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                v = float(r["Counter_Value"])
+                agg[kernel_short_name(r["Kernel_Name"])].append(v)
+                full.append((r["Kernel_Name"], v))
+        return agg, full
+
+    fetch, ffull = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, wfull = per_kernel(write_csv, "WRITE_SIZE")
+    calib_kib = calib_mb * 1024.0
+    red = max(v for n, v in ffull if "reduce_kernel" in n)
+    cpy = max(v for n, v in wfull if "copyBuffer" in n)
+    fr, fw = calib_kib / red, calib_kib / cpy
+    mean = lambda xs: sum(xs) / len(xs) if xs else 0.0
+    spmv = next(k for k in fetch if k.startswith("k_pcg_spmv_p<"))
+    spmv_bytes = (mean(fetch[spmv]) * fr + mean(write[spmv]) * fw) * 1024.0
+    digest = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+    lines = [
+        "# HBM traffic per dispatch from rocprofv3 counters: 619,830-tet ellipsoid bench (learned leg, kernel",
+        "# timing leg and block-Jacobi leg), one MI355X.  Commands (repository root):",
+        f"#   {command_f}",
+        f"#   {command_w}",
+        f"#   python bench.py --counter-summary <fetch counter_collection.csv> <write counter_collection.csv> "
+        f"--calib-copy-mb {calib_mb}",
+        f"# calibration: the {calib_mb} MiB cache-cold sum reads FETCH_SIZE {red:.0f} KiB (x{fr:.3f}); "
+        f"the {calib_mb} MiB copy reads WRITE_SIZE {cpy:.0f} KiB (x{fw:.3f})",
+        "# table: dispatches, mean FETCH_SIZE KiB, mean WRITE_SIZE KiB, calibrated MB per dispatch",
+        f"kernels_hip_sha256 {digest}",
+        f"calib_read_factor {fr:.4f}",
+        f"calib_write_factor {fw:.4f}",
+        f"spmv_hbm_bytes_per_launch {spmv_bytes:.0f}",
+    ]
+    names = sorted(set(fetch) | set(write), key=lambda k: -sum(fetch.get(k, [0.0])))
+    for k in names:
+        if not k.startswith("k_"):
+            continue
+        f_, w_ = mean(fetch.get(k, [])), mean(write.get(k, []))
+        lines.append(f"#  {len(fetch.get(k, [])):6d} {f_:12.1f} {w_:12.1f} {(f_ * fr + w_ * fw) * 1024 / 1e6:10.2f}  {k}")
+    open(COUNTERS, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def cpu_baseline(prob, n_threads=1):
-    """FP64 oracle, one step of the same workload from rest, on host cores."""
+    """FP64 oracle, the first two steps of the same workload from rest, on host cores."""
     from threadpoolctl import threadpool_limits
 
     from oracle import gfem_oracle as O
@@ -62,11 +124,14 @@ def cpu_baseline(prob, n_threads=1):
         st = O.initial_state(mesh)
         O.break_pairs(mesh, st, prob.broken_pairs)
         t0 = time.perf_counter()
-        st, h = O.step(mesh, st, prob.dir_nodes, prob.dir_vel)
+        iters = []
+        for _ in range(2):
+            st, h = O.step(mesh, st, prob.dir_nodes, prob.dir_vel)
+            iters.append(h["iters"])
         dt = time.perf_counter() - t0
-    return dict(value=1.0 / dt, unit="timesteps/s", cores=n_threads, kind="oracle",
-                sample=f"1 step from rest of the same {prob.n_tets}-tet workload "
-                       f"(FP64 NumPy/SciPy oracle, {h['iters']} PCG iterations, {dt:.1f} s)")
+    return dict(value=2.0 / dt, unit="timesteps/s", cores=n_threads, kind="oracle",
+                sample=f"first 2 steps from rest of the same {prob.n_tets}-tet workload "
+                       f"(FP64 NumPy/SciPy oracle, block-Jacobi PCG, {iters} iterations, {dt:.1f} s)")
 
 
 def timed_steps(m, steps, warmup):
@@ -121,7 +186,16 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the legs, one device-to-device copy of this many MiB from a cache-cold "
                          "source (calibrates the HBM byte counters)")
+    ap.add_argument("--counter-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM counter summary from two rocprofv3 --pmc runs and exit (no GPU)")
     args = ap.parse_args()
+    if args.counter_summary:
+        cmd = ("timeout -s KILL 240 rocprofv3 --pmc {} --output-format csv -d gpurun_out/pmc{} -o run -- "
+               "python bench.py --steps 10 --warmup 5 --no-cpu-baseline --calib-copy-mb {}")
+        write_counter_summary(*args.counter_summary, args.calib_copy_mb or 512,
+                              cmd.format("FETCH_SIZE", "F", args.calib_copy_mb or 512),
+                              cmd.format("WRITE_SIZE", "W", args.calib_copy_mb or 512))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)
@@ -162,9 +236,12 @@ def main():
             gfem.attach_net(m, net)
         return m
 
+    log = lambda msg: print(f"bench: {msg}", file=sys.stderr, flush=True)
+    log(f"timed leg ({args.precond})")
     m = make_mesh(net is not None)
     main_leg = timed_steps(m, args.steps, args.warmup)
     m.close()
+    log("kernel timing leg")
     m = make_mesh(net is not None)
     kus, kn = kernel_times(m, args.steps, args.warmup)
     n_edges, n_blocks = m.n_edges, m.n_blocks
@@ -181,6 +258,7 @@ def main():
     m.close()
     jac = None
     if net is not None:
+        log("block-Jacobi leg")
         mj = make_mesh(False)
         jac = timed_steps(mj, args.steps, args.warmup)
         mj.close()
@@ -222,6 +300,7 @@ def main():
                                "ms_per_step": 1000.0 * jac["elapsed"] / args.steps}
         out["speedup_vs_block_jacobi"] = main_leg["value"] / jac["value"]
     if not args.no_cpu_baseline:
+        log("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(prob)
         out["cpu_baseline"]["host_cpus"] = os.cpu_count()
     print(json.dumps(out), flush=True)
