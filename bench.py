@@ -190,7 +190,7 @@ def main():
                     help="write the HBM counter summary from two rocprofv3 --pmc runs and exit (no GPU)")
     args = ap.parse_args()
     if args.counter_summary:
-        cmd = ("timeout -s KILL 240 rocprofv3 --pmc {} --output-format csv -d gpurun_out/pmc{} -o run -- "
+        cmd = ("timeout -s KILL 280 rocprofv3 --pmc {} --output-format csv -d gpurun_out/pmc{} -o run -- "
                "python bench.py --steps 10 --warmup 5 --no-cpu-baseline --calib-copy-mb {}")
         write_counter_summary(*args.counter_summary, args.calib_copy_mb or 512,
                               cmd.format("FETCH_SIZE", "F", args.calib_copy_mb or 512),
