@@ -32,13 +32,13 @@ COUNTERS = os.path.join(ROOT, "profiles", "pcg_ellipsoid620k_hbm_counters.txt")
 KERNELS_SRC = os.path.join(ROOT, "paper_2103_14870_amd", "csrc", "kernels.hip")
 
 
-def measured_traffic():
+def measured_traffic(path=COUNTERS):
     """HBM bytes per SpMV launch from the committed rocprofv3 counter summary,
     or None when the kernel source changed since the counters were taken."""
     import hashlib
 
     try:
-        lines = open(COUNTERS).read().splitlines()
+        lines = open(path).read().splitlines()
     except OSError:
         return None
     kv = dict(ln.split(None, 1) for ln in lines if ln and not ln.startswith("#") and len(ln.split(None, 1)) == 2)
@@ -58,7 +58,7 @@ def kernel_short_name(name):
     return (m.group(1) + (m.group(2) or "")) if m else name.split("(")[0][-60:]
 
 
-def write_counter_summary(fetch_csv, write_csv, calib_mb, command_f, command_w):
+def write_counter_summary(fetch_csv, write_csv, calib_mb, command_f, command_w, out_path=COUNTERS):
     """Per-kernel HBM traffic from two rocprofv3 counter runs of
     `bench.py --calib-copy-mb calib_mb` (FETCH_SIZE, then WRITE_SIZE, KiB per
     dispatch), each scaled by what the same counter reads for the cache-cold
@@ -109,7 +109,7 @@ def write_counter_summary(fetch_csv, write_csv, calib_mb, command_f, command_w):
             continue
         f_, w_ = mean(fetch.get(k, [])), mean(write.get(k, []))
         lines.append(f"#  {len(fetch.get(k, [])):6d} {f_:12.1f} {w_:12.1f} {(f_ * fr + w_ * fw) * 1024 / 1e6:10.2f}  {k}")
-    open(COUNTERS, "w").write("\n".join(lines) + "\n")
+    open(out_path, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 

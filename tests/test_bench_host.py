@@ -1,0 +1,46 @@
+"""Host logic of bench.py (no GPU): the rocprofv3 counter summary and the
+traffic lookup that the roofline line reports."""
+import csv
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+FIELDS = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+
+
+def write_csv(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=FIELDS)
+        w.writeheader()
+        for i, (name, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": v})
+
+
+def test_counter_summary_calibrates_and_round_trips(tmp_path):
+    spmv = "void gfem::(anonymous namespace)::k_pcg_spmv_p<float, 256>(gfem::MatView, int)"
+    red = "void at::native::reduce_kernel<512, 1>(at::native::ReduceOp<float>)"
+    fetch = tmp_path / "f.csv"
+    wr = tmp_path / "w.csv"
+    # calibration: the 64 MiB sum reads FETCH 32768 KiB (factor 2); the copy writes 65536 KiB (factor 1)
+    write_csv(fetch, "FETCH_SIZE", [(red, 32768.0), (spmv, 30000.0), (spmv, 32000.0), ("__amd_rocclr_copyBuffer", 10.0)])
+    write_csv(wr, "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 65536.0), (spmv, 1000.0), (spmv, 3000.0)])
+    out = tmp_path / "counters.txt"
+    bench.write_counter_summary(str(fetch), str(wr), 64, "cmd F", "cmd W", out_path=str(out))
+    text = out.read_text()
+    assert "calib_read_factor 2.0000" in text and "calib_write_factor 1.0000" in text
+    expect = (2.0 * 31000.0 + 1.0 * 2000.0) * 1024.0
+    assert bench.measured_traffic(str(out)) == pytest.approx(expect)
+    assert "k_pcg_spmv_p<float, 256>" in text
+    # a summary taken from other kernel sources is not reported
+    out.write_text(text.replace(text.split("kernels_hip_sha256 ")[1].split()[0], "0" * 64))
+    assert bench.measured_traffic(str(out)) is None
+
+
+def test_kernel_short_name():
+    assert bench.kernel_short_name("void gfem::(anonymous namespace)::k_pcg_gpass<float, false, 256>(int, a)") == \
+        "k_pcg_gpass<float, false, 256>"
+    assert bench.kernel_short_name("void gfem::k_damage(int, int const*)") == "k_damage"

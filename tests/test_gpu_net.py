@@ -191,6 +191,36 @@ def test_learned_trajectory_matches_block_jacobi():
     net.close()
 
 
+def test_restored_state_is_solved_as_on_a_fresh_mesh():
+    # a checkpoint restored on a mesh that has run learned steps (cached network
+    # outputs, iteration history) gives bitwise the steps of a fresh mesh
+    # restored from the same checkpoint
+    import os
+
+    say("case learned checkpoint restore vs fresh mesh")
+    prob = meshgen.notched_beam(16, 4, 4, h=0.01, notch_cells=1, crack_fraction=0.1)
+    prob.params["net_every_n_steps"] = 4
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    net = gfem.Net(seed=1)
+    net.set_weights(np.load(os.path.join(root, "paper_2103_14870_amd", "weights", "precond_net.npy")))
+    with gfem.mesh_from_problem(prob) as m1, gfem.mesh_from_problem(prob) as m2:
+        gfem.attach_net(m1, net)
+        gfem.attach_net(m2, net)
+        m1.step(3)
+        st = m1.get_state()
+        m1.step(3)
+        m1.set_state(st)
+        a = [m1.step(1)["inner_iters"] for _ in range(3)]
+        xa = m1.positions()
+        m2.set_state(st)
+        b = [m2.step(1)["inner_iters"] for _ in range(3)]
+        xb = m2.positions()
+    say(f"  iterations restored {a} fresh {b}")
+    assert a == b
+    assert np.array_equal(xa, xb)
+    net.close()
+
+
 def test_random_network_solve_meets_tolerance():
     say("case random learned solve")
     prob = meshgen.notched_beam(16, 4, 4, h=0.01, notch_cells=1)
