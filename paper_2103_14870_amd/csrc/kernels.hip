@@ -781,11 +781,11 @@ __global__ __launch_bounds__(NT) void k_pcg_init(int n, const d4* __restrict__ s
 // stop when |r_k|^2 <= rel2 |r_0|^2 (threshold fixed by the k = 0 launch);
 // else p_k = z_k + beta_k p_{k-1} (k > 0; for k = 0 p_new already holds
 // p_0 = z_0 and is only read), q = A p_k and the partial p_k.q.
-// kRowLanes lanes share a block row, two rows in flight per lane group; each
-// neighbour's p_k entry is formed on the fly with the same fused operation as
-// its owner uses, so all copies agree bitwise.  The first row pair's loads
-// (row bounds, column, block, gathered z and p_{k-1}) are issued before the
-// scalar reduction so the two memory latencies overlap.
+// kSpmvLanes lanes share a block row, each with its first two blocks in
+// flight; each neighbour's p_k entry is formed on the fly with the same fused
+// operation as its owner uses, so all copies agree bitwise.  The first row's
+// loads (row bounds, columns, blocks, gathered z and p_{k-1}) are issued before
+// the scalar reduction so the two memory latencies overlap.
 template <typename T, bool DIR>
 struct SpmvSlot {
   bool on;
@@ -825,23 +825,20 @@ __global__ __launch_bounds__(NT) void k_pcg_spmv(int k, int Ga, MatView Am, cons
   const int L = xcd_logical(blockIdx.x, G);
   const int chunk = (n + G - 1) / G;
   const int r0 = min(n, L * chunk), r1 = min(n, r0 + chunk);
-  const int lane = threadIdx.x & (kRowLanes - 1);
-  const int grp = threadIdx.x / kRowLanes;
-  constexpr int NG = NT / kRowLanes;
+  constexpr int LN = kSpmvLanes;
+  const int lane = threadIdx.x & (LN - 1);
+  const int grp = threadIdx.x / LN;
+  constexpr int NG = NT / LN;
   const T* __restrict__ val = static_cast<const T*>(Am.val);
-  // peeled first pair: bounds and first slot of each row
+  // peeled first row: bounds and first two slots
   int ra = r0 + grp;
-  int sa = 0, ea = 0, sb = 0, eb = 0;
+  int sa = 0, cnt = 0;
   if (ra < r1) {
     sa = Am.row_ptr[ra];
-    ea = Am.row_ptr[ra + 1];
-    if (ra + NG < r1) {
-      sb = Am.row_ptr[ra + NG];
-      eb = Am.row_ptr[ra + NG + 1];
-    }
+    cnt = Am.row_ptr[ra + 1] - sa;
   }
-  SpmvSlot<T, DIR> fa = spmv_load<T, DIR>(Am, val, sa + lane, lane < ea - sa, z, p_old, p_new);
-  SpmvSlot<T, DIR> fb = spmv_load<T, DIR>(Am, val, sb + lane, lane < eb - sb, z, p_old, p_new);
+  SpmvSlot<T, DIR> fa = spmv_load<T, DIR>(Am, val, sa + lane, lane < cnt, z, p_old, p_new);
+  SpmvSlot<T, DIR> fb = spmv_load<T, DIR>(Am, val, sa + lane + LN, lane + LN < cnt, z, p_old, p_new);
 
   const double* cur = part_rz + (size_t)(k & 1) * 2 * kMaxPart;
   const double* prv = part_rz + (size_t)((k + 1) & 1) * 2 * kMaxPart;
@@ -866,49 +863,32 @@ __global__ __launch_bounds__(NT) void k_pcg_spmv(int k, int Ga, MatView Am, cons
   const T beta = DIR ? (T)(rz / rzp) : T(0);
   double dot = 0;
   bool first = true;
-  for (; ra < r1; ra += 2 * NG) {
-    const int rb = ra + NG;
-    const bool hb = rb < r1;
+  for (; ra < r1; ra += NG) {
     if (!first) {
       sa = Am.row_ptr[ra];
-      ea = Am.row_ptr[ra + 1];
-      sb = hb ? Am.row_ptr[rb] : 0;
-      eb = hb ? Am.row_ptr[rb + 1] : 0;
-      fa = spmv_load<T, DIR>(Am, val, sa + lane, lane < ea - sa, z, p_old, p_new);
-      fb = spmv_load<T, DIR>(Am, val, sb + lane, lane < eb - sb, z, p_old, p_new);
+      cnt = Am.row_ptr[ra + 1] - sa;
+      fa = spmv_load<T, DIR>(Am, val, sa + lane, lane < cnt, z, p_old, p_new);
+      fb = spmv_load<T, DIR>(Am, val, sa + lane + LN, lane + LN < cnt, z, p_old, p_new);
     }
     first = false;
-    T ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
+    T ax = 0, ay = 0, az = 0;
     if (fa.on) blk_fma(fa.k, DIR ? dir_comb(fa.z, beta, fa.p) : fa.p, ax, ay, az);
-    if (fb.on) blk_fma(fb.k, DIR ? dir_comb(fb.z, beta, fb.p) : fb.p, bx, by, bz);
-    // rows longer than kRowLanes blocks
-    const int len = max(ea - sa, eb - sb);
-    for (int o = lane + kRowLanes; o < len; o += kRowLanes) {
-      const SpmvSlot<T, DIR> ta = spmv_load<T, DIR>(Am, val, sa + o, o < ea - sa, z, p_old, p_new);
-      const SpmvSlot<T, DIR> tb = spmv_load<T, DIR>(Am, val, sb + o, o < eb - sb, z, p_old, p_new);
-      if (ta.on) blk_fma(ta.k, DIR ? dir_comb(ta.z, beta, ta.p) : ta.p, ax, ay, az);
-      if (tb.on) blk_fma(tb.k, DIR ? dir_comb(tb.z, beta, tb.p) : tb.p, bx, by, bz);
+    if (fb.on) blk_fma(fb.k, DIR ? dir_comb(fb.z, beta, fb.p) : fb.p, ax, ay, az);
+    for (int o = lane + 2 * LN; o < cnt; o += LN) {
+      const SpmvSlot<T, DIR> t = spmv_load<T, DIR>(Am, val, sa + o, true, z, p_old, p_new);
+      blk_fma(t.k, DIR ? dir_comb(t.z, beta, t.p) : t.p, ax, ay, az);
     }
 #pragma unroll
-    for (int o = kRowLanes / 2; o > 0; o >>= 1) {
-      ax += __shfl_xor(ax, o, kRowLanes);
-      ay += __shfl_xor(ay, o, kRowLanes);
-      az += __shfl_xor(az, o, kRowLanes);
-      bx += __shfl_xor(bx, o, kRowLanes);
-      by += __shfl_xor(by, o, kRowLanes);
-      bz += __shfl_xor(bz, o, kRowLanes);
+    for (int o = LN / 2; o > 0; o >>= 1) {
+      ax += __shfl_xor(ax, o, LN);
+      ay += __shfl_xor(ay, o, LN);
+      az += __shfl_xor(az, o, LN);
     }
     if (lane == 0) {
       const v4<T> pa = DIR ? dir_comb(z[ra], beta, p_old[ra]) : p_new[ra];
       if (DIR) p_new[ra] = pa;
       q[ra] = v4<T>{ax, ay, az, T(0)};
       dot += (double)pa.x * ax + (double)pa.y * ay + (double)pa.z * az;
-      if (hb) {
-        const v4<T> pb = DIR ? dir_comb(z[rb], beta, p_old[rb]) : p_new[rb];
-        if (DIR) p_new[rb] = pb;
-        q[rb] = v4<T>{bx, by, bz, T(0)};
-        dot += (double)pb.x * bx + (double)pb.y * by + (double)pb.z * bz;
-      }
     }
   }
   double u1 = 0, u2 = 0;
@@ -1268,8 +1248,9 @@ __global__ __launch_bounds__(NT) void k_pcg_gtpass(int k, FactView F, const v4<T
 }
 
 // SpMV of the factorised path: q = A p (p formed by the G^T pass), partial
-// p.q.  kRowLanes lanes per block row, one row per lane group at a time, no
-// scalar prologue; launched on its own (larger) grid.
+// p.q.  kSpmvLanes lanes per block row, each lane's first two blocks loaded
+// before any arithmetic (rows have 14.4 blocks on average), no scalar
+// prologue.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_pcg_spmv_p(MatView Am, const v4<T>* __restrict__ p, v4<T>* __restrict__ q,
                                                    PcgCtl* ctl, double* __restrict__ part_pq) {
@@ -1280,23 +1261,28 @@ __global__ __launch_bounds__(NT) void k_pcg_spmv_p(MatView Am, const v4<T>* __re
   const int L = xcd_logical(blockIdx.x, G);
   const int chunk = (n + G - 1) / G;
   const int r0 = min(n, L * chunk), r1 = min(n, r0 + chunk);
-  const int lane = threadIdx.x & (kRowLanes - 1);
-  const int grp = threadIdx.x / kRowLanes;
-  constexpr int NG = NT / kRowLanes;
+  constexpr int LN = kSpmvLanes;
+  const int lane = threadIdx.x & (LN - 1);
+  const int grp = threadIdx.x / LN;
+  constexpr int NG = NT / LN;
   const T* __restrict__ val = static_cast<const T*>(Am.val);
   double dot = 0;
   for (int ra = r0 + grp; ra < r1; ra += NG) {
-    const int sa = Am.row_ptr[ra], ea = Am.row_ptr[ra + 1];
+    const int sa = Am.row_ptr[ra], cnt = Am.row_ptr[ra + 1] - sa;
+    const SpmvSlot<T, false> ta = spmv_load<T, false>(Am, val, sa + lane, lane < cnt, nullptr, nullptr, p);
+    const SpmvSlot<T, false> tb = spmv_load<T, false>(Am, val, sa + lane + LN, lane + LN < cnt, nullptr, nullptr, p);
     T ax = 0, ay = 0, az = 0;
-    for (int o = lane; o < ea - sa; o += kRowLanes) {
+    if (ta.on) blk_fma(ta.k, ta.p, ax, ay, az);
+    if (tb.on) blk_fma(tb.k, tb.p, ax, ay, az);
+    for (int o = lane + 2 * LN; o < cnt; o += LN) {
       const SpmvSlot<T, false> t = spmv_load<T, false>(Am, val, sa + o, true, nullptr, nullptr, p);
       blk_fma(t.k, t.p, ax, ay, az);
     }
 #pragma unroll
-    for (int o = kRowLanes / 2; o > 0; o >>= 1) {
-      ax += __shfl_xor(ax, o, kRowLanes);
-      ay += __shfl_xor(ay, o, kRowLanes);
-      az += __shfl_xor(az, o, kRowLanes);
+    for (int o = LN / 2; o > 0; o >>= 1) {
+      ax += __shfl_xor(ax, o, LN);
+      ay += __shfl_xor(ay, o, LN);
+      az += __shfl_xor(az, o, LN);
     }
     if (lane == 0) {
       const v4<T> pa = p[ra];
