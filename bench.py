@@ -178,7 +178,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--dt", type=float, default=1e-2)
+    ap.add_argument("--workload", default="ellipsoid", choices=["ellipsoid", "beam"],
+                    help="ellipsoid: the 619,830-tet ductile ellipsoid (the metric's workload); beam: the "
+                         "122,880-tet notched beam in three-point bending, with --crack-fraction pre-broken edges")
+    ap.add_argument("--crack-fraction", type=float, default=0.0)
+    ap.add_argument("--dt", type=float, default=None, help="time step (default: 1e-2 ellipsoid, 1e-4 beam)")
     ap.add_argument("--precond", default="learned", choices=["learned", "block_jacobi"])
     ap.add_argument("--net-every", type=int, default=4, help="network inference every N steps (factor every step)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2103_14870_amd", "weights", "precond_net.npy"))
@@ -221,7 +225,16 @@ def main():
         torch.cuda.synchronize()
         del src, dst, evict
 
-    prob = meshgen.make_config(3, dt=args.dt)
+    if args.workload == "ellipsoid":
+        args.dt = args.dt or 1e-2
+        prob = meshgen.make_config(3, dt=args.dt)
+        workload = (f"ellipsoid {prob.n_tets} tets / {prob.n_nodes} nodes, ductile (yield 0.05, damage 0.3), "
+                    f"end caps pulled 1 cm/step, dt={args.dt:g}, PCG to 1e-6 FP64 rel. residual")
+    else:
+        args.dt = args.dt or 1e-4
+        prob = meshgen.make_config(5, crack_fraction=args.crack_fraction, dt=args.dt)
+        workload = (f"notched beam {prob.n_tets} tets / {prob.n_nodes} nodes, three-point bending, "
+                    f"{100 * args.crack_fraction:g} % pre-broken edges, dt={args.dt:g}, PCG to 1e-6 FP64 rel. residual")
     prob.params["net_every_n_steps"] = args.net_every
     stream = torch.cuda.Stream()
     net = None
@@ -277,8 +290,7 @@ def main():
         "dtype": "f32+f64 (bf16 network and factor)" if net is not None else "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": f"ellipsoid {prob.n_tets} tets / {prob.n_nodes} nodes, ductile (yield 0.05, damage 0.3), "
-                        f"end caps pulled 1 cm/step, dt={args.dt:g}, PCG to 1e-6 FP64 rel. residual",
+            "workload": workload,
             "tets": prob.n_tets, "nodes": prob.n_nodes, "edges": n_edges, "blocks": n_blocks,
             "precond": args.precond, "net_every_n_steps": args.net_every if net is not None else None,
             "dt": args.dt, "parallelism": "single GPU",
