@@ -125,11 +125,14 @@ def test_zero_network_factor_is_block_jacobi():
     net.close()
 
 
-def test_training_reduces_the_loss():
-    say("case net training on one system")
+@pytest.mark.parametrize("k", [0, 16])
+def test_training_reduces_the_loss(k):
+    # plain Kaporin (k = 0) and the power-weighted loss the shipped weights use
+    say(f"case net training on one system, {k} power steps")
     prob, U, V = seeded_state(5)
     probe = np.random.default_rng(5).choice([-1.0, 1.0], size=prob.X.shape)
     net = gfem.Net(seed=7)
+    net.set_power_steps(k)
     with gfem.mesh_from_problem(prob) as m:
         gfem.set_displacement(m, U, V)
         before = net.eval(m, probe)[0]
