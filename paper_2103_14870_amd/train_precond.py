@@ -106,7 +106,7 @@ def train(n_systems: int, seed: int, max_steps: int, lr0: float, lr1: float, log
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--systems", type=int, default=40000)
+    ap.add_argument("--systems", type=int, default=80000)
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--max-steps", type=int, default=100, help="longest episode (ellipsoids; others half)")
     ap.add_argument("--lr", type=float, default=2e-3)
