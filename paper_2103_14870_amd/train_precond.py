@@ -11,7 +11,7 @@ largest eigenvalues.  Episodes are seeded variants of the beam, cube and
 ellipsoid workloads (smaller meshes, varied jitter, damage threshold, load
 rate and pre-cracked fraction).  The shipped weights come from the defaults:
 
-    python -m paper_2103_14870_amd.train_precond --log-every 10000 \
+    python -m paper_2103_14870_amd.train_precond --log-every 20000 \
         --out paper_2103_14870_amd/weights/precond_net.npy
 """
 from __future__ import annotations
