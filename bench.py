@@ -135,22 +135,20 @@ def cpu_baseline(prob, n_threads=1):
 
 
 def timed_steps(m, steps, warmup):
+    """The K timed steps are one gf_step(K) call (one host round trip per
+    step fewer than K calls of one step); the stats are summed over them."""
     import torch
 
-    for _ in range(warmup):
-        m.step(1)
+    if warmup > 0:
+        m.step(warmup)
     torch.cuda.synchronize()
-    iters, outer, fb = [], [], 0
     t0 = time.perf_counter()
-    for _ in range(steps):
-        s = m.step(1)
-        iters.append(s["inner_iters"])
-        outer.append(s["outer_iters"])
-        fb += s["used_fallback"]
+    s = m.step(steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    return dict(value=steps / elapsed, elapsed=elapsed, iters=sum(iters) / len(iters),
-                outer=sum(outer) / len(outer), fallback=fb)
+    assert s["steps_done"] == steps
+    return dict(value=steps / elapsed, elapsed=elapsed, iters=s["inner_iters"] / steps,
+                outer=s["outer_iters"] / steps, fallback=s["used_fallback"])
 
 
 def kernel_times(m, steps, warmup):

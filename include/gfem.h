@@ -129,7 +129,10 @@ gf_status gf_set_edge_damage(gf_mesh* m, const uint8_t* zeta);
 /* Advance n_steps timesteps.  Each step is committed only when its solve
  * reaches the FP64 tolerance; otherwise the call stops, leaves positions,
  * velocities, damage and plastic state as they were before that step and
- * returns GF_ENOTCONVERGED.  stats may be NULL. */
+ * returns GF_ENOTCONVERGED.  stats may be NULL.  The last step's integration
+ * may still be running on the library's stream when the call returns; every
+ * call that reads or replaces device state waits for it, and a device fault
+ * in it is reported by the next such call. */
 gf_status gf_step(gf_mesh* m, int32_t n_steps, gf_step_stats* stats);
 
 /* Current positions (rest + displacement), n_nodes*3 doubles, caller order. */

@@ -676,7 +676,10 @@ gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
     M->zcur = 1 - M->zcur;
     if (M->plastic) M->plcur = 1 - M->plcur;
     ++M->step_index;
-    M->sync();
+    // the integration stays queued: the next step's kernels follow it on the
+    // stream, and every call that reads device state synchronises first
+    // (timing reads its events, so it waits here)
+    if (M->timing) M->sync();
     M->flush_times(st);
     if (st) st->steps_done += 1;
   }

@@ -240,6 +240,46 @@ def test_random_network_solve_meets_tolerance():
     net.close()
 
 
+def shipped_weights():
+    import os
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    return np.load(os.path.join(root, "paper_2103_14870_amd", "weights", "precond_net.npy"))
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 4])
+def test_learned_path_on_tiny_and_ragged_meshes(n):
+    # the network's GEMMs work on 64-row tiles: a single tet (4 nodes), 8 nodes,
+    # exactly one tile (64 nodes) and a ragged second tile (125 nodes); learned
+    # steps match block-Jacobi steps, and a training step stays finite
+    say(f"case learned path on {'a single tet' if n == 0 else f'{n}^3 cubes'}")
+    if n == 0:
+        X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float) * 0.1
+        prob = meshgen.Problem(name="single tet", X=X, tets=np.array([[0, 1, 3, 2]], np.int32),
+                               params=meshgen.default_params(precision="split", cg_rel_tol=1e-6),
+                               dir_nodes=np.zeros(0, np.int32), dir_vel=np.zeros((0, 3)),
+                               broken_pairs=np.zeros((0, 2), np.int32), n_steps=5)
+    else:
+        prob = meshgen.tiny_cube(n, h=0.1, jitter_frac=0.05, seed=n, top_speed=0.5, precision="split",
+                                 cg_rel_tol=1e-6)
+    V = 0.2 * np.random.default_rng(n).normal(size=prob.X.shape)
+    net = gfem.Net(seed=0)
+    net.set_weights(shipped_weights())
+    with gfem.mesh_from_problem(prob) as mj, gfem.mesh_from_problem(prob) as ml:
+        for m in (mj, ml):
+            gfem.set_displacement(m, np.zeros_like(V), V)
+        gfem.attach_net(ml, net)
+        sj = mj.step(5)
+        sl = ml.step(5)
+        d = rel(ml.positions() - prob.X, mj.positions() - prob.X)
+        loss = net.train_step(ml, 1e-4)
+    say(f"  iters block-Jacobi {sj['inner_iters']} learned {sl['inner_iters']} positions rel {d:.2e} loss {loss:.4f}")
+    assert sl["steps_done"] == 5 and sl["used_fallback"] == 0 and sl["rel_residual"] <= 1e-6
+    assert d <= 1e-5
+    assert np.isfinite(loss) and np.all(np.isfinite(net.get_weights()))
+    net.close()
+
+
 def test_factor_stays_finite_under_extreme_stretch():
     # bounded features and outputs: a random network on a wildly stretched mesh
     # still gives a finite factor and a learned solve that meets the tolerance
