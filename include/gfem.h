@@ -209,6 +209,16 @@ gf_status gf_net_set_weights(gf_net* net, const float* w); /* also resets the op
  * GF_PC_LEARNED steps, and select the preconditioner of the following steps. */
 gf_status gf_set_precond_net(gf_mesh* m, gf_net* net);
 gf_status gf_set_precond(gf_mesh* m, int32_t precond);
+/* Row normalisation of the learned factor (off by default): after each factor
+ * build every block row G_i is scaled from the left by the inverse lower
+ * Cholesky factor of its diagonal block of G A G^T, so that block becomes I;
+ * a row whose block is not positive definite in FP32 is left unscaled.  It
+ * caps the large eigenvalues that strongly anisotropic rows of heavily damaged
+ * states give G A G^T, at the cost of one more pass per step (~85 us at 620k
+ * tets: the blocks of A between every pair of a row's pattern nodes are
+ * gathered); the network's per-node scaling L_i has no effect while it is on.
+ * on: 0 or 1. */
+gf_status gf_set_precond_normalise(gf_mesh* m, int32_t on);
 /* One training step on the system of the mesh's next timestep at its current
  * state (assembled, not solved, not committed).  Loss: Kaporin's condition
  * number of X = G A G^T estimated with a +-1 probe v (drawn from a

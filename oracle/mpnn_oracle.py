@@ -56,6 +56,7 @@ from dataclasses import dataclass
 
 import numpy as np
 import scipy.sparse as sp
+from scipy.linalg import solve_triangular
 
 HIDDEN = 64
 N_IN = 8
@@ -264,6 +265,22 @@ def apply(fac: Factor, Gd: np.ndarray, Gl: np.ndarray, r: np.ndarray) -> np.ndar
     z = np.einsum("nji,nj->ni", Gd, y)
     np.add.at(z, fac.cols, np.einsum("bji,bj->bi", Gl, y[fac.rows]))
     return z
+
+
+def normalise_rows(fac: Factor, Gd: np.ndarray, Gl: np.ndarray, A: sp.csr_matrix):
+    """Row normalisation: every block row of G is multiplied from the left by
+    N_i, the inverse of the lower Cholesky factor of the diagonal block
+    (G A G^T)_ii, so that block becomes I.  A row whose block is not positive
+    definite is left as it is.  Returns the new (Gd, Gl)."""
+    G = G_matrix(fac, Gd, Gl)
+    Xd = diagonal_blocks((G @ A @ G.T).tocsr())
+    N = np.empty_like(Xd)
+    for i in range(fac.n):
+        try:
+            N[i] = solve_triangular(np.linalg.cholesky(Xd[i]), np.eye(3), lower=True)
+        except np.linalg.LinAlgError:
+            N[i] = np.eye(3)
+    return N @ Gd, N[fac.rows] @ Gl
 
 
 def power_probe(fac: Factor, Gd: np.ndarray, Gl: np.ndarray, A: sp.csr_matrix, v: np.ndarray, k: int) -> np.ndarray:

@@ -172,6 +172,9 @@ struct gf_mesh {
   gf_net* net = nullptr;
   int precond = GF_PC_BLOCK_JACOBI;
   bool netw_ready = false, net_train_ready = false, net_cached = false;
+  bool fact_norm = false;                 // row normalisation of the learned factor
+  int32_t* norm_ptr = nullptr;            // per-row pattern pairs for it (built on first use)
+  int4* norm_pairs = nullptr;
   int net_age = 0;
   double inv_mean_len = 1.0;
   gfem::NetWork netw;
@@ -531,20 +534,51 @@ gfem::NetInputs net_inputs(gf_mesh* M, const uint8_t* zeta) {
                          zeta,    M->inv_mean_len, static_cast<const float*>(M->binv), M->dflag};
 }
 
+// Stored blocks A_ab between the factor pattern positions a <= b of every row
+// (position 0 the row itself, a >= 1 its lower slot a - 1), for the row
+// normalisation: (block index, a, b, 0).
+void ensure_norm_pairs(gf_mesh* M) {
+  if (M->norm_ptr) return;
+  const gfem::Topology& T = M->topo;
+  std::vector<int32_t> ptr(M->n + 1, 0);
+  std::vector<int4> pairs;
+  std::vector<int32_t> P;
+  for (int i = 0; i < M->n; ++i) {
+    P.assign(1, i);
+    for (int l = T.lptr[i]; l < T.lptr[i + 1]; ++l) P.push_back(T.lcol[l]);
+    for (int a = 0; a < (int)P.size(); ++a) {
+      const int32_t* c0 = T.col.data() + T.row_ptr[P[a]];
+      const int32_t* c1 = T.col.data() + T.row_ptr[P[a] + 1];
+      for (int b = a; b < (int)P.size(); ++b) {
+        const int32_t* hit = std::lower_bound(c0, c1, P[b]);
+        if (hit != c1 && *hit == P[b]) pairs.push_back(int4{(int)(hit - T.col.data()), a, b, 0});
+      }
+    }
+    ptr[i + 1] = (int32_t)pairs.size();
+  }
+  M->norm_ptr = upload(M, ptr);
+  M->norm_pairs = upload(M, pairs);
+}
+
 // Factor of the learned path for the assembled step: the network runs every
 // net_every_n_steps steps; in between its cached head outputs are combined
 // with the current system.
 void learned_precond(gf_mesh* M) {
   ensure_netw(M);
+  if (M->fact_norm) ensure_norm_pairs(M);
   const gfem::NetInputs in = net_inputs(M, M->zeta[1 - M->zcur]);
   const int every = std::max(1, (int)M->p.net_every_n_steps);
   M->timed(3, -1, 0, [&] {
-    if (!M->net_cached || M->net_age >= every) {
+    const bool fresh = !M->net_cached || M->net_age >= every;
+    if (fresh) {
       gfem::net_forward(M->stream, M->net->P, M->netw, in, M->Gb);
       M->net_cached = true;
       M->net_age = 0;
     }
     gfem::net_build_factor(M->stream, M->net->P, M->netw, in, M->Gb, false);
+    // a row normalisation from an earlier A does not fit the current rows:
+    // it is computed for every factor
+    if (M->fact_norm) gfem::net_normalise_factor(M->stream, M->netw, in, M->Gb, M->norm_ptr, M->norm_pairs);
   });
   ++M->net_age;
   M->check_launch();
@@ -1346,6 +1380,12 @@ static gf_status net_train_eval(gf_net* net, gf_mesh* m, bool train, double lr, 
     m->net_cached = false;
     return GF_OK;
   })
+}
+
+gf_status gf_set_precond_normalise(gf_mesh* m, int32_t on) {
+  if (gf_status s = guard(m, "gf_set_precond_normalise")) return s;
+  m->fact_norm = on != 0;
+  return GF_OK;
 }
 
 gf_status gf_net_set_power_steps(gf_net* net, int32_t k) {

@@ -389,6 +389,107 @@ __global__ __launch_bounds__(256) void k_fact_build(NetInputs in, const float* _
   }
 }
 
+// ---------------------------------------------------------------- row normalisation of the factor
+
+// Block row i of the packed BF16 factor at pattern position a (0: G_ii, lower
+// triangular in the diagonal record; a >= 1: the row's lower slot a - 1).
+__device__ __forceinline__ void load_grow_blk(const FactOut& F, int i, int l0, int a, float B[3][3]) {
+  if (a == 0) {
+    const bf16x8 d = __builtin_bit_cast(bf16x8, F.gdv[i]);
+    B[0][0] = (float)d[0]; B[0][1] = 0.f;         B[0][2] = 0.f;
+    B[1][0] = (float)d[1]; B[1][1] = (float)d[2]; B[1][2] = 0.f;
+    B[2][0] = (float)d[3]; B[2][1] = (float)d[4]; B[2][2] = (float)d[5];
+  } else {
+    const bf16x8 v = __builtin_bit_cast(bf16x8, F.glv[l0 + a - 1]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) B[q / 3][q % 3] = (float)v[q];
+    B[2][2] = (float)F.gl8[l0 + a - 1];
+  }
+}
+
+// Scales every block row of the factor from the left by the inverse lower
+// Cholesky factor N_i of its diagonal block of X = G A G^T,
+//   X_ii = sum over pattern pairs (a, b) of G_ia A_ab G_ib^T,
+// so that X_ii = I.  pairs[ptr[i] .. ptr[i+1]) lists the stored blocks A_ab
+// with a <= b among the row's pattern {i, lower neighbours} (a = b once, a < b
+// standing for both orders).  kBuildLanes lanes per row; a row's blocks are
+// read (for X_ii) and then rewritten by the same lanes, lower records and
+// their transposed upper copies; no other row touches them.  A row whose X_ii
+// is not positive definite in FP32 is left as it is.
+__global__ __launch_bounds__(256) void k_fact_normalise(NetInputs in, const int32_t* __restrict__ ptr,
+                                                        const int4* __restrict__ pairs, FactOut F) {
+  const int n = in.n, nbp = in.A.nbp;
+  const int lane = threadIdx.x & (kBuildLanes - 1);
+  const float* __restrict__ val = static_cast<const float*>(in.A.val);
+  for (int i = blockIdx.x * (256 / kBuildLanes) + threadIdx.x / kBuildLanes; i < n;
+       i += gridDim.x * (256 / kBuildLanes)) {
+    const int l0 = in.lptr[i], k = in.lptr[i + 1] - l0;
+    float X[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    for (int p = ptr[i] + lane; p < ptr[i + 1]; p += kBuildLanes) {
+      const int4 pr = pairs[p];  // (block of A, a, b, unused)
+      float Ga[3][3], Gb[3][3], Am[3][3], T[3][3], S[3][3];
+      load_grow_blk(F, i, l0, pr.y, Ga);
+      load_grow_blk(F, i, l0, pr.z, Gb);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) Am[c / 3][c % 3] = val[(size_t)c * nbp + pr.x];
+      mat3_mul(Ga, Am, T);
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) S[r][c] = T[r][0] * Gb[c][0] + T[r][1] * Gb[c][1] + T[r][2] * Gb[c][2];
+      const bool both = pr.y != pr.z;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) X[r][c] += S[r][c] + (both ? S[c][r] : 0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int o = kBuildLanes / 2; o > 0; o >>= 1) X[r][c] += __shfl_xor(X[r][c], o, kBuildLanes);
+    // every lane of the row holds X_ii: lower Cholesky factor R, N = R^-1
+    const float r00s = X[0][0];
+    const float r00 = sqrtf(fmaxf(r00s, 0.f)), r10 = X[1][0] / r00, r20 = X[2][0] / r00;
+    const float r11s = X[1][1] - r10 * r10;
+    const float r11 = sqrtf(fmaxf(r11s, 0.f)), r21 = (X[2][1] - r20 * r10) / r11;
+    const float r22s = X[2][2] - r20 * r20 - r21 * r21;
+    const bool spd = r00s > 0.f && r11s > 0.f && r22s > 0.f && isfinite(r22s);
+    if (!spd) continue;
+    const float r22 = sqrtf(r22s);
+    const float n00 = 1.f / r00, n11 = 1.f / r11, n22 = 1.f / r22;
+    const float n10 = -r10 * n00 * n11, n21 = -r21 * n11 * n22;
+    const float n20 = -(r20 * n00 + r21 * n10) * n22;
+    const float N[3][3] = {{n00, 0.f, 0.f}, {n10, n11, 0.f}, {n20, n21, n22}};
+    for (int a = lane; a <= k; a += kBuildLanes) {
+      float B[3][3], NB[3][3];
+      load_grow_blk(F, i, l0, a, B);
+      mat3_mul(N, B, NB);
+      if (a == 0) {
+        bf16x8 v;
+        v[0] = (bf16)NB[0][0];
+        v[1] = (bf16)NB[1][0];
+        v[2] = (bf16)NB[1][1];
+        v[3] = (bf16)NB[2][0];
+        v[4] = (bf16)NB[2][1];
+        v[5] = (bf16)NB[2][2];
+        v[6] = v[7] = (bf16)0.f;
+        F.gdv[i] = __builtin_bit_cast(uint4, v);
+      } else {
+        float Nt[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) Nt[c][r] = NB[r][c];
+        const int e = in.blk_edge[in.A.row_ptr[i] + a - 1];
+        store_gblock<false>(F, in.ne, l0 + a - 1, true, NB);
+        store_gblock<false>(F, in.ne, in.upos[e], false, Nt);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- training (Kaporin probe loss)
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
@@ -864,6 +965,12 @@ void net_build_factor(hipStream_t s, const NetParamsDev& P, NetWork& w, const Ne
     k_fact_build<true><<<Gb, 256, 0, s>>>(in, w.o, P.master, out);
   else
     k_fact_build<false><<<Gb, 256, 0, s>>>(in, w.o, P.master, out);
+}
+
+void net_normalise_factor(hipStream_t s, NetWork& w, const NetInputs& in, int Gb, const int32_t* ptr,
+                          const int4* pairs) {
+  const FactOut out{w.gl32, w.gu32, w.gd32, w.glv, w.guv, w.gdv, w.gl8, w.gu8};
+  k_fact_normalise<<<Gb, 256, 0, s>>>(in, ptr, pairs, out);
 }
 
 FactView net_factor_view(const NetWork& w, const NetInputs& in) {

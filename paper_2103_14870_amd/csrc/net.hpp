@@ -113,6 +113,13 @@ void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInpu
 // Factor values from the head outputs w.o and the current system: packed
 // BF16 (fp32 = false) or FP32 SoA into w.gl32/gu32/gd32.
 void net_build_factor(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int Gb, bool fp32);
+// Scales each block row of the packed BF16 factor by the inverse Cholesky
+// factor of its diagonal block of G A G^T (which becomes I); pairs/ptr list,
+// per row, the stored blocks A_ab between its pattern positions a <= b as
+// (block index, a, b, 0), position 0 being the row itself and a >= 1 its
+// lower slot a - 1.
+void net_normalise_factor(hipStream_t s, NetWork& w, const NetInputs& in, int Gb, const int32_t* ptr,
+                          const int4* pairs);
 // View of the BF16 factor for the solve.
 FactView net_factor_view(const NetWork& w, const NetInputs& in);
 // Rademacher probe from a counter-based generator (SplitMix64 of seed and index).

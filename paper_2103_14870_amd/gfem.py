@@ -80,6 +80,7 @@ _SIGS = {
     "gf_net_set_weights": ([C.c_void_p, _P(C.c_float)], C.c_int),
     "gf_set_precond_net": ([C.c_void_p, C.c_void_p], C.c_int),
     "gf_set_precond": ([C.c_void_p, C.c_int32], C.c_int),
+    "gf_set_precond_normalise": ([C.c_void_p, C.c_int32], C.c_int),
     "gf_net_train_step": ([C.c_void_p, C.c_void_p, C.c_double, _P(C.c_double)], C.c_int),
     "gf_net_set_power_steps": ([C.c_void_p, C.c_int32], C.c_int),
     "gf_net_eval": ([C.c_void_p, C.c_void_p, _P(C.c_double), _P(C.c_double), _P(C.c_float), _P(C.c_float),
@@ -325,6 +326,11 @@ class Net:
 def attach_net(mesh: "Mesh", net: "Net | None", use: bool = True):
     _check(load().gf_set_precond_net(mesh._h, net._h if net is not None else None))
     _check(load().gf_set_precond(mesh._h, PRECOND["learned"] if (use and net is not None) else 0))
+
+
+def set_precond_normalise(mesh: "Mesh", on: bool):
+    """Row normalisation of the learned factor ((G A G^T)_ii = I per block row)."""
+    _check(load().gf_set_precond_normalise(mesh._h, int(bool(on))))
 
 
 def set_precond(mesh: "Mesh", name: str):

@@ -176,6 +176,44 @@ def test_factorised_pcg_tracks_oracle_iterations():
     net.close()
 
 
+def test_normalised_factor_tracks_oracle_iterations():
+    # row normalisation ((G A G^T)_ii = I) on a cracked, displaced beam with the
+    # shipped weights: the GPU's split-precision solve with the normalised BF16
+    # factor needs about as many iterations as the oracle's FP64 PCG with the
+    # normalised oracle factor, and its velocity change solves the oracle's
+    # system to the tolerance (plus the FP32 rounding of the stored blocks)
+    say("case normalised factor vs oracle")
+    prob, U, V = seeded_state(8, n=(16, 4, 4), frac=0.1)
+    prob.params["cg_rel_tol"] = 1e-6
+    w = shipped_weights()
+    net = gfem.Net(seed=0)
+    net.set_weights(w)
+    with gfem.mesh_from_problem(prob) as mj, gfem.mesh_from_problem(prob) as ml, \
+            gfem.mesh_from_problem(prob) as mn:
+        for m in (mj, ml, mn):
+            gfem.set_displacement(m, U, V)
+        gfem.attach_net(ml, net)
+        gfem.attach_net(mn, net)
+        gfem.set_precond_normalise(mn, True)
+        sj, sl, sn = mj.step(1), ml.step(1), mn.step(1)
+        assert sn["used_fallback"] == 0 and sn["rel_residual"] <= 1e-6
+        dv = {k: (m.velocities() - V).ravel() for k, m in (("j", mj), ("l", ml), ("n", mn))}
+    a, P, PT, fac, sysm = oracle_system(prob, U, V)
+    w64 = w.astype(np.float64)
+    Gd, Gl, _ = N.factor_blocks(N.forward(w64, a, P)["o"], w64, fac)
+    Gd, Gl = N.normalise_rows(fac, Gd, Gl, sysm.A.tocsr())
+    G = N.G_matrix(fac, Gd, Gl)
+    _, it_o, _, ok = O.pcg(sysm.A, sysm.b, (G.T @ G).tocsr(), 1e-6, 5000)
+    res = {k: np.linalg.norm(sysm.b - sysm.A @ v) / np.linalg.norm(sysm.b) for k, v in dv.items()}
+    say(f"  iterations: GPU normalised {sn['inner_iters']}, oracle {it_o}, GPU learned {sl['inner_iters']}, "
+        f"GPU Jacobi {sj['inner_iters']}; oracle residual of the GPU dv: normalised {res['n']:.2e}, "
+        f"learned {res['l']:.2e}, Jacobi {res['j']:.2e}")
+    assert ok
+    assert 0.8 * it_o <= sn["inner_iters"] <= 1.25 * it_o
+    assert res["n"] <= 5e-6
+    net.close()
+
+
 def test_learned_trajectory_matches_block_jacobi():
     say("case learned trajectory vs block Jacobi, 20 steps")
     prob = meshgen.notched_beam(16, 4, 4, h=0.01, notch_cells=1, crack_fraction=0.1)

@@ -191,3 +191,41 @@ def test_power_loss_rises_to_the_largest_eigenvalue():
     assert rq[-1] == pytest.approx(np.log(lmax), abs=1e-6)
     # k = 0 is the plain Kaporin probe loss
     assert N.loss_and_grad_power(w, a, P, PT, fac, A, v, 0)[0] == N.loss_and_grad(w, a, P, PT, fac, A, v)[0]
+
+
+def test_row_normalisation_gives_unit_diagonal_blocks():
+    # after normalisation the diagonal blocks of the dense G A G^T are I, and G
+    # keeps its block lower triangular shape with lower-triangular G_ii
+    a, P, PT, fac, A, b, _ = small_system(12)
+    w = N.init_weights(13, head_scale=0.3)
+    Gd, Gl, _ = N.factor_blocks(N.forward(w, a, P)["o"], w, fac)
+    Gd2, Gl2 = N.normalise_rows(fac, Gd, Gl, A)
+    G = N.G_matrix(fac, Gd2, Gl2).toarray()
+    X = G @ A.toarray() @ G.T
+    blk = np.arange(X.shape[0]) // 3
+    np.testing.assert_allclose(np.where(blk[:, None] == blk[None, :], X, 0.0), np.eye(X.shape[0]), atol=1e-10)
+    assert np.all(G[blk[:, None] < blk[None, :]] == 0.0)
+    assert np.all(np.triu(Gd2, 1) == 0.0)
+
+
+def test_row_normalisation_ignores_a_lower_triangular_row_scaling():
+    # (L G)_i normalised equals G_i normalised for any lower-triangular L_i with
+    # positive diagonal: chol(L X L^T) = L chol(X)
+    a, P, PT, fac, A, b, _ = small_system(14)
+    w = N.init_weights(15, head_scale=0.3)
+    Gd, Gl, _ = N.factor_blocks(N.forward(w, a, P)["o"], w, fac)
+    rng = np.random.default_rng(16)
+    L = np.tril(rng.normal(size=(fac.n, 3, 3)), -1) + np.eye(3) * rng.uniform(0.3, 3.0, size=(fac.n, 1, 3))
+    ref = N.normalise_rows(fac, Gd, Gl, A)
+    got = N.normalise_rows(fac, L @ Gd, L[fac.rows] @ Gl, A)
+    np.testing.assert_allclose(got[0], ref[0], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(got[1], ref[1], rtol=1e-9, atol=1e-12)
+
+
+def test_row_normalisation_leaves_block_jacobi_unchanged():
+    a, P, PT, fac, A, b, _ = small_system(17)
+    w = N.init_weights(0, head_scale=0.0)
+    Gd, Gl, _ = N.factor_blocks(N.forward(w, a, P)["o"], w, fac)
+    Gd2, Gl2 = N.normalise_rows(fac, Gd, Gl, A)
+    np.testing.assert_allclose(Gd2, Gd, rtol=1e-12, atol=1e-14)
+    assert np.all(Gl2 == 0.0)
