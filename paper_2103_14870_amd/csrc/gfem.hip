@@ -298,7 +298,7 @@ void assemble(gf_mesh* M, bool flow, d4* f_out) {
   const double mass_fac = 1.0 + dt * M->p.rayleigh_alpha;
   const double stiff_fac = dt * dt + dt * M->p.rayleigh_beta;
   M->timed(2, -1, 0, [&] {
-    gfem::launch_edge<T>(s, M->ne, M->m, M->edge_ptr, M->edge_slot, static_cast<const T*>(M->contrib),
+    gfem::launch_edge<T>(s, M->ne, M->edge_ptr, M->edge_slot, static_cast<const T*>(M->contrib),
                          M->edge_mass, mass_fac, stiff_fac, M->blk_ij, M->blk_ji, static_cast<T*>(M->val), M->nbp,
                          static_cast<T*>(M->edge_w));
   });

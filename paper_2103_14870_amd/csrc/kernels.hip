@@ -505,7 +505,7 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
 // the consistent mass, and write A_ij and A_ji = A_ij^T into the block matrix:
 // A_ij = m_ij (1 + dt alpha) I + (dt^2 + dt beta) K_ij.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_edge(int ne, int m6, const int32_t* __restrict__ edge_ptr,
+__global__ __launch_bounds__(kThreads) void k_edge(int ne, const int32_t* __restrict__ edge_ptr,
                                                    const int32_t* __restrict__ edge_slot,
                                                    const T* __restrict__ contrib,
                                                    const double* __restrict__ edge_mass, double mass_fac,
@@ -1405,10 +1405,10 @@ void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_e
 }
 
 template <typename T>
-void launch_edge(hipStream_t s, int ne, int m, const int32_t* edge_ptr, const int32_t* edge_slot,
+void launch_edge(hipStream_t s, int ne, const int32_t* edge_ptr, const int32_t* edge_slot,
                  const T* contrib, const double* edge_mass, double mass_fac, double stiff_fac,
                  const int32_t* blk_ij, const int32_t* blk_ji, T* val, int nbp, T* edge_w) {
-  k_edge<T><<<blocks_for(ne), kThreads, 0, s>>>(ne, 6 * m, edge_ptr, edge_slot, contrib, edge_mass, mass_fac,
+  k_edge<T><<<blocks_for(ne), kThreads, 0, s>>>(ne, edge_ptr, edge_slot, contrib, edge_mass, mass_fac,
                                                stiff_fac, blk_ij, blk_ji, val, nbp, edge_w);
 }
 
@@ -1527,7 +1527,7 @@ void launch_integrate(hipStream_t s, int n, const d4* X64, d4* V, d4* U, const u
 #define GFEM_INST(T)                                                                                         \
   template void launch_element<T>(hipStream_t, int, const int4*, const int32_t*, const uint8_t*, const d4*,  \
                                   const d4*, const uint8_t*, const T*, T*, ElemConst, T*, Counters*);        \
-  template void launch_edge<T>(hipStream_t, int, int, const int32_t*, const int32_t*, const T*,              \
+  template void launch_edge<T>(hipStream_t, int, const int32_t*, const int32_t*, const T*,                   \
                                const double*, double, double, const int32_t*, const int32_t*, T*, int, T*);  \
   template void launch_row<T>(hipStream_t, int, int, MatView, const int32_t*, const int32_t*, const double*, \
                               const T*, const double*, const d4*, const d4*, const d4*, const uint8_t*,      \

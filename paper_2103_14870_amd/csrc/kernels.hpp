@@ -75,7 +75,7 @@ void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_e
                     const T* pl_in, T* pl_out, ElemConst c, T* contrib, Counters* ctr);
 
 template <typename T>
-void launch_edge(hipStream_t s, int ne, int m, const int32_t* edge_ptr, const int32_t* edge_slot,
+void launch_edge(hipStream_t s, int ne, const int32_t* edge_ptr, const int32_t* edge_slot,
                  const T* contrib, const double* edge_mass, double mass_fac, double stiff_fac,
                  const int32_t* blk_ij, const int32_t* blk_ji, T* val, int nbp, T* edge_w);
 
