@@ -262,6 +262,38 @@ def test_restored_state_is_solved_as_on_a_fresh_mesh():
     net.close()
 
 
+def test_rejected_learned_attempt_falls_back_and_backs_off():
+    # an accepted learned step sets the cap of the next attempt (3x its
+    # iterations + 100); a factor that needs more is abandoned, the step is
+    # re-solved with block-Jacobi and meets the tolerance, the next 4 steps use
+    # block-Jacobi directly, and the pause doubles after the next rejection
+    say("case learned fallback and back-off")
+    prob = meshgen.notched_beam(16, 4, 4, h=0.01, notch_cells=1)
+    prob.params["net_every_n_steps"] = 1
+    net = gfem.Net(seed=0)
+    net.set_weights(damped_weights(0.6))
+    tol = prob.params["cg_rel_tol"]
+    with gfem.mesh_from_problem(prob) as m:
+        gfem.attach_net(m, net)
+        s1 = m.step(1)
+        assert s1["used_fallback"] == 0
+        net.set_weights(damped_weights(-1.5))  # couplings of the wrong sign: a poor but SPD factor
+        s2 = m.step(1)
+        s3 = m.step(4)
+        s4 = m.step(1)
+        s5 = m.step(8)
+        s6 = m.step(1)
+    say(f"  accepted {s1['inner_iters']}; rejected step {s2['inner_iters']} (fallback {s2['used_fallback']}), "
+        f"back-off {s3['used_fallback']}/4, {s4['used_fallback']}/1, {s5['used_fallback']}/8, {s6['used_fallback']}/1")
+    assert s2["used_fallback"] == 1 and s2["rel_residual"] <= tol
+    assert s2["inner_iters"] > 3 * s1["inner_iters"] + 100
+    assert s3["used_fallback"] == 4 and s3["steps_done"] == 4
+    assert s4["used_fallback"] == 1  # the next attempt is rejected again ...
+    assert s5["used_fallback"] == 8  # ... and the pause doubles
+    assert s6["used_fallback"] == 1 and s6["rel_residual"] <= tol
+    net.close()
+
+
 def test_random_network_solve_meets_tolerance():
     say("case random learned solve")
     prob = meshgen.notched_beam(16, 4, 4, h=0.01, notch_cells=1)
