@@ -26,7 +26,7 @@ using d4 = v4<double>;
 
 constexpr int kThreads = 256;     // 4 waves of 64
 constexpr int kMaxPart = 2048;    // max workgroups that leave a reduction partial
-constexpr int kRowLanes = 16;     // lanes cooperating on one block row in the SpMV
+constexpr int kRowLanes = 16;     // lanes cooperating on one block row in the row pass and the FP64 residual
 constexpr int kSpmvThreads = 256; // workgroup size of the PCG SpMV
 constexpr int kSpmvLanes = 8;    // lanes per block row in the two PCG SpMV kernels (two blocks each in flight)
 constexpr int kVecThreads = 256;  // workgroup size of the PCG vector kernels
