@@ -1,0 +1,73 @@
+"""Host topology builder (no GPU): built with g++ under AddressSanitizer and
+UndefinedBehaviorSanitizer and run on valid meshes (single tet, jittered cube,
+notched beam, coarse ellipsoid) and on invalid ones (node id out of range,
+repeated node, flat tet): the pattern, its compact halves and the
+contribution slots are consistent, invalid meshes are rejected, and the
+sanitizers report nothing."""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2103_14870_amd import meshgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def write_mesh(path, X, T):
+    with open(path, "wb") as f:
+        np.array([X.shape[0], T.shape[0]], np.int32).tofile(f)
+        np.ascontiguousarray(X, np.float64).tofile(f)
+        np.ascontiguousarray(T, np.int32).tofile(f)
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("topo") / "topo_check")
+    csrc = os.path.join(ROOT, "paper_2103_14870_amd", "csrc")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-fno-omit-frame-pointer", "-I", csrc, "-o", exe, os.path.join(ROOT, "tests", "topo_check.cpp"),
+                    os.path.join(csrc, "topo.cpp")], check=True, capture_output=True)
+    return exe
+
+
+def run(exe, path):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", UBSAN_OPTIONS="print_stacktrace=1")
+    return subprocess.run([exe, path], capture_output=True, text=True, env=env, timeout=120)
+
+
+def test_valid_meshes(checker, tmp_path):
+    tet = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    h = 0.08
+    grid = (int(math.ceil(2.1 / h)) | 1, int(math.ceil(1.1 / h)) | 1, int(math.ceil(1.1 / h)) | 1)
+    cases = {"tet": (tet, np.array([[0, 1, 3, 2]])),
+             "cube": meshgen.tiny_cube(3, h=0.1, jitter_frac=0.05, seed=1),
+             "beam": meshgen.notched_beam(16, 4, 4, h=0.01, notch_cells=1),
+             "ellipsoid": meshgen.ellipsoid(h=h, grid=grid)}
+    for name, c in cases.items():
+        X, T = c if isinstance(c, tuple) else (c.X, c.tets)
+        path = str(tmp_path / f"{name}.bin")
+        write_mesh(path, X, T)
+        r = run(checker, path)
+        assert r.returncode == 0 and r.stdout.strip() == "bad 0", (name, r.stdout, r.stderr[-2000:])
+        assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
+
+
+def test_invalid_meshes_are_rejected(checker, tmp_path):
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    flat = X.copy()
+    flat[3] = [0.5, 0.5, 0.0]
+    cases = {"id": (X, [[0, 1, 3, 7]], "outside"), "repeat": (X, [[0, 1, 1, 2]], "repeats"),
+             "flat": (flat, [[0, 1, 3, 2]], "zero volume")}
+    for name, (Xc, T, msg) in cases.items():
+        path = str(tmp_path / f"{name}.bin")
+        write_mesh(path, Xc, np.array(T))
+        r = run(checker, path)
+        assert r.returncode == 1 and r.stdout.startswith("err") and msg in r.stdout, (name, r.stdout, r.stderr[-2000:])
+        assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr

@@ -1,0 +1,64 @@
+// Host check of the topology builder (built with g++ and sanitizers by
+// tests/test_topology_host.py): reads a mesh (int32 n, m; n*3 f64; m*4 i32),
+// builds the topology and checks the compact lower/upper halves, their slot
+// maps and the contribution slots.  Prints "err <message>" and exits 1 when
+// the builder rejects the mesh, else "bad <count>" and exits with count != 0.
+#include <cstdio>
+#include <fstream>
+#include <vector>
+
+#include "topo.hpp"
+
+int main(int argc, char** argv) {
+  if (argc < 2) return 2;
+  std::ifstream f(argv[1], std::ios::binary);
+  int n = 0, m = 0;
+  f.read(reinterpret_cast<char*>(&n), 4);
+  f.read(reinterpret_cast<char*>(&m), 4);
+  std::vector<double> X(3 * (size_t)n);
+  std::vector<int32_t> T(4 * (size_t)m);
+  f.read(reinterpret_cast<char*>(X.data()), 8 * X.size());
+  f.read(reinterpret_cast<char*>(T.data()), 4 * T.size());
+  gfem::Topology t;
+  bool deg = false;
+  const std::string err = gfem::build_topology(X.data(), n, T.data(), m, 1000.0, &t, &deg);
+  if (!err.empty()) {
+    printf("err %s\n", err.c_str());
+    return 1;
+  }
+  int bad = 0;
+  if (t.lptr[n] != t.ne || t.uptr[n] != t.ne || t.nb != n + 2 * t.ne) bad++;
+  for (int i = 0; i < n; ++i) {
+    for (int k = t.lptr[i]; k < t.lptr[i + 1]; ++k)
+      if (t.lcol[k] >= i || (k > t.lptr[i] && t.lcol[k] <= t.lcol[k - 1])) bad++;
+    for (int k = t.uptr[i]; k < t.uptr[i + 1]; ++k)
+      if (t.ucol[k] <= i || (k > t.uptr[i] && t.ucol[k] <= t.ucol[k - 1])) bad++;
+    if (t.col[t.diag_blk[i]] != i) bad++;
+  }
+  for (int e = 0; e < t.ne; ++e) {
+    const int i = t.edges[2 * e], j = t.edges[2 * e + 1];
+    const int lp = t.lpos[e], up = t.upos[e];
+    if (i >= j) bad++;
+    if (lp < t.lptr[j] || lp >= t.lptr[j + 1] || t.lcol[lp] != i) bad++;
+    if (up < t.uptr[i] || up >= t.uptr[i + 1] || t.ucol[up] != j) bad++;
+    if (t.col[t.blk_ji[e]] != i || t.blk_ji[e] - t.row_ptr[j] != lp - t.lptr[j]) bad++;
+    if (t.col[t.blk_ij[e]] != j || t.blk_ij[e] - t.diag_blk[i] - 1 != up - t.uptr[i]) bad++;
+    if (t.blk_edge[t.blk_ij[e]] != e || t.blk_edge[t.blk_ji[e]] != e) bad++;
+  }
+  // every (tet, local edge) contribution slot appears once, under its own edge
+  std::vector<int> seen(6 * (size_t)m, 0);
+  for (int e = 0; e < t.ne; ++e)
+    for (int s = t.edge_ptr[e]; s < t.edge_ptr[e + 1]; ++s) {
+      const int r = t.edge_slot[s];
+      if (r < 0 || r >= 6 * m) {
+        bad++;
+        continue;
+      }
+      seen[r]++;
+      if (t.tet_edge[r] != e) bad++;
+    }
+  for (int c : seen)
+    if (c != 1) bad++;
+  printf("bad %d\n", bad);
+  return bad != 0;
+}
