@@ -203,14 +203,14 @@ class State:
     x: np.ndarray                    # (n,3) positions
     v: np.ndarray                    # (n,3) velocities
     zeta: np.ndarray                 # (ne,) bool, True = broken
-    Ep: np.ndarray                   # (m,3,3) plastic Green strain (material frame)
+    Cp: np.ndarray                   # (m,3,3) plastic right Cauchy-Green tensor (material frame, det 1)
     step: int = 0
 
 
 def initial_state(mesh: Mesh) -> State:
     n, m = mesh.X.shape[0], mesh.tets.shape[0]
     return State(mesh.X.copy(), np.zeros((n, 3)), np.zeros(mesh.edges.shape[0], bool),
-                 np.zeros((m, 3, 3)))
+                 np.tile(np.eye(3), (m, 1, 1)))
 
 
 def break_pairs(mesh: Mesh, state: State, pairs: np.ndarray) -> None:
@@ -252,7 +252,8 @@ def damage_update(mesh: Mesh, x: np.ndarray, zeta: np.ndarray, near_tol: float =
 
 
 # --------------------------------------------------------------------------
-# Plasticity (ductile case): additive Green-strain flow with instant return
+# Plasticity (ductile case): multiplicative, volume-preserving flow with an
+# instant radial return of the deviatoric elastic Hencky strain
 # --------------------------------------------------------------------------
 
 def deformation_gradient(mesh: Mesh, x: np.ndarray) -> np.ndarray:
@@ -261,80 +262,142 @@ def deformation_gradient(mesh: Mesh, x: np.ndarray) -> np.ndarray:
     return Ds @ mesh.Dm_inv
 
 
-def plastic_update(mesh: Mesh, x: np.ndarray, Ep: np.ndarray) -> np.ndarray:
-    """E_e = E - E_p; if |dev E_e|_F > yield, move the excess into E_p."""
+def plastic_update(mesh: Mesh, x: np.ndarray, Cp: np.ndarray) -> np.ndarray:
+    """F = Fe Fp with Cp = Fp^T Fp (det 1).  The elastic stretches are the
+    generalised eigenvalues lam_i of C v = lam Cp v (C = F^T F); their Hencky
+    strains h_i = log(lam_i) / 2 have deviator d = h - mean(h).  If |d| exceeds
+    the yield strain, d is scaled back onto the yield surface and Cp is moved
+    so that C has the returned elastic stretches over it; the mean (volumetric)
+    part never flows, so det Cp stays 1."""
     ey = mesh.params.get("yield_strain", 0.0)
     if ey <= 0:
-        return Ep
+        return Cp
     F = deformation_gradient(mesh, x)
     C = np.einsum("tji,tjk->tik", F, F)
-    Ee = 0.5 * (C - np.eye(3)) - Ep
-    dev = Ee - np.trace(Ee, axis1=1, axis2=2)[:, None, None] / 3.0 * np.eye(3)
-    nrm = np.sqrt(np.sum(dev * dev, axis=(1, 2)))
-    fac = np.where(nrm > ey, 1.0 - ey / np.where(nrm > 0, nrm, 1.0), 0.0)
-    return Ep + fac[:, None, None] * dev
+    # generalised symmetric eigenproblem through the Cholesky factor of Cp:
+    # S = L^-1 C L^-T = W diag(lam) W^T, V = L^-T W
+    L = np.linalg.cholesky(Cp)
+    Li = np.linalg.inv(L)
+    S = Li @ C @ np.swapaxes(Li, 1, 2)
+    lam, W = np.linalg.eigh(0.5 * (S + np.swapaxes(S, 1, 2)))
+    h = 0.5 * np.log(lam)
+    hm = h.mean(axis=1, keepdims=True)
+    d = h - hm
+    nd = np.linalg.norm(d, axis=1)
+    flow = nd > ey
+    h_new = hm + d * np.where(flow, ey / np.where(flow, nd, 1.0), 1.0)[:, None]
+    # Cp' = L W diag(lam / lam') W^T L^T: C over Cp' has the returned stretches
+    LW = L @ W
+    Cp_new = np.einsum("tij,tj,tkj->tik", LW, lam / np.exp(2.0 * h_new), LW)
+    return np.where(flow[:, None, None], Cp_new, Cp)
 
 
-def gram_offset(mesh: Mesh, Ep: np.ndarray) -> np.ndarray:
-    """Plastic strain expressed on the Gram matrix: P = 2 Dm^T Ep Dm, so the
-    elastic Gram matrix is G - P."""
-    return 2.0 * np.einsum("tji,tjk,tkl->til", mesh.Dm, Ep, mesh.Dm)
+def gram_offset(mesh: Mesh, Cp: np.ndarray) -> np.ndarray:
+    """The plastic rest shape on the Gram matrix: Gp = Dm^T Cp Dm = G0 + P,
+    P = Dm^T (Cp - I) Dm (zero without plastic flow)."""
+    return np.einsum("tji,tjk,tkl->til", mesh.Dm, Cp - np.eye(3), mesh.Dm)
 
 
 # --------------------------------------------------------------------------
 # Edge-length element (Theorem 3.1 + Eq. 12 + Eq. 35)
 # --------------------------------------------------------------------------
 
+# Below this |J| the volume terms of the energy are evaluated in cofactor form
+# (the edge-length form of J divides by J: one over the volume of a flat tet).
+J_MIN = 0.05
+
+
 @dataclass
 class Element:
     s: np.ndarray        # (m,6) current squared edge lengths
     d: np.ndarray        # (m,6,3) current edge vectors x_b - x_a
-    IC: np.ndarray
-    J: np.ndarray
+    IC: np.ndarray       # elastic I_C = tr(G Gp^-1)
+    J: np.ndarray        # det F
     G: np.ndarray
-    Ginv: np.ndarray
-    g: np.ndarray        # (m,6) dPsi/ds_k
-    v: np.ndarray        # (m,6) tr(G^-1 E_k)
-    Mkl: np.ndarray      # (m,6,6)
-    coef: np.ndarray     # (m,3) unclamped Hessian coefficients
+    c: np.ndarray        # (m,6) dI_C/ds_k = tr(E_k Gp^-1)
+    g: np.ndarray        # (m,6) dPsi/ds_k (small tets: the I_C terms only)
+    v: np.ndarray        # (m,6) tr(G^-1 E_k) (zero on small tets)
+    Mkl: np.ndarray      # (m,6,6) (zero on small tets)
+    coef: np.ndarray     # (m,3) unclamped edge-Hessian coefficients (small tets: a2 = a3 = 0)
     psi: np.ndarray
-    collapsed: np.ndarray
+    small: np.ndarray    # |J| < J_MIN: volume terms in cofactor form
+    gradJ: np.ndarray    # (m,4,3) dJ/dx_a (cofactor form; used on small tets)
+    hessJ: np.ndarray    # (m,12,12) d^2 J/dx^2 (cofactor form; used on small tets, unclamped only)
 
 
-def element(mesh: Mesh, x: np.ndarray, Ep: np.ndarray | None = None) -> Element:
+def cofactor_gradient(Ds: np.ndarray, detDm: np.ndarray):
+    """dJ/dx_a for J = det(Ds)/det(Dm), Ds = [x1-x0, x2-x0, x3-x0]: the
+    cofactor columns x2'x x3', x3' x x1', x1' x x2' over det Dm (nodes 1-3) and
+    minus their sum (node 0); and the 12x12 second derivative of the triple
+    product (entries +-d_c, independent of the differentiated pair)."""
+    d1, d2, d3 = Ds[:, :, 0], Ds[:, :, 1], Ds[:, :, 2]
+    g = np.zeros((Ds.shape[0], 4, 3))
+    g[:, 1] = np.cross(d2, d3)
+    g[:, 2] = np.cross(d3, d1)
+    g[:, 3] = np.cross(d1, d2)
+    g[:, 0] = -(g[:, 1] + g[:, 2] + g[:, 3])
+    g /= detDm[:, None, None]
+    # d^2 (d1 . d2 x d3) / dd_a dd_b = [d_c]x-type blocks with the sign of the
+    # permutation (a, b, c); the node-0 rows/columns follow from translation
+    # invariance (d_i = x_i - x_0)
+    eps = np.zeros((3, 3, 3))
+    for i, j, k in itertools.permutations(range(3)):
+        eps[i, j, k] = np.linalg.det(np.eye(3)[[i, j, k]])
+    Hd = np.zeros((Ds.shape[0], 3, 3, 3, 3))      # [a, b] blocks over d_1..d_3
+    dd = (d1, d2, d3)
+    for a in range(3):
+        for b in range(3):
+            if a == b:
+                continue
+            c = 3 - a - b
+            sgn = np.linalg.det(np.eye(3)[[a, b, c]])
+            Hd[:, a, b] = sgn * np.einsum("ijk,tk->tij", eps, dd[c])
+    T = np.zeros((4, 3))
+    T[0] = -1.0
+    T[1:] = np.eye(3)                              # d_i = sum_a T[a, i] x_a
+    H = np.einsum("ai,bj,tijpq->tapbq", T, T, Hd).reshape(-1, 12, 12)
+    return g, H / detDm[:, None, None]
+
+
+def element(mesh: Mesh, x: np.ndarray, Cp: np.ndarray | None = None) -> Element:
     t = mesh.tets
+    m = t.shape[0]
     d = np.stack([x[t[:, b]] - x[t[:, a]] for a, b in LOCAL_EDGES], axis=1)
     s = np.sum(d * d, axis=2)
     G = np.einsum("tk,kij->tij", s, EK)
-    if Ep is not None:
-        G = G - gram_offset(mesh, Ep)
+    Gp = mesh.G0 if Cp is None else mesh.G0 + gram_offset(mesh, Cp)
+    Gp_inv = np.linalg.inv(Gp)
     mu, lam, al = mesh.mu, mesh.lam, mesh.alpha
-    # A collapsed tet (det G = 0) has no finite edge-space derivatives; it is
-    # evaluated at its rest Gram matrix instead and must carry chi = 0.
-    collapsed = np.linalg.det(G) <= 1e-12 * mesh.detG0
-    G = np.where(collapsed[:, None, None], mesh.G0, G)
-    IC = np.einsum("tij,tji->t", G, mesh.G0_inv)
+    IC = np.einsum("tij,tji->t", G, Gp_inv)
+    c = np.einsum("kij,tji->tk", EK, Gp_inv)
     Ds = np.stack([x[t[:, i]] - x[t[:, 0]] for i in (1, 2, 3)], axis=2)
-    sign = np.where(np.linalg.det(Ds) < 0, -1.0, 1.0)
-    J = sign * np.sqrt(np.maximum(np.linalg.det(G) / mesh.detG0, 0.0))
-    Ginv = np.linalg.inv(G)
-    W = np.einsum("tij,kjl->tkil", Ginv, EK)           # G^-1 E_k
-    v = np.einsum("tkii->tk", W)
-    Mkl = np.einsum("tkij,tlji->tkl", W, W)
-    g = 0.5 * mu * (1.0 - 1.0 / (IC + 1.0))[:, None] * mesh.c \
-        + 0.5 * lam * ((J - al) * J)[:, None] * v
+    detDm = np.linalg.det(mesh.Dm)
+    J = np.linalg.det(Ds) / detDm                  # = sign(det Ds) sqrt(det G / det G0)
+    small = np.abs(J) < J_MIN
+    big = ~small
+    v = np.zeros((m, 6))
+    Mkl = np.zeros((m, 6, 6))
+    if np.any(big):
+        Ginv = np.linalg.inv(G[big])
+        W = np.einsum("tij,kjl->tkil", Ginv, EK)   # G^-1 E_k
+        v[big] = np.einsum("tkii->tk", W)
+        Mkl[big] = np.einsum("tkij,tlji->tkl", W, W)
+    gJ = np.where(big, 0.5 * lam * (J - al) * J, 0.0)
+    g = 0.5 * mu * (1.0 - 1.0 / (IC + 1.0))[:, None] * c + gJ[:, None] * v
     coef = np.stack([0.5 * mu / (IC + 1.0) ** 2,
-                     0.25 * lam * (2.0 * J - al) * J,
-                     -0.5 * lam * (J - al) * J], axis=1)
+                     np.where(big, 0.25 * lam * (2.0 * J - al) * J, 0.0),
+                     np.where(big, -0.5 * lam * (J - al) * J, 0.0)], axis=1)
     psi = 0.5 * mu * (IC - 3.0) + 0.5 * lam * (J - al) ** 2 - 0.5 * mu * np.log(IC + 1.0)
-    return Element(s, d, IC, J, G, Ginv, g, v, Mkl, coef, psi, collapsed)
+    gradJ, hessJ = cofactor_gradient(Ds, detDm)
+    return Element(s, d, IC, J, G, c, g, v, Mkl, coef, psi, small, gradJ, hessJ)
 
 
 def edge_hessian(mesh: Mesh, el: Element, clamp: bool = True) -> np.ndarray:
     """d^2 Psi / ds_k ds_l = a1 c c^T + a2 v v^T + a3 M; clamped: each a_i >= 0
-    (c c^T, v v^T and the Gram matrix M are PSD, so the result is PSD)."""
+    (c c^T, v v^T and the Gram matrix M are PSD, so the result is PSD).  On
+    small tets only the I_C term is in edge form."""
     a = np.maximum(el.coef, 0.0) if clamp else el.coef
-    c, v = mesh.c, el.v
+    c, v = el.c, el.v
     return (a[:, 0, None, None] * c[:, :, None] * c[:, None, :]
             + a[:, 1, None, None] * v[:, :, None] * v[:, None, :]
             + a[:, 2, None, None] * el.Mkl)
@@ -360,22 +423,31 @@ for _k, (_a, _b) in enumerate(LOCAL_EDGES):
 def element_forces(mesh: Mesh, el: Element, chi: np.ndarray) -> np.ndarray:
     """Restoring nodal forces (m,4,3): f_a = 2 V chi sum_{k ∋ a} g_k (x_b - x_a)
     (Eq. 12 with the unit vector pointing from a to the other node, times the
-    energy fraction of Eq. 32)."""
+    energy fraction of Eq. 32).  On small tets the volume term's force
+    -V chi lambda (J - alpha) dJ/dx_a is added in cofactor form."""
     f = np.zeros((el.d.shape[0], 4, 3))
     w = 2.0 * (mesh.V * chi)[:, None] * el.g
     for k, (a, b) in enumerate(LOCAL_EDGES):
         f[:, a] += w[:, k, None] * el.d[:, k]
         f[:, b] -= w[:, k, None] * el.d[:, k]
-    return f
+    fJ = np.where(el.small, -mesh.V * chi * mesh.lam * (el.J - mesh.alpha), 0.0)
+    return f + fJ[:, None, None] * el.gradJ
 
 
 def element_stiffness(mesh: Mesh, el: Element, chi: np.ndarray, clamp: bool = True) -> np.ndarray:
     """k*_e = chi V [Js^T H Js + sum_k 2 g_k L_k]  (Eq. 10, 33), with the clamped
-    H and g_k -> max(g_k, 0) for a PSD tangent."""
+    H and g_k -> max(g_k, 0) for a PSD tangent.  On small tets the volume term
+    adds lambda dJ dJ^T (PSD) and, unclamped only, lambda (J - alpha) d^2 J
+    (indefinite, dropped by the clamp)."""
     H = edge_hessian(mesh, el, clamp)
     Js = edge_jacobian(el)
     gg = np.maximum(el.g, 0.0) if clamp else el.g
     K = np.einsum("tki,tkl,tlj->tij", Js, H, Js) + 2.0 * np.einsum("tk,kij->tij", gg, LAPLACE)
+    gJ = el.gradJ.reshape(-1, 12)
+    KJ = mesh.lam * gJ[:, :, None] * gJ[:, None, :]
+    if not clamp:
+        KJ = KJ + (mesh.lam * (el.J - mesh.alpha))[:, None, None] * el.hessJ
+    K = K + np.where(el.small[:, None, None], KJ, 0.0)
     return (mesh.V * chi)[:, None, None] * K
 
 
@@ -383,27 +455,50 @@ def element_stiffness(mesh: Mesh, el: Element, chi: np.ndarray, clamp: bool = Tr
 # Energy fraction chi (Eq. 22-25)
 # --------------------------------------------------------------------------
 
-def edge_normal_stress(mesh: Mesh, x: np.ndarray, Ep: np.ndarray | None = None) -> np.ndarray:
+def scaled_edge_stress(mesh: Mesh, x: np.ndarray, Cp: np.ndarray | None = None):
     """sigma_k = q_k^T S q_k: the 2nd Piola-Kirchhoff stress S = 2 dPsi/dC of
     Eq. 35 projected on the rest unit direction q_k of each edge (Eq. 16-19,
-    as a tensor projection)."""
+    as a tensor projection).  With plastic flow the I_C term is taken relative
+    to Cp: S = mu (1 - 1/(I_C + 1)) Cp^-1 + lambda (J - alpha) J C^-1.
+    On small tets (|J| < J_MIN) every sigma_k is returned multiplied by |J|
+    (J C^-1 = adj(C) / J), which leaves chi's ratios unchanged and keeps
+    them finite on a flat tet.  Returns (sigma (m,6), small, J)."""
     F = deformation_gradient(mesh, x)
     C = np.einsum("tji,tjk->tik", F, F)
-    if Ep is not None:
-        C = C - 2.0 * Ep
+    m = C.shape[0]
+    Cpi = np.tile(np.eye(3), (m, 1, 1)) if Cp is None else np.linalg.inv(Cp)
     mu, lam, al = mesh.mu, mesh.lam, mesh.alpha
-    IC = np.trace(C, axis1=1, axis2=2)
-    J = np.sign(np.linalg.det(F)) * np.sqrt(np.maximum(np.linalg.det(C), 0.0))
-    Cinv = np.linalg.inv(C)
-    Sst = (mu * (1.0 - 1.0 / (IC + 1.0)))[:, None, None] * np.eye(3) \
-        + (lam * (J - al) * J)[:, None, None] * Cinv
+    IC = np.einsum("tij,tji->t", C, Cpi)
+    J = np.linalg.det(F)
+    small = np.abs(J) < J_MIN
+    # adjugate of the symmetric C (its cofactor matrix)
+    adj = np.empty_like(C)
+    for i in range(3):
+        for j in range(3):
+            r = [k for k in range(3) if k != i]
+            cl = [k for k in range(3) if k != j]
+            adj[:, j, i] = (-1) ** (i + j) * (C[:, r[0], cl[0]] * C[:, r[1], cl[1]]
+                                              - C[:, r[0], cl[1]] * C[:, r[1], cl[0]])
+    sgn = np.where(J >= 0, 1.0, -1.0)
+    scale = np.where(small, np.abs(J), 1.0)
+    # J C^-1 = adj(C) / J on big tets; |J| J C^-1 = sign(J) adj(C) on small ones
+    jc = np.where(small, sgn, 1.0 / np.where(small, 1.0, J))[:, None, None] * adj
+    Sst = (scale * mu * (1.0 - 1.0 / (IC + 1.0)))[:, None, None] * Cpi \
+        + (lam * (J - al))[:, None, None] * jc
     t = mesh.tets
     q = np.stack([mesh.X[t[:, b]] - mesh.X[t[:, a]] for a, b in LOCAL_EDGES], axis=1)
     q /= np.linalg.norm(q, axis=2, keepdims=True)
-    return np.einsum("tki,tij,tkj->tk", q, Sst, q)
+    return np.einsum("tki,tij,tkj->tk", q, Sst, q), small, J
 
 
-def energy_fraction(mesh: Mesh, x: np.ndarray, zeta: np.ndarray, Ep: np.ndarray | None = None):
+def edge_normal_stress(mesh: Mesh, x: np.ndarray, Cp: np.ndarray | None = None) -> np.ndarray:
+    """The unscaled sigma_k (m,6) (infinite on an exactly flat tet)."""
+    sig, small, J = scaled_edge_stress(mesh, x, Cp)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(small[:, None], sig / np.abs(J)[:, None], sig)
+
+
+def energy_fraction(mesh: Mesh, x: np.ndarray, zeta: np.ndarray, Cp: np.ndarray | None = None):
     """chi of Eq. 25 with sigma' = (1 - zeta) sigma; 0 for disconnected tets;
     n_unbroken/6 when the stress is (numerically) zero.  Returns (chi, mask)."""
     zt = zeta[mesh.tet_edge]
@@ -411,11 +506,14 @@ def energy_fraction(mesh: Mesh, x: np.ndarray, zeta: np.ndarray, Ep: np.ndarray 
     chi = np.ones(mesh.tets.shape[0])
     dmg = mask != 0
     if np.any(dmg):
-        sig = np.abs(edge_normal_stress(mesh, x, Ep))
+        sig, small, J = scaled_edge_stress(mesh, x, Cp)
+        sig = np.abs(sig)
         den = sig.sum(axis=1)
         num = np.where(zt, 0.0, sig).sum(axis=1)
-        small = den <= 1e-12 * (mesh.mu + mesh.lam)
-        ratio = np.where(small, (6 - zt.sum(axis=1)) / 6.0, num / np.where(small, 1.0, den))
+        # the zero-stress test on the unscaled stresses: |J| sum|sigma| on small tets
+        lim = 1e-12 * (mesh.mu + mesh.lam) * np.where(small, np.abs(J), 1.0)
+        zero = den <= lim
+        ratio = np.where(zero, (6 - zt.sum(axis=1)) / 6.0, num / np.where(zero, 1.0, den))
         chi = np.where(dmg, ratio, 1.0)
     chi = np.where(DISCONNECTED[mask], 0.0, chi)
     return chi, mask
@@ -441,13 +539,13 @@ def assemble_stiffness(n: int, tets: np.ndarray, Ke: np.ndarray) -> sp.csr_matri
 
 def restoring_forces(mesh: Mesh, state: State) -> np.ndarray:
     """f* = sum_e chi_e f_e at the state's positions and labels (n,3)."""
-    chi, _ = energy_fraction(mesh, state.x, state.zeta, state.Ep)
-    el = element(mesh, state.x, state.Ep)
+    chi, _ = energy_fraction(mesh, state.x, state.zeta, state.Cp)
+    el = element(mesh, state.x, state.Cp)
     return scatter_forces(mesh.X.shape[0], mesh.tets, element_forces(mesh, el, chi))
 
 
-def total_energy(mesh: Mesh, x: np.ndarray, chi: np.ndarray, Ep=None) -> float:
-    el = element(mesh, x, Ep)
+def total_energy(mesh: Mesh, x: np.ndarray, chi: np.ndarray, Cp=None) -> float:
+    el = element(mesh, x, Cp)
     return float(np.sum(mesh.V * chi * el.psi))
 
 
@@ -460,14 +558,14 @@ class System:
     stats: dict = field(default_factory=dict)
 
 
-def build_system(mesh: Mesh, state: State, dir_nodes, dir_vel, zeta: np.ndarray, Ep) -> System:
+def build_system(mesh: Mesh, state: State, dir_nodes, dir_vel, zeta: np.ndarray, Cp) -> System:
     """A = M + dt (aM + bK*) + dt^2 K*;
     b = dt (f_ext + f* - (aM + bK*) v) - dt^2 K* v; then Dirichlet elimination."""
     p = mesh.params
     n = mesh.X.shape[0]
     dt = p["dt"]
-    chi, mask = energy_fraction(mesh, state.x, zeta, Ep)
-    el = element(mesh, state.x, Ep)
+    chi, mask = energy_fraction(mesh, state.x, zeta, Cp)
+    el = element(mesh, state.x, Cp)
     f = scatter_forces(n, mesh.tets, element_forces(mesh, el, chi)).ravel()
     K = assemble_stiffness(n, mesh.tets, element_stiffness(mesh, el, chi))
     M = mesh.M
@@ -491,7 +589,7 @@ def build_system(mesh: Mesh, state: State, dir_nodes, dir_vel, zeta: np.ndarray,
         b[cdof] = dv_c.ravel()
     A.eliminate_zeros()
     stats = dict(chi_zero_tets=int(np.sum(chi == 0.0)),
-                 degenerate_tets=int(np.sum(np.abs(el.J) < 0.05)))
+                 degenerate_tets=int(np.sum(el.small)))
     return System(A, b, dv_c, chi, stats)
 
 
@@ -547,8 +645,8 @@ def step(mesh: Mesh, state: State, dir_nodes, dir_vel, override: dict | None = N
     (new_state, stats); on non-convergence returns (state unchanged, stats)."""
     p = mesh.params
     zeta, near = damage_update(mesh, state.x, state.zeta, override=override)
-    Ep = plastic_update(mesh, state.x, state.Ep)
-    sysm = build_system(mesh, state, dir_nodes, dir_vel, zeta, Ep)
+    Cp = plastic_update(mesh, state.x, state.Cp)
+    sysm = build_system(mesh, state, dir_nodes, dir_vel, zeta, Cp)
     if solver == "direct":
         import scipy.sparse.linalg as spla
         dv = spla.spsolve(sysm.A.tocsc(), sysm.b)
@@ -564,7 +662,7 @@ def step(mesh: Mesh, state: State, dir_nodes, dir_vel, override: dict | None = N
         return state, stats
     v = state.v + dv.reshape(-1, 3)
     x = state.x + p["dt"] * v
-    return State(x, v, zeta, Ep, state.step + 1), stats
+    return State(x, v, zeta, Cp, state.step + 1), stats
 
 
 def run(mesh: Mesh, state: State, dir_nodes, dir_vel, n_steps: int, overrides=None):

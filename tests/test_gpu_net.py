@@ -47,7 +47,7 @@ def oracle_system(prob, U, V):
     st.v = V.copy()
     O.break_pairs(mesh, st, prob.broken_pairs)
     zeta, _ = O.damage_update(mesh, st.x, st.zeta)
-    sysm = O.build_system(mesh, st, prob.dir_nodes, prob.dir_vel, zeta, st.Ep)
+    sysm = O.build_system(mesh, st, prob.dir_nodes, prob.dir_vel, zeta, st.Cp)
     a, P, PT, fac = N.system_inputs(mesh, st.x, zeta, sysm.A, prob.dir_nodes)
     return a, P, PT, fac, sysm
 
@@ -162,7 +162,7 @@ def test_factorised_pcg_tracks_oracle_iterations():
     st = O.initial_state(mesh)
     O.break_pairs(mesh, st, prob.broken_pairs)
     zeta, _ = O.damage_update(mesh, st.x, st.zeta)
-    sysm = O.build_system(mesh, st, prob.dir_nodes, prob.dir_vel, zeta, st.Ep)
+    sysm = O.build_system(mesh, st, prob.dir_nodes, prob.dir_vel, zeta, st.Cp)
     a, P, PT, fac = N.system_inputs(mesh, st.x, zeta, sysm.A, prob.dir_nodes)
     Gd, Gl, _ = N.factor_blocks(N.forward(w.astype(np.float64), a, P)["o"], w.astype(np.float64), fac)
     G = N.G_matrix(fac, Gd, Gl)

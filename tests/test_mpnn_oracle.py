@@ -21,7 +21,7 @@ def small_system(seed=0, n=2):
     st.v = 0.1 * rng.normal(size=prob.X.shape)
     st.zeta = rng.random(mesh.edges.shape[0]) < 0.2
     zeta, _ = O.damage_update(mesh, st.x, st.zeta)
-    sysm = O.build_system(mesh, st, prob.dir_nodes, prob.dir_vel, zeta, st.Ep)
+    sysm = O.build_system(mesh, st, prob.dir_nodes, prob.dir_vel, zeta, st.Cp)
     a, P, PT, fac = N.system_inputs(mesh, st.x, zeta, sysm.A, prob.dir_nodes)
     return a, P, PT, fac, sysm.A.tocsr(), sysm.b, mesh
 
@@ -144,7 +144,7 @@ def test_damped_factor_reduces_cg_iterations():
     st = O.initial_state(mesh)
     O.break_pairs(mesh, st, prob.broken_pairs)
     zeta, _ = O.damage_update(mesh, st.x, st.zeta)
-    sysm = O.build_system(mesh, st, prob.dir_nodes, prob.dir_vel, zeta, st.Ep)
+    sysm = O.build_system(mesh, st, prob.dir_nodes, prob.dir_vel, zeta, st.Cp)
     a, P, PT, fac = N.system_inputs(mesh, st.x, zeta, sysm.A, prob.dir_nodes)
     w = N.init_weights(0)
     w[N.offset("be"):N.offset("be") + 9] = 2.0 * np.arctanh(0.75 / 2.0) * np.eye(3).ravel()

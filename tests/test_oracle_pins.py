@@ -415,7 +415,7 @@ def test_pcg_step_equals_dense_solve(n):
     st.x = prob.X + 0.002 * rng.normal(size=prob.X.shape)
     s1, h1 = O.step(mesh, st, prob.dir_nodes, prob.dir_vel)
     sysm = O.build_system(mesh, st, prob.dir_nodes, prob.dir_vel,
-                          O.damage_update(mesh, st.x, st.zeta)[0], st.Ep)
+                          O.damage_update(mesh, st.x, st.zeta)[0], st.Cp)
     dv = np.linalg.solve(sysm.A.toarray(), sysm.b)
     np.testing.assert_allclose(s1.v, st.v + dv.reshape(-1, 3), rtol=1e-9, atol=1e-12)
     assert h1["rel_residual"] <= 1e-12
