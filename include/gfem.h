@@ -117,9 +117,14 @@ gf_status gf_get_sizes(const gf_mesh* m, int32_t* n_nodes, int32_t* n_tets, int3
 /* Canonical edge list: ij_out holds n_edges*2 node ids, i < j, lexicographic. */
 gf_status gf_get_edges(const gf_mesh* m, int32_t* ij_out);
 
-/* Prescribed velocities: nodes[n] (caller ids, distinct), vel[n*3] m/s.  These
- * nodes move at exactly that velocity every step (their rows and columns are
- * eliminated from the solve).  Replaces any previous set; n = 0 clears it. */
+/* Prescribed velocities (the fixed or moved points of the experiments of
+ * Sec. 5.1, and Algorithm 1's external conditions applied before the system is
+ * built): nodes[n] (caller ids, distinct), vel[n*3] m/s.  These nodes move at
+ * exactly that velocity every step: their rows and columns are eliminated
+ * from the backward-Euler system (right-hand side b_f -= A_fc dv_c, identity
+ * rows, b_c = dv_c).  Replaces any previous set; n = 0 clears it.  GF_EINVAL
+ * for an id out of range, a repeated id or a non-finite velocity (the set is
+ * then unchanged). */
 gf_status gf_set_dirichlet(gf_mesh* m, const int32_t* nodes, int32_t n, const double* vel);
 
 /* OR labels into the damage variable zeta (Eq. 21): zeta[n_edges] in
@@ -135,12 +140,25 @@ gf_status gf_set_edge_damage(gf_mesh* m, const uint8_t* zeta);
  * in it is reported by the next such call. */
 gf_status gf_step(gf_mesh* m, int32_t n_steps, gf_step_stats* stats);
 
-/* Current positions (rest + displacement), n_nodes*3 doubles, caller order. */
+/* Current positions x = X + u after the last committed step (Algorithm 1's
+ * update x += dt v of Sec. 4.3), n_nodes*3 doubles, caller order, into a
+ * caller-owned buffer.  Waits for the library's stream. */
 gf_status gf_get_positions(const gf_mesh* m, double* xyz_out);
 /* Current velocities, n_nodes*3 doubles, caller order. */
 gf_status gf_get_velocities(const gf_mesh* m, double* vel_out);
-/* Damage labels, n_edges bytes (0/1), canonical edge order. */
+/* Damage labels zeta of Eq. 21 after the last committed step (1 = broken,
+ * irreversible, Sec. 3.3), n_edges bytes (0/1), canonical edge order, into a
+ * caller-owned buffer.  Waits for the library's stream. */
 gf_status gf_get_edge_damage(const gf_mesh* m, uint8_t* zeta_out);
+
+/* Edges whose Green strain was within 1e-6 of the damage threshold in the
+ * last damage pass (Eq. 21: labels there depend on rounding, so they are
+ * reported rather than graded): canonical edge ids, ascending.  At most
+ * `capacity` ids are written to the caller-owned ids_out (may be NULL when
+ * capacity is 0); *n_out receives the total count.  The last damage pass is
+ * the one of the last gf_step attempt (committed or not), gf_eval_forces or
+ * gf_get_system. */
+gf_status gf_get_near_threshold_edges(const gf_mesh* m, int32_t* ids_out, int32_t capacity, int32_t* n_out);
 
 /* Test hook: restoring force f* = sum_e chi_e f_e (Eq. 12, 32) at the current
  * state and labels, n_nodes*3 doubles, caller order. */
@@ -161,6 +179,12 @@ gf_status gf_get_system(gf_mesh* m, int32_t* bi_out, int32_t* bj_out, double* va
  * restored state is solved as from a fresh mesh. */
 gf_status gf_get_state(const gf_mesh* m, void* buf, size_t* bytes);
 gf_status gf_set_state(gf_mesh* m, const void* buf, size_t bytes);
+
+/* Test hook (split precision only): always = 1 re-runs every step in FP64
+ * (element pass, blocks, block-Jacobi PCG into FP64 buffers; the committed
+ * state stays split), the path taken automatically when a step's FP32
+ * operator cannot be solved; always = 0 restores the automatic choice. */
+gf_status gf_set_fp64_rerun(gf_mesh* m, int32_t always);
 
 /* Per-kernel device timing with HIP events on the library's stream
  * (fills gf_step_stats.kernel_us / n_launch); the PCG kernels' events are
@@ -198,13 +222,27 @@ gf_status gf_net_create(uint64_t seed, gf_net** out);
 gf_status gf_net_destroy(gf_net* net);
 /* Number of FP32 parameters (same for every network). */
 gf_status gf_net_num_params(int32_t* n);
-/* FP32 master weights in this order: W0 (64x8), b0 (64), then for each of 3
- * layers W (64x128, columns 0-63 act on h, 64-127 on the neighbour mean), b (64),
- * then the node head Wh (24x64), bh (24) (outputs 0-5: L_i, 6-14: s_i,
- * 15-23: t_i) and the edge term We (9x3), be (9), with
- * W_ij = s_i + t_j + We f_ij + be (row-major 3x3); matrices row-major [out][in]. */
-gf_status gf_net_get_weights(const gf_net* net, float* w_out);
-gf_status gf_net_set_weights(gf_net* net, const float* w); /* also resets the optimiser */
+/* Weights travel as a self-describing blob of exactly 16 + 4 * n_params bytes:
+ * a header of four little-endian uint32 (magic 0x574e4647 "GFNW", format
+ * version 1, parameter count = gf_net_num_params, element type 0 = FP32)
+ * followed by the FP32 master weights in this order: W0 (64x8), b0 (64), then
+ * for each of 3 layers W (64x128, columns 0-63 act on h, 64-127 on the
+ * neighbour mean), b (64), then the node head Wh (24x64), bh (24) (outputs 0-5:
+ * L_i, 6-14: s_i, 15-23: t_i) and the edge term We (9x3), be (9), with
+ * W_ij = s_i + t_j + We f_ij + be (row-major 3x3); matrices row-major [out][in].
+ *
+ * gf_net_check_weights: host-only validation of a blob (no device needed).
+ * Returns GF_EINVAL when the blob is null, shorter than its header, has
+ * another magic, version, element type or parameter count, when bytes differs
+ * from 16 + 4 * n_params, or when a weight is not finite.
+ * gf_net_get_weights: blob == NULL stores the size in *bytes; otherwise
+ * *bytes is the capacity of the caller-owned buffer (GF_EINVAL if too
+ * small) and receives the size written.
+ * gf_net_set_weights: copies a blob that passes gf_net_check_weights (the
+ * network is unchanged otherwise) and resets the optimiser. */
+gf_status gf_net_check_weights(const void* blob, size_t bytes);
+gf_status gf_net_get_weights(const gf_net* net, void* blob, size_t* bytes);
+gf_status gf_net_set_weights(gf_net* net, const void* blob, size_t bytes);
 /* Attach (borrowed: must outlive its use) or detach (NULL) the network used by
  * GF_PC_LEARNED steps, and select the preconditioner of the following steps. */
 gf_status gf_set_precond_net(gf_mesh* m, gf_net* net);

@@ -125,6 +125,7 @@ struct gf_mesh {
   double *edge_S = nullptr, *edge_mass = nullptr;
   uint8_t* zeta[2] = {nullptr, nullptr};
   int zcur = 0;
+  int32_t* near_ids = nullptr;  // near-threshold edges of the last damage pass (internal ids)
   int32_t *edge_ptr = nullptr, *edge_slot = nullptr, *blk_ij = nullptr, *blk_ji = nullptr;
   void* edge_w = nullptr;
   // block matrix
@@ -164,6 +165,7 @@ struct gf_mesh {
   int learned_skip = 0;        // steps left that use block-Jacobi directly after a rejected learned solve
   int learned_backoff = 4;     // length of the next such pause (doubles per rejection, up to 64)
   bool timing = false;
+  bool force_fp64 = false;  // test hook: re-run every split step in FP64
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<TimeRec> recs;
@@ -259,8 +261,8 @@ template <typename T>
 void alloc_precision(gf_mesh* M) {
   const int n = M->n, m = M->m;
   M->val = M->al.get<T>((size_t)9 * M->nbp);
-  M->contrib = M->al.get<T>((size_t)60 * m);
-  M->edge_w = M->al.get<T>(M->ne);
+  M->contrib = M->al.get<gfem::Rec<T>>((size_t)6 * m);
+  M->edge_w = M->al.get<double>(M->ne);
   M->binv = M->al.get<T>((size_t)6 * n);
   if (M->plastic) {
     M->pl[0] = M->al.get<T>((size_t)6 * m);
@@ -285,27 +287,38 @@ void assemble(gf_mesh* M, bool flow, d4* f_out) {
   const int zi = M->zcur, zo = 1 - M->zcur;
   M->timed(0, -1, 0, [&] {
     gfem::launch_damage(s, M->ne, M->edges, M->X, M->U, M->edge_S, M->zeta[zi], M->zeta[zo], M->p.damage_strain,
-                        M->ctr);
+                        M->ctr, M->near_ids);
   });
-  gfem::ElemConst ec{M->mu, M->lam, M->alpha_m1, flow ? M->p.yield_strain : 0.0};
-  const T* pin = M->plastic ? static_cast<const T*>(M->pl[M->plcur]) : nullptr;
-  T* pout = (M->plastic && flow) ? static_cast<T*>(M->pl[1 - M->plcur]) : nullptr;
+  gfem::ElemConst ec{M->mu, M->lam, M->alpha_m1};
+  const T* pl = nullptr;
+  if (M->plastic) {
+    if (flow) {
+      // plastic flow at x_n into the spare buffer, which the element pass reads
+      M->timed(1, -1, 0, [&] {
+        gfem::launch_plastic<T>(s, M->m, M->tets, M->X, M->U, static_cast<const T*>(M->pl[M->plcur]),
+                                static_cast<T*>(M->pl[1 - M->plcur]), M->p.yield_strain);
+      });
+      pl = static_cast<const T*>(M->pl[1 - M->plcur]);
+    } else {
+      pl = static_cast<const T*>(M->pl[M->plcur]);
+    }
+  }
   M->timed(1, -1, 0, [&] {
-    gfem::launch_element<T>(s, M->m, M->tets, M->tet_edge, M->flip, M->X, M->U, M->zeta[flow ? zo : zi], pin,
-                            pout, ec, static_cast<T*>(M->contrib), M->ctr);
+    gfem::launch_element<T>(s, M->m, M->tets, M->tet_edge, M->flip, M->X, M->U, M->zeta[flow ? zo : zi], pl, ec,
+                            static_cast<gfem::Rec<T>*>(M->contrib), M->ctr);
   });
   const double dt = M->p.dt;
   const double mass_fac = 1.0 + dt * M->p.rayleigh_alpha;
   const double stiff_fac = dt * dt + dt * M->p.rayleigh_beta;
   M->timed(2, -1, 0, [&] {
-    gfem::launch_edge<T>(s, M->ne, M->edge_ptr, M->edge_slot, static_cast<const T*>(M->contrib),
+    gfem::launch_edge<T>(s, M->ne, M->edge_ptr, M->edge_slot, static_cast<const gfem::Rec<T>*>(M->contrib),
                          M->edge_mass, mass_fac, stiff_fac, M->blk_ij, M->blk_ji, static_cast<T*>(M->val), M->nbp,
-                         static_cast<T*>(M->edge_w));
+                         static_cast<double*>(M->edge_w));
   });
   gfem::RowConst rc{dt, M->p.rayleigh_alpha, mass_fac, {M->p.gravity[0], M->p.gravity[1], M->p.gravity[2]}};
   M->timed(2, -1, 0, [&] {
     gfem::launch_row<T>(s, M->n, M->Gs, M->mat(), M->diag_blk, M->blk_edge, M->edge_mass,
-                        static_cast<const T*>(M->edge_w), M->lumped, M->X, M->U, M->V, M->dflag, M->dvel, rc,
+                        static_cast<const double*>(M->edge_w), M->lumped, M->X, M->U, M->V, M->dflag, M->dvel, rc,
                         static_cast<T*>(M->val), M->b, M->X64, static_cast<T*>(M->binv), f_out, M->part_a);
   });
   M->check_launch();
@@ -590,7 +603,7 @@ void ensure_esc(gf_mesh* M) {
   const size_t n = M->n, m = M->m;
   gf_mesh::PrecBufs& b = M->esc;
   b.val = M->al.get<double>(9 * (size_t)M->nbp);
-  b.contrib = M->al.get<double>(60 * m);
+  b.contrib = M->al.get<gfem::Rec<double>>(6 * m);
   b.edge_w = M->al.get<double>(M->ne);
   b.binv = M->al.get<double>(6 * n);
   b.pl[0] = M->plastic ? M->al.get<double>(6 * m) : nullptr;
@@ -675,7 +688,7 @@ gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
     }
     int escalated = 0;
     if constexpr (std::is_same<T, float>::value) {
-      if (!r.ok) {
+      if (!r.ok || M->force_fp64) {
         escalated = 1;
         const int prev_inner = r.inner, prev_outer = r.outer;
         r = fp64_rerun(M);
@@ -826,6 +839,7 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     M->edge_mass = upload(M, T.edge_mass);
     M->zeta[0] = M->al.get<uint8_t>(T.ne);
     M->zeta[1] = M->al.get<uint8_t>(T.ne);
+    M->near_ids = M->al.get<int32_t>(T.ne);
     M->edge_ptr = upload(M, T.edge_ptr);
     M->edge_slot = upload(M, T.edge_slot);
     M->blk_ij = upload(M, T.blk_ij);
@@ -982,6 +996,27 @@ gf_status gf_get_edge_damage(const gf_mesh* m, uint8_t* zeta_out) {
   })
 }
 
+gf_status gf_get_near_threshold_edges(const gf_mesh* m, int32_t* ids_out, int32_t capacity, int32_t* n_out) {
+  if (!m || !n_out || capacity < 0 || (capacity > 0 && !ids_out))
+    return fail(GF_EINVAL, "gf_get_near_threshold_edges: bad argument");
+  GF_TRY({
+    gfem::Counters c;
+    hchk(hipStreamSynchronize(m->stream), "sync");
+    hchk(hipMemcpy(&c.near_n, &m->ctr->near_n, sizeof(int), hipMemcpyDeviceToHost), "D2H");
+    const int n = std::min(std::max(c.near_n, 0), m->ne);
+    std::vector<int32_t> h(n);
+    if (n) hchk(hipMemcpy(h.data(), m->near_ids, sizeof(int32_t) * n, hipMemcpyDeviceToHost), "D2H");
+    // internal -> canonical edge ids, ascending
+    std::vector<int32_t> inv(m->ne);
+    for (int c2 = 0; c2 < m->ne; ++c2) inv[m->topo.edge_internal[c2]] = c2;
+    for (int32_t& e : h) e = inv[e];
+    std::sort(h.begin(), h.end());
+    for (int i = 0; i < std::min(n, (int)capacity); ++i) ids_out[i] = h[i];
+    *n_out = n;
+    return GF_OK;
+  })
+}
+
 gf_status gf_eval_forces(gf_mesh* m, double* f_out) {
   if (gf_status s = guard(m, "gf_eval_forces")) return s;
   if (!f_out) return fail(GF_EINVAL, "gf_eval_forces: null output");
@@ -1133,6 +1168,13 @@ gf_status gf_set_state(gf_mesh* m, const void* buf, size_t bytes) {
   })
 }
 
+gf_status gf_set_fp64_rerun(gf_mesh* m, int32_t always) {
+  if (gf_status s = guard(m, "gf_set_fp64_rerun")) return s;
+  if (always && !m->split) return fail(GF_EINVAL, "gf_set_fp64_rerun: needs the split precision mode");
+  m->force_fp64 = always != 0;
+  return GF_OK;
+}
+
 gf_status gf_set_timing(gf_mesh* m, int32_t on) {
   if (gf_status s = guard(m, "gf_set_timing")) return s;
   m->timing = on != 0;
@@ -1240,20 +1282,68 @@ gf_status gf_net_destroy(gf_net* net) {
   return GF_OK;
 }
 
-gf_status gf_net_get_weights(const gf_net* net, float* w_out) {
-  if (!net || !w_out) return fail(GF_EINVAL, "gf_net_get_weights: null argument");
-  std::memcpy(w_out, net->host.data(), sizeof(float) * gfem::kNetParams);
+namespace {
+// Weight blob: header (magic "GFNW", format version, parameter count, element
+// type 0 = FP32) followed by the FP32 master weights in the documented order.
+struct NetBlobHeader {
+  uint32_t magic, version, n_params, dtype;
+};
+constexpr uint32_t kNetMagic = 0x574e4647;  // "GFNW"
+constexpr uint32_t kNetBlobVersion = 1;
+constexpr size_t kNetBlobBytes = sizeof(NetBlobHeader) + sizeof(float) * (size_t)gfem::kNetParams;
+
+// Host-only validation of a weight blob; on success *w points at its weights.
+gf_status check_net_blob(const void* blob, size_t bytes, const float** w, const char* who) {
+  if (!blob) return fail(GF_EINVAL, std::string(who) + ": null blob");
+  if (bytes < sizeof(NetBlobHeader)) return fail(GF_EINVAL, std::string(who) + ": blob shorter than its header");
+  NetBlobHeader h;
+  std::memcpy(&h, blob, sizeof h);
+  if (h.magic != kNetMagic) return fail(GF_EINVAL, std::string(who) + ": not a weight blob (bad magic)");
+  if (h.version != kNetBlobVersion) return fail(GF_EINVAL, std::string(who) + ": unsupported blob version");
+  if (h.dtype != 0) return fail(GF_EINVAL, std::string(who) + ": unsupported weight type");
+  if (h.n_params != (uint32_t)gfem::kNetParams)
+    return fail(GF_EINVAL, std::string(who) + ": parameter count does not match this network");
+  if (bytes != kNetBlobBytes) return fail(GF_EINVAL, std::string(who) + ": blob size does not match its header");
+  const float* p = reinterpret_cast<const float*>(static_cast<const char*>(blob) + sizeof h);
+  for (int i = 0; i < gfem::kNetParams; ++i) {
+    float v;
+    std::memcpy(&v, p + i, sizeof v);
+    if (!std::isfinite(v)) return fail(GF_EINVAL, std::string(who) + ": non-finite weight");
+  }
+  if (w) *w = p;
+  return GF_OK;
+}
+}  // namespace
+
+gf_status gf_net_check_weights(const void* blob, size_t bytes) {
+  g_err.clear();
+  return check_net_blob(blob, bytes, nullptr, "gf_net_check_weights");
+}
+
+gf_status gf_net_get_weights(const gf_net* net, void* blob, size_t* bytes) {
+  if (!net || !bytes) return fail(GF_EINVAL, "gf_net_get_weights: null argument");
+  if (!blob) {
+    *bytes = kNetBlobBytes;
+    return GF_OK;
+  }
+  if (*bytes < kNetBlobBytes) return fail(GF_EINVAL, "gf_net_get_weights: buffer too small");
+  const NetBlobHeader h{kNetMagic, kNetBlobVersion, (uint32_t)gfem::kNetParams, 0};
+  std::memcpy(blob, &h, sizeof h);
+  std::memcpy(static_cast<char*>(blob) + sizeof h, net->host.data(), sizeof(float) * gfem::kNetParams);
+  *bytes = kNetBlobBytes;
   return GF_OK;
 }
 
-gf_status gf_net_set_weights(gf_net* net, const float* w) {
-  if (!net || !w) return fail(GF_EINVAL, "gf_net_set_weights: null argument");
-  for (int i = 0; i < gfem::kNetParams; ++i)
-    if (!std::isfinite(w[i])) return fail(GF_EINVAL, "gf_net_set_weights: non-finite weight");
+gf_status gf_net_set_weights(gf_net* net, const void* blob, size_t bytes) {
+  if (!net) return fail(GF_EINVAL, "gf_net_set_weights: null network");
+  const float* w = nullptr;
+  if (gf_status st = check_net_blob(blob, bytes, &w, "gf_net_set_weights")) return st;
   GF_TRY({
     hchk(hipDeviceSynchronize(), "hipDeviceSynchronize");
-    net->host.assign(w, w + gfem::kNetParams);
-    hchk(hipMemcpy(net->P.master, w, sizeof(float) * gfem::kNetParams, hipMemcpyHostToDevice), "H2D");
+    std::vector<float> hw(gfem::kNetParams);
+    std::memcpy(hw.data(), w, sizeof(float) * gfem::kNetParams);
+    net->host = hw;
+    hchk(hipMemcpy(net->P.master, hw.data(), sizeof(float) * gfem::kNetParams, hipMemcpyHostToDevice), "H2D");
     hchk(hipMemset(net->P.adam_m, 0, sizeof(float) * gfem::kNetParams), "hipMemset");
     hchk(hipMemset(net->P.adam_v, 0, sizeof(float) * gfem::kNetParams), "hipMemset");
     net->adam_t = 0;

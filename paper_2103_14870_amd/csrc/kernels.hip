@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_damage(int ne, const int2* __restr
                                                      const double* __restrict__ S,
                                                      const uint8_t* __restrict__ z_in,
                                                      uint8_t* __restrict__ z_out, double thr,
-                                                     Counters* ctr) {
+                                                     Counters* ctr, int32_t* __restrict__ near_ids) {
   int e = blockIdx.x * kThreads + threadIdx.x;
   bool act = e < ne;
   bool hit = false, was = false, near = false;
@@ -146,23 +146,203 @@ __global__ __launch_bounds__(kThreads) void k_damage(int ne, const int2* __restr
   }
   const bool pr[3] = {act && hit && !was, act && (hit || was), act && near};
   block_counts<3>(ctr, kNewBroken, pr);
+  // near-threshold edges: one atomic per wave reserves the wave's entries
+  const unsigned long long bal = __ballot(act && near);
+  if (bal) {
+    const int l = threadIdx.x & 63;
+    int base = 0;
+    if (l == 0) base = atomicAdd(&ctr->near_n, (int)__popcll(bal));
+    base = __shfl(base, 0, 64);
+    if (act && near) near_ids[base + (int)__popcll(bal & ((1ull << l) - 1ull))] = e;
+  }
+}
+
+// ---------------------------------------------------------------- plasticity
+
+// Cyclic Jacobi eigen-decomposition of a symmetric 3x3 (FP64): on return a
+// is diagonal (the eigenvalues) and the columns of v are the eigenvectors.
+__device__ __forceinline__ void jacobi_rot(double (&a)[3][3], double (&v)[3][3], int p, int q) {
+  const double apq = a[p][q];
+  if (apq == 0.0) return;
+  const double th = (a[q][q] - a[p][p]) / (2.0 * apq);
+  const double tn = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+  const double c = 1.0 / sqrt(tn * tn + 1.0), s = tn * c;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {  // columns p, q
+    const double akp = a[k][p], akq = a[k][q];
+    a[k][p] = c * akp - s * akq;
+    a[k][q] = s * akp + c * akq;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {  // rows p, q
+    const double apk = a[p][k], aqk = a[q][k];
+    a[p][k] = c * apk - s * aqk;
+    a[q][k] = s * apk + c * aqk;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double vkp = v[k][p], vkq = v[k][q];
+    v[k][p] = c * vkp - s * vkq;
+    v[k][q] = s * vkp + c * vkq;
+  }
+}
+
+__device__ __forceinline__ void sym_eig3(double (&a)[3][3], double (&v)[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) v[i][j] = i == j ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const double dg = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (!(off > 1e-32 * dg)) break;
+    jacobi_rot(a, v, 0, 1);
+    jacobi_rot(a, v, 0, 2);
+    jacobi_rot(a, v, 1, 2);
+  }
+}
+
+// One thread per tet (ductile workload).  The plastic state is the plastic
+// rest shape on the Gram matrix of the tet's edges from node 0,
+// Gp = G0 + P (P = 0 before any flow), with det Gp = det G0 (volume-
+// preserving flow).  The elastic stretches are the generalised eigenvalues of
+// G v = lam Gp v; their Hencky strains h = log(lam)/2 have deviator
+// d = h - mean(h).  When |d| exceeds the yield strain, d is scaled back onto
+// the yield surface and Gp is replaced by L W diag(lam/lam') W^T L^T
+// (Gp = L L^T, L^-1 G L^-T = W diag(lam) W^T): the same eigenvectors, the
+// returned elastic stretches lam', the same determinant.  A flat or inverted
+// tet (det F < 0.05) keeps its plastic state.  FP64 throughout.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_plastic(int m, const int4* __restrict__ tets,
+                                                      const d4* __restrict__ X, const d4* __restrict__ U,
+                                                      const T* __restrict__ pl_in, T* __restrict__ pl_out,
+                                                      double ey) {
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= m) return;
+  const int4 nd = tets[t];
+  const int ids[4] = {nd.x, nd.y, nd.z, nd.w};
+  const d4 X0 = X[nd.x], U0 = U[nd.x];
+  double Dm[3][3], Ds[3][3];  // [edge from node 0][component]
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const d4 Xk = X[ids[k + 1]], Uk = U[ids[k + 1]];
+    Dm[k][0] = Xk.x - X0.x;
+    Dm[k][1] = Xk.y - X0.y;
+    Dm[k][2] = Xk.z - X0.z;
+    Ds[k][0] = Dm[k][0] + (Uk.x - U0.x);
+    Ds[k][1] = Dm[k][1] + (Uk.y - U0.y);
+    Ds[k][2] = Dm[k][2] + (Uk.z - U0.z);
+  }
+  double P[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) P[c] = (double)pl_in[(size_t)c * m + t];
+  auto det3 = [](const double (&a)[3][3]) {
+    return a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) - a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+           a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+  };
+  const double J = det3(Ds) / det3(Dm);
+  bool flow = J >= 0.05;
+  double Pn[6] = {P[0], P[1], P[2], P[3], P[4], P[5]};
+  if (flow) {
+    constexpr int R[6] = {0, 1, 2, 0, 0, 1}, C[6] = {0, 1, 2, 1, 2, 2};
+    double G0[6], G[6], Gp[3][3];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int i = R[c], j = C[c];
+      G0[c] = Dm[i][0] * Dm[j][0] + Dm[i][1] * Dm[j][1] + Dm[i][2] * Dm[j][2];
+      G[c] = Ds[i][0] * Ds[j][0] + Ds[i][1] * Ds[j][1] + Ds[i][2] * Ds[j][2];
+    }
+    double Gf[3][3];
+    Gf[0][0] = G[0]; Gf[1][1] = G[1]; Gf[2][2] = G[2];
+    Gf[0][1] = Gf[1][0] = G[3]; Gf[0][2] = Gf[2][0] = G[4]; Gf[1][2] = Gf[2][1] = G[5];
+    Gp[0][0] = G0[0] + P[0]; Gp[1][1] = G0[1] + P[1]; Gp[2][2] = G0[2] + P[2];
+    Gp[0][1] = Gp[1][0] = G0[3] + P[3]; Gp[0][2] = Gp[2][0] = G0[4] + P[4]; Gp[1][2] = Gp[2][1] = G0[5] + P[5];
+    // Cholesky Gp = L L^T
+    double L[3][3] = {};
+    L[0][0] = sqrt(Gp[0][0]);
+    L[1][0] = Gp[1][0] / L[0][0];
+    L[2][0] = Gp[2][0] / L[0][0];
+    L[1][1] = sqrt(Gp[1][1] - L[1][0] * L[1][0]);
+    L[2][1] = (Gp[2][1] - L[2][0] * L[1][0]) / L[1][1];
+    L[2][2] = sqrt(Gp[2][2] - L[2][0] * L[2][0] - L[2][1] * L[2][1]);
+    // Li = L^-1 (lower triangular)
+    double Li[3][3] = {};
+    Li[0][0] = 1.0 / L[0][0];
+    Li[1][1] = 1.0 / L[1][1];
+    Li[2][2] = 1.0 / L[2][2];
+    Li[1][0] = -L[1][0] * Li[0][0] * Li[1][1];
+    Li[2][1] = -L[2][1] * Li[1][1] * Li[2][2];
+    Li[2][0] = -(L[2][0] * Li[0][0] + L[2][1] * Li[1][0]) * Li[2][2];
+    // S = Li G Li^T
+    double T1[3][3], S[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) T1[i][j] = Li[i][0] * Gf[0][j] + Li[i][1] * Gf[1][j] + Li[i][2] * Gf[2][j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) S[i][j] = T1[i][0] * Li[j][0] + T1[i][1] * Li[j][1] + T1[i][2] * Li[j][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 3; ++j) S[i][j] = S[j][i] = 0.5 * (S[i][j] + S[j][i]);
+    double W[3][3];
+    sym_eig3(S, W);
+    const double lam[3] = {S[0][0], S[1][1], S[2][2]};
+    flow = lam[0] > 0.0 && lam[1] > 0.0 && lam[2] > 0.0;
+    if (flow) {
+      double h[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) h[i] = 0.5 * log(lam[i]);
+      const double hm = (h[0] + h[1] + h[2]) / 3.0;
+      const double d0 = h[0] - hm, d1 = h[1] - hm, d2 = h[2] - hm;
+      const double ndv = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      flow = ndv > ey;
+      if (flow) {
+        const double sc = ey / ndv;
+        const double hn[3] = {hm + d0 * sc, hm + d1 * sc, hm + d2 * sc};
+        double r[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) r[i] = lam[i] / exp(2.0 * hn[i]);
+        double LW[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) LW[i][j] = L[i][0] * W[0][j] + L[i][1] * W[1][j] + L[i][2] * W[2][j];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const int i = R[c], j = C[c];
+          Pn[c] = (LW[i][0] * r[0] * LW[j][0] + LW[i][1] * r[1] * LW[j][1] + LW[i][2] * r[2] * LW[j][2]) - G0[c];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) pl_out[(size_t)c * m + t] = (T)Pn[c];
 }
 
 // ---------------------------------------------------------------- element
 
 __constant__ unsigned long long c_disc_lut;  // bit mask set: broken-edge mask disconnects the tet
 
+// Below this |J| the volume term of the energy is evaluated from the
+// adjugate of the Gram matrix and the cofactors of the edge matrix in FP64:
+// its edge-length form divides by J (one over the volume of a flat tet).
+constexpr double kJMin = 0.05;
+
 // One thread per tet.  Kinematics (edge vectors, squared-length changes) in
 // FP64, the rest in T.  Writes, per local edge k, the 3x3 stiffness block
-// K(i,j) in global orientation (i < j) and the force weight w_k = 2 V chi g_k.
+// K(i,j) in global orientation (i < j) and the FP64 force weight
+// w_k = 2 V chi dPsi/ds_k (Eq. 12).  pl: the plastic rest shapes
+// Gp - G0 [6][m] (null: no plasticity).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restrict__ tets,
                                                       const int32_t* __restrict__ tet_edge,
                                                       const uint8_t* __restrict__ flip,
                                                       const d4* __restrict__ X, const d4* __restrict__ U,
-                                                      const uint8_t* __restrict__ zeta,
-                                                      const T* __restrict__ pl_in, T* __restrict__ pl_out,
-                                                      ElemConst cst, T* __restrict__ contrib,
+                                                      const uint8_t* __restrict__ zeta, const T* __restrict__ pl,
+                                                      ElemConst cst, Rec<T>* __restrict__ contrib,
                                                       Counters* ctr) {
   const int t0 = blockIdx.x * kThreads + threadIdx.x;
   const bool act = t0 < m;
@@ -176,7 +356,7 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
   // Rest and current edge vectors; squared lengths S_k and their change ds_k
   // (Theorem 3.1: the energy is a function of these six lengths).
   T Dr[6][3], dcur[6][3], S[6], ds[6];
-  double Dsd[3][3];
+  double Dsd[3][3], Dmd[3][3];
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const int a = EA(k), b = EB(k);
@@ -198,7 +378,10 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
       dcur[k][d] = (T)(D[d] + dU[d]);
     }
     if (k < 3)
-      for (int d = 0; d < 3; ++d) Dsd[k][d] = D[d] + dU[d];
+      for (int d = 0; d < 3; ++d) {
+        Dsd[k][d] = D[d] + dU[d];
+        Dmd[k][d] = D[d];
+      }
   }
   // Rest Gram matrix G0 = Dm^T Dm (symmetric: 00,11,22,01,02,12) and its inverse.
   T G0[6];
@@ -211,12 +394,16 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
   const T det0 = sym3_det(G0[0], G0[1], G0[2], G0[3], G0[4], G0[5]);
   T G0i[6];
   sym3_inv(G0, det0, G0i);
-  // signed rest volume (positive after reorientation)
-  const T Dm[3][3] = {{Dr[0][0], Dr[1][0], Dr[2][0]}, {Dr[0][1], Dr[1][1], Dr[2][1]}, {Dr[0][2], Dr[1][2], Dr[2][2]}};
-  const T detDm = Dm[0][0] * (Dm[1][1] * Dm[2][2] - Dm[1][2] * Dm[2][1]) -
-                  Dm[0][1] * (Dm[1][0] * Dm[2][2] - Dm[1][2] * Dm[2][0]) +
-                  Dm[0][2] * (Dm[1][0] * Dm[2][1] - Dm[1][1] * Dm[2][0]);
-  const T vol = detDm / T(6);
+  // signed volumes in FP64: J = det Ds / det Dm decides the small-J form on
+  // both sides of any comparison in the same precision
+  auto det3 = [](const double (&a)[3][3]) {
+    return a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) - a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+           a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+  };
+  const double detDmd = det3(Dmd), detDs = det3(Dsd);
+  const double Jd = detDs / detDmd;
+  const bool small = fabs(Jd) < kJMin;
+  const T vol = (T)(detDmd / 6.0);
 
   // Gram change from the squared-length changes by polarisation:
   // dG_ii = ds_0i, dG_ij = (ds_0i + ds_0j - ds_ij) / 2.
@@ -228,142 +415,154 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
   dG[4] = T(0.5) * (ds[0] + ds[2] - ds[4]);
   dG[5] = T(0.5) * (ds[1] + ds[2] - ds[5]);
 
-  // Ductile case: additive Green-strain plasticity held as a Gram offset P
-  // (elastic Gram = G - P); instant return of the deviatoric excess.
-  if (pl_in) {
-    T P[6];
-    for (int c = 0; c < 6; ++c) P[c] = pl_in[(size_t)c * m + t];
-    if (cst.yield > 0) {
-    T Di[3][3];  // Dm^-1
-    const T idm = T(1) / detDm;
-    Di[0][0] = (Dm[1][1] * Dm[2][2] - Dm[1][2] * Dm[2][1]) * idm;
-    Di[0][1] = (Dm[0][2] * Dm[2][1] - Dm[0][1] * Dm[2][2]) * idm;
-    Di[0][2] = (Dm[0][1] * Dm[1][2] - Dm[0][2] * Dm[1][1]) * idm;
-    Di[1][0] = (Dm[1][2] * Dm[2][0] - Dm[1][0] * Dm[2][2]) * idm;
-    Di[1][1] = (Dm[0][0] * Dm[2][2] - Dm[0][2] * Dm[2][0]) * idm;
-    Di[1][2] = (Dm[0][2] * Dm[1][0] - Dm[0][0] * Dm[1][2]) * idm;
-    Di[2][0] = (Dm[1][0] * Dm[2][1] - Dm[1][1] * Dm[2][0]) * idm;
-    Di[2][1] = (Dm[0][1] * Dm[2][0] - Dm[0][0] * Dm[2][1]) * idm;
-    Di[2][2] = (Dm[0][0] * Dm[1][1] - Dm[0][1] * Dm[1][0]) * idm;
-    T Q[3][3], Qs[6];
-    for (int c = 0; c < 6; ++c) Qs[c] = dG[c] - P[c];
-    sym_full(Qs, Q);
-    // Ee = 1/2 Dm^-T Q Dm^-1
-    T QD[3][3], Ee[3][3];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) QD[i][j] = Q[i][0] * Di[0][j] + Q[i][1] * Di[1][j] + Q[i][2] * Di[2][j];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j)
-        Ee[i][j] = T(0.5) * (Di[0][i] * QD[0][j] + Di[1][i] * QD[1][j] + Di[2][i] * QD[2][j]);
-    const T tr3 = (Ee[0][0] + Ee[1][1] + Ee[2][2]) / T(3);
-    T dev[3][3];
-    T nrm2 = 0;
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        dev[i][j] = T(0.5) * (Ee[i][j] + Ee[j][i]) - (i == j ? tr3 : T(0));
-        nrm2 += dev[i][j] * dev[i][j];
-      }
-    const T nrm = sqrt(nrm2);
-    const T ey = (T)cst.yield;
-    if (nrm > ey) {
-      const T fac = T(2) * (T(1) - ey / nrm);
-      // P += 2 fac' Dm^T dev Dm
-      T DvD[3][3], tmp[3][3];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) tmp[i][j] = dev[i][0] * Dm[0][j] + dev[i][1] * Dm[1][j] + dev[i][2] * Dm[2][j];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) DvD[i][j] = Dm[0][i] * tmp[0][j] + Dm[1][i] * tmp[1][j] + Dm[2][i] * tmp[2][j];
-      P[0] += fac * DvD[0][0];
-      P[1] += fac * DvD[1][1];
-      P[2] += fac * DvD[2][2];
-      P[3] += fac * T(0.5) * (DvD[0][1] + DvD[1][0]);
-      P[4] += fac * T(0.5) * (DvD[0][2] + DvD[2][0]);
-      P[5] += fac * T(0.5) * (DvD[1][2] + DvD[2][1]);
+  // Plastic rest shape Gp = G0 + P: the I_C term is measured from it,
+  // the volume term from G0 (volume-preserving flow).
+  T Gpi[6], dGe[6];
+  if (pl) {
+    T Gp[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const T P = pl[(size_t)c * m + t];
+      Gp[c] = G0[c] + P;
+      dGe[c] = dG[c] - P;
     }
-    }
-    if (act && pl_out)
-      for (int c = 0; c < 6; ++c) pl_out[(size_t)c * m + t] = P[c];
-    for (int c = 0; c < 6; ++c) dG[c] -= P[c];
-  }
-
-  // Invariants without cancellation at the stress-free state:
-  //   a = I_C - 3 = tr(dG G0^-1),  J^2 - 1 = det(I + G0^-1 dG) - 1.
-  T A[3][3], B[3][3];
-  sym_full(G0i, A);
-  sym_full(dG, B);
-  T Xm[3][3];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) Xm[i][j] = A[i][0] * B[0][j] + A[i][1] * B[1][j] + A[i][2] * B[2][j];
-  T aI = Xm[0][0] + Xm[1][1] + Xm[2][2];
-  T trX2 = 0;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) trX2 += Xm[i][j] * Xm[j][i];
-  const T detX = Xm[0][0] * (Xm[1][1] * Xm[2][2] - Xm[1][2] * Xm[2][1]) -
-                 Xm[0][1] * (Xm[1][0] * Xm[2][2] - Xm[1][2] * Xm[2][0]) +
-                 Xm[0][2] * (Xm[1][0] * Xm[2][1] - Xm[1][1] * Xm[2][0]);
-  T jm1 = aI + T(0.5) * (aI * aI - trX2) + detX;
-  // orientation of the current tet (six lengths cannot see inversion)
-  const double detDs = Dsd[0][0] * (Dsd[1][1] * Dsd[2][2] - Dsd[1][2] * Dsd[2][1]) -
-                       Dsd[0][1] * (Dsd[1][0] * Dsd[2][2] - Dsd[1][2] * Dsd[2][0]) +
-                       Dsd[0][2] * (Dsd[1][0] * Dsd[2][1] - Dsd[1][1] * Dsd[2][0]);
-  const bool collapsed = (T(1) + jm1) <= T(1e-12);
-  if (collapsed) {  // evaluated at the rest Gram matrix; such a tet must carry chi = 0
-    for (int c = 0; c < 6; ++c) dG[c] = 0;
-    aI = 0;
-    jm1 = 0;
-  }
-  const T Jsq = T(1) + jm1;
-  T J, delta;
-  if (detDs >= 0.0) {
-    J = sqrt(Jsq);
-    delta = jm1 / (J + T(1));
+    sym3_inv(Gp, sym3_det(Gp[0], Gp[1], Gp[2], Gp[3], Gp[4], Gp[5]), Gpi);
   } else {
-    J = -sqrt(Jsq);
-    delta = J - T(1);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      Gpi[c] = G0i[c];
+      dGe[c] = dG[c];
+    }
   }
-  T G[6], Gi[6];
-  for (int c = 0; c < 6; ++c) G[c] = G0[c] + dG[c];
-  sym3_inv(G, det0 * Jsq, Gi);
-  // Y = G0^-1 - G^-1 = G^-1 dG G0^-1 (formed as a product, never as the difference)
-  T Ys[6];
-  {
-    T Gf[3][3], M1[3][3], Y[3][3];
-    sym_full(Gi, Gf);
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) M1[i][j] = B[i][0] * A[0][j] + B[i][1] * A[1][j] + B[i][2] * A[2][j];
-    if (collapsed)
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) M1[i][j] = 0;
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) Y[i][j] = Gf[i][0] * M1[0][j] + Gf[i][1] * M1[1][j] + Gf[i][2] * M1[2][j];
-    Ys[0] = Y[0][0];
-    Ys[1] = Y[1][1];
-    Ys[2] = Y[2][2];
-    Ys[3] = T(0.5) * (Y[0][1] + Y[1][0]);
-    Ys[4] = T(0.5) * (Y[0][2] + Y[2][0]);
-    Ys[5] = T(0.5) * (Y[1][2] + Y[2][1]);
-  }
-  T Gam[4][4], Gam0[4][4], GamY[4][4];
-  gram4(Gi, Gam);
-  gram4(G0i, Gam0);
-  gram4(Ys, GamY);
 
-  // Edge-space gradient of Eq. 35 (squared (J - alpha) term, reparametrised
-  // Lame constants), rewritten so that the rest-state cancellation happens
-  // analytically:  dPsi/ds_k = 3mu/8 t_k + mu a/(8(4+a)) c_k + lam/2 (d(2-alpha)+d^2) v_k
-  // with c_k = tr(E_k G0^-1), v_k = tr(E_k G^-1), t_k = tr(E_k Y) = c_k - v_k.
+  // a = I_C - 3 = tr(dGe Gp^-1) without cancellation at the stress-free state
+  T Ap[3][3], Be[3][3];
+  sym_full(Gpi, Ap);
+  sym_full(dGe, Be);
+  T aI = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) aI += Ap[i][j] * Be[j][i];
   const T IC1 = T(4) + aI;  // I_C + 1
   const T cmu = mu * aI / (T(8) * IC1);
-  const T dj = delta * (T(1) - am1) + delta * delta;  // (J - alpha) J - (1 - alpha)
-  const T lamt = T(0.5) * lam * dj;
+
+  T GamP[4][4];
+  gram4(Gpi, GamP);
   T cc[6], vv[6], g[6];
+  double wJ[6];  // FP64 volume-term force weights of a small-J tet
+  T J, delta, Jsq;
+  T Gam[4][4], GamY[4][4];
+  T Ys[6];
+  double gJd[4][3];  // dJ/dx_a (small-J tets)
+  double adjG[6];    // adjugate of the current Gram matrix, FP64 (small-J tets)
+  if (!small) {
+    // J^2 - 1 = det(I + G0^-1 dG) - 1 without cancellation at rest
+    T A0[3][3], B[3][3], Xm[3][3];
+    sym_full(G0i, A0);
+    sym_full(dG, B);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Xm[i][j] = A0[i][0] * B[0][j] + A0[i][1] * B[1][j] + A0[i][2] * B[2][j];
+    const T a0 = Xm[0][0] + Xm[1][1] + Xm[2][2];
+    T trX2 = 0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) trX2 += Xm[i][j] * Xm[j][i];
+    const T detX = Xm[0][0] * (Xm[1][1] * Xm[2][2] - Xm[1][2] * Xm[2][1]) -
+                   Xm[0][1] * (Xm[1][0] * Xm[2][2] - Xm[1][2] * Xm[2][0]) +
+                   Xm[0][2] * (Xm[1][0] * Xm[2][1] - Xm[1][1] * Xm[2][0]);
+    const T jm1 = a0 + T(0.5) * (a0 * a0 - trX2) + detX;
+    Jsq = T(1) + jm1;
+    if (detDs >= 0.0) {
+      J = sqrt(Jsq);
+      delta = jm1 / (J + T(1));
+    } else {
+      J = -sqrt(Jsq);
+      delta = J - T(1);
+    }
+    T G[6], Gi[6];
+    for (int c = 0; c < 6; ++c) G[c] = G0[c] + dG[c];
+    sym3_inv(G, det0 * Jsq, Gi);
+    // Y = Gp^-1 - G^-1 = G^-1 dGe Gp^-1 (formed as a product, never as the difference)
+    {
+      T Gf[3][3], M1[3][3], Y[3][3];
+      sym_full(Gi, Gf);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M1[i][j] = Be[i][0] * Ap[0][j] + Be[i][1] * Ap[1][j] + Be[i][2] * Ap[2][j];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Y[i][j] = Gf[i][0] * M1[0][j] + Gf[i][1] * M1[1][j] + Gf[i][2] * M1[2][j];
+      Ys[0] = Y[0][0];
+      Ys[1] = Y[1][1];
+      Ys[2] = Y[2][2];
+      Ys[3] = T(0.5) * (Y[0][1] + Y[1][0]);
+      Ys[4] = T(0.5) * (Y[0][2] + Y[2][0]);
+      Ys[5] = T(0.5) * (Y[1][2] + Y[2][1]);
+    }
+    gram4(Gi, Gam);
+    gram4(Ys, GamY);
+    // Edge-space gradient of Eq. 35 (squared (J - alpha) term, reparametrised
+    // Lame constants), rewritten so that the rest-state cancellation happens
+    // analytically:  dPsi/ds_k = 3mu/8 t_k + mu a/(8(4+a)) c_k + lam/2 (d(2-alpha)+d^2) v_k
+    // with c_k = tr(E_k Gp^-1), v_k = tr(E_k G^-1), t_k = tr(E_k Y) = c_k - v_k.
+    const T dj = delta * (T(1) - am1) + delta * delta;  // (J - alpha) J - (1 - alpha)
+    const T lamt = T(0.5) * lam * dj;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const int a = EA(k), b = EB(k);
-    cc[k] = -Gam0[a][b];
-    vv[k] = -Gam[a][b];
-    const T tk = -GamY[a][b];
-    g[k] = T(0.375) * mu * tk + cmu * cc[k] + lamt * vv[k];
+    for (int k = 0; k < 6; ++k) {
+      const int a = EA(k), b = EB(k);
+      cc[k] = -GamP[a][b];
+      vv[k] = -Gam[a][b];
+      const T tk = -GamY[a][b];
+      g[k] = T(0.375) * mu * tk + cmu * cc[k] + lamt * vv[k];
+      wJ[k] = 0.0;
+    }
+  } else {
+    // Small |J|: the I_C term in edge form, the volume term (lam/2)(J - alpha)^2
+    // through dJ/ds_k = J tr(E_k G^-1) / 2 = tr(E_k adj G) / (2 J det G0)
+    // (force weights, FP64) and dJ/dx (cofactors of the edge matrix, FP64).
+    J = (T)Jd;
+    delta = J - T(1);
+    Jsq = J * J;
+    double Gd[6];
+    {
+      constexpr int R[6] = {0, 1, 2, 0, 0, 1}, C[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        Gd[c] = Dsd[R[c]][0] * Dsd[C[c]][0] + Dsd[R[c]][1] * Dsd[C[c]][1] + Dsd[R[c]][2] * Dsd[C[c]][2];
+    }
+    adjG[0] = Gd[1] * Gd[2] - Gd[5] * Gd[5];
+    adjG[1] = Gd[0] * Gd[2] - Gd[4] * Gd[4];
+    adjG[2] = Gd[0] * Gd[1] - Gd[3] * Gd[3];
+    adjG[3] = Gd[4] * Gd[5] - Gd[3] * Gd[2];
+    adjG[4] = Gd[3] * Gd[5] - Gd[4] * Gd[1];
+    adjG[5] = Gd[3] * Gd[4] - Gd[0] * Gd[5];
+    double GamA[4][4];
+    gram4(adjG, GamA);
+    // J det G0 = det Ds det Dm; below 1e-12 of det Dm^2 the weights are
+    // formed at that floor (their reconstruction of the force loses
+    // accuracy as 1e-16 / |J| in FP64)
+    const double floor = 1e-12 * detDmd * detDmd;
+    const double den = (fabs(detDs * detDmd) > floor) ? detDs * detDmd : (detDs >= 0.0 ? floor : -floor);
+    const double cJ = 0.5 * cst.lam * (Jd - (1.0 + cst.alpha_m1));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int a = EA(k), b = EB(k);
+      cc[k] = -GamP[a][b];
+      vv[k] = 0;
+      g[k] = (T(0.375) * mu + cmu) * cc[k];  // (mu/2)(1 - 1/(I_C+1)) c_k
+      wJ[k] = cJ * (-GamA[a][b] / den);
+    }
+    // dJ/dx_a: (x2'-x0') x (x3'-x0') / det Dm etc., node 0 minus their sum
+    const double idm = 1.0 / detDmd;
+    gJd[1][0] = (Dsd[1][1] * Dsd[2][2] - Dsd[1][2] * Dsd[2][1]) * idm;
+    gJd[1][1] = (Dsd[1][2] * Dsd[2][0] - Dsd[1][0] * Dsd[2][2]) * idm;
+    gJd[1][2] = (Dsd[1][0] * Dsd[2][1] - Dsd[1][1] * Dsd[2][0]) * idm;
+    gJd[2][0] = (Dsd[2][1] * Dsd[0][2] - Dsd[2][2] * Dsd[0][1]) * idm;
+    gJd[2][1] = (Dsd[2][2] * Dsd[0][0] - Dsd[2][0] * Dsd[0][2]) * idm;
+    gJd[2][2] = (Dsd[2][0] * Dsd[0][1] - Dsd[2][1] * Dsd[0][0]) * idm;
+    gJd[3][0] = (Dsd[0][1] * Dsd[1][2] - Dsd[0][2] * Dsd[1][1]) * idm;
+    gJd[3][1] = (Dsd[0][2] * Dsd[1][0] - Dsd[0][0] * Dsd[1][2]) * idm;
+    gJd[3][2] = (Dsd[0][0] * Dsd[1][1] - Dsd[0][1] * Dsd[1][0]) * idm;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gJd[0][d] = -(gJd[1][d] + gJd[2][d] + gJd[3][d]);
   }
 
   // Energy fraction chi (Eq. 22-25): 2nd Piola-Kirchhoff stress projected on
@@ -377,27 +576,55 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
     if ((c_disc_lut >> mask) & 1ull) {
       chi = T(0);
     } else {
-      // sigma_k = mu (1 - 1/(I_C+1)) + lam (J - alpha) J w_k, w_k = q^T C^-1 q,
-      // with 1 - w_k = e_k^T G0 Y G0 e_k / S_k (e_k: reference edge)
-      T Yf[3][3], G0f[3][3], GY[3][3], Z[3][3];
-      sym_full(Ys, Yf);
+      // sigma_k = mu (1 - 1/(I_C+1)) p_k + lam (J - alpha) J w_k with
+      // p_k = q^T Cp^-1 q = e^T G0 Gp^-1 G0 e / S_k and w_k = q^T C^-1 q
+      // (e: reference edge, q: rest unit direction); p_k - w_k =
+      // e^T G0 Y G0 e / S_k.  Small |J|: every sigma_k times |J|, with
+      // |J| J w_k = sign(J) e^T G0 adj(G) G0 e / (det G0 S_k).
+      T G0f[3][3];
       sym_full(G0, G0f);
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) GY[i][j] = G0f[i][0] * Yf[0][j] + G0f[i][1] * Yf[1][j] + G0f[i][2] * Yf[2][j];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) Z[i][j] = GY[i][0] * G0f[0][j] + GY[i][1] * G0f[1][j] + GY[i][2] * G0f[2][j];
+      auto quad = [&](const T* Ms, T (&Z)[3][3]) {  // Z = G0 M G0
+        T Mf[3][3], GM[3][3];
+        sym_full(Ms, Mf);
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) GM[i][j] = G0f[i][0] * Mf[0][j] + G0f[i][1] * Mf[1][j] + G0f[i][2] * Mf[2][j];
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) Z[i][j] = GM[i][0] * G0f[0][j] + GM[i][1] * G0f[1][j] + GM[i][2] * G0f[2][j];
+      };
+      auto edge_quad = [](const T (&Z)[3][3], int k) {  // e_k^T Z e_k
+        const int a = EA(k), b = EB(k);
+        if (a == 0) return Z[b - 1][b - 1];
+        return Z[a - 1][a - 1] + Z[b - 1][b - 1] - (Z[a - 1][b - 1] + Z[b - 1][a - 1]);
+      };
+      T Zp[3][3];
+      const bool plastic = pl != nullptr;
+      if (plastic) quad(Gpi, Zp);
+      T Zs[3][3];
+      T sgnJ = T(1), scl = T(1);
+      if (!small) {
+        quad(Ys, Zs);
+      } else {
+        T adjT[6];
+        for (int c = 0; c < 6; ++c) adjT[c] = (T)adjG[c];
+        quad(adjT, Zs);
+        sgnJ = Jd >= 0.0 ? T(1) : T(-1);
+        scl = fabs(J);
+      }
+      const T lamJ = small ? lam * (J - T(1) - am1) * sgnJ / det0 : T(0);
       T num = 0, den = 0;
       int nub = 0;
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        const int a = EA(k), b = EB(k);
-        T q;
-        if (a == 0)
-          q = Z[b - 1][b - 1];
-        else
-          q = Z[a - 1][a - 1] + Z[b - 1][b - 1] - T(0.5) * (Z[a - 1][b - 1] + Z[b - 1][a - 1]) * T(2);
-        const T omw = q / S[k];
-        const T sig = T(0.75) * mu * omw + mu * aI / (T(4) * IC1) + lam * dj * (T(1) - omw);
+        const T pk = plastic ? edge_quad(Zp, k) / S[k] : T(1);
+        T sig;
+        if (!small) {
+          const T omw = edge_quad(Zs, k) / S[k];  // p_k - w_k
+          const T dj = delta * (T(1) - am1) + delta * delta;
+          // mu (1 - 1/(I_C+1)) = 3mu/4 + mu a/(4(4+a)); lam (J-alpha) J = -3mu/4 + lam dj
+          sig = T(0.75) * mu * omw + mu * aI / (T(4) * IC1) * pk + lam * dj * (pk - omw);
+        } else {
+          sig = scl * (T(0.75) * mu + mu * aI / (T(4) * IC1)) * pk + lamJ * edge_quad(Zs, k) / S[k];
+        }
         const T as = fabs(sig);
         den += as;
         if (!((mask >> k) & 1)) {
@@ -405,12 +632,12 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
           ++nub;
         }
       }
-      chi = (den <= T(1e-12) * (mu + lam)) ? T(nub) / T(6) : num / den;
+      chi = (den <= T(1e-12) * (mu + lam) * scl) ? T(nub) / T(6) : num / den;
     }
   }
 
   {
-    const bool pr[2] = {act && chi == T(0), act && fabs(J) < T(0.05)};
+    const bool pr[2] = {act && chi == T(0), act && small};
     block_counts<2>(ctr, kChiZero, pr);
   }
   if (!act) return;
@@ -418,28 +645,35 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
   if (chi == T(0)) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      T* rec = contrib + ((size_t)k * m + t) * 10;
+      Rec<T> r;
 #pragma unroll
-      for (int c = 0; c < 10; ++c) rec[c] = T(0);
+      for (int c = 0; c < 9; ++c) r.b[c] = T(0);
+      r.w = 0.0;
+      contrib[(size_t)k * m + t] = r;
     }
     return;
   }
 
   // Clamped edge Hessian: H = A1 c c^T + A2 v v^T + A3 M, M_kl = tr(G^-1 E_k G^-1 E_l)
   // = (Gam_ac Gam_bd + Gam_ad Gam_bc)/2; each coefficient clamped at >= 0.
+  // Small |J|: only the I_C term (A1); the volume term adds lam dJ dJ^T.
   const T Vc = vol * chi;
   const T A1 = T(0.5) * mu / (IC1 * IC1);
-  const T JmA = delta - am1;              // J - alpha
-  const T A2 = fmax(T(0.25) * lam * (T(2) * J - T(1) - am1) * J, T(0));
-  const T A3 = fmax(T(-0.5) * lam * JmA * J, T(0));
+  const T JmA = delta - am1;  // J - alpha
+  const T A2 = small ? T(0) : fmax(T(0.25) * lam * (T(2) * J - T(1) - am1) * J, T(0));
+  const T A3 = small ? T(0) : fmax(T(-0.5) * lam * JmA * J, T(0));
   T H[6][6];
 #pragma unroll
   for (int k = 0; k < 6; ++k)
 #pragma unroll
     for (int l = k; l < 6; ++l) {
       const int a = EA(k), b = EB(k), c = EA(l), d = EB(l);
-      const T Mkl = T(0.5) * (Gam[a][c] * Gam[b][d] + Gam[a][d] * Gam[b][c]);
-      H[k][l] = H[l][k] = A1 * cc[k] * cc[l] + A2 * vv[k] * vv[l] + A3 * Mkl;
+      T hkl = A1 * cc[k] * cc[l];
+      if (!small) {
+        const T Mkl = T(0.5) * (Gam[a][c] * Gam[b][d] + Gam[a][d] * Gam[b][c]);
+        hkl += A2 * vv[k] * vv[l] + A3 * Mkl;
+      }
+      H[k][l] = H[l][k] = hkl;
     }
 
   // Stiffness (Eq. 10, 33): K(a,b) = V chi [ sum_{p at a, q at b} H_pq ds_p/dx_a ds_q/dx_b^T
@@ -448,6 +682,7 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
   constexpr int inc_e[4][3] = {{0, 1, 2}, {0, 3, 4}, {1, 3, 5}, {2, 4, 5}};
   constexpr int inc_s[4][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {1, 1, 1}};
   const uint8_t fl = flip[t];
+  const double Vcd = (double)vol * (double)chi;
 #pragma unroll
   for (int b = 1; b < 4; ++b) {
     T Tb[6][3];
@@ -483,18 +718,21 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
       Kab[0][0] -= lap;
       Kab[1][1] -= lap;
       Kab[2][2] -= lap;
+      if (small) {
+        const T kJ = (T)(Vcd * cst.lam);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) Kab[r][c] += kJ * (T)(gJd[a][r] * gJd[b][c]);
+      }
       const bool tr = (fl >> k) & 1;
-      // one 10-value record written as five aligned pairs
-      typedef T T2 __attribute__((ext_vector_type(2)));
-      T v[10];
+      Rec<T> rec;
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) v[3 * r + c] = tr ? Kab[c][r] : Kab[r][c];
-      v[9] = T(2) * Vc * g[k];
-      T2* rec = reinterpret_cast<T2*>(contrib + ((size_t)k * m + t) * 10);
-#pragma unroll
-      for (int c = 0; c < 5; ++c) rec[c] = T2{v[2 * c], v[2 * c + 1]};
+        for (int c = 0; c < 3; ++c) rec.b[3 * r + c] = tr ? Kab[c][r] : Kab[r][c];
+      rec.w = 2.0 * Vcd * ((double)g[k] + wJ[k]);
+      contrib[(size_t)k * m + t] = rec;
     }
   }
 }
@@ -503,32 +741,28 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
 
 // One thread per edge: sum the tets' contributions in slot order (fixed), add
 // the consistent mass, and write A_ij and A_ji = A_ij^T into the block matrix:
-// A_ij = m_ij (1 + dt alpha) I + (dt^2 + dt beta) K_ij.
+// A_ij = m_ij (1 + dt alpha) I + (dt^2 + dt beta) K_ij; the force weights are
+// summed in FP64.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_edge(int ne, const int32_t* __restrict__ edge_ptr,
                                                    const int32_t* __restrict__ edge_slot,
-                                                   const T* __restrict__ contrib,
+                                                   const Rec<T>* __restrict__ contrib,
                                                    const double* __restrict__ edge_mass, double mass_fac,
                                                    double stiff_fac, const int32_t* __restrict__ blk_ij,
                                                    const int32_t* __restrict__ blk_ji, T* __restrict__ val,
-                                                   int nbp, T* __restrict__ edge_w) {
+                                                   int nbp, double* __restrict__ edge_w) {
   int e = blockIdx.x * kThreads + threadIdx.x;
   if (e >= ne) return;
-  T acc[10];
+  T acc[9];
 #pragma unroll
-  for (int c = 0; c < 10; ++c) acc[c] = 0;
+  for (int c = 0; c < 9; ++c) acc[c] = 0;
+  double accw = 0.0;
   const int s0 = edge_ptr[e], s1 = edge_ptr[e + 1];
-  // records are 10 values at a 10-value stride: 8-byte (FP32) or 16-byte
-  // (FP64) aligned, read as five pairs
-  typedef T T2 __attribute__((ext_vector_type(2)));
   for (int s = s0; s < s1; ++s) {
-    const T2* rec = reinterpret_cast<const T2*>(contrib + (size_t)edge_slot[s] * 10);
+    const Rec<T> r = contrib[edge_slot[s]];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      const T2 v = rec[c];
-      acc[2 * c] += v.x;
-      acc[2 * c + 1] += v.y;
-    }
+    for (int c = 0; c < 9; ++c) acc[c] += r.b[c];
+    accw += r.w;
   }
   const double md = edge_mass[e] * mass_fac;
   const int bij = blk_ij[e], bji = blk_ji[e];
@@ -540,7 +774,7 @@ __global__ __launch_bounds__(kThreads) void k_edge(int ne, const int32_t* __rest
       val[(size_t)(3 * r + c) * nbp + bij] = v;
       val[(size_t)(3 * c + r) * nbp + bji] = v;
     }
-  edge_w[e] = acc[9];
+  edge_w[e] = accw;
 }
 
 // ---------------------------------------------------------------- row pass
@@ -567,7 +801,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32_t* __restrict__ diag_blk,
                                                   const int32_t* __restrict__ blk_edge,
                                                   const double* __restrict__ edge_mass,
-                                                  const T* __restrict__ edge_w, const double* __restrict__ lumped,
+                                                  const double* __restrict__ edge_w, const double* __restrict__ lumped,
                                                   const d4* __restrict__ X, const d4* __restrict__ U,
                                                   const d4* __restrict__ V, const uint8_t* __restrict__ dflag,
                                                   const d4* __restrict__ dvel, RowConst cst, T* __restrict__ val,
@@ -596,7 +830,7 @@ __global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32
       const int j = Am.col[b];
       const int ed = blk_edge[b];
       const double me = edge_mass[ed];
-      const double w = (double)edge_w[ed];
+      const double w = edge_w[ed];
       const d4 Xj = X[j], Uj = U[j], vj = V[j];
       const double dx[3] = {(Xj.x - Xi.x) + (Uj.x - Ui.x), (Xj.y - Xi.y) + (Uj.y - Ui.y),
                             (Xj.z - Xi.z) + (Uj.z - Ui.z)};
@@ -1391,30 +1625,36 @@ void set_disconnected_lut(unsigned long long lut) {
 }
 
 void launch_damage(hipStream_t s, int ne, const int2* edges, const d4* X, const d4* U, const double* S,
-                   const uint8_t* z_in, uint8_t* z_out, double thr, Counters* ctr) {
+                   const uint8_t* z_in, uint8_t* z_out, double thr, Counters* ctr, int32_t* near_ids) {
   if (ne <= 0) return;
-  k_damage<<<blocks_for(ne), kThreads, 0, s>>>(ne, edges, X, U, S, z_in, z_out, thr, ctr);
+  k_damage<<<blocks_for(ne), kThreads, 0, s>>>(ne, edges, X, U, S, z_in, z_out, thr, ctr, near_ids);
+}
+
+template <typename T>
+void launch_plastic(hipStream_t s, int m, const int4* tets, const d4* X, const d4* U, const T* pl_in, T* pl_out,
+                    double yield) {
+  if (m <= 0) return;
+  k_plastic<T><<<blocks_for(m), kThreads, 0, s>>>(m, tets, X, U, pl_in, pl_out, yield);
 }
 
 template <typename T>
 void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_edge, const uint8_t* flip,
-                    const d4* X, const d4* U, const uint8_t* zeta, const T* pl_in, T* pl_out, ElemConst c,
-                    T* contrib, Counters* ctr) {
-  k_element<T><<<blocks_for(m), kThreads, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta, pl_in, pl_out, c,
-                                                  contrib, ctr);
+                    const d4* X, const d4* U, const uint8_t* zeta, const T* pl, ElemConst c, Rec<T>* contrib,
+                    Counters* ctr) {
+  k_element<T><<<blocks_for(m), kThreads, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta, pl, c, contrib, ctr);
 }
 
 template <typename T>
 void launch_edge(hipStream_t s, int ne, const int32_t* edge_ptr, const int32_t* edge_slot,
-                 const T* contrib, const double* edge_mass, double mass_fac, double stiff_fac,
-                 const int32_t* blk_ij, const int32_t* blk_ji, T* val, int nbp, T* edge_w) {
+                 const Rec<T>* contrib, const double* edge_mass, double mass_fac, double stiff_fac,
+                 const int32_t* blk_ij, const int32_t* blk_ji, T* val, int nbp, double* edge_w) {
   k_edge<T><<<blocks_for(ne), kThreads, 0, s>>>(ne, edge_ptr, edge_slot, contrib, edge_mass, mass_fac,
                                                stiff_fac, blk_ij, blk_ji, val, nbp, edge_w);
 }
 
 template <typename T>
 void launch_row(hipStream_t s, int n, int G, MatView A, const int32_t* diag_blk, const int32_t* blk_edge,
-                const double* edge_mass, const T* edge_w, const double* lumped, const d4* X, const d4* U,
+                const double* edge_mass, const double* edge_w, const double* lumped, const d4* X, const d4* U,
                 const d4* V, const uint8_t* dflag, const d4* dvel, RowConst c, T* val_mut, d4* b, d4* X64,
                 T* binv, d4* f_out, double* part_bb) {
   k_row<T><<<G, kThreads, 0, s>>>(n, A, diag_blk, blk_edge, edge_mass, edge_w, lumped, X, U, V, dflag, dvel, c,
@@ -1525,12 +1765,14 @@ void launch_integrate(hipStream_t s, int n, const d4* X64, d4* V, d4* U, const u
 }
 
 #define GFEM_INST(T)                                                                                         \
+  template void launch_plastic<T>(hipStream_t, int, const int4*, const d4*, const d4*, const T*, T*, double); \
   template void launch_element<T>(hipStream_t, int, const int4*, const int32_t*, const uint8_t*, const d4*,  \
-                                  const d4*, const uint8_t*, const T*, T*, ElemConst, T*, Counters*);        \
-  template void launch_edge<T>(hipStream_t, int, const int32_t*, const int32_t*, const T*,                   \
-                               const double*, double, double, const int32_t*, const int32_t*, T*, int, T*);  \
+                                  const d4*, const uint8_t*, const T*, ElemConst, Rec<T>*, Counters*);       \
+  template void launch_edge<T>(hipStream_t, int, const int32_t*, const int32_t*, const Rec<T>*,              \
+                               const double*, double, double, const int32_t*, const int32_t*, T*, int,       \
+                               double*);                                                                     \
   template void launch_row<T>(hipStream_t, int, int, MatView, const int32_t*, const int32_t*, const double*, \
-                              const T*, const double*, const d4*, const d4*, const d4*, const uint8_t*,      \
+                              const double*, const double*, const d4*, const d4*, const d4*, const uint8_t*, \
                               const d4*, RowConst, T*, d4*, d4*, T*, d4*, double*);                          \
   template void launch_pcg_init<T>(hipStream_t, int, int, const d4*, const T*, v4<T>*, v4<T>*, v4<T>*,      \
                                    v4<T>*, double*, PcgCtl*);                                                \

@@ -5,9 +5,10 @@
 //   tets           : int4 node ids; tet_edge SoA [6][m]; flip bits [m]
 //   block matrix   : BSR 3x3, values SoA [9][nbp] (component-major, so the
 //                    lanes of a wave read consecutive blocks with unit stride)
-//   contributions  : [6][m][10] (9 block entries + 1 force weight per tet
-//                    edge, 40 B per record), written tet-major by the element
-//                    pass and read as whole records per edge by the edge pass
+//   contributions  : [6][m] records (9 block entries in T + one FP64 force
+//                    weight per tet edge, 48 B in FP32), written tet-major by
+//                    the element pass and read as whole records per edge by
+//                    the edge pass
 // No floating-point atomics anywhere: every sum has a fixed order, so a step
 // is bitwise reproducible.
 #pragma once
@@ -53,11 +54,21 @@ constexpr int kCtrStride = 32;  // ints per slot (128 B)
 enum CounterField { kNewBroken = 0, kTotalBroken, kNearThreshold, kChiZero, kDegenerate, kNumCounters };
 struct Counters {
   int v[kCtrSlots * kCtrStride];
+  int near_n;  // entries appended to the near-threshold edge list by the damage pass
 };
 
 struct ElemConst {
   double mu, lam, alpha_m1;  // mu', lambda', alpha - 1 (Eq. 35 with the reparametrised constants)
-  double yield;              // <= 0: no plasticity
+};
+
+// Per tet edge contribution: the 3x3 stiffness block in global orientation
+// and the force weight 2 V chi dPsi/ds_k (FP64: on nearly flat tets the
+// weights of the volume term grow as 1/J while their sum along the edges
+// stays finite).
+template <typename T>
+struct alignas(16) Rec {
+  T b[9];
+  double w;
 };
 
 // 64-bit table: bit `mask` set when that broken-edge mask leaves the tet's
@@ -65,19 +76,28 @@ struct ElemConst {
 void set_disconnected_lut(unsigned long long lut);
 
 // Launch helpers (defined in kernels.hip).  All are asynchronous on `s`.
+// near_ids (capacity ne): internal ids of the edges with |strain - thr| < 1e-6,
+// in no particular order, count in ctr->near_n.
 void launch_damage(hipStream_t s, int ne, const int2* edges, const d4* X, const d4* U,
                    const double* S, const uint8_t* z_in, uint8_t* z_out, double thr,
-                   Counters* ctr);
+                   Counters* ctr, int32_t* near_ids);
 
+// Plastic flow of the ductile workload: pl_in -> pl_out, each [6][m] plastic
+// rest-shape offsets Gp - G0 (symmetric 00,11,22,01,02,12).
+template <typename T>
+void launch_plastic(hipStream_t s, int m, const int4* tets, const d4* X, const d4* U, const T* pl_in, T* pl_out,
+                    double yield);
+
+// pl: plastic rest-shape offsets [6][m], or null.
 template <typename T>
 void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_edge,
                     const uint8_t* flip, const d4* X, const d4* U, const uint8_t* zeta,
-                    const T* pl_in, T* pl_out, ElemConst c, T* contrib, Counters* ctr);
+                    const T* pl, ElemConst c, Rec<T>* contrib, Counters* ctr);
 
 template <typename T>
 void launch_edge(hipStream_t s, int ne, const int32_t* edge_ptr, const int32_t* edge_slot,
-                 const T* contrib, const double* edge_mass, double mass_fac, double stiff_fac,
-                 const int32_t* blk_ij, const int32_t* blk_ji, T* val, int nbp, T* edge_w);
+                 const Rec<T>* contrib, const double* edge_mass, double mass_fac, double stiff_fac,
+                 const int32_t* blk_ij, const int32_t* blk_ji, T* val, int nbp, double* edge_w);
 
 struct RowConst {
   double dt, ra;      // dt, Rayleigh alpha
@@ -87,7 +107,7 @@ struct RowConst {
 
 template <typename T>
 void launch_row(hipStream_t s, int n, int G, MatView A, const int32_t* diag_blk,
-                const int32_t* blk_edge, const double* edge_mass, const T* edge_w,
+                const int32_t* blk_edge, const double* edge_mass, const double* edge_w,
                 const double* lumped, const d4* X, const d4* U, const d4* V,
                 const uint8_t* dflag, const d4* dvel, RowConst c, T* val_mut, d4* b,
                 d4* X64, T* binv, d4* f_out, double* part_bb);

@@ -67,17 +67,20 @@ _SIGS = {
     "gf_get_velocities": ([C.c_void_p, _P(C.c_double)], C.c_int),
     "gf_get_edge_damage": ([C.c_void_p, _P(C.c_uint8)], C.c_int),
     "gf_eval_forces": ([C.c_void_p, _P(C.c_double)], C.c_int),
+    "gf_get_near_threshold_edges": ([C.c_void_p, _P(C.c_int32), C.c_int32, _P(C.c_int32)], C.c_int),
     "gf_get_system": ([C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_double), _P(C.c_double)], C.c_int),
     "gf_get_state": ([C.c_void_p, C.c_void_p, _P(C.c_size_t)], C.c_int),
     "gf_set_state": ([C.c_void_p, C.c_void_p, C.c_size_t], C.c_int),
     "gf_set_timing": ([C.c_void_p, C.c_int32], C.c_int),
+    "gf_set_fp64_rerun": ([C.c_void_p, C.c_int32], C.c_int),
     "gf_bench_spmv": ([C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_double)], C.c_int),
     "gf_last_error": ([], C.c_char_p),
     "gf_net_create": ([C.c_uint64, _P(C.c_void_p)], C.c_int),
     "gf_net_destroy": ([C.c_void_p], C.c_int),
     "gf_net_num_params": ([_P(C.c_int32)], C.c_int),
-    "gf_net_get_weights": ([C.c_void_p, _P(C.c_float)], C.c_int),
-    "gf_net_set_weights": ([C.c_void_p, _P(C.c_float)], C.c_int),
+    "gf_net_check_weights": ([C.c_void_p, C.c_size_t], C.c_int),
+    "gf_net_get_weights": ([C.c_void_p, C.c_void_p, _P(C.c_size_t)], C.c_int),
+    "gf_net_set_weights": ([C.c_void_p, C.c_void_p, C.c_size_t], C.c_int),
     "gf_set_precond_net": ([C.c_void_p, C.c_void_p], C.c_int),
     "gf_set_precond": ([C.c_void_p, C.c_int32], C.c_int),
     "gf_set_precond_normalise": ([C.c_void_p, C.c_int32], C.c_int),
@@ -230,6 +233,14 @@ class Mesh:
         _check(self._lib.gf_get_edge_damage(self._h, _u8ptr(z)))
         return z
 
+    def near_threshold_edges(self) -> np.ndarray:
+        """Canonical ids of the edges within 1e-6 of the threshold in the last damage pass."""
+        n = C.c_int32()
+        _check(self._lib.gf_get_near_threshold_edges(self._h, None, 0, C.byref(n)))
+        ids = np.zeros(max(n.value, 1), np.int32)
+        _check(self._lib.gf_get_near_threshold_edges(self._h, _iptr(ids), ids.size, C.byref(n)))
+        return ids[: n.value]
+
     def eval_forces(self) -> np.ndarray:
         f = np.zeros((self.n_nodes, 3))
         _check(self._lib.gf_eval_forces(self._h, _dptr(f)))
@@ -254,6 +265,10 @@ class Mesh:
     def set_state(self, blob: bytes):
         buf = C.create_string_buffer(blob, len(blob))
         _check(self._lib.gf_set_state(self._h, buf, len(blob)))
+
+    def set_fp64_rerun(self, always: bool):
+        """Test hook: re-run every split-precision step in FP64."""
+        _check(self._lib.gf_set_fp64_rerun(self._h, int(bool(always))))
 
     def set_timing(self, on: bool):
         _check(self._lib.gf_set_timing(self._h, int(bool(on))))
@@ -287,15 +302,17 @@ class Net:
             pass
 
     def get_weights(self) -> np.ndarray:
-        w = np.zeros(self.n_params, np.float32)
-        _check(self._lib.gf_net_get_weights(self._h, w.ctypes.data_as(_P(C.c_float))))
-        return w
+        n = C.c_size_t()
+        _check(self._lib.gf_net_get_weights(self._h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(self._lib.gf_net_get_weights(self._h, buf, C.byref(n)))
+        return weights_from_blob(buf.raw[: n.value])
 
     def set_weights(self, w):
-        w = np.ascontiguousarray(w, dtype=np.float32)
-        if w.size != self.n_params:
-            raise ValueError("wrong number of weights")
-        _check(self._lib.gf_net_set_weights(self._h, w.ctypes.data_as(_P(C.c_float))))
+        """FP32 weights (n_params) or a weight blob (bytes)."""
+        blob = w if isinstance(w, (bytes, bytearray)) else weights_blob(w)
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _check(self._lib.gf_net_set_weights(self._h, buf, len(blob)))
 
     def set_power_steps(self, k: int):
         """Power steps on G A G^T applied to the training probe (0: Kaporin)."""
@@ -321,6 +338,27 @@ class Net:
                                      C.byref(loss), gd.ctypes.data_as(_P(C.c_float)),
                                      gl.ctypes.data_as(_P(C.c_float)), grad.ctypes.data_as(_P(C.c_float))))
         return loss.value, gd, gl, grad
+
+
+NET_BLOB_MAGIC, NET_BLOB_VERSION = 0x574E4647, 1
+
+
+def weights_blob(w) -> bytes:
+    """Header (magic, version, parameter count, type 0 = FP32) + FP32 weights."""
+    w = np.ascontiguousarray(w, dtype=np.float32).ravel()
+    hdr = np.array([NET_BLOB_MAGIC, NET_BLOB_VERSION, w.size, 0], dtype="<u4")
+    return hdr.tobytes() + w.astype("<f4").tobytes()
+
+
+def weights_from_blob(blob: bytes) -> np.ndarray:
+    hdr = np.frombuffer(blob[:16], dtype="<u4")
+    return np.frombuffer(blob[16:], dtype="<f4", count=int(hdr[2])).copy()
+
+
+def check_weights(blob: bytes) -> int:
+    """Host-only validation of a weight blob through the library (status)."""
+    buf = C.create_string_buffer(bytes(blob), len(blob)) if blob is not None else None
+    return load().gf_net_check_weights(buf, len(blob) if blob is not None else 0)
 
 
 def attach_net(mesh: "Mesh", net: "Net | None", use: bool = True):

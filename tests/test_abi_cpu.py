@@ -25,7 +25,7 @@ def lib():
 def declared_functions():
     txt = open(os.path.join(ROOT, "include", "gfem.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(gf_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(gf_[a-z_0-9]+)\s*\(", txt)))
 
 
 def test_header_declares_the_boundary():
@@ -88,3 +88,37 @@ def test_valid_mesh_without_device_reports_device_error(lib):
         pytest.skip("a GPU is present")
     st, msg = _create(lib, X1, [[0, 1, 3, 2]])
     assert st == gfem.GF_EDEVICE, msg
+
+
+def test_weight_blob_is_validated_on_the_host(lib):
+    """The network's weights cross the boundary as a sized, versioned blob;
+    every malformed variant is rejected with GF_EINVAL before any device work."""
+    n = C.c_int32()
+    assert lib.gf_net_num_params(C.byref(n)) == gfem.GF_OK
+    good = gfem.weights_blob(np.linspace(-1, 1, n.value).astype(np.float32))
+    assert len(good) == 16 + 4 * n.value
+    assert gfem.check_weights(good) == gfem.GF_OK
+    bad = {
+        "short header": good[:12],
+        "truncated": good[:-4],
+        "trailing byte": good + b"\0",
+        "magic": b"XXXX" + good[4:],
+        "version": good[:4] + np.array([2], "<u4").tobytes() + good[8:],
+        "count": gfem.weights_blob(np.zeros(n.value - 1, np.float32)) + b"\0\0\0\0",
+        "dtype": good[:12] + np.array([1], "<u4").tobytes() + good[16:],
+        "nan": good[:16] + np.array([np.nan], "<f4").tobytes() + good[20:],
+    }
+    for what, blob in bad.items():
+        assert gfem.check_weights(blob) == gfem.GF_EINVAL, what
+        assert lib.gf_last_error().decode(), what
+    assert lib.gf_net_check_weights(None, 0) == gfem.GF_EINVAL
+    # a null network is rejected before the blob is read
+    buf = C.create_string_buffer(good, len(good))
+    assert lib.gf_net_set_weights(None, buf, len(good)) == gfem.GF_EINVAL
+    sz = C.c_size_t()
+    assert lib.gf_net_get_weights(None, None, C.byref(sz)) == gfem.GF_EINVAL
+
+
+def test_shipped_weights_pass_the_blob_check(lib):
+    w = np.load(os.path.join(ROOT, "paper_2103_14870_amd", "weights", "precond_net.npy"))
+    assert gfem.check_weights(gfem.weights_blob(w)) == gfem.GF_OK
