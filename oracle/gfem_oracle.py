@@ -17,8 +17,10 @@ Fracture"):
   Theorem 3.1, Eq. 27-31): the Gram matrix of the edge vectors is linear in
   the squared lengths, so I_C = tr(G G0^-1) and J^2 = det G / det G0.  Nodal
   forces are sums along the tet's edges (Sec. 3.2, Eq. 12).
-* Per-edge binary damage, irreversible (Sec. 3.3, Eq. 20-21, local kernel
-  R_d = 0), evaluated as a Green normal-strain threshold along the edge.
+* Per-edge binary damage, irreversible (Sec. 3.3, Eq. 20-21), evaluated as a
+  Green normal-strain threshold along the edge: locally (R_d = 0), or on the
+  kernel-weighted average of the strain tensors of the tets whose rest
+  centroids lie within R_d (Eq. 20's non-local support).
 * Per-tet energy fraction chi (Sec. 3.4, Eq. 22-25), zero when the tet's
   unbroken edges no longer connect its four nodes.
 * The fractured system f* = chi f, K* = sum chi k (Sec. 3.6, Eq. 32-34),
@@ -153,6 +155,7 @@ class Mesh:
     mu: float = 0.0
     lam: float = 0.0
     alpha: float = 0.0
+    nonlocal_support: tuple | None = None   # (ptr, idx, w) of Eq. 20's support when R_d > 0
 
 
 def setup(X: np.ndarray, tets: np.ndarray, params: dict) -> Mesh:
@@ -176,8 +179,12 @@ def setup(X: np.ndarray, tets: np.ndarray, params: dict) -> Mesh:
     c = np.einsum("kij,tji->tk", EK, G0_inv)
     M = consistent_mass(X.shape[0], tets, V, params["density"])
     mu, lam, alpha = material(params["youngs"], params["poisson"])
-    return Mesh(X, tets, edges, tet_edge, Dm, np.linalg.inv(Dm), G0, G0_inv,
+    mesh = Mesh(X, tets, edges, tet_edge, Dm, np.linalg.inv(Dm), G0, G0_inv,
                 np.linalg.det(G0), V, S, c, S_edge, M, params, mu, lam, alpha)
+    radius = params.get("damage_radius", 0.0)
+    if radius > 0:
+        mesh.nonlocal_support = nonlocal_neighbours(mesh, radius)
+    return mesh
 
 
 def consistent_mass(n: int, tets: np.ndarray, V: np.ndarray, rho: float) -> sp.csr_matrix:
@@ -238,17 +245,78 @@ def damage_update(mesh: Mesh, x: np.ndarray, zeta: np.ndarray, near_tol: float =
                   override: dict | None = None):
     """zeta <- zeta OR (strain >= threshold); labels never revert (Sec. 3.3).
     Returns (new zeta, indices of edges within near_tol of the threshold).
-    `override` maps edge id -> label for near-threshold edges only."""
-    eps = edge_strain(mesh, x)
+    `override` maps edge id -> label for near-threshold edges only.
+    With a non-local support (R_d > 0, Eq. 20) an edge breaks when the
+    averaged normal strain along it reaches the threshold in any tet that
+    contains it, and is near the threshold when it is so in any of them."""
     thr = mesh.params["damage_strain"]
-    hit = eps >= thr
-    near = np.nonzero(np.abs(eps - thr) < near_tol)[0]
+    if mesh.nonlocal_support is not None:
+        eps_t = nonlocal_edge_strain(mesh, x)
+        ne = mesh.edges.shape[0]
+        hit = np.zeros(ne, bool)
+        np.logical_or.at(hit, mesh.tet_edge.ravel(), (eps_t >= thr).ravel())
+        nr = np.zeros(ne, bool)
+        np.logical_or.at(nr, mesh.tet_edge.ravel(), (np.abs(eps_t - thr) < near_tol).ravel())
+        near = np.nonzero(nr)[0]
+    else:
+        eps = edge_strain(mesh, x)
+        hit = eps >= thr
+        near = np.nonzero(np.abs(eps - thr) < near_tol)[0]
     if override:
         near_set = set(near.tolist())
         for e, lab in override.items():
             if e in near_set:
                 hit[e] = bool(lab)
     return zeta | hit, near
+
+
+# --------------------------------------------------------------------------
+# Non-local damage criterion (Eq. 20 with a support R_d > 0)
+# --------------------------------------------------------------------------
+
+def rest_centroids(mesh: Mesh) -> np.ndarray:
+    return mesh.X[mesh.tets].mean(axis=1)
+
+
+def nonlocal_neighbours(mesh: Mesh, radius: float):
+    """Eq. 20's support: for each tet t the tets t' whose rest centroid lies
+    within `radius` of t's, ascending, with the kernel weights
+    w = (1 - (r / R_d)^2)^2 normalised to sum 1 over the support (r the
+    centroid distance; the tet itself has w = 1 before normalisation).
+    Returns CSR arrays (ptr (m+1), idx, w)."""
+    from scipy.spatial import cKDTree
+
+    c = rest_centroids(mesh)
+    m = c.shape[0]
+    lists = cKDTree(c).query_ball_point(c, r=radius)
+    ptr = np.zeros(m + 1, np.int64)
+    idx, wts = [], []
+    for t in range(m):
+        nb = np.array(sorted(lists[t]), np.int64)
+        r2 = np.sum((c[nb] - c[t]) ** 2, axis=1) / (radius * radius)
+        w = (1.0 - r2) ** 2
+        idx.append(nb)
+        wts.append(w / w.sum())
+        ptr[t + 1] = ptr[t] + nb.size
+    return ptr, np.concatenate(idx), np.concatenate(wts)
+
+
+def nonlocal_edge_strain(mesh: Mesh, x: np.ndarray) -> np.ndarray:
+    """Per tet and local edge, the normal strain q_k^T E* q_k of the weighted
+    average E* of the Green strain tensors of the tets in the support
+    (Eq. 20 with the strain reading of the criterion), q_k the rest unit
+    direction of the edge.  (m,6)."""
+    ptr, idx, w = mesh.nonlocal_support
+    F = deformation_gradient(mesh, x)
+    E = 0.5 * (np.einsum("tji,tjk->tik", F, F) - np.eye(3))
+    m = E.shape[0]
+    row = np.repeat(np.arange(m), np.diff(ptr))
+    Eavg = np.zeros_like(E)
+    np.add.at(Eavg, row, w[:, None, None] * E[idx])
+    t = mesh.tets
+    q = np.stack([mesh.X[t[:, b]] - mesh.X[t[:, a]] for a, b in LOCAL_EDGES], axis=1)
+    q /= np.linalg.norm(q, axis=2, keepdims=True)
+    return np.einsum("tki,tij,tkj->tk", q, Eavg, q)
 
 
 # --------------------------------------------------------------------------
