@@ -319,6 +319,12 @@ def nonlocal_edge_strain(mesh: Mesh, x: np.ndarray) -> np.ndarray:
     return np.einsum("tki,tij,tkj->tk", q, Eavg, q)
 
 
+# Below this |J| the volume terms of the energy are evaluated in cofactor form
+# (the edge-length form of J divides by J: one over the volume of a flat
+# tet), and plastic flow is not applied.
+J_MIN = 0.05
+
+
 # --------------------------------------------------------------------------
 # Plasticity (ductile case): multiplicative, volume-preserving flow with an
 # instant radial return of the deviatoric elastic Hencky strain
@@ -336,11 +342,14 @@ def plastic_update(mesh: Mesh, x: np.ndarray, Cp: np.ndarray) -> np.ndarray:
     strains h_i = log(lam_i) / 2 have deviator d = h - mean(h).  If |d| exceeds
     the yield strain, d is scaled back onto the yield surface and Cp is moved
     so that C has the returned elastic stretches over it; the mean (volumetric)
-    part never flows, so det Cp stays 1."""
+    part never flows, so det Cp stays 1.  Tets with det F < J_MIN (nearly flat
+    or inverted) do not flow: C = F^T F cannot tell an inverted tet from its
+    mirror image, so its stretches are no measure of plastic strain there."""
     ey = mesh.params.get("yield_strain", 0.0)
     if ey <= 0:
         return Cp
     F = deformation_gradient(mesh, x)
+    J = np.linalg.det(F)
     C = np.einsum("tji,tjk->tik", F, F)
     # generalised symmetric eigenproblem through the Cholesky factor of Cp:
     # S = L^-1 C L^-T = W diag(lam) W^T, V = L^-T W
@@ -352,7 +361,7 @@ def plastic_update(mesh: Mesh, x: np.ndarray, Cp: np.ndarray) -> np.ndarray:
     hm = h.mean(axis=1, keepdims=True)
     d = h - hm
     nd = np.linalg.norm(d, axis=1)
-    flow = nd > ey
+    flow = (nd > ey) & (J >= J_MIN)
     h_new = hm + d * np.where(flow, ey / np.where(flow, nd, 1.0), 1.0)[:, None]
     # Cp' = L W diag(lam / lam') W^T L^T: C over Cp' has the returned stretches
     LW = L @ W
@@ -370,9 +379,6 @@ def gram_offset(mesh: Mesh, Cp: np.ndarray) -> np.ndarray:
 # Edge-length element (Theorem 3.1 + Eq. 12 + Eq. 35)
 # --------------------------------------------------------------------------
 
-# Below this |J| the volume terms of the energy are evaluated in cofactor form
-# (the edge-length form of J divides by J: one over the volume of a flat tet).
-J_MIN = 0.05
 
 
 @dataclass

@@ -10,6 +10,7 @@ a different eigen-routine than the oracle's:
   * after the return the deviatoric elastic Hencky strain has norm equal to
     the yield strain and points the same way as before, its volumetric part
     is untouched, and det Cp stays 1 (isochoric flow);
+  * a nearly flat or inverted tet (det F < 0.05) does not flow;
   * a uniaxial isochoric stretch returns to the closed-form plastic stretch;
   * the plastic rest Gram matrix gives I_C = tr(C Cp^-1) and J = det F.
 The system (one linearised backward-Euler step, Sec. 4.3, consistent mass of
@@ -115,6 +116,21 @@ def test_plastic_no_flow_below_yield(seed):
     # plasticity switched off: never moves
     mesh0 = O.setup(X, np.arange(4)[None], dict(PARAMS, yield_strain=0.0))
     np.testing.assert_array_equal(O.plastic_update(mesh0, x * 3.0, Cp), Cp)
+
+
+@pytest.mark.parametrize("J", [0.04, 1e-3, -0.2, -1.5])
+def test_no_flow_in_flat_or_inverted_tets(J):
+    """A tet far above yield whose det F is below 0.05 (nearly flat, or
+    inverted) keeps its plastic state; the same shear with det F = 1 flows."""
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float) * 0.1
+    mesh = O.setup(X, np.arange(4)[None], dict(PARAMS, yield_strain=0.05))
+    X = mesh.X[mesh.tets[0]]
+    shear = np.eye(3) + np.array([[0, 0.8, 0], [0, 0, 0], [0, 0, 0]])
+    Cp = np.eye(3)[None]
+    flows = O.plastic_update(mesh, X @ shear.T, Cp)
+    assert np.abs(flows - Cp).max() > 0.1
+    F = shear @ np.diag([1.0, 1.0, J])  # det F = J
+    np.testing.assert_array_equal(O.plastic_update(mesh, X @ F.T, Cp), Cp)
 
 
 def test_uniaxial_isochoric_stretch_closed_form():
