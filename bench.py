@@ -171,6 +171,51 @@ def kernel_times(m, steps, warmup):
     return kus, kn
 
 
+def trajectory(make_mesh, n_steps, window, learned, log):
+    """n_steps from rest, one gf_step call per step, with per-window totals:
+    steps/s (wall clock, synchronised at window ends), PCG iterations per
+    step, learned attempts re-solved with block-Jacobi, steps re-run in FP64,
+    broken edges at the window's end.  Stops at the first step that does not
+    converge and reports it."""
+    import torch
+
+    from paper_2103_14870_amd import gfem
+
+    m = make_mesh(learned)
+    rows, cur, failed = [], None, None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_steps):
+        if cur is None:
+            cur = dict(first=i + 1, steps=0, iters=0, fallback=0, fp64=0)
+        s = m.step(1, raise_on_error=False)
+        if s["status"] != gfem.GF_OK:
+            failed = dict(step=i + 1, status=gfem.STATUS_NAMES.get(s["status"], s["status"]),
+                          rel_residual=s["rel_residual"], iters=s["inner_iters"])
+        else:
+            cur["steps"] += 1
+            cur["iters"] += s["inner_iters"]
+            cur["fallback"] += s["used_fallback"]
+            cur["fp64"] += s["fp64_steps"]
+            cur["broken"] = s["total_broken"]
+        if failed or (i + 1) % window == 0 or i + 1 == n_steps:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if cur["steps"]:
+                cur.update(last=cur["first"] + cur["steps"] - 1, seconds=t1 - t0,
+                           steps_per_s=cur["steps"] / (t1 - t0), iters_per_step=cur["iters"] / cur["steps"])
+                rows.append(cur)
+                log(f"{'learned' if learned else 'block-Jacobi'} steps {cur['first']}-{cur['last']}: "
+                    f"{cur['iters_per_step']:.1f} it/step {cur['steps_per_s']:.1f} steps/s "
+                    f"fb {cur['fallback']} fp64 {cur['fp64']} broken {cur['broken']}")
+            cur, t0 = None, t1
+        if failed:
+            log(f"step {failed['step']} did not converge: {failed}")
+            break
+    m.close()
+    return dict(windows=rows, failed=failed)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +233,10 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the legs, one device-to-device copy of this many MiB from a cache-cold "
                          "source (calibrates the HBM byte counters)")
+    ap.add_argument("--trajectory", type=int, default=0, metavar="N",
+                    help="instead of the metric: N steps from rest with each preconditioner, one call per step, "
+                         "printing per-window iterations and steps/s (one JSON line)")
+    ap.add_argument("--window", type=int, default=25, help="window length of --trajectory")
     ap.add_argument("--counter-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM counter summary from two rocprofv3 --pmc runs and exit (no GPU)")
     args = ap.parse_args()
@@ -248,6 +297,15 @@ def main():
         return m
 
     log = lambda msg: print(f"bench: {msg}", file=sys.stderr, flush=True)
+    if args.trajectory > 0:
+        out = {"mode": "trajectory", "workload": workload, "steps": args.trajectory, "window": args.window,
+               "net_every_n_steps": args.net_every}
+        legs = (("learned", True), ("block_jacobi", False)) if net is not None else (("block_jacobi", False),)
+        for name, learned in legs:
+            log(f"trajectory leg ({name})")
+            out[name] = trajectory(make_mesh, args.trajectory, args.window, learned, log)
+        print(json.dumps(out), flush=True)
+        return
     log(f"timed leg ({args.precond})")
     m = make_mesh(net is not None)
     main_leg = timed_steps(m, args.steps, args.warmup)

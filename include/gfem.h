@@ -57,6 +57,12 @@ typedef struct {
   double poisson;         /* nu in (-1, 0.5) */
   double density;         /* rho [kg/m^3]: consistent mass of Eq. 5 */
   double damage_strain;   /* an edge breaks when its Green normal strain >= this (Eq. 21) */
+  double damage_radius;   /* R_d of Eq. 20 [m]: 0 = local criterion (each edge's own strain);
+                             > 0 = non-local: the strain tensors of the tets whose rest
+                             centroids lie within R_d are averaged with the weights
+                             (1 - (r/R_d)^2)^2 normalised to 1, and an edge breaks when the
+                             averaged normal strain along it reaches damage_strain in any tet
+                             that contains it (the support is built once, at create) */
   double yield_strain;    /* ductile yield on |dev E_elastic|_F; <= 0 disables plasticity */
   double dt;              /* timestep [s] */
   double rayleigh_alpha;  /* damping b = alpha M + beta K* (Sec. 3.1, Sec. 3.6) */

@@ -126,6 +126,12 @@ struct gf_mesh {
   uint8_t* zeta[2] = {nullptr, nullptr};
   int zcur = 0;
   int32_t* near_ids = nullptr;  // near-threshold edges of the last damage pass (internal ids)
+  // non-local damage criterion (R_d > 0): support CSR and two strain buffers
+  int64_t* nl_ptr = nullptr;
+  int32_t* nl_idx = nullptr;
+  double* nl_w = nullptr;
+  gfem::Sym6 *nl_E = nullptr, *nl_Eavg = nullptr;
+  size_t nl_entries = 0;
   int32_t *edge_ptr = nullptr, *edge_slot = nullptr, *blk_ij = nullptr, *blk_ji = nullptr;
   void* edge_w = nullptr;
   // block matrix
@@ -286,8 +292,13 @@ void assemble(gf_mesh* M, bool flow, d4* f_out) {
   hchk(hipMemsetAsync(M->ctr, 0, sizeof(gfem::Counters), s), "hipMemsetAsync");
   const int zi = M->zcur, zo = 1 - M->zcur;
   M->timed(0, -1, 0, [&] {
-    gfem::launch_damage(s, M->ne, M->edges, M->X, M->U, M->edge_S, M->zeta[zi], M->zeta[zo], M->p.damage_strain,
-                        M->ctr, M->near_ids);
+    if (M->nl_ptr)
+      gfem::launch_damage_nonlocal(s, M->m, M->ne, M->tets, M->X, M->U, M->nl_ptr, M->nl_idx, M->nl_w, M->nl_E,
+                                   M->nl_Eavg, M->edges, M->edge_ptr, M->edge_slot, M->zeta[zi], M->zeta[zo],
+                                   M->p.damage_strain, M->ctr, M->near_ids);
+    else
+      gfem::launch_damage(s, M->ne, M->edges, M->X, M->U, M->edge_S, M->zeta[zi], M->zeta[zo], M->p.damage_strain,
+                          M->ctr, M->near_ids);
   });
   gfem::ElemConst ec{M->mu, M->lam, M->alpha_m1};
   const T* pl = nullptr;
@@ -763,7 +774,8 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
   const gf_params& p = *params;
   if (!(p.youngs > 0) || !(p.poisson > -1.0 && p.poisson < 0.5) || !(p.density > 0) || !(p.dt > 0) ||
       !(p.cg_rel_tol > 0) || p.cg_max_iter <= 0 || (p.precision != GF_PREC_FP64 && p.precision != GF_PREC_SPLIT) ||
-      (p.precond != GF_PC_BLOCK_JACOBI && p.precond != GF_PC_LEARNED) || !std::isfinite(p.damage_strain))
+      (p.precond != GF_PC_BLOCK_JACOBI && p.precond != GF_PC_LEARNED) || !std::isfinite(p.damage_strain) ||
+      !(p.damage_radius >= 0.0) || !std::isfinite(p.damage_radius))
     return fail(GF_EINVAL, "gf_mesh_create: invalid parameters");
   if (p.precond == GF_PC_LEARNED && p.precision != GF_PREC_SPLIT)
     return fail(GF_EINVAL, "gf_mesh_create: the learned preconditioner needs the split precision mode");
@@ -775,6 +787,15 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     bool degen = false;
     std::string err = gfem::build_topology(rest_xyz, n_nodes, tets, n_tets, p.density, topo.get(), &degen);
     if (!err.empty()) return fail(degen ? GF_EDEGENERATE : GF_EINVAL, "gf_mesh_create: " + err);
+    // support of the non-local criterion (Eq. 20), also host-side
+    std::vector<int64_t> nl_ptr;
+    std::vector<int32_t> nl_idx;
+    std::vector<double> nl_w;
+    if (p.damage_radius > 0.0) {
+      // at most 2^31 entries (12 B each: 24 GiB of the 288 GiB of HBM)
+      err = gfem::build_nonlocal_support(*topo, p.damage_radius, (size_t)1 << 31, &nl_ptr, &nl_idx, &nl_w);
+      if (!err.empty()) return fail(GF_EINVAL, "gf_mesh_create: " + err);
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(GF_EDEVICE, "no HIP device");
     int dev = 0;
@@ -840,6 +861,14 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     M->zeta[0] = M->al.get<uint8_t>(T.ne);
     M->zeta[1] = M->al.get<uint8_t>(T.ne);
     M->near_ids = M->al.get<int32_t>(T.ne);
+    if (!nl_ptr.empty()) {
+      M->nl_ptr = upload(M, nl_ptr);
+      M->nl_idx = upload(M, nl_idx);
+      M->nl_w = upload(M, nl_w);
+      M->nl_E = M->al.get<gfem::Sym6>(T.m);
+      M->nl_Eavg = M->al.get<gfem::Sym6>(T.m);
+      M->nl_entries = nl_idx.size();
+    }
     M->edge_ptr = upload(M, T.edge_ptr);
     M->edge_slot = upload(M, T.edge_slot);
     M->blk_ij = upload(M, T.blk_ij);

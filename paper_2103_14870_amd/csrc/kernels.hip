@@ -119,6 +119,23 @@ __device__ __forceinline__ constexpr int EB(int k) { return k < 3 ? k + 1 : (k =
 
 // ---------------------------------------------------------------- damage
 
+// Counters (new, total broken, near threshold) and the near-threshold edge
+// list, shared by the local and the non-local damage passes; every thread of
+// the workgroup calls it.  One atomic per wave reserves the wave's entries.
+__device__ __forceinline__ void damage_tail(bool act, bool hit, bool was, bool near, int e, Counters* ctr,
+                                            int32_t* __restrict__ near_ids) {
+  const bool pr[3] = {act && hit && !was, act && (hit || was), act && near};
+  block_counts<3>(ctr, kNewBroken, pr);
+  const unsigned long long bal = __ballot(act && near);
+  if (bal) {
+    const int l = threadIdx.x & 63;
+    int base = 0;
+    if (l == 0) base = atomicAdd(&ctr->near_n, (int)__popcll(bal));
+    base = __shfl(base, 0, 64);
+    if (act && near) near_ids[base + (int)__popcll(bal & ((1ull << l) - 1ull))] = e;
+  }
+}
+
 // Per edge: Green normal strain along the rest edge, (s - S) / (2 S) with
 // s - S = 2 dX.dU + dU.dU from the displacement (no cancellation of the
 // absolute positions); zeta <- zeta OR (strain >= threshold) (Eq. 21; labels
@@ -144,17 +161,111 @@ __global__ __launch_bounds__(kThreads) void k_damage(int ne, const int2* __restr
     near = fabs(eps - thr) < 1e-6;
     z_out[e] = (uint8_t)(was || hit);
   }
-  const bool pr[3] = {act && hit && !was, act && (hit || was), act && near};
-  block_counts<3>(ctr, kNewBroken, pr);
-  // near-threshold edges: one atomic per wave reserves the wave's entries
-  const unsigned long long bal = __ballot(act && near);
-  if (bal) {
-    const int l = threadIdx.x & 63;
-    int base = 0;
-    if (l == 0) base = atomicAdd(&ctr->near_n, (int)__popcll(bal));
-    base = __shfl(base, 0, 64);
-    if (act && near) near_ids[base + (int)__popcll(bal & ((1ull << l) - 1ull))] = e;
+  damage_tail(act, hit, was, near, e, ctr, near_ids);
+}
+
+// ---------------------------------------------------------------- non-local damage (Eq. 20, R_d > 0)
+
+// Per tet: Green strain E = (H + H^T + H^T H)/2 with H = grad u = Du Dm^-1
+// (F = I + H), from the displacement in FP64, so that no absolute positions
+// cancel.  F does not depend on the tet's vertex order.
+__global__ __launch_bounds__(kThreads) void k_nl_strain(int m, const int4* __restrict__ tets,
+                                                        const d4* __restrict__ X, const d4* __restrict__ U,
+                                                        Sym6* __restrict__ E) {
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= m) return;
+  const int4 v = tets[t];
+  const d4 x0 = X[v.x], x1 = X[v.y], x2 = X[v.z], x3 = X[v.w];
+  const d4 u0 = U[v.x], u1 = U[v.y], u2 = U[v.z], u3 = U[v.w];
+  // columns i = 1..3: rest edge vectors Dm and displacement differences Du
+  const double D[3][3] = {{x1.x - x0.x, x2.x - x0.x, x3.x - x0.x},
+                          {x1.y - x0.y, x2.y - x0.y, x3.y - x0.y},
+                          {x1.z - x0.z, x2.z - x0.z, x3.z - x0.z}};
+  const double W[3][3] = {{u1.x - u0.x, u2.x - u0.x, u3.x - u0.x},
+                          {u1.y - u0.y, u2.y - u0.y, u3.y - u0.y},
+                          {u1.z - u0.z, u2.z - u0.z, u3.z - u0.z}};
+  // Dm^-1 = adj(Dm) / det(Dm)
+  double A[3][3];
+  A[0][0] = D[1][1] * D[2][2] - D[1][2] * D[2][1];
+  A[0][1] = D[0][2] * D[2][1] - D[0][1] * D[2][2];
+  A[0][2] = D[0][1] * D[1][2] - D[0][2] * D[1][1];
+  A[1][0] = D[1][2] * D[2][0] - D[1][0] * D[2][2];
+  A[1][1] = D[0][0] * D[2][2] - D[0][2] * D[2][0];
+  A[1][2] = D[0][2] * D[1][0] - D[0][0] * D[1][2];
+  A[2][0] = D[1][0] * D[2][1] - D[1][1] * D[2][0];
+  A[2][1] = D[0][1] * D[2][0] - D[0][0] * D[2][1];
+  A[2][2] = D[0][0] * D[1][1] - D[0][1] * D[1][0];
+  const double inv_det = 1.0 / (D[0][0] * A[0][0] + D[0][1] * A[1][0] + D[0][2] * A[2][0]);
+  double H[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) H[r][c] = (W[r][0] * A[0][c] + W[r][1] * A[1][c] + W[r][2] * A[2][c]) * inv_det;
+  auto e = [&](int a, int b) {
+    return 0.5 * (H[a][b] + H[b][a] + H[0][a] * H[0][b] + H[1][a] * H[1][b] + H[2][a] * H[2][b]);
+  };
+  Sym6 o;
+  o.v[0] = e(0, 0);
+  o.v[1] = e(1, 1);
+  o.v[2] = e(2, 2);
+  o.v[3] = e(0, 1);
+  o.v[4] = e(0, 2);
+  o.v[5] = e(1, 2);
+  E[t] = o;
+}
+
+// Per tet: E*_t = sum_j w_tj E_j over the support (Eq. 20's weighted average).
+__global__ __launch_bounds__(kThreads) void k_nl_average(int m, const int64_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ idx,
+                                                         const double* __restrict__ w,
+                                                         const Sym6* __restrict__ E, Sym6* __restrict__ Eavg) {
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= m) return;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const int64_t j1 = ptr[t + 1];
+  for (int64_t j = ptr[t]; j < j1; ++j) {
+    const Sym6 ej = E[idx[j]];
+    const double wj = w[j];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] = fmadd(wj, ej.v[c], acc[c]);
   }
+  Sym6 o;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) o.v[c] = acc[c];
+  Eavg[t] = o;
+}
+
+// Per edge: averaged normal strain d^T E* d / d^T d (d the rest edge vector)
+// in each tet that contains the edge (slots k*m + t); the edge breaks when
+// the largest reaches the threshold (Eq. 21).
+__global__ __launch_bounds__(kThreads) void k_nl_damage(int ne, int m, const int2* __restrict__ edges,
+                                                        const d4* __restrict__ X,
+                                                        const int32_t* __restrict__ edge_ptr,
+                                                        const int32_t* __restrict__ edge_slot,
+                                                        const Sym6* __restrict__ Eavg,
+                                                        const uint8_t* __restrict__ z_in,
+                                                        uint8_t* __restrict__ z_out, double thr, Counters* ctr,
+                                                        int32_t* __restrict__ near_ids) {
+  const int e = blockIdx.x * kThreads + threadIdx.x;
+  const bool act = e < ne;
+  bool hit = false, was = false, near = false;
+  if (act) {
+    const int2 ij = edges[e];
+    const d4 xi = X[ij.x], xj = X[ij.y];
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+    const double inv_dd = 1.0 / (dx * dx + dy * dy + dz * dz);
+    for (int i = edge_ptr[e]; i < edge_ptr[e + 1]; ++i) {
+      const Sym6 a = Eavg[edge_slot[i] % m];
+      const double q = a.v[0] * dx * dx + a.v[1] * dy * dy + a.v[2] * dz * dz +
+                       2.0 * (a.v[3] * dx * dy + a.v[4] * dx * dz + a.v[5] * dy * dz);
+      const double eps = q * inv_dd;
+      hit = hit || eps >= thr;
+      near = near || fabs(eps - thr) < 1e-6;
+    }
+    was = z_in[e] != 0;
+    z_out[e] = (uint8_t)(was || hit);
+  }
+  damage_tail(act, hit, was, near, e, ctr, near_ids);
 }
 
 // ---------------------------------------------------------------- plasticity
@@ -1628,6 +1739,17 @@ void launch_damage(hipStream_t s, int ne, const int2* edges, const d4* X, const 
                    const uint8_t* z_in, uint8_t* z_out, double thr, Counters* ctr, int32_t* near_ids) {
   if (ne <= 0) return;
   k_damage<<<blocks_for(ne), kThreads, 0, s>>>(ne, edges, X, U, S, z_in, z_out, thr, ctr, near_ids);
+}
+
+void launch_damage_nonlocal(hipStream_t s, int m, int ne, const int4* tets, const d4* X, const d4* U,
+                            const int64_t* nl_ptr, const int32_t* nl_idx, const double* nl_w, Sym6* E,
+                            Sym6* Eavg, const int2* edges, const int32_t* edge_ptr, const int32_t* edge_slot,
+                            const uint8_t* z_in, uint8_t* z_out, double thr, Counters* ctr, int32_t* near_ids) {
+  if (ne <= 0 || m <= 0) return;
+  k_nl_strain<<<blocks_for(m), kThreads, 0, s>>>(m, tets, X, U, E);
+  k_nl_average<<<blocks_for(m), kThreads, 0, s>>>(m, nl_ptr, nl_idx, nl_w, E, Eavg);
+  k_nl_damage<<<blocks_for(ne), kThreads, 0, s>>>(ne, m, edges, X, edge_ptr, edge_slot, Eavg, z_in, z_out, thr,
+                                                  ctr, near_ids);
 }
 
 template <typename T>

@@ -82,6 +82,22 @@ void launch_damage(hipStream_t s, int ne, const int2* edges, const d4* X, const 
                    const double* S, const uint8_t* z_in, uint8_t* z_out, double thr,
                    Counters* ctr, int32_t* near_ids);
 
+// Non-local damage criterion (Sec. 3.3, Eq. 20, support R_d > 0): per-tet
+// Green strain tensors E = (F^T F - I)/2 from the displacement (FP64, entries
+// 00,11,22,01,02,12), their weighted averages over each tet's support (CSR
+// nl_ptr/nl_idx/nl_w, built once on the host), then per edge the largest
+// averaged normal strain q^T E* q (q the rest edge direction) over the tets
+// that contain it: zeta <- zeta OR (that strain >= thr); labels, counters and
+// the near-threshold list as launch_damage (near: within 1e-6 in any of those
+// tets).  E and Eavg are work buffers of m records.
+struct alignas(16) Sym6 {
+  double v[6];
+};
+void launch_damage_nonlocal(hipStream_t s, int m, int ne, const int4* tets, const d4* X, const d4* U,
+                            const int64_t* nl_ptr, const int32_t* nl_idx, const double* nl_w, Sym6* E,
+                            Sym6* Eavg, const int2* edges, const int32_t* edge_ptr, const int32_t* edge_slot,
+                            const uint8_t* z_in, uint8_t* z_out, double thr, Counters* ctr, int32_t* near_ids);
+
 // Plastic flow of the ductile workload: pl_in -> pl_out, each [6][m] plastic
 // rest-shape offsets Gp - G0 (symmetric 00,11,22,01,02,12).
 template <typename T>

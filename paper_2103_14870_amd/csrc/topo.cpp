@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <numeric>
+#include <utility>
 
 namespace gfem {
 
@@ -225,6 +226,86 @@ std::string build_topology(const double* xyz, int n, const int32_t* tets_in, int
   for (int c = 0; c < T.ne; ++c) {
     T.edge_internal[c] = ce[c].second;
     T.edge_canon[ce[c].second] = c;
+  }
+  return "";
+}
+
+std::string build_nonlocal_support(const Topology& T, double radius, size_t max_entries,
+                                   std::vector<int64_t>* ptr, std::vector<int32_t>* idx,
+                                   std::vector<double>* w) {
+  if (!(radius > 0.0) || !std::isfinite(radius)) return "non-local support radius must be positive and finite";
+  const int m = T.m;
+  std::vector<double> c(3 * (size_t)m);
+  double lo[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, hi[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+  for (int t = 0; t < m; ++t)
+    for (int d = 0; d < 3; ++d) {
+      double acc = 0.0;
+      for (int a = 0; a < 4; ++a) acc += T.X[3 * (size_t)T.tets[4 * (size_t)t + a] + d];
+      c[3 * (size_t)t + d] = acc / 4.0;
+      lo[d] = std::min(lo[d], c[3 * (size_t)t + d]);
+      hi[d] = std::max(hi[d], c[3 * (size_t)t + d]);
+    }
+  // cells of edge >= radius, at most 512 per axis: a neighbour within radius
+  // is always in one of the 27 cells around a tet's own
+  double cell = radius;
+  for (int d = 0; d < 3; ++d) cell = std::max(cell, (hi[d] - lo[d]) / 512.0);
+  int dim[3];
+  for (int d = 0; d < 3; ++d) dim[d] = std::max(1, (int)std::floor((hi[d] - lo[d]) / cell) + 1);
+  auto cell_of = [&](int t, int* q) {
+    for (int d = 0; d < 3; ++d)
+      q[d] = std::min(dim[d] - 1, std::max(0, (int)std::floor((c[3 * (size_t)t + d] - lo[d]) / cell)));
+  };
+  const size_t ncell = (size_t)dim[0] * dim[1] * dim[2];
+  std::vector<int32_t> cstart(ncell + 1, 0), order(m);
+  for (int t = 0; t < m; ++t) {
+    int q[3];
+    cell_of(t, q);
+    ++cstart[((size_t)q[2] * dim[1] + q[1]) * dim[0] + q[0] + 1];
+  }
+  for (size_t i = 0; i < ncell; ++i) cstart[i + 1] += cstart[i];
+  {
+    std::vector<int32_t> fill(cstart.begin(), cstart.end() - 1);
+    for (int t = 0; t < m; ++t) {  // ascending within each cell
+      int q[3];
+      cell_of(t, q);
+      order[fill[((size_t)q[2] * dim[1] + q[1]) * dim[0] + q[0]]++] = t;
+    }
+  }
+  const double r2 = radius * radius;
+  ptr->assign((size_t)m + 1, 0);
+  idx->clear();
+  w->clear();
+  std::vector<std::pair<int32_t, double>> nb;
+  for (int t = 0; t < m; ++t) {
+    int q[3];
+    cell_of(t, q);
+    nb.clear();
+    for (int z = std::max(0, q[2] - 1); z <= std::min(dim[2] - 1, q[2] + 1); ++z)
+      for (int y = std::max(0, q[1] - 1); y <= std::min(dim[1] - 1, q[1] + 1); ++y)
+        for (int x = std::max(0, q[0] - 1); x <= std::min(dim[0] - 1, q[0] + 1); ++x) {
+          const size_t ci = ((size_t)z * dim[1] + y) * dim[0] + x;
+          for (int i = cstart[ci]; i < cstart[ci + 1]; ++i) {
+            const int j = order[i];
+            double d2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+              const double dd = c[3 * (size_t)j + d] - c[3 * (size_t)t + d];
+              d2 += dd * dd;
+            }
+            if (d2 <= r2) {
+              const double u = 1.0 - d2 / r2;
+              nb.push_back({j, u * u});
+            }
+          }
+        }
+    std::sort(nb.begin(), nb.end());
+    double sum = 0.0;
+    for (const auto& e : nb) sum += e.second;
+    if (idx->size() + nb.size() > max_entries) return "non-local support too large for the device buffers";
+    for (const auto& e : nb) {
+      idx->push_back(e.first);
+      w->push_back(e.second / sum);
+    }
+    (*ptr)[t + 1] = (int64_t)idx->size();
   }
   return "";
 }

@@ -57,4 +57,15 @@ struct Topology {
 std::string build_topology(const double* xyz, int n, const int32_t* tets, int m, double density,
                            Topology* out, bool* degenerate);
 
+// Support of the non-local fracture criterion (Sec. 3.3, Eq. 20): for each tet
+// t the tets whose rest centroids lie within `radius` of t's (t included),
+// ascending, with the kernel weights (1 - (r/radius)^2)^2 normalised to sum 1
+// over the support.  CSR: entries ptr[t] .. ptr[t+1] of idx / w.  Built on a
+// uniform grid of cell size >= radius (each tet scans the 27 cells around its
+// own).  Returns "" on success, otherwise an error message (radius not
+// positive and finite, or more than max_entries entries in total).
+std::string build_nonlocal_support(const Topology& T, double radius, size_t max_entries,
+                                   std::vector<int64_t>* ptr, std::vector<int32_t>* idx,
+                                   std::vector<double>* w);
+
 }  // namespace gfem

@@ -25,7 +25,8 @@ KERNEL_CATEGORIES = ("damage", "element", "assembly", "precond", "spmv", "pcg_ve
 
 class GfParams(C.Structure):
     _fields_ = [("youngs", C.c_double), ("poisson", C.c_double), ("density", C.c_double),
-                ("damage_strain", C.c_double), ("yield_strain", C.c_double), ("dt", C.c_double),
+                ("damage_strain", C.c_double), ("damage_radius", C.c_double), ("yield_strain", C.c_double),
+                ("dt", C.c_double),
                 ("rayleigh_alpha", C.c_double), ("rayleigh_beta", C.c_double), ("gravity", C.c_double * 3),
                 ("cg_rel_tol", C.c_double), ("cg_max_iter", C.c_int32), ("precision", C.c_int32),
                 ("precond", C.c_int32), ("net_every_n_steps", C.c_int32)]
@@ -127,7 +128,8 @@ def _u8ptr(a: np.ndarray):
 def make_params(p: dict) -> GfParams:
     g = p.get("gravity", (0.0, 0.0, 0.0))
     return GfParams(float(p["youngs"]), float(p["poisson"]), float(p["density"]), float(p["damage_strain"]),
-                    float(p.get("yield_strain", 0.0)), float(p["dt"]), float(p.get("rayleigh_alpha", 0.0)),
+                    float(p.get("damage_radius", 0.0)), float(p.get("yield_strain", 0.0)), float(p["dt"]),
+                    float(p.get("rayleigh_alpha", 0.0)),
                     float(p.get("rayleigh_beta", 0.0)), (C.c_double * 3)(*[float(x) for x in g]),
                     float(p["cg_rel_tol"]), int(p.get("cg_max_iter", 5000)), PREC[p.get("precision", "fp64")],
                     PRECOND[p.get("precond", "block_jacobi")], int(p.get("net_every_n_steps", 1)))

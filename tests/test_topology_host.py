@@ -71,3 +71,33 @@ def test_invalid_meshes_are_rejected(checker, tmp_path):
         r = run(checker, path)
         assert r.returncode == 1 and r.stdout.startswith("err") and msg in r.stdout, (name, r.stdout, r.stderr[-2000:])
         assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
+
+
+def test_nonlocal_support_matches_the_oracle(checker, tmp_path):
+    """The library's support of Eq. 20 (uniform-grid search, host side) equals
+    the oracle's (k-d tree query) entry for entry: the same neighbour sets in
+    ascending order and the same normalised weights; a radius below the
+    centroid spacing leaves each tet alone; a non-positive radius is refused."""
+    from oracle import gfem_oracle as O
+
+    prob = meshgen.cube_block(5, 4, 3, h=0.1, jitter_frac=0.08, seed=3)
+    path = str(tmp_path / "cube.bin")
+    write_mesh(path, prob.X, prob.tets)
+    for radius in (1e-4, 0.17, 0.31):
+        out = str(tmp_path / "support.bin")
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+        r = subprocess.run([checker, path, repr(radius), out], capture_output=True, text=True, env=env, timeout=120)
+        assert r.returncode == 0 and r.stdout.strip() == "bad 0", r.stdout + r.stderr[-2000:]
+        raw = open(out, "rb").read()
+        m, ne = np.frombuffer(raw[:16], np.int64)
+        ptr = np.frombuffer(raw[16:16 + 8 * (m + 1)], np.int64)
+        idx = np.frombuffer(raw[16 + 8 * (m + 1):16 + 8 * (m + 1) + 4 * ne], np.int32)
+        w = np.frombuffer(raw[16 + 8 * (m + 1) + 4 * ne:], np.float64)
+        mesh = O.setup(prob.X, prob.tets, dict(prob.params, damage_radius=radius))
+        optr, oidx, ow = mesh.nonlocal_support
+        assert np.array_equal(ptr, optr) and np.array_equal(idx, oidx)
+        np.testing.assert_allclose(w, ow, rtol=1e-13, atol=1e-15)
+        if radius < 0.01:
+            assert np.array_equal(np.diff(ptr), np.ones(m))
+    bad = subprocess.run([checker, path, "0", str(tmp_path / "x.bin")], capture_output=True, text=True, timeout=60)
+    assert bad.returncode == 1 and "radius" in bad.stdout

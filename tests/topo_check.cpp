@@ -3,7 +3,11 @@
 // builds the topology and checks the compact lower/upper halves, their slot
 // maps and the contribution slots.  Prints "err <message>" and exits 1 when
 // the builder rejects the mesh, else "bad <count>" and exits with count != 0.
+// With two more arguments (radius, output path) it also builds the support of
+// the non-local damage criterion and writes it as int64 m, int64 entries,
+// (m+1) int64 ptr, entries int32 idx, entries f64 weights (tets in input order).
 #include <cstdio>
+#include <cstdlib>
 #include <fstream>
 #include <vector>
 
@@ -59,6 +63,22 @@ int main(int argc, char** argv) {
     }
   for (int c : seen)
     if (c != 1) bad++;
+  if (argc >= 4) {
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> idx;
+    std::vector<double> w;
+    const std::string e2 = gfem::build_nonlocal_support(t, std::atof(argv[2]), (size_t)1 << 31, &ptr, &idx, &w);
+    if (!e2.empty()) {
+      printf("err %s\n", e2.c_str());
+      return 1;
+    }
+    std::ofstream o(argv[3], std::ios::binary);
+    const int64_t hdr[2] = {m, (int64_t)idx.size()};
+    o.write(reinterpret_cast<const char*>(hdr), sizeof hdr);
+    o.write(reinterpret_cast<const char*>(ptr.data()), 8 * ptr.size());
+    o.write(reinterpret_cast<const char*>(idx.data()), 4 * idx.size());
+    o.write(reinterpret_cast<const char*>(w.data()), 8 * w.size());
+  }
   printf("bad %d\n", bad);
   return bad != 0;
 }
