@@ -13,10 +13,12 @@ Fracture"):
 * Linear tetrahedra; consistent element mass (Sec. 3.1, Eq. 5); forces and
   tangent stiffness of the per-element energy (Eq. 7, 9, 10, 11).
 * The element energy is the stable neo-Hookean density (Sec. 5.1, Eq. 35),
-  evaluated from the six squared edge lengths of the tet (Sec. 3.5,
+  or the Saint-Venant Kirchhoff density of the dynamic runs (Sec. 5.2,
+  Eq. 37), evaluated from the six squared edge lengths of the tet (Sec. 3.5,
   Theorem 3.1, Eq. 27-31): the Gram matrix of the edge vectors is linear in
-  the squared lengths, so I_C = tr(G G0^-1) and J^2 = det G / det G0.  Nodal
-  forces are sums along the tet's edges (Sec. 3.2, Eq. 12).
+  the squared lengths, so I_C = tr(G G0^-1), II_C = tr((G G0^-1)^2) and
+  J^2 = det G / det G0.  Nodal forces are sums along the tet's edges
+  (Sec. 3.2, Eq. 12).
 * Per-edge binary damage, irreversible (Sec. 3.3, Eq. 20-21), evaluated as a
   Green normal-strain threshold along the edge: locally (R_d = 0), or on the
   kernel-weighted average of the strain tensors of the tets whose rest
@@ -119,12 +121,21 @@ def disconnected_masks() -> np.ndarray:
 DISCONNECTED = disconnected_masks()
 
 
-def material(youngs: float, poisson: float):
-    """Lame constants of (E, nu), then the stable neo-Hookean reparametrisation
-    mu' = 4 mu / 3, lambda' = lambda + 5 mu / 6 (so that the small-strain
-    response of Eq. 35 has the given E and nu), and alpha of Eq. 35."""
+ENERGIES = ("stable_neo_hookean", "stvk")
+
+
+def material(youngs: float, poisson: float, energy: str = "stable_neo_hookean"):
+    """Lame constants of (E, nu).  Stable neo-Hookean (Eq. 35): the
+    reparametrisation mu' = 4 mu / 3, lambda' = lambda + 5 mu / 6 (so that the
+    small-strain response has the given E and nu) and alpha of Eq. 35.
+    Saint-Venant Kirchhoff (Eq. 37): the plain constants (its small-strain
+    response is linear elasticity with them); alpha unused (0)."""
     mu = youngs / (2.0 * (1.0 + poisson))
     lam = youngs * poisson / ((1.0 + poisson) * (1.0 - 2.0 * poisson))
+    if energy == "stvk":
+        return mu, lam, 0.0
+    if energy != "stable_neo_hookean":
+        raise ValueError(f"unknown energy {energy!r}")
     mu_s = 4.0 * mu / 3.0
     lam_s = lam + 5.0 * mu / 6.0
     alpha = 1.0 + mu_s / lam_s - mu_s / (4.0 * lam_s)
@@ -156,6 +167,7 @@ class Mesh:
     lam: float = 0.0
     alpha: float = 0.0
     nonlocal_support: tuple | None = None   # (ptr, idx, w) of Eq. 20's support when R_d > 0
+    energy: str = "stable_neo_hookean"      # or "stvk" (Eq. 37)
 
 
 def setup(X: np.ndarray, tets: np.ndarray, params: dict) -> Mesh:
@@ -178,9 +190,10 @@ def setup(X: np.ndarray, tets: np.ndarray, params: dict) -> Mesh:
     S_edge = np.sum((X[edges[:, 1]] - X[edges[:, 0]]) ** 2, axis=1)
     c = np.einsum("kij,tji->tk", EK, G0_inv)
     M = consistent_mass(X.shape[0], tets, V, params["density"])
-    mu, lam, alpha = material(params["youngs"], params["poisson"])
+    energy = params.get("energy", "stable_neo_hookean")
+    mu, lam, alpha = material(params["youngs"], params["poisson"], energy)
     mesh = Mesh(X, tets, edges, tet_edge, Dm, np.linalg.inv(Dm), G0, G0_inv,
-                np.linalg.det(G0), V, S, c, S_edge, M, params, mu, lam, alpha)
+                np.linalg.det(G0), V, S, c, S_edge, M, params, mu, lam, alpha, energy=energy)
     radius = params.get("damage_radius", 0.0)
     if radius > 0:
         mesh.nonlocal_support = nonlocal_neighbours(mesh, radius)
@@ -434,6 +447,8 @@ def cofactor_gradient(Ds: np.ndarray, detDm: np.ndarray):
 
 
 def element(mesh: Mesh, x: np.ndarray, Cp: np.ndarray | None = None) -> Element:
+    if mesh.energy == "stvk":
+        return element_stvk(mesh, x, Cp)
     t = mesh.tets
     m = t.shape[0]
     d = np.stack([x[t[:, b]] - x[t[:, a]] for a, b in LOCAL_EDGES], axis=1)
@@ -464,6 +479,40 @@ def element(mesh: Mesh, x: np.ndarray, Cp: np.ndarray | None = None) -> Element:
     psi = 0.5 * mu * (IC - 3.0) + 0.5 * lam * (J - al) ** 2 - 0.5 * mu * np.log(IC + 1.0)
     gradJ, hessJ = cofactor_gradient(Ds, detDm)
     return Element(s, d, IC, J, G, c, g, v, Mkl, coef, psi, small, gradJ, hessJ)
+
+
+def element_stvk(mesh: Mesh, x: np.ndarray, Cp: np.ndarray | None = None) -> Element:
+    """Saint-Venant Kirchhoff density of Eq. 37 in edge form:
+    Psi = lam/8 (I_C - 3)^2 + mu/4 (II_C - 2 I_C + 3) with A = Gp^-1,
+    I_C = tr(G A), II_C = tr(G A G A).  Its edge derivatives:
+    dPsi/ds_k = lam/4 (I_C - 3) c_k + mu/2 (t_k - c_k), c_k = tr(E_k A),
+    t_k = tr(E_k A G A); d2Psi/ds_k ds_l = lam/4 c_k c_l + mu/2 N_kl,
+    N_kl = tr(E_k A E_l A).  No J enters, so flat and inverted tets need no
+    special form; the edge Hessian is PSD as it stands (returned as the
+    coefficients (lam/4, 0, mu/2) on (c c^T, v v^T, N), with v = 0)."""
+    t = mesh.tets
+    m = t.shape[0]
+    d = np.stack([x[t[:, b]] - x[t[:, a]] for a, b in LOCAL_EDGES], axis=1)
+    s = np.sum(d * d, axis=2)
+    G = np.einsum("tk,kij->tij", s, EK)
+    Gp = mesh.G0 if Cp is None else mesh.G0 + gram_offset(mesh, Cp)
+    A = np.linalg.inv(Gp)
+    mu, lam = mesh.mu, mesh.lam
+    GA = G @ A
+    IC = np.einsum("tii->t", GA)
+    II = np.einsum("tij,tji->t", GA, GA)
+    c = np.einsum("kij,tji->tk", EK, A)
+    AGA = A @ G @ A
+    tk = np.einsum("kij,tji->tk", EK, AGA)
+    g = 0.25 * lam * (IC - 3.0)[:, None] * c + 0.5 * mu * (tk - c)
+    EA_ = np.einsum("kij,tjl->tkil", EK, A)          # E_k A
+    N = np.einsum("tkij,tlji->tkl", EA_, EA_)
+    coef = np.stack([np.full(m, 0.25 * lam), np.zeros(m), np.full(m, 0.5 * mu)], axis=1)
+    psi = lam / 8.0 * (IC - 3.0) ** 2 + mu / 4.0 * (II - 2.0 * IC + 3.0)
+    Ds = np.stack([x[t[:, i]] - x[t[:, 0]] for i in (1, 2, 3)], axis=2)
+    J = np.linalg.det(Ds) / np.linalg.det(mesh.Dm)
+    return Element(s, d, IC, J, G, c, g, np.zeros((m, 6)), N, coef, psi, np.zeros(m, bool),
+                   np.zeros((m, 4, 3)), np.zeros((m, 12, 12)))
 
 
 def edge_hessian(mesh: Mesh, el: Element, clamp: bool = True) -> np.ndarray:
@@ -531,7 +580,7 @@ def element_stiffness(mesh: Mesh, el: Element, chi: np.ndarray, clamp: bool = Tr
 
 def scaled_edge_stress(mesh: Mesh, x: np.ndarray, Cp: np.ndarray | None = None):
     """sigma_k = q_k^T S q_k: the 2nd Piola-Kirchhoff stress S = 2 dPsi/dC of
-    Eq. 35 projected on the rest unit direction q_k of each edge (Eq. 16-19,
+    Eq. 35 (or Eq. 37) projected on the rest unit direction q_k of each edge (Eq. 16-19,
     as a tensor projection).  With plastic flow the I_C term is taken relative
     to Cp: S = mu (1 - 1/(I_C + 1)) Cp^-1 + lambda (J - alpha) J C^-1.
     On small tets (|J| < J_MIN) every sigma_k is returned multiplied by |J|
@@ -544,6 +593,13 @@ def scaled_edge_stress(mesh: Mesh, x: np.ndarray, Cp: np.ndarray | None = None):
     mu, lam, al = mesh.mu, mesh.lam, mesh.alpha
     IC = np.einsum("tij,tji->t", C, Cpi)
     J = np.linalg.det(F)
+    t = mesh.tets
+    q = np.stack([mesh.X[t[:, b]] - mesh.X[t[:, a]] for a, b in LOCAL_EDGES], axis=1)
+    q /= np.linalg.norm(q, axis=2, keepdims=True)
+    if mesh.energy == "stvk":
+        # S = 2 dPsi/dC = lam/2 (I_C - 3) Cp^-1 + mu (Cp^-1 C Cp^-1 - Cp^-1)
+        Sst = (0.5 * lam * (IC - 3.0))[:, None, None] * Cpi + mu * (Cpi @ C @ Cpi - Cpi)
+        return np.einsum("tki,tij,tkj->tk", q, Sst, q), np.zeros(m, bool), J
     small = np.abs(J) < J_MIN
     # adjugate of the symmetric C (its cofactor matrix)
     adj = np.empty_like(C)
@@ -559,9 +615,6 @@ def scaled_edge_stress(mesh: Mesh, x: np.ndarray, Cp: np.ndarray | None = None):
     jc = np.where(small, sgn, 1.0 / np.where(small, 1.0, J))[:, None, None] * adj
     Sst = (scale * mu * (1.0 - 1.0 / (IC + 1.0)))[:, None, None] * Cpi \
         + (lam * (J - al))[:, None, None] * jc
-    t = mesh.tets
-    q = np.stack([mesh.X[t[:, b]] - mesh.X[t[:, a]] for a, b in LOCAL_EDGES], axis=1)
-    q /= np.linalg.norm(q, axis=2, keepdims=True)
     return np.einsum("tki,tij,tkj->tk", q, Sst, q), small, J
 
 
@@ -663,7 +716,7 @@ def build_system(mesh: Mesh, state: State, dir_nodes, dir_vel, zeta: np.ndarray,
         b[cdof] = dv_c.ravel()
     A.eliminate_zeros()
     stats = dict(chi_zero_tets=int(np.sum(chi == 0.0)),
-                 degenerate_tets=int(np.sum(el.small)))
+                 degenerate_tets=int(np.sum(np.abs(el.J) < J_MIN)))
     return System(A, b, dv_c, chi, stats)
 
 
