@@ -6,7 +6,8 @@
  * Algorithm 1 (Sec. 4.3) without collisions and visualisation:
  *   1. per-edge damage update and relabel (Sec. 3.3, Eq. 20-21, local support),
  *   2. per-tet energy fraction chi (Sec. 3.4, Eq. 22-25),
- *   3. element pass: stable neo-Hookean energy (Sec. 5.1, Eq. 35) written in
+ *   3. element pass: stable neo-Hookean energy (Sec. 5.1, Eq. 35) or
+ *      Saint-Venant Kirchhoff energy (Sec. 5.2, Eq. 37) written in
  *      the six squared edge lengths (Sec. 3.5, Theorem 3.1), nodal forces
  *      along the edges (Sec. 3.2, Eq. 12), tangent stiffness (Eq. 10), both
  *      scaled by chi (Sec. 3.6, Eq. 32-34), scattered into a block-sparse
@@ -50,6 +51,12 @@ typedef enum {
 
 typedef enum { GF_PREC_FP64 = 0, GF_PREC_SPLIT = 1 } gf_precision;
 typedef enum { GF_PC_BLOCK_JACOBI = 0, GF_PC_LEARNED = 1 } gf_precond;
+/* Element energy: the stable neo-Hookean density of the quasi-static runs
+ * (Sec. 5.1, Eq. 35, with the Lame constants reparametrised so that the
+ * small-strain response has the given E and nu) or the Saint-Venant Kirchhoff
+ * density of the dynamic runs (Sec. 5.2, Eq. 37, plain Lame constants), both
+ * written in the six squared edge lengths (Sec. 3.5, Theorem 3.1). */
+typedef enum { GF_ENERGY_STABLE_NEO_HOOKEAN = 0, GF_ENERGY_STVK = 1 } gf_energy;
 
 /* Material, integrator and solver parameters (copied at create). */
 typedef struct {
@@ -73,6 +80,7 @@ typedef struct {
   int32_t precision;      /* gf_precision: FP64 everything, or FP32 element/SpMV + FP64 dots/residual */
   int32_t precond;        /* gf_precond */
   int32_t net_every_n_steps; /* learned preconditioner: run the network every n steps (>= 1) */
+  int32_t energy;         /* gf_energy */
 } gf_params;
 
 /* Per-call statistics (summed over the steps of one gf_step call, except

@@ -300,7 +300,7 @@ void assemble(gf_mesh* M, bool flow, d4* f_out) {
       gfem::launch_damage(s, M->ne, M->edges, M->X, M->U, M->edge_S, M->zeta[zi], M->zeta[zo], M->p.damage_strain,
                           M->ctr, M->near_ids);
   });
-  gfem::ElemConst ec{M->mu, M->lam, M->alpha_m1};
+  gfem::ElemConst ec{M->mu, M->lam, M->alpha_m1, M->p.energy};
   const T* pl = nullptr;
   if (M->plastic) {
     if (flow) {
@@ -775,7 +775,8 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
   if (!(p.youngs > 0) || !(p.poisson > -1.0 && p.poisson < 0.5) || !(p.density > 0) || !(p.dt > 0) ||
       !(p.cg_rel_tol > 0) || p.cg_max_iter <= 0 || (p.precision != GF_PREC_FP64 && p.precision != GF_PREC_SPLIT) ||
       (p.precond != GF_PC_BLOCK_JACOBI && p.precond != GF_PC_LEARNED) || !std::isfinite(p.damage_strain) ||
-      !(p.damage_radius >= 0.0) || !std::isfinite(p.damage_radius))
+      !(p.damage_radius >= 0.0) || !std::isfinite(p.damage_radius) ||
+      (p.energy != GF_ENERGY_STABLE_NEO_HOOKEAN && p.energy != GF_ENERGY_STVK))
     return fail(GF_EINVAL, "gf_mesh_create: invalid parameters");
   if (p.precond == GF_PC_LEARNED && p.precision != GF_PREC_SPLIT)
     return fail(GF_EINVAL, "gf_mesh_create: the learned preconditioner needs the split precision mode");
@@ -829,9 +830,15 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     M->Gp = M->Gb;
     const double E = p.youngs, nu = p.poisson;
     const double mu0 = E / (2 * (1 + nu)), lam0 = E * nu / ((1 + nu) * (1 - 2 * nu));
-    M->mu = 4.0 * mu0 / 3.0;             // Smith et al. reparametrisation of Eq. 35
-    M->lam = lam0 + 5.0 * mu0 / 6.0;
-    M->alpha_m1 = 0.75 * M->mu / M->lam;  // alpha - 1 = mu/lam - mu/(4 lam)
+    if (p.energy == GF_ENERGY_STVK) {
+      M->mu = mu0;  // Eq. 37 with the plain Lame constants
+      M->lam = lam0;
+      M->alpha_m1 = 0.0;
+    } else {
+      M->mu = 4.0 * mu0 / 3.0;             // Smith et al. reparametrisation of Eq. 35
+      M->lam = lam0 + 5.0 * mu0 / 6.0;
+      M->alpha_m1 = 0.75 * M->mu / M->lam;  // alpha - 1 = mu/lam - mu/(4 lam)
+    }
     hchk(hipStreamCreate(&M->own), "hipStreamCreate");
     M->stream = M->own;
     gfem::set_disconnected_lut(disconnected_lut());

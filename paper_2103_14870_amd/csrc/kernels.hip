@@ -446,8 +446,11 @@ constexpr double kJMin = 0.05;
 // FP64, the rest in T.  Writes, per local edge k, the 3x3 stiffness block
 // K(i,j) in global orientation (i < j) and the FP64 force weight
 // w_k = 2 V chi dPsi/ds_k (Eq. 12).  pl: the plastic rest shapes
-// Gp - G0 [6][m] (null: no plasticity).
-template <typename T>
+// Gp - G0 [6][m] (null: no plasticity).  EN: kEnergyStableNeoHookean
+// (Eq. 35) or kEnergyStVK (Eq. 37: with A = Gp^-1, dPsi/ds_k =
+// lam/4 (I_C - 3) c_k + mu/2 tr(E_k A dGe A), edge Hessian
+// lam/4 c c^T + mu/2 tr(E_k A E_l A), PSD without clamping; no J enters).
+template <typename T, int EN>
 __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restrict__ tets,
                                                       const int32_t* __restrict__ tet_edge,
                                                       const uint8_t* __restrict__ flip,
@@ -513,7 +516,8 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
   };
   const double detDmd = det3(Dmd), detDs = det3(Dsd);
   const double Jd = detDs / detDmd;
-  const bool small = fabs(Jd) < kJMin;
+  const bool small = fabs(Jd) < kJMin;  // counted for either energy
+  const bool cof = EN == kEnergyStableNeoHookean && small;  // volume term in cofactor form
   const T vol = (T)(detDmd / 6.0);
 
   // Gram change from the squared-length changes by polarisation:
@@ -567,7 +571,33 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
   T Ys[6];
   double gJd[4][3];  // dJ/dx_a (small-J tets)
   double adjG[6];    // adjugate of the current Gram matrix, FP64 (small-J tets)
-  if (!small) {
+  T Wst[6];          // StVK: A dGe A, A = Gp^-1 (symmetric)
+  if constexpr (EN == kEnergyStVK) {
+    T Wf[3][3], M1[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) M1[i][j] = Be[i][0] * Ap[0][j] + Be[i][1] * Ap[1][j] + Be[i][2] * Ap[2][j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Wf[i][j] = Ap[i][0] * M1[0][j] + Ap[i][1] * M1[1][j] + Ap[i][2] * M1[2][j];
+    Wst[0] = Wf[0][0];
+    Wst[1] = Wf[1][1];
+    Wst[2] = Wf[2][2];
+    Wst[3] = T(0.5) * (Wf[0][1] + Wf[1][0]);
+    Wst[4] = T(0.5) * (Wf[0][2] + Wf[2][0]);
+    Wst[5] = T(0.5) * (Wf[1][2] + Wf[2][1]);
+    T GamW[4][4];
+    gram4(Wst, GamW);
+    J = (T)Jd;
+    delta = J - T(1);
+    Jsq = J * J;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int a = EA(k), b = EB(k);
+      cc[k] = -GamP[a][b];
+      vv[k] = T(0);
+      g[k] = T(0.25) * lam * aI * cc[k] - T(0.5) * mu * GamW[a][b];
+      wJ[k] = 0.0;
+    }
+  } else if (!small) {
     // J^2 - 1 = det(I + G0^-1 dG) - 1 without cancellation at rest
     T A0[3][3], B[3][3], Xm[3][3];
     sym_full(G0i, A0);
@@ -712,7 +742,9 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
       if (plastic) quad(Gpi, Zp);
       T Zs[3][3];
       T sgnJ = T(1), scl = T(1);
-      if (!small) {
+      if constexpr (EN == kEnergyStVK) {
+        quad(Wst, Zs);  // G0 A dGe A G0
+      } else if (!small) {
         quad(Ys, Zs);
       } else {
         T adjT[6];
@@ -721,14 +753,17 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
         sgnJ = Jd >= 0.0 ? T(1) : T(-1);
         scl = fabs(J);
       }
-      const T lamJ = small ? lam * (J - T(1) - am1) * sgnJ / det0 : T(0);
+      const T lamJ = cof ? lam * (J - T(1) - am1) * sgnJ / det0 : T(0);
       T num = 0, den = 0;
       int nub = 0;
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         const T pk = plastic ? edge_quad(Zp, k) / S[k] : T(1);
         T sig;
-        if (!small) {
+        if constexpr (EN == kEnergyStVK) {
+          // q^T S q, S = lam/2 (I_C - 3) Cp^-1 + mu (Cp^-1 C Cp^-1 - Cp^-1)
+          sig = T(0.5) * lam * aI * pk + mu * edge_quad(Zs, k) / S[k];
+        } else if (!small) {
           const T omw = edge_quad(Zs, k) / S[k];  // p_k - w_k
           const T dj = delta * (T(1) - am1) + delta * delta;
           // mu (1 - 1/(I_C+1)) = 3mu/4 + mu a/(4(4+a)); lam (J-alpha) J = -3mu/4 + lam dj
@@ -768,11 +803,13 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
   // Clamped edge Hessian: H = A1 c c^T + A2 v v^T + A3 M, M_kl = tr(G^-1 E_k G^-1 E_l)
   // = (Gam_ac Gam_bd + Gam_ad Gam_bc)/2; each coefficient clamped at >= 0.
   // Small |J|: only the I_C term (A1); the volume term adds lam dJ dJ^T.
+  // StVK: A1 = lam/4, A2 = 0, A3 = mu/2 with M_kl = tr(E_k A E_l A) (Gam of A).
   const T Vc = vol * chi;
-  const T A1 = T(0.5) * mu / (IC1 * IC1);
+  constexpr bool kSt = EN == kEnergyStVK;
+  const T A1 = kSt ? T(0.25) * lam : T(0.5) * mu / (IC1 * IC1);
   const T JmA = delta - am1;  // J - alpha
-  const T A2 = small ? T(0) : fmax(T(0.25) * lam * (T(2) * J - T(1) - am1) * J, T(0));
-  const T A3 = small ? T(0) : fmax(T(-0.5) * lam * JmA * J, T(0));
+  const T A2 = (kSt || small) ? T(0) : fmax(T(0.25) * lam * (T(2) * J - T(1) - am1) * J, T(0));
+  const T A3 = kSt ? T(0.5) * mu : (small ? T(0) : fmax(T(-0.5) * lam * JmA * J, T(0)));
   T H[6][6];
 #pragma unroll
   for (int k = 0; k < 6; ++k)
@@ -780,7 +817,9 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
     for (int l = k; l < 6; ++l) {
       const int a = EA(k), b = EB(k), c = EA(l), d = EB(l);
       T hkl = A1 * cc[k] * cc[l];
-      if (!small) {
+      if (kSt) {
+        hkl += A3 * T(0.5) * (GamP[a][c] * GamP[b][d] + GamP[a][d] * GamP[b][c]);
+      } else if (!small) {
         const T Mkl = T(0.5) * (Gam[a][c] * Gam[b][d] + Gam[a][d] * Gam[b][c]);
         hkl += A2 * vv[k] * vv[l] + A3 * Mkl;
       }
@@ -829,7 +868,7 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
       Kab[0][0] -= lap;
       Kab[1][1] -= lap;
       Kab[2][2] -= lap;
-      if (small) {
+      if (cof) {
         const T kJ = (T)(Vcd * cst.lam);
 #pragma unroll
         for (int r = 0; r < 3; ++r)
@@ -1763,7 +1802,12 @@ template <typename T>
 void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_edge, const uint8_t* flip,
                     const d4* X, const d4* U, const uint8_t* zeta, const T* pl, ElemConst c, Rec<T>* contrib,
                     Counters* ctr) {
-  k_element<T><<<blocks_for(m), kThreads, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta, pl, c, contrib, ctr);
+  if (c.energy == kEnergyStVK)
+    k_element<T, kEnergyStVK><<<blocks_for(m), kThreads, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta, pl, c,
+                                                                  contrib, ctr);
+  else
+    k_element<T, kEnergyStableNeoHookean><<<blocks_for(m), kThreads, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta,
+                                                                             pl, c, contrib, ctr);
 }
 
 template <typename T>

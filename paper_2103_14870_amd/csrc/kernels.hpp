@@ -57,8 +57,14 @@ struct Counters {
   int near_n;  // entries appended to the near-threshold edge list by the damage pass
 };
 
+// Element energies: the stable neo-Hookean density of Eq. 35 (reparametrised
+// Lame constants) or the Saint-Venant Kirchhoff density of Eq. 37 (plain ones).
+constexpr int kEnergyStableNeoHookean = 0;
+constexpr int kEnergyStVK = 1;
+
 struct ElemConst {
-  double mu, lam, alpha_m1;  // mu', lambda', alpha - 1 (Eq. 35 with the reparametrised constants)
+  double mu, lam, alpha_m1;  // Eq. 35: mu', lambda', alpha - 1; Eq. 37: mu, lambda, unused
+  int energy;                // kEnergyStableNeoHookean or kEnergyStVK
 };
 
 // Per tet edge contribution: the 3x3 stiffness block in global orientation

@@ -51,7 +51,7 @@ def default_params(**kw) -> dict:
     p = dict(youngs=1e5, poisson=0.3, density=1000.0, damage_strain=0.01, damage_radius=0.0,
              yield_strain=0.0, dt=1e-3, rayleigh_alpha=0.0, rayleigh_beta=0.0,
              gravity=(0.0, 0.0, 0.0), cg_rel_tol=1e-8, cg_max_iter=5000,
-             precision="fp64", precond="block_jacobi", net_every_n_steps=1)
+             precision="fp64", precond="block_jacobi", net_every_n_steps=1, energy="stable_neo_hookean")
     p.update(kw)
     return p
 
