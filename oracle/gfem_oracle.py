@@ -802,3 +802,93 @@ def run(mesh: Mesh, state: State, dir_nodes, dir_vel, n_steps: int, overrides=No
         if not st["converged"]:
             break
     return state, hist
+
+
+# --------------------------------------------------------------------------
+# Quasi-static load step: Newton with a backtracking line search (Eq. 36)
+# --------------------------------------------------------------------------
+
+def energy_fixed_chi(mesh: Mesh, x: np.ndarray, chi: np.ndarray, Cp=None) -> float:
+    """E(x) = sum_e chi_e V_e Psi_e(x) with chi held fixed: the potential whose
+    negative gradient is the restoring force f* of Eq. 32 at that chi."""
+    return float(np.sum(mesh.V * chi * element(mesh, x, Cp).psi))
+
+
+def quasi_static_step(mesh: Mesh, state: State, dir_nodes, dir_vel, newton_rtol: float = 1e-6,
+                      max_newton: int = 50, armijo: float = 1e-4, min_step: float = 2.0 ** -20):
+    """One load step of the quasi-static problem of Eq. 36, sum chi k u =
+    sum chi f, solved for equilibrium by Newton's method with a backtracking
+    line search on the total energy (Sec. 4.3, Sec. 5.1):
+
+    1. damage and plastic flow at the previous equilibrium x_n;
+    2. the prescribed nodes move by dt * their prescribed velocity;
+    3. chi is evaluated at that first iterate and held fixed, so that
+       E(x) = sum chi V Psi is the potential of the forces;
+    4. Newton: f = f*(x) on the free nodes; stop when |f| <= newton_rtol |f_0|
+       (f_0: the out-of-balance force of the first iterate) or f = 0; else
+       solve (M / dt^2 + K*) dx = f with the prescribed rows fixed (the mass
+       term is a regulariser that vanishes as dt grows and keeps the rows of
+       detached fragments definite), then take the largest alpha in
+       1, 1/2, 1/4, ... with E(x + alpha dx) <= E(x) - armijo alpha f.dx
+       (accepted outright once the energy change is below FP64 resolution,
+       |E(x + alpha dx) - E(x)| <= 1e-14 |E(x)|), x += alpha dx.
+    Velocities are zero after the step.  Returns (new_state, stats); on
+    failure (no equilibrium within max_newton iterations, a step below
+    min_step, or a linear solve that misses its tolerance) the state is
+    returned unchanged."""
+    p = mesh.params
+    dt = p["dt"]
+    n = mesh.X.shape[0]
+    zeta, near = damage_update(mesh, state.x, state.zeta)
+    Cp = plastic_update(mesh, state.x, state.Cp)
+    dir_nodes = np.asarray(dir_nodes, dtype=np.int64)
+    x = state.x.copy()
+    if dir_nodes.size:
+        x[dir_nodes] += dt * np.asarray(dir_vel, float)
+    chi, _ = energy_fraction(mesh, x, zeta, Cp)
+    cdof = (3 * dir_nodes[:, None] + np.arange(3)).ravel()
+    keep = np.ones(3 * n)
+    keep[cdof] = 0.0
+    Dk = sp.diags(keep)
+    stats = dict(newton_iters=0, halvings=0, inner_iters=0, converged=False, energy=[], force=[],
+                 new_broken=int(np.sum(zeta & ~state.zeta)), total_broken=int(zeta.sum()), near_threshold=near)
+    f0 = None
+    for it in range(max_newton + 1):
+        el = element(mesh, x, Cp)
+        f = scatter_forces(n, mesh.tets, element_forces(mesh, el, chi)).ravel() * keep
+        fn = float(np.linalg.norm(f))
+        stats["force"].append(fn)
+        if f0 is None:
+            f0 = fn
+        if fn == 0.0 or fn <= newton_rtol * f0:
+            stats["converged"] = True
+            break
+        if it == max_newton:
+            break
+        K = assemble_stiffness(n, mesh.tets, element_stiffness(mesh, el, chi))
+        A = (Dk @ (mesh.M / (dt * dt) + K) @ Dk + sp.diags(1.0 - keep)).tocsr()
+        dx, its, rel, ok = pcg(A, f, block_jacobi(A), p["cg_rel_tol"], p["cg_max_iter"])
+        stats["inner_iters"] += its
+        if not ok:
+            break
+        dx = dx.reshape(-1, 3)
+        E0 = energy_fixed_chi(mesh, x, chi, Cp)
+        slope = float(f @ dx.ravel())
+        alpha = 1.0
+        while True:
+            E1 = energy_fixed_chi(mesh, x + alpha * dx, chi, Cp)
+            if E1 <= E0 - armijo * alpha * slope or abs(E1 - E0) <= 1e-14 * abs(E0):
+                break
+            alpha *= 0.5
+            stats["halvings"] += 1
+            if alpha < min_step:
+                break
+        if alpha < min_step:
+            break
+        x = x + alpha * dx
+        stats["energy"].append(E1)
+        stats["newton_iters"] = it + 1
+    if not stats["converged"]:
+        return state, stats
+    return State(x, np.zeros_like(state.v), zeta, Cp, state.step + 1), stats
+
