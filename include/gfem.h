@@ -154,6 +154,42 @@ gf_status gf_set_edge_damage(gf_mesh* m, const uint8_t* zeta);
  * in it is reported by the next such call. */
 gf_status gf_step(gf_mesh* m, int32_t n_steps, gf_step_stats* stats);
 
+/* Statistics of gf_quasi_static_step (summed over its load steps, except
+ * the last four fields, which describe the last one). */
+typedef struct {
+  int32_t steps_done;            /* committed load steps */
+  int32_t newton_iters;          /* Newton iterations (linear solves) */
+  int32_t line_search_halvings;  /* step halvings of the line search */
+  int32_t inner_iters;           /* PCG iterations over all Newton solves */
+  int32_t new_broken;            /* edges newly labelled broken */
+  int32_t total_broken;          /* broken edges after the last load step */
+  double force_initial;          /* |f| on the free nodes at the first iterate of the last load step */
+  double force_residual;         /* |f| at its last iterate */
+  double energy;                 /* total energy sum chi V Psi there */
+} gf_qs_stats;
+
+/* Quasi-static load steps: equilibrium of Eq. 36, sum chi k u = sum chi f,
+ * by Newton's method with a backtracking line search on the total energy
+ * (Sec. 4.3, Sec. 5.1).  Per load step: damage (and plastic flow) at the
+ * previous equilibrium; the prescribed nodes of gf_set_dirichlet move by dt
+ * times their prescribed velocity; chi is evaluated at that first iterate and
+ * held fixed, so the energy E = sum chi V Psi is the potential of the forces;
+ * each Newton system is (M/dt^2 + K*) dx = f* on the free nodes (the backward-
+ * Euler operator at zero velocity: the mass term regularises detached
+ * fragments and vanishes as dt grows), solved by block-Jacobi PCG to
+ * cg_rel_tol; the step length is the largest of 1, 1/2, 1/4, ... (down to
+ * 2^-20) with E(x + a dx) <= E(x) - armijo a f.dx, a change of E below FP64
+ * resolution (1e-14 |E|) being accepted; iteration stops at
+ * |f| <= newton_rel_tol |f_0|, f_0 the force of the first iterate.  Velocities
+ * are zero after a load step.  newton_rel_tol and armijo in (0, 1);
+ * max_newton >= 0.  Returns GF_ENOTCONVERGED (displacement restored, nothing
+ * committed) when a load step has no equilibrium within max_newton Newton
+ * iterations, the line search fails or a linear solve misses its tolerance;
+ * GF_EINVAL for bad arguments or a nonzero gravity (the quasi-static
+ * experiments of Sec. 5.1 have none).  stats may be NULL. */
+gf_status gf_quasi_static_step(gf_mesh* m, int32_t n_steps, double newton_rel_tol, int32_t max_newton,
+                               double armijo, gf_qs_stats* stats);
+
 /* Current positions x = X + u after the last committed step (Algorithm 1's
  * update x += dt v of Sec. 4.3), n_nodes*3 doubles, caller order, into a
  * caller-owned buffer.  Waits for the library's stream. */

@@ -815,7 +815,8 @@ def energy_fixed_chi(mesh: Mesh, x: np.ndarray, chi: np.ndarray, Cp=None) -> flo
 
 
 def quasi_static_step(mesh: Mesh, state: State, dir_nodes, dir_vel, newton_rtol: float = 1e-6,
-                      max_newton: int = 50, armijo: float = 1e-4, min_step: float = 2.0 ** -20):
+                      max_newton: int = 50, armijo: float = 1e-4, min_step: float = 2.0 ** -20,
+                      override: dict | None = None):
     """One load step of the quasi-static problem of Eq. 36, sum chi k u =
     sum chi f, solved for equilibrium by Newton's method with a backtracking
     line search on the total energy (Sec. 4.3, Sec. 5.1):
@@ -835,11 +836,12 @@ def quasi_static_step(mesh: Mesh, state: State, dir_nodes, dir_vel, newton_rtol:
     Velocities are zero after the step.  Returns (new_state, stats); on
     failure (no equilibrium within max_newton iterations, a step below
     min_step, or a linear solve that misses its tolerance) the state is
-    returned unchanged."""
+    returned unchanged.  `override` as in `step` (labels of near-threshold
+    edges only)."""
     p = mesh.params
     dt = p["dt"]
     n = mesh.X.shape[0]
-    zeta, near = damage_update(mesh, state.x, state.zeta)
+    zeta, near = damage_update(mesh, state.x, state.zeta, override=override)
     Cp = plastic_update(mesh, state.x, state.Cp)
     dir_nodes = np.asarray(dir_nodes, dtype=np.int64)
     x = state.x.copy()

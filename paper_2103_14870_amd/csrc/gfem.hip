@@ -132,6 +132,9 @@ struct gf_mesh {
   double* nl_w = nullptr;
   gfem::Sym6 *nl_E = nullptr, *nl_Eavg = nullptr;
   size_t nl_entries = 0;
+  // quasi-static load steps: zero node vector, chi held fixed, displacement at the step's start
+  d4 *qs_zero = nullptr, *qs_U0 = nullptr;
+  void* qs_chi = nullptr;
   int32_t *edge_ptr = nullptr, *edge_slot = nullptr, *blk_ij = nullptr, *blk_ji = nullptr;
   void* edge_w = nullptr;
   // block matrix
@@ -284,13 +287,27 @@ void alloc_precision(gf_mesh* M) {
   M->vy = M->al.get<v4<T>>(n);
 }
 
+// What one assembly does (defaults: a timestep's system).
+struct AsmOpt {
+  bool damage = true;      // damage pass into the spare label buffer (counters reset first)
+  bool flow = true;        // plastic flow at the current state into the spare plastic buffer
+  bool next_state = true;  // the element pass reads the spare (updated) labels and plastic state
+  const void* chi_in = nullptr;  // per-tet chi held fixed (T[m]) instead of Eq. 25
+  void* chi_out = nullptr;       // receives the chi used (T[m])
+  bool quasi_static = false;     // zero velocities and prescribed velocities, no damping or gravity
+  d4* f_out = nullptr;           // restoring forces, when wanted
+};
+
 // Damage (into the spare label buffer), element pass (+ plastic flow into the
 // spare plastic buffer), edge pass and row pass: the system of the next step.
 template <typename T>
-void assemble(gf_mesh* M, bool flow, d4* f_out) {
+void assemble(gf_mesh* M, const AsmOpt& o) {
   hipStream_t s = M->stream;
-  hchk(hipMemsetAsync(M->ctr, 0, sizeof(gfem::Counters), s), "hipMemsetAsync");
+  const bool flow = o.flow;
+  d4* f_out = o.f_out;
   const int zi = M->zcur, zo = 1 - M->zcur;
+  if (o.damage) {
+  hchk(hipMemsetAsync(M->ctr, 0, sizeof(gfem::Counters), s), "hipMemsetAsync");
   M->timed(0, -1, 0, [&] {
     if (M->nl_ptr)
       gfem::launch_damage_nonlocal(s, M->m, M->ne, M->tets, M->X, M->U, M->nl_ptr, M->nl_idx, M->nl_w, M->nl_E,
@@ -300,6 +317,7 @@ void assemble(gf_mesh* M, bool flow, d4* f_out) {
       gfem::launch_damage(s, M->ne, M->edges, M->X, M->U, M->edge_S, M->zeta[zi], M->zeta[zo], M->p.damage_strain,
                           M->ctr, M->near_ids);
   });
+  }
   gfem::ElemConst ec{M->mu, M->lam, M->alpha_m1, M->p.energy};
   const T* pl = nullptr;
   if (M->plastic) {
@@ -309,27 +327,30 @@ void assemble(gf_mesh* M, bool flow, d4* f_out) {
         gfem::launch_plastic<T>(s, M->m, M->tets, M->X, M->U, static_cast<const T*>(M->pl[M->plcur]),
                                 static_cast<T*>(M->pl[1 - M->plcur]), M->p.yield_strain);
       });
-      pl = static_cast<const T*>(M->pl[1 - M->plcur]);
-    } else {
-      pl = static_cast<const T*>(M->pl[M->plcur]);
     }
+    pl = static_cast<const T*>(M->pl[o.next_state ? 1 - M->plcur : M->plcur]);
   }
   M->timed(1, -1, 0, [&] {
-    gfem::launch_element<T>(s, M->m, M->tets, M->tet_edge, M->flip, M->X, M->U, M->zeta[flow ? zo : zi], pl, ec,
+    gfem::launch_element<T>(s, M->m, M->tets, M->tet_edge, M->flip, M->X, M->U, M->zeta[o.next_state ? zo : zi], pl,
+                            static_cast<const T*>(o.chi_in), static_cast<T*>(o.chi_out), ec,
                             static_cast<gfem::Rec<T>*>(M->contrib), M->ctr);
   });
   const double dt = M->p.dt;
-  const double mass_fac = 1.0 + dt * M->p.rayleigh_alpha;
-  const double stiff_fac = dt * dt + dt * M->p.rayleigh_beta;
+  const double ra = o.quasi_static ? 0.0 : M->p.rayleigh_alpha;
+  const double mass_fac = 1.0 + dt * ra;
+  const double stiff_fac = dt * dt + (o.quasi_static ? 0.0 : dt * M->p.rayleigh_beta);
   M->timed(2, -1, 0, [&] {
     gfem::launch_edge<T>(s, M->ne, M->edge_ptr, M->edge_slot, static_cast<const gfem::Rec<T>*>(M->contrib),
                          M->edge_mass, mass_fac, stiff_fac, M->blk_ij, M->blk_ji, static_cast<T*>(M->val), M->nbp,
                          static_cast<double*>(M->edge_w));
   });
-  gfem::RowConst rc{dt, M->p.rayleigh_alpha, mass_fac, {M->p.gravity[0], M->p.gravity[1], M->p.gravity[2]}};
+  gfem::RowConst rc{dt, ra, mass_fac, {M->p.gravity[0], M->p.gravity[1], M->p.gravity[2]}};
+  if (o.quasi_static) rc.g[0] = rc.g[1] = rc.g[2] = 0.0;
+  const d4* V = o.quasi_static ? M->qs_zero : M->V;
+  const d4* dvel = o.quasi_static ? M->qs_zero : M->dvel;
   M->timed(2, -1, 0, [&] {
     gfem::launch_row<T>(s, M->n, M->Gs, M->mat(), M->diag_blk, M->blk_edge, M->edge_mass,
-                        static_cast<const double*>(M->edge_w), M->lumped, M->X, M->U, M->V, M->dflag, M->dvel, rc,
+                        static_cast<const double*>(M->edge_w), M->lumped, M->X, M->U, V, M->dflag, dvel, rc,
                         static_cast<T*>(M->val), M->b, M->X64, static_cast<T*>(M->binv), f_out, M->part_a);
   });
   M->check_launch();
@@ -645,7 +666,7 @@ SolveResult fp64_rerun(gf_mesh* M) {
   M->split = false;
   SolveResult r{false, 0, 0, 0.0};
   try {
-    assemble<double>(M, true, nullptr);
+    assemble<double>(M, AsmOpt{});
     r = solve<double>(M, M->binv, nullptr, 0, 2);
   } catch (...) {
     M->use(keep);
@@ -664,7 +685,7 @@ SolveResult fp64_rerun(gf_mesh* M) {
 template <typename T>
 gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
   for (int i = 0; i < n_steps; ++i) {
-    assemble<T>(M, true, nullptr);
+    assemble<T>(M, AsmOpt{});
     hchk(hipMemcpyAsync(M->h_ctr, M->ctr, sizeof(gfem::Counters), hipMemcpyDeviceToHost, M->stream), "D2H");
     SolveResult r;
     int fallback = 0;
@@ -739,6 +760,139 @@ gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
     // (timing reads its events, so it waits here)
     if (M->timing) M->sync();
     M->flush_times(st);
+    if (st) st->steps_done += 1;
+  }
+  return GF_OK;
+}
+
+// Buffers of the quasi-static load step (allocated on first use).
+void ensure_qs(gf_mesh* M) {
+  if (M->qs_zero) return;
+  M->qs_zero = M->al.get<d4>(M->n);  // zero-filled by the allocator, never written
+  M->qs_U0 = M->al.get<d4>(M->n);
+  M->qs_chi = M->split ? (void*)M->al.get<float>(M->m) : (void*)M->al.get<double>(M->m);
+}
+
+// Quasi-static load steps (Eq. 36; Sec. 4.3 names Newton with a line search):
+// damage and plastic flow at the previous equilibrium; prescribed nodes move
+// by dt times their prescribed velocity; chi evaluated at that first iterate
+// and held fixed; Newton systems (M/dt^2 + K*) dx = f* (the backward-Euler
+// operator at zero velocity, dx = dt dv; the mass term regularises detached
+// fragments and vanishes as dt grows); backtracking Armijo line search on
+// E = sum chi V Psi (FP64); stop at |f| <= rtol |f_0|.  A failed load step
+// restores the displacement and commits nothing.
+template <typename T>
+gf_status qs_step_impl(gf_mesh* M, int n_steps, double rtol, int max_newton, double armijo, gf_qs_stats* st) {
+  ensure_qs(M);
+  hipStream_t s = M->stream;
+  const double dt = M->p.dt;
+  const int Ge = std::min(gfem::kMaxPart, std::max(8, (M->m + gfem::kThreads - 1) / gfem::kThreads));
+  const int Gd = std::min(gfem::kMaxPart, std::max(8, (M->n + gfem::kThreads - 1) / gfem::kThreads));
+  const gfem::ElemConst ec{M->mu, M->lam, M->alpha_m1, M->p.energy};
+  constexpr double kMinStep = 1.0 / (1 << 20);
+  for (int step = 0; step < n_steps; ++step) {
+    hchk(hipMemcpyAsync(M->qs_U0, M->U, sizeof(d4) * M->n, hipMemcpyDeviceToDevice, s), "D2D");
+    // 1. damage and plastic flow at x_n
+    hchk(hipMemsetAsync(M->ctr, 0, sizeof(gfem::Counters), s), "hipMemsetAsync");
+    const int zi = M->zcur, zo = 1 - M->zcur;
+    if (M->nl_ptr)
+      gfem::launch_damage_nonlocal(s, M->m, M->ne, M->tets, M->X, M->U, M->nl_ptr, M->nl_idx, M->nl_w, M->nl_E,
+                                   M->nl_Eavg, M->edges, M->edge_ptr, M->edge_slot, M->zeta[zi], M->zeta[zo],
+                                   M->p.damage_strain, M->ctr, M->near_ids);
+    else
+      gfem::launch_damage(s, M->ne, M->edges, M->X, M->U, M->edge_S, M->zeta[zi], M->zeta[zo], M->p.damage_strain,
+                          M->ctr, M->near_ids);
+    const T* pl = nullptr;
+    if (M->plastic) {
+      gfem::launch_plastic<T>(s, M->m, M->tets, M->X, M->U, static_cast<const T*>(M->pl[M->plcur]),
+                              static_cast<T*>(M->pl[1 - M->plcur]), M->p.yield_strain);
+      pl = static_cast<const T*>(M->pl[1 - M->plcur]);
+    }
+    // 2. the prescribed nodes move
+    gfem::launch_move_prescribed(s, M->n, M->dflag, M->dvel, dt, M->U);
+    M->check_launch();
+    hchk(hipMemcpyAsync(M->h_ctr, M->ctr, sizeof(gfem::Counters), hipMemcpyDeviceToHost, s), "D2H");
+    // 3. first iterate: chi evaluated and stored
+    AsmOpt o;
+    o.damage = o.flow = false;
+    o.next_state = true;
+    o.quasi_static = true;
+    o.chi_out = M->qs_chi;
+    assemble<T>(M, o);
+    o.chi_out = nullptr;
+    o.chi_in = M->qs_chi;
+    double f0 = -1.0, fn = 0.0;
+    int iters = 0, halvings = 0, inner = 0;
+    bool ok = false;
+    double energy = 0.0;
+    for (int it = 0;; ++it) {
+      // |b| = dt |f| on the free nodes (prescribed rows carry dv_c = 0)
+      fn = std::sqrt(read_partials(M, M->part_a, M->Gs)) / dt;
+      if (f0 < 0.0) f0 = fn;
+      if (!std::isfinite(fn)) break;
+      if (fn == 0.0 || fn <= rtol * f0) {
+        ok = true;
+        break;
+      }
+      if (it >= max_newton) break;
+      const SolveResult r = solve<T>(M, M->binv);
+      inner += r.inner;
+      if (!r.ok) break;
+      // slope f.dx = b.dv (dx = dt dv, b = dt f)
+      gfem::launch_dot(s, Gd, M->n, M->b, M->X64, M->part_r);
+      M->check_launch();
+      const double slope = read_partials(M, M->part_r, Gd);
+      gfem::launch_energy<T>(s, Ge, M->m, M->tets, M->X, M->U, M->X64, 0.0, pl, static_cast<const T*>(M->qs_chi),
+                             ec, M->part_r);
+      M->check_launch();
+      const double E0 = read_partials(M, M->part_r, Ge);
+      double alpha = 1.0, E1 = E0;
+      while (true) {
+        gfem::launch_energy<T>(s, Ge, M->m, M->tets, M->X, M->U, M->X64, alpha * dt, pl,
+                               static_cast<const T*>(M->qs_chi), ec, M->part_r);
+        M->check_launch();
+        E1 = read_partials(M, M->part_r, Ge);
+        if (E1 <= E0 - armijo * alpha * slope || std::fabs(E1 - E0) <= 1e-14 * std::fabs(E0)) break;
+        alpha *= 0.5;
+        ++halvings;
+        if (alpha < kMinStep) break;
+      }
+      if (alpha < kMinStep) break;
+      gfem::launch_axpy(s, M->n, alpha * dt, M->X64, M->U);
+      energy = E1;
+      iters = it + 1;
+      assemble<T>(M, o);
+    }
+    M->recs.clear();
+    M->ev_used = 0;
+    M->solve_iters.clear();
+    if (st) {
+      st->newton_iters += iters;
+      st->line_search_halvings += halvings;
+      st->inner_iters += inner;
+      st->force_residual = fn;
+      st->force_initial = f0;
+      st->energy = energy;
+      int cnt[gfem::kNumCounters] = {0, 0, 0, 0, 0};
+      for (int sl = 0; sl < gfem::kCtrSlots; ++sl)
+        for (int c = 0; c < gfem::kNumCounters; ++c) cnt[c] += M->h_ctr->v[sl * gfem::kCtrStride + c];
+      st->new_broken += cnt[gfem::kNewBroken];
+      st->total_broken = cnt[gfem::kTotalBroken];
+    }
+    if (!ok) {
+      hchk(hipMemcpyAsync(M->U, M->qs_U0, sizeof(d4) * M->n, hipMemcpyDeviceToDevice, s), "D2D");
+      M->sync();
+      char buf[200];
+      snprintf(buf, sizeof buf,
+               "quasi-static step %d: no equilibrium (|f| %.3e of %.3e after %d Newton iterations, %d halvings)",
+               M->step_index, fn, f0, iters, halvings);
+      return fail(GF_ENOTCONVERGED, buf);
+    }
+    hchk(hipMemsetAsync(M->V, 0, sizeof(d4) * M->n, s), "hipMemsetAsync");
+    M->zcur = 1 - M->zcur;
+    if (M->plastic) M->plcur = 1 - M->plcur;
+    ++M->step_index;
+    M->sync();
     if (st) st->steps_done += 1;
   }
   return GF_OK;
@@ -1032,6 +1186,21 @@ gf_status gf_get_edge_damage(const gf_mesh* m, uint8_t* zeta_out) {
   })
 }
 
+gf_status gf_quasi_static_step(gf_mesh* m, int32_t n_steps, double newton_rel_tol, int32_t max_newton,
+                               double armijo, gf_qs_stats* stats) {
+  if (gf_status s = guard(m, "gf_quasi_static_step")) return s;
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (n_steps < 0 || !(newton_rel_tol > 0.0 && newton_rel_tol < 1.0) || max_newton < 0 ||
+      !(armijo > 0.0 && armijo < 1.0))
+    return fail(GF_EINVAL, "gf_quasi_static_step: bad arguments");
+  if (m->p.gravity[0] != 0.0 || m->p.gravity[1] != 0.0 || m->p.gravity[2] != 0.0)
+    return fail(GF_EINVAL, "gf_quasi_static_step: the quasi-static problem has no gravity (set it to zero)");
+  GF_TRY({
+    return m->split ? qs_step_impl<float>(m, n_steps, newton_rel_tol, max_newton, armijo, stats)
+                    : qs_step_impl<double>(m, n_steps, newton_rel_tol, max_newton, armijo, stats);
+  })
+}
+
 gf_status gf_get_near_threshold_edges(const gf_mesh* m, int32_t* ids_out, int32_t capacity, int32_t* n_out) {
   if (!m || !n_out || capacity < 0 || (capacity > 0 && !ids_out))
     return fail(GF_EINVAL, "gf_get_near_threshold_edges: bad argument");
@@ -1057,10 +1226,13 @@ gf_status gf_eval_forces(gf_mesh* m, double* f_out) {
   if (gf_status s = guard(m, "gf_eval_forces")) return s;
   if (!f_out) return fail(GF_EINVAL, "gf_eval_forces: null output");
   GF_TRY({
+    AsmOpt o;
+    o.flow = o.next_state = false;
+    o.f_out = m->fbuf;
     if (m->split)
-      assemble<float>(m, false, m->fbuf);
+      assemble<float>(m, o);
     else
-      assemble<double>(m, false, m->fbuf);
+      assemble<double>(m, o);
     m->sync();
     m->recs.clear();
     m->ev_used = 0;
@@ -1072,9 +1244,9 @@ gf_status gf_get_system(gf_mesh* m, int32_t* bi_out, int32_t* bj_out, double* va
   if (gf_status s = guard(m, "gf_get_system")) return s;
   GF_TRY({
     if (m->split)
-      assemble<float>(m, true, nullptr);
+      assemble<float>(m, AsmOpt{});
     else
-      assemble<double>(m, true, nullptr);
+      assemble<double>(m, AsmOpt{});
     m->sync();
     m->recs.clear();
     m->ev_used = 0;
@@ -1422,7 +1594,7 @@ static gf_status net_train_eval(gf_net* net, gf_mesh* m, bool train, double lr, 
   GF_TRY({
     hipStream_t s = m->stream;
     ensure_net_train(m);
-    assemble<float>(m, true, nullptr);
+    assemble<float>(m, AsmOpt{});
     m->recs.clear();
     m->ev_used = 0;
     m->solve_iters.clear();

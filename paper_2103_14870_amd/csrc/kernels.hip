@@ -456,6 +456,7 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
                                                       const uint8_t* __restrict__ flip,
                                                       const d4* __restrict__ X, const d4* __restrict__ U,
                                                       const uint8_t* __restrict__ zeta, const T* __restrict__ pl,
+                                                      const T* __restrict__ chi_in, T* __restrict__ chi_out,
                                                       ElemConst cst, Rec<T>* __restrict__ contrib,
                                                       Counters* ctr) {
   const int t0 = blockIdx.x * kThreads + threadIdx.x;
@@ -713,7 +714,9 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
 #pragma unroll
   for (int k = 0; k < 6; ++k) mask |= (zeta[tet_edge[(size_t)k * m + t]] != 0) << k;
   T chi = T(1);
-  if (mask) {
+  if (chi_in) {
+    chi = chi_in[t];  // held fixed from an earlier pass (quasi-static Newton iterates)
+  } else if (mask) {
     if ((c_disc_lut >> mask) & 1ull) {
       chi = T(0);
     } else {
@@ -787,6 +790,7 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
     block_counts<2>(ctr, kChiZero, pr);
   }
   if (!act) return;
+  if (chi_out) chi_out[t] = chi;
 
   if (chi == T(0)) {
 #pragma unroll
@@ -885,6 +889,120 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
       contrib[(size_t)k * m + t] = rec;
     }
   }
+}
+
+// ---------------------------------------------------------------- quasi-static Newton (Eq. 36)
+
+// Total energy E = sum_e chi_e V_e Psi_e at the displacement U + step X64,
+// chi fixed (Eq. 32 with the energy fraction of Eq. 25 held constant, so
+// that -grad E is the restoring force of the Newton system).  FP64 from the
+// rest edge vectors and the displacement differences; Psi of Eq. 35 or
+// Eq. 37 from I_C = tr(G Gp^-1), J = det Ds / det Dm, II_C = tr((G Gp^-1)^2).
+// Grid-stride over the tets; one FP64 partial per workgroup.
+template <typename T, int EN>
+__global__ __launch_bounds__(kThreads) void k_energy(int m, const int4* __restrict__ tets,
+                                                     const d4* __restrict__ X, const d4* __restrict__ U,
+                                                     const d4* __restrict__ X64, double step,
+                                                     const T* __restrict__ pl, const T* __restrict__ chi_in,
+                                                     ElemConst cst, double* __restrict__ part) {
+  __shared__ double sh[16];
+  double acc = 0.0;
+  for (int t = blockIdx.x * kThreads + threadIdx.x; t < m; t += gridDim.x * kThreads) {
+    const double chi = (double)chi_in[t];
+    if (chi == 0.0) continue;
+    const int4 nd = tets[t];
+    const int ids[4] = {nd.x, nd.y, nd.z, nd.w};
+    const d4 X0 = X[nd.x], U0 = U[nd.x], W0 = X64[nd.x];
+    const double u0[3] = {U0.x + step * W0.x, U0.y + step * W0.y, U0.z + step * W0.z};
+    double Dm[3][3], Ds[3][3];  // [edge from node 0][component]
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const d4 Xk = X[ids[k + 1]], Uk = U[ids[k + 1]], Wk = X64[ids[k + 1]];
+      Dm[k][0] = Xk.x - X0.x;
+      Dm[k][1] = Xk.y - X0.y;
+      Dm[k][2] = Xk.z - X0.z;
+      Ds[k][0] = Dm[k][0] + ((Uk.x + step * Wk.x) - u0[0]);
+      Ds[k][1] = Dm[k][1] + ((Uk.y + step * Wk.y) - u0[1]);
+      Ds[k][2] = Dm[k][2] + ((Uk.z + step * Wk.z) - u0[2]);
+    }
+    constexpr int R[6] = {0, 1, 2, 0, 0, 1}, C[6] = {0, 1, 2, 1, 2, 2};
+    double G[6], Gp[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int i = R[c], j = C[c];
+      G[c] = Ds[i][0] * Ds[j][0] + Ds[i][1] * Ds[j][1] + Ds[i][2] * Ds[j][2];
+      Gp[c] = Dm[i][0] * Dm[j][0] + Dm[i][1] * Dm[j][1] + Dm[i][2] * Dm[j][2] +
+              (pl ? (double)pl[(size_t)c * m + t] : 0.0);
+    }
+    double Gpi[6];
+    sym3_inv(Gp, sym3_det(Gp[0], Gp[1], Gp[2], Gp[3], Gp[4], Gp[5]), Gpi);
+    double Gf[3][3], Af[3][3], P[3][3];
+    sym_full(G, Gf);
+    sym_full(Gpi, Af);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) P[i][j] = Gf[i][0] * Af[0][j] + Gf[i][1] * Af[1][j] + Gf[i][2] * Af[2][j];
+    const double IC = P[0][0] + P[1][1] + P[2][2];
+    auto det3 = [](const double (&a)[3][3]) {
+      return a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) - a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+             a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+    };
+    const double detDm = det3(Dm);
+    double psi;
+    if constexpr (EN == kEnergyStVK) {
+      double II = 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) II += P[i][j] * P[j][i];
+      psi = cst.lam / 8.0 * (IC - 3.0) * (IC - 3.0) + cst.mu / 4.0 * (II - 2.0 * IC + 3.0);
+    } else {
+      const double J = det3(Ds) / detDm;
+      const double JmA = J - 1.0 - cst.alpha_m1;
+      psi = 0.5 * cst.mu * (IC - 3.0) + 0.5 * cst.lam * JmA * JmA - 0.5 * cst.mu * log(IC + 1.0);
+    }
+    acc += chi * (detDm / 6.0) * psi;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kThreads) void k_dot(int n, const d4* __restrict__ a, const d4* __restrict__ b,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[16];
+  double acc = 0.0;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+    const d4 x = a[i], y = b[i];
+    acc += x.x * y.x + x.y * y.y + x.z * y.z;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kThreads) void k_axpy(int n, double sc, const d4* __restrict__ x,
+                                                   d4* __restrict__ y) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const d4 a = x[i];
+  d4 c = y[i];
+  c.x += sc * a.x;
+  c.y += sc * a.y;
+  c.z += sc * a.z;
+  y[i] = c;
+}
+
+__global__ __launch_bounds__(kThreads) void k_move_prescribed(int n, const uint8_t* __restrict__ dflag,
+                                                              const d4* __restrict__ dvel, double dt,
+                                                              d4* __restrict__ U) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n || !dflag[i]) return;
+  const d4 v = dvel[i];
+  d4 u = U[i];
+  u.x += dt * v.x;
+  u.y += dt * v.y;
+  u.z += dt * v.z;
+  U[i] = u;
 }
 
 // ---------------------------------------------------------------- edge pass
@@ -1800,14 +1918,14 @@ void launch_plastic(hipStream_t s, int m, const int4* tets, const d4* X, const d
 
 template <typename T>
 void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_edge, const uint8_t* flip,
-                    const d4* X, const d4* U, const uint8_t* zeta, const T* pl, ElemConst c, Rec<T>* contrib,
-                    Counters* ctr) {
+                    const d4* X, const d4* U, const uint8_t* zeta, const T* pl, const T* chi_in, T* chi_out,
+                    ElemConst c, Rec<T>* contrib, Counters* ctr) {
   if (c.energy == kEnergyStVK)
-    k_element<T, kEnergyStVK><<<blocks_for(m), kThreads, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta, pl, c,
-                                                                  contrib, ctr);
+    k_element<T, kEnergyStVK><<<blocks_for(m), kThreads, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta, pl, chi_in,
+                                                                  chi_out, c, contrib, ctr);
   else
     k_element<T, kEnergyStableNeoHookean><<<blocks_for(m), kThreads, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta,
-                                                                             pl, c, contrib, ctr);
+                                                                             pl, chi_in, chi_out, c, contrib, ctr);
 }
 
 template <typename T>
@@ -1930,10 +2048,34 @@ void launch_integrate(hipStream_t s, int n, const d4* X64, d4* V, d4* U, const u
   k_integrate<<<blocks_for(n), kThreads, 0, s>>>(n, X64, V, U, dflag, dvel, dt);
 }
 
+template <typename T>
+void launch_energy(hipStream_t s, int G, int m, const int4* tets, const d4* X, const d4* U, const d4* X64,
+                   double step, const T* pl, const T* chi_in, ElemConst c, double* part) {
+  if (c.energy == kEnergyStVK)
+    k_energy<T, kEnergyStVK><<<G, kThreads, 0, s>>>(m, tets, X, U, X64, step, pl, chi_in, c, part);
+  else
+    k_energy<T, kEnergyStableNeoHookean><<<G, kThreads, 0, s>>>(m, tets, X, U, X64, step, pl, chi_in, c, part);
+}
+
+void launch_dot(hipStream_t s, int G, int n, const d4* a, const d4* b, double* part) {
+  k_dot<<<G, kThreads, 0, s>>>(n, a, b, part);
+}
+
+void launch_axpy(hipStream_t s, int n, double sc, const d4* x, d4* y) {
+  if (n > 0) k_axpy<<<blocks_for(n), kThreads, 0, s>>>(n, sc, x, y);
+}
+
+void launch_move_prescribed(hipStream_t s, int n, const uint8_t* dflag, const d4* dvel, double dt, d4* U) {
+  if (n > 0) k_move_prescribed<<<blocks_for(n), kThreads, 0, s>>>(n, dflag, dvel, dt, U);
+}
+
 #define GFEM_INST(T)                                                                                         \
   template void launch_plastic<T>(hipStream_t, int, const int4*, const d4*, const d4*, const T*, T*, double); \
+  template void launch_energy<T>(hipStream_t, int, int, const int4*, const d4*, const d4*, const d4*, double, \
+                                 const T*, const T*, ElemConst, double*);                                    \
   template void launch_element<T>(hipStream_t, int, const int4*, const int32_t*, const uint8_t*, const d4*,  \
-                                  const d4*, const uint8_t*, const T*, ElemConst, Rec<T>*, Counters*);       \
+                                  const d4*, const uint8_t*, const T*, const T*, T*, ElemConst, Rec<T>*,     \
+                                  Counters*);                                                                \
   template void launch_edge<T>(hipStream_t, int, const int32_t*, const int32_t*, const Rec<T>*,              \
                                const double*, double, double, const int32_t*, const int32_t*, T*, int,       \
                                double*);                                                                     \

@@ -110,11 +110,26 @@ template <typename T>
 void launch_plastic(hipStream_t s, int m, const int4* tets, const d4* X, const d4* U, const T* pl_in, T* pl_out,
                     double yield);
 
-// pl: plastic rest-shape offsets [6][m], or null.
+// pl: plastic rest-shape offsets [6][m], or null.  chi_in (nullable): per-tet
+// energy fractions to use instead of evaluating Eq. 25; chi_out (nullable):
+// receives the fractions used.
 template <typename T>
 void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_edge,
                     const uint8_t* flip, const d4* X, const d4* U, const uint8_t* zeta,
-                    const T* pl, ElemConst c, Rec<T>* contrib, Counters* ctr);
+                    const T* pl, const T* chi_in, T* chi_out, ElemConst c, Rec<T>* contrib, Counters* ctr);
+
+// Quasi-static Newton (Eq. 36) helpers.
+// Total energy sum_e chi_e V_e Psi_e at the displacement U + s X64 (FP64),
+// chi held fixed (chi_in[m]); per-workgroup partials into part[G], G <= kMaxPart.
+template <typename T>
+void launch_energy(hipStream_t s, int G, int m, const int4* tets, const d4* X, const d4* U, const d4* X64,
+                   double step, const T* pl, const T* chi_in, ElemConst c, double* part);
+// Partials of a.b over the node records into part[G].
+void launch_dot(hipStream_t s, int G, int n, const d4* a, const d4* b, double* part);
+// y += s x over the node records (x, y: d4[n]).
+void launch_axpy(hipStream_t s, int n, double sc, const d4* x, d4* y);
+// U += dt * dvel on the prescribed nodes (dflag != 0).
+void launch_move_prescribed(hipStream_t s, int n, const uint8_t* dflag, const d4* dvel, double dt, d4* U);
 
 template <typename T>
 void launch_edge(hipStream_t s, int ne, const int32_t* edge_ptr, const int32_t* edge_slot,

@@ -47,6 +47,15 @@ class GfStepStats(C.Structure):
         return d
 
 
+class GfQsStats(C.Structure):
+    _fields_ = [("steps_done", C.c_int32), ("newton_iters", C.c_int32), ("line_search_halvings", C.c_int32),
+                ("inner_iters", C.c_int32), ("new_broken", C.c_int32), ("total_broken", C.c_int32),
+                ("force_initial", C.c_double), ("force_residual", C.c_double), ("energy", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class GfemError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -65,6 +74,7 @@ _SIGS = {
     "gf_set_dirichlet": ([C.c_void_p, _P(C.c_int32), C.c_int32, _P(C.c_double)], C.c_int),
     "gf_set_edge_damage": ([C.c_void_p, _P(C.c_uint8)], C.c_int),
     "gf_step": ([C.c_void_p, C.c_int32, _P(GfStepStats)], C.c_int),
+    "gf_quasi_static_step": ([C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_double, _P(GfQsStats)], C.c_int),
     "gf_get_positions": ([C.c_void_p, _P(C.c_double)], C.c_int),
     "gf_get_velocities": ([C.c_void_p, _P(C.c_double)], C.c_int),
     "gf_get_edge_damage": ([C.c_void_p, _P(C.c_uint8)], C.c_int),
@@ -208,6 +218,18 @@ class Mesh:
     def step(self, n_steps: int = 1, raise_on_error: bool = True) -> dict:
         st = GfStepStats()
         s = self._lib.gf_step(self._h, int(n_steps), C.byref(st))
+        d = st.as_dict()
+        d["status"] = s
+        if s != GF_OK and raise_on_error:
+            _check(s)
+        return d
+
+    def quasi_static_step(self, n_steps: int = 1, newton_rel_tol: float = 1e-6, max_newton: int = 50,
+                          armijo: float = 1e-4, raise_on_error: bool = True) -> dict:
+        """Quasi-static load steps (Eq. 36): Newton with a backtracking line search."""
+        st = GfQsStats()
+        s = self._lib.gf_quasi_static_step(self._h, int(n_steps), float(newton_rel_tol), int(max_newton),
+                                           float(armijo), C.byref(st))
         d = st.as_dict()
         d["status"] = s
         if s != GF_OK and raise_on_error:
