@@ -894,3 +894,66 @@ def quasi_static_step(mesh: Mesh, state: State, dir_nodes, dir_vel, newton_rtol:
         return state, stats
     return State(x, np.zeros_like(state.v), zeta, Cp, state.step + 1), stats
 
+
+# --------------------------------------------------------------------------
+# Visualisation mesh (Sec. 4.1): node-associated four-split of each tet
+# --------------------------------------------------------------------------
+
+def _component(nodes, start, unbroken):
+    """Nodes of `nodes` reachable from `start` through unbroken edges whose
+    both ends lie in `nodes`."""
+    comp, stack = {start}, [start]
+    while stack:
+        a = stack.pop()
+        for b in nodes:
+            if b not in comp and unbroken(a, b):
+                comp.add(b)
+                stack.append(b)
+    return comp
+
+
+def visual_mesh(X: np.ndarray, x: np.ndarray, tets: np.ndarray, edges: np.ndarray, zeta: np.ndarray):
+    """The split visualisation mesh of Sec. 4.1, one sub-cell per tet corner
+    (the node-associated four-split: the corner, the centroids of its three
+    edges, of its three faces and of the tet).  Each split point has one
+    child per group of the tet's corners that its unbroken edges connect
+    within that edge, face or tet; the child of corner a sits at the split
+    point's rest position plus the mean displacement of a's group (a broken
+    edge: each child follows its own parent; the face of the paper's example
+    with both edges at PF1 broken: SF1 follows PF1, SF2 and SF3 the average
+    of PF2 and PF3).  Loops over tets: small meshes only.
+
+    Returns (xyz (m,4,8,3): per tet (caller order) and corner (caller local
+    order) the sub-cell vertices [corner, edge points towards the other
+    corners b1 < b2 < b3, face points (b1,b2), (b1,b3), (b2,b3), tet point];
+    group (m,4) uint8: the smallest local corner index connected to each
+    corner through unbroken edges of the tet)."""
+    X = np.asarray(X, float)
+    u = np.asarray(x, float) - X
+    key = {(int(i), int(j)): bool(z) for (i, j), z in zip(edges, zeta)}
+    m = tets.shape[0]
+    xyz = np.zeros((m, 4, 8, 3))
+    group = np.zeros((m, 4), np.uint8)
+    for t in range(m):
+        nd = [int(v) for v in tets[t]]
+
+        def unbroken(a, b):
+            i, j = nd[a], nd[b]
+            return not key[(min(i, j), max(i, j))]
+
+        def child(simplex, a):
+            comp = _component(simplex, a, unbroken)
+            rest = np.mean([X[nd[c]] for c in simplex], axis=0)
+            return rest + np.mean([u[nd[c]] for c in comp], axis=0)
+
+        for a in range(4):
+            others = [b for b in range(4) if b != a]
+            verts = [X[nd[a]] + u[nd[a]]]
+            verts += [child([a, b], a) for b in others]
+            verts += [child([a, b, c], a) for b, c in ((others[0], others[1]), (others[0], others[2]),
+                                                        (others[1], others[2]))]
+            verts.append(child([0, 1, 2, 3], a))
+            xyz[t, a] = verts
+            group[t, a] = min(_component([0, 1, 2, 3], a, unbroken))
+    return xyz, group
+
