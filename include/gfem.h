@@ -201,6 +201,24 @@ gf_status gf_get_velocities(const gf_mesh* m, double* vel_out);
  * caller-owned buffer.  Waits for the library's stream. */
 gf_status gf_get_edge_damage(const gf_mesh* m, uint8_t* zeta_out);
 
+/* Split visualisation mesh of the current state (Sec. 4.1): the computational
+ * mesh is never remeshed; for rendering, each tet is split into one sub-cell
+ * per corner (the node-associated four-split: the corner, the centroids of
+ * its three edges, of its three faces and of the tet).  A split point has one
+ * child per group of the tet's corners that its unbroken edges connect within
+ * that edge, face or tet, placed at the point's rest position plus the mean
+ * displacement of the group: a broken edge gives each parent its own child;
+ * unbroken, the children coincide.  Outputs (caller-owned host buffers, each
+ * may be NULL), tets in caller order, corners in the caller's local order a:
+ *   subcell_xyz_out[n_tets*4*8*3] doubles: per tet and corner a the vertices
+ *     [corner a, edge points towards the other corners b1 < b2 < b3, face
+ *     points (b1,b2), (b1,b3), (b2,b3), tet point], each x, y, z;
+ *   group_out[n_tets*4]: the smallest local corner index joined to a by
+ *     unbroken edges of the tet (sub-cells of one group render as one piece;
+ *     faces between groups are crack surfaces).
+ * Off the timestep path; uses the library's stream and waits for it. */
+gf_status gf_get_visual_mesh(gf_mesh* m, double* subcell_xyz_out, uint8_t* group_out);
+
 /* Edges whose Green strain was within 1e-6 of the damage threshold in the
  * last damage pass (Eq. 21: labels there depend on rounding, so they are
  * reported rather than graded): canonical edge ids, ascending.  At most

@@ -135,6 +135,10 @@ struct gf_mesh {
   // quasi-static load steps: zero node vector, chi held fixed, displacement at the step's start
   d4 *qs_zero = nullptr, *qs_U0 = nullptr;
   void* qs_chi = nullptr;
+  // split visualisation mesh (built on first use, in chunks of tets)
+  uint8_t* tet_swapped = nullptr;
+  double* vis_xyz = nullptr;
+  uint8_t* vis_group = nullptr;
   int32_t *edge_ptr = nullptr, *edge_slot = nullptr, *blk_ij = nullptr, *blk_ji = nullptr;
   void* edge_w = nullptr;
   // block matrix
@@ -1198,6 +1202,34 @@ gf_status gf_quasi_static_step(gf_mesh* m, int32_t n_steps, double newton_rel_to
   GF_TRY({
     return m->split ? qs_step_impl<float>(m, n_steps, newton_rel_tol, max_newton, armijo, stats)
                     : qs_step_impl<double>(m, n_steps, newton_rel_tol, max_newton, armijo, stats);
+  })
+}
+
+gf_status gf_get_visual_mesh(gf_mesh* m, double* subcell_xyz_out, uint8_t* group_out) {
+  if (gf_status s = guard(m, "gf_get_visual_mesh")) return s;
+  GF_TRY({
+    constexpr int kChunk = 1 << 16;
+    if (!m->vis_xyz) {
+      m->tet_swapped = upload(m, m->topo.tet_swapped);
+      m->vis_xyz = m->al.get<double>((size_t)96 * kChunk);
+      m->vis_group = m->al.get<uint8_t>((size_t)4 * kChunk);
+    }
+    for (int t0 = 0; t0 < m->m; t0 += kChunk) {
+      const int cnt = std::min(kChunk, m->m - t0);
+      gfem::launch_visual(m->stream, t0, cnt, m->m, m->tets, m->tet_swapped, m->tet_edge, m->zeta[m->zcur], m->X,
+                          m->U, m->vis_xyz, m->vis_group);
+      m->check_launch();
+      if (subcell_xyz_out)
+        hchk(hipMemcpyAsync(subcell_xyz_out + (size_t)96 * t0, m->vis_xyz, sizeof(double) * 96 * (size_t)cnt,
+                            hipMemcpyDeviceToHost, m->stream),
+             "D2H");
+      if (group_out)
+        hchk(hipMemcpyAsync(group_out + (size_t)4 * t0, m->vis_group, 4 * (size_t)cnt, hipMemcpyDeviceToHost,
+                            m->stream),
+             "D2H");
+      m->sync();
+    }
+    return GF_OK;
   })
 }
 

@@ -1005,6 +1005,96 @@ __global__ __launch_bounds__(kThreads) void k_move_prescribed(int n, const uint8
   U[i] = u;
 }
 
+// ---------------------------------------------------------------- visualisation mesh (Sec. 4.1)
+
+// One thread per tet: the node-associated four-split with children placed by
+// the unbroken-edge groups of each edge, face and the tet.  FP64.
+__global__ __launch_bounds__(kThreads) void k_visual(int t0, int cnt, int m, const int4* __restrict__ tets,
+                                                     const uint8_t* __restrict__ swapped,
+                                                     const int32_t* __restrict__ tet_edge,
+                                                     const uint8_t* __restrict__ zeta, const d4* __restrict__ X,
+                                                     const d4* __restrict__ U, double* __restrict__ xyz,
+                                                     uint8_t* __restrict__ group) {
+  const int r = blockIdx.x * kThreads + threadIdx.x;
+  if (r >= cnt) return;
+  const int t = t0 + r;
+  const int4 nd = tets[t];
+  const int ids[4] = {nd.x, nd.y, nd.z, nd.w};
+  double Xp[4][3], Up[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const d4 x = X[ids[a]], u = U[ids[a]];
+    Xp[a][0] = x.x;
+    Xp[a][1] = x.y;
+    Xp[a][2] = x.z;
+    Up[a][0] = u.x;
+    Up[a][1] = u.y;
+    Up[a][2] = u.z;
+  }
+  // unbroken[i][j] between internal corners
+  bool ub[4][4] = {};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const bool u = zeta[tet_edge[(size_t)k * m + t]] == 0;
+    ub[EA(k)][EB(k)] = ub[EB(k)][EA(k)] = u;
+  }
+  // caller corner -> internal corner (an involution)
+  const bool sw = swapped[t] != 0;
+  const int cmap[4] = {0, 1, sw ? 3 : 2, sw ? 2 : 3};
+  double* out = xyz + (size_t)r * 96;
+  auto put = [&](int a, int v, const double (&p)[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[(a * 8 + v) * 3 + d] = p[d];
+  };
+  for (int a = 0; a < 4; ++a) {
+    const int ia = cmap[a];
+    int ob[3], j = 0;
+    for (int b = 0; b < 4; ++b)
+      if (b != a) ob[j++] = cmap[b];
+    double p[3];
+    for (int d = 0; d < 3; ++d) p[d] = Xp[ia][d] + Up[ia][d];
+    put(a, 0, p);
+    for (int q = 0; q < 3; ++q) {  // edge points
+      const int ib = ob[q];
+      const bool join = ub[ia][ib];
+      for (int d = 0; d < 3; ++d)
+        p[d] = (Xp[ia][d] + Xp[ib][d]) / 2.0 + (join ? (Up[ia][d] + Up[ib][d]) / 2.0 : Up[ia][d]);
+      put(a, 1 + q, p);
+    }
+    const int fp[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int q = 0; q < 3; ++q) {  // face points
+      const int ib = ob[fp[q][0]], ic = ob[fp[q][1]];
+      const bool inb = ub[ia][ib] || (ub[ia][ic] && ub[ic][ib]);
+      const bool inc = ub[ia][ic] || (ub[ia][ib] && ub[ib][ic]);
+      const int cntg = 1 + (int)inb + (int)inc;
+      for (int d = 0; d < 3; ++d) {
+        const double us = Up[ia][d] + (inb ? Up[ib][d] : 0.0) + (inc ? Up[ic][d] : 0.0);
+        p[d] = (Xp[ia][d] + Xp[ib][d] + Xp[ic][d]) / 3.0 + us / cntg;
+      }
+      put(a, 4 + q, p);
+    }
+    // tet point: the component of ia in the unbroken-edge graph
+    bool in[4] = {false, false, false, false};
+    in[ia] = true;
+    for (int it = 0; it < 3; ++it)
+      for (int i = 0; i < 4; ++i)
+        if (in[i])
+          for (int k = 0; k < 4; ++k)
+            if (ub[i][k]) in[k] = true;
+    int cntc = 0, gmin = 4;
+    double us[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 4; ++i)
+      if (in[i]) {
+        ++cntc;
+        gmin = min(gmin, cmap[i]);
+        for (int d = 0; d < 3; ++d) us[d] += Up[i][d];
+      }
+    for (int d = 0; d < 3; ++d) p[d] = (Xp[0][d] + Xp[1][d] + Xp[2][d] + Xp[3][d]) / 4.0 + us[d] / cntc;
+    put(a, 7, p);
+    group[(size_t)r * 4 + a] = (uint8_t)gmin;
+  }
+}
+
 // ---------------------------------------------------------------- edge pass
 
 // One thread per edge: sum the tets' contributions in slot order (fixed), add
@@ -2067,6 +2157,12 @@ void launch_axpy(hipStream_t s, int n, double sc, const d4* x, d4* y) {
 
 void launch_move_prescribed(hipStream_t s, int n, const uint8_t* dflag, const d4* dvel, double dt, d4* U) {
   if (n > 0) k_move_prescribed<<<blocks_for(n), kThreads, 0, s>>>(n, dflag, dvel, dt, U);
+}
+
+void launch_visual(hipStream_t s, int t0, int cnt, int m, const int4* tets, const uint8_t* swapped,
+                   const int32_t* tet_edge, const uint8_t* zeta, const d4* X, const d4* U, double* xyz,
+                   uint8_t* group) {
+  if (cnt > 0) k_visual<<<blocks_for(cnt), kThreads, 0, s>>>(t0, cnt, m, tets, swapped, tet_edge, zeta, X, U, xyz, group);
 }
 
 #define GFEM_INST(T)                                                                                         \

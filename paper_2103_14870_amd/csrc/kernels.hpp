@@ -118,6 +118,18 @@ void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_e
                     const uint8_t* flip, const d4* X, const d4* U, const uint8_t* zeta,
                     const T* pl, const T* chi_in, T* chi_out, ElemConst c, Rec<T>* contrib, Counters* ctr);
 
+// Split visualisation mesh (Sec. 4.1) of tets t0 .. t0 + cnt - 1: per tet and
+// caller-order corner a the 8 sub-cell vertices (FP64 x, y, z) [corner, edge
+// points towards the other corners b1 < b2 < b3, face points (b1,b2), (b1,b3),
+// (b2,b3), tet point] into xyz[(t - t0) * 96 ..], and the smallest corner
+// index connected to a through unbroken edges into group[(t - t0) * 4 + a].
+// A split point's child for a sits at its rest position plus the mean
+// displacement of the corners that unbroken edges join to a within that
+// edge, face or tet.  swapped[t]: local nodes 2 and 3 were exchanged.
+void launch_visual(hipStream_t s, int t0, int cnt, int m, const int4* tets, const uint8_t* swapped,
+                   const int32_t* tet_edge, const uint8_t* zeta, const d4* X, const d4* U, double* xyz,
+                   uint8_t* group);
+
 // Quasi-static Newton (Eq. 36) helpers.
 // Total energy sum_e chi_e V_e Psi_e at the displacement U + s X64 (FP64),
 // chi held fixed (chi_in[m]); per-workgroup partials into part[G], G <= kMaxPart.

@@ -39,6 +39,7 @@ std::string build_topology(const double* xyz, int n, const int32_t* tets_in, int
 
   // Validate ids, reorient negative tets (swap local nodes 2 and 3), reject flat ones.
   T.tets.resize(4 * (size_t)m);
+  T.tet_swapped.assign(m, 0);
   T.vol.resize(m);
   T.reoriented = 0;
   for (int t = 0; t < m; ++t) {
@@ -81,6 +82,7 @@ std::string build_topology(const double* xyz, int n, const int32_t* tets_in, int
       std::swap(v[2], v[3]);
       vol6 = -vol6;
       ++T.reoriented;
+      T.tet_swapped[t] = 1;
     }
     T.vol[t] = vol6 / 6.0;
     for (int a = 0; a < 4; ++a) T.tets[4 * (size_t)t + a] = v[a];

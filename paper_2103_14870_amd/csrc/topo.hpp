@@ -27,6 +27,7 @@ struct Topology {
   std::vector<int32_t> edges;     // ne*2, i < j, sorted (internal ids)
   std::vector<int32_t> tet_edge;  // 6*m, SoA: tet_edge[k*m + t]
   std::vector<uint8_t> tet_flip;  // m: bit k set when the global edge runs b -> a
+  std::vector<uint8_t> tet_swapped;  // m: 1 when local nodes 2 and 3 were swapped (negative input orientation)
   std::vector<int32_t> edge_ptr;  // ne+1: contributions of edge e are
   std::vector<int32_t> edge_slot; //   edge_slot[edge_ptr[e] .. edge_ptr[e+1]) = k*m + t
   std::vector<int32_t> row_ptr;   // n+1 block rows

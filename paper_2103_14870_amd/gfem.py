@@ -75,6 +75,7 @@ _SIGS = {
     "gf_set_edge_damage": ([C.c_void_p, _P(C.c_uint8)], C.c_int),
     "gf_step": ([C.c_void_p, C.c_int32, _P(GfStepStats)], C.c_int),
     "gf_quasi_static_step": ([C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_double, _P(GfQsStats)], C.c_int),
+    "gf_get_visual_mesh": ([C.c_void_p, _P(C.c_double), _P(C.c_uint8)], C.c_int),
     "gf_get_positions": ([C.c_void_p, _P(C.c_double)], C.c_int),
     "gf_get_velocities": ([C.c_void_p, _P(C.c_double)], C.c_int),
     "gf_get_edge_damage": ([C.c_void_p, _P(C.c_uint8)], C.c_int),
@@ -248,6 +249,14 @@ class Mesh:
         x = np.zeros((self.n_nodes, 3))
         _check(self._lib.gf_get_positions(self._h, _dptr(x)))
         return x
+
+    def visual_mesh(self):
+        """Split visualisation mesh (Sec. 4.1): sub-cell vertices (n_tets, 4, 8, 3)
+        and corner groups (n_tets, 4)."""
+        xyz = np.zeros((self.n_tets, 4, 8, 3))
+        grp = np.zeros((self.n_tets, 4), np.uint8)
+        _check(self._lib.gf_get_visual_mesh(self._h, _dptr(xyz), _u8ptr(grp)))
+        return xyz, grp
 
     def velocities(self) -> np.ndarray:
         v = np.zeros((self.n_nodes, 3))
