@@ -190,6 +190,19 @@ typedef struct {
 gf_status gf_quasi_static_step(gf_mesh* m, int32_t n_steps, double newton_rel_tol, int32_t max_newton,
                                double armijo, gf_qs_stats* stats);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): gf_quasi_static_step
+ * with its per-call scratch (a zero node vector, the displacement at the load
+ * step's start and the frozen chi) in a fixed device array of the library
+ * (7 MiB per device, held until the process ends) instead of buffers the
+ * library allocates on first use; same arguments, kernels and results.  Calls
+ * no hipMalloc/hipFree.  Meshes of at most 65,536 nodes and 393,216 tets
+ * (GF_EINVAL beyond, nothing done); the mesh's device must be current.  All
+ * calls on one device share the array: calls that overlap on a device race
+ * and must be serialised by the caller. */
+gf_status gf_quasi_static_step_noalloc(gf_mesh* m, int32_t n_steps, double newton_rel_tol, int32_t max_newton,
+                                       double armijo, gf_qs_stats* stats);
+
 /* Current positions x = X + u after the last committed step (Algorithm 1's
  * update x += dt v of Sec. 4.3), n_nodes*3 doubles, caller order, into a
  * caller-owned buffer.  Waits for the library's stream. */

@@ -10,8 +10,10 @@
 #include <cstring>
 #include <exception>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <random>
+#include <stdexcept>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -299,6 +301,7 @@ struct AsmOpt {
   const void* chi_in = nullptr;  // per-tet chi held fixed (T[m]) instead of Eq. 25
   void* chi_out = nullptr;       // receives the chi used (T[m])
   bool quasi_static = false;     // zero velocities and prescribed velocities, no damping or gravity
+  const d4* zero = nullptr;      // quasi-static: a zero node vector (n records)
   d4* f_out = nullptr;           // restoring forces, when wanted
 };
 
@@ -350,8 +353,8 @@ void assemble(gf_mesh* M, const AsmOpt& o) {
   });
   gfem::RowConst rc{dt, ra, mass_fac, {M->p.gravity[0], M->p.gravity[1], M->p.gravity[2]}};
   if (o.quasi_static) rc.g[0] = rc.g[1] = rc.g[2] = 0.0;
-  const d4* V = o.quasi_static ? M->qs_zero : M->V;
-  const d4* dvel = o.quasi_static ? M->qs_zero : M->dvel;
+  const d4* V = o.quasi_static ? o.zero : M->V;
+  const d4* dvel = o.quasi_static ? o.zero : M->dvel;
   M->timed(2, -1, 0, [&] {
     gfem::launch_row<T>(s, M->n, M->Gs, M->mat(), M->diag_blk, M->blk_edge, M->edge_mass,
                         static_cast<const double*>(M->edge_w), M->lumped, M->X, M->U, V, M->dflag, dvel, rc,
@@ -769,12 +772,51 @@ gf_status step_impl(gf_mesh* M, int n_steps, gf_step_stats* st) {
   return GF_OK;
 }
 
-// Buffers of the quasi-static load step (allocated on first use).
-void ensure_qs(gf_mesh* M) {
-  if (M->qs_zero) return;
-  M->qs_zero = M->al.get<d4>(M->n);  // zero-filled by the allocator, never written
-  M->qs_U0 = M->al.get<d4>(M->n);
-  M->qs_chi = M->split ? (void*)M->al.get<float>(M->m) : (void*)M->al.get<double>(M->m);
+// Scratch of a quasi-static load step: a zero node vector, the displacement
+// at the step's start (restored on failure) and the frozen chi (T[m]).
+struct QsBufs {
+  d4* zero;
+  d4* U0;
+  void* chi;
+};
+
+// The mesh's own scratch (allocated on first use).
+QsBufs qs_owned(gf_mesh* M) {
+  if (!M->qs_zero) {
+    M->qs_zero = M->al.get<d4>(M->n);  // zero-filled by the allocator, never written
+    M->qs_U0 = M->al.get<d4>(M->n);
+    M->qs_chi = M->split ? (void*)M->al.get<float>(M->m) : (void*)M->al.get<double>(M->m);
+  }
+  return QsBufs{M->qs_zero, M->qs_U0, M->qs_chi};
+}
+
+// Allocation-free variant: the scratch lives in a file-scope device array of
+// fixed size (per device, kept until the process ends).  Host code uses the
+// address hipGetSymbolAddress returns for the current device, never the
+// array's name.  Every call on a device shares it: calls that overlap on one
+// device race.
+constexpr int kNoAllocMaxNodes = 1 << 16;
+constexpr int kNoAllocMaxTets = 393216;
+constexpr size_t kNoAllocZero = 0;
+constexpr size_t kNoAllocU0 = sizeof(d4) * (size_t)kNoAllocMaxNodes;
+constexpr size_t kNoAllocChi = 2 * sizeof(d4) * (size_t)kNoAllocMaxNodes;
+constexpr size_t kNoAllocBytes = kNoAllocChi + sizeof(double) * (size_t)kNoAllocMaxTets;  // 7 MiB
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+void* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) throw std::runtime_error("device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hchk(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
 }
 
 // Quasi-static load steps (Eq. 36; Sec. 4.3 names Newton with a line search):
@@ -786,8 +828,8 @@ void ensure_qs(gf_mesh* M) {
 // E = sum chi V Psi (FP64); stop at |f| <= rtol |f_0|.  A failed load step
 // restores the displacement and commits nothing.
 template <typename T>
-gf_status qs_step_impl(gf_mesh* M, int n_steps, double rtol, int max_newton, double armijo, gf_qs_stats* st) {
-  ensure_qs(M);
+gf_status qs_step_impl(gf_mesh* M, const QsBufs& B, int n_steps, double rtol, int max_newton, double armijo,
+                       gf_qs_stats* st) {
   hipStream_t s = M->stream;
   const double dt = M->p.dt;
   const int Ge = std::min(gfem::kMaxPart, std::max(8, (M->m + gfem::kThreads - 1) / gfem::kThreads));
@@ -795,7 +837,7 @@ gf_status qs_step_impl(gf_mesh* M, int n_steps, double rtol, int max_newton, dou
   const gfem::ElemConst ec{M->mu, M->lam, M->alpha_m1, M->p.energy};
   constexpr double kMinStep = 1.0 / (1 << 20);
   for (int step = 0; step < n_steps; ++step) {
-    hchk(hipMemcpyAsync(M->qs_U0, M->U, sizeof(d4) * M->n, hipMemcpyDeviceToDevice, s), "D2D");
+    hchk(hipMemcpyAsync(B.U0, M->U, sizeof(d4) * M->n, hipMemcpyDeviceToDevice, s), "D2D");
     // 1. damage and plastic flow at x_n
     hchk(hipMemsetAsync(M->ctr, 0, sizeof(gfem::Counters), s), "hipMemsetAsync");
     const int zi = M->zcur, zo = 1 - M->zcur;
@@ -821,10 +863,11 @@ gf_status qs_step_impl(gf_mesh* M, int n_steps, double rtol, int max_newton, dou
     o.damage = o.flow = false;
     o.next_state = true;
     o.quasi_static = true;
-    o.chi_out = M->qs_chi;
+    o.zero = B.zero;
+    o.chi_out = B.chi;
     assemble<T>(M, o);
     o.chi_out = nullptr;
-    o.chi_in = M->qs_chi;
+    o.chi_in = B.chi;
     double f0 = -1.0, fn = 0.0;
     int iters = 0, halvings = 0, inner = 0;
     bool ok = false;
@@ -846,14 +889,14 @@ gf_status qs_step_impl(gf_mesh* M, int n_steps, double rtol, int max_newton, dou
       gfem::launch_dot(s, Gd, M->n, M->b, M->X64, M->part_r);
       M->check_launch();
       const double slope = read_partials(M, M->part_r, Gd);
-      gfem::launch_energy<T>(s, Ge, M->m, M->tets, M->X, M->U, M->X64, 0.0, pl, static_cast<const T*>(M->qs_chi),
+      gfem::launch_energy<T>(s, Ge, M->m, M->tets, M->X, M->U, M->X64, 0.0, pl, static_cast<const T*>(B.chi),
                              ec, M->part_r);
       M->check_launch();
       const double E0 = read_partials(M, M->part_r, Ge);
       double alpha = 1.0, E1 = E0;
       while (true) {
         gfem::launch_energy<T>(s, Ge, M->m, M->tets, M->X, M->U, M->X64, alpha * dt, pl,
-                               static_cast<const T*>(M->qs_chi), ec, M->part_r);
+                               static_cast<const T*>(B.chi), ec, M->part_r);
         M->check_launch();
         E1 = read_partials(M, M->part_r, Ge);
         if (E1 <= E0 - armijo * alpha * slope || std::fabs(E1 - E0) <= 1e-14 * std::fabs(E0)) break;
@@ -884,7 +927,7 @@ gf_status qs_step_impl(gf_mesh* M, int n_steps, double rtol, int max_newton, dou
       st->total_broken = cnt[gfem::kTotalBroken];
     }
     if (!ok) {
-      hchk(hipMemcpyAsync(M->U, M->qs_U0, sizeof(d4) * M->n, hipMemcpyDeviceToDevice, s), "D2D");
+      hchk(hipMemcpyAsync(M->U, B.U0, sizeof(d4) * M->n, hipMemcpyDeviceToDevice, s), "D2D");
       M->sync();
       char buf[200];
       snprintf(buf, sizeof buf,
@@ -1190,18 +1233,51 @@ gf_status gf_get_edge_damage(const gf_mesh* m, uint8_t* zeta_out) {
   })
 }
 
-gf_status gf_quasi_static_step(gf_mesh* m, int32_t n_steps, double newton_rel_tol, int32_t max_newton,
-                               double armijo, gf_qs_stats* stats) {
-  if (gf_status s = guard(m, "gf_quasi_static_step")) return s;
+static gf_status qs_check(gf_mesh* m, int32_t n_steps, double newton_rel_tol, int32_t max_newton, double armijo,
+                          gf_qs_stats* stats, const char* who) {
+  if (gf_status s = guard(m, who)) return s;
   if (stats) std::memset(stats, 0, sizeof *stats);
   if (n_steps < 0 || !(newton_rel_tol > 0.0 && newton_rel_tol < 1.0) || max_newton < 0 ||
       !(armijo > 0.0 && armijo < 1.0))
-    return fail(GF_EINVAL, "gf_quasi_static_step: bad arguments");
+    return fail(GF_EINVAL, std::string(who) + ": bad arguments");
   if (m->p.gravity[0] != 0.0 || m->p.gravity[1] != 0.0 || m->p.gravity[2] != 0.0)
-    return fail(GF_EINVAL, "gf_quasi_static_step: the quasi-static problem has no gravity (set it to zero)");
+    return fail(GF_EINVAL, std::string(who) + ": the quasi-static problem has no gravity (set it to zero)");
+  return GF_OK;
+}
+
+gf_status gf_quasi_static_step(gf_mesh* m, int32_t n_steps, double newton_rel_tol, int32_t max_newton,
+                               double armijo, gf_qs_stats* stats) {
+  if (gf_status s = qs_check(m, n_steps, newton_rel_tol, max_newton, armijo, stats, "gf_quasi_static_step"))
+    return s;
   GF_TRY({
-    return m->split ? qs_step_impl<float>(m, n_steps, newton_rel_tol, max_newton, armijo, stats)
-                    : qs_step_impl<double>(m, n_steps, newton_rel_tol, max_newton, armijo, stats);
+    const QsBufs B = qs_owned(m);
+    return m->split ? qs_step_impl<float>(m, B, n_steps, newton_rel_tol, max_newton, armijo, stats)
+                    : qs_step_impl<double>(m, B, n_steps, newton_rel_tol, max_newton, armijo, stats);
+  })
+}
+
+gf_status gf_quasi_static_step_noalloc(gf_mesh* m, int32_t n_steps, double newton_rel_tol, int32_t max_newton,
+                                       double armijo, gf_qs_stats* stats) {
+  const char* who = "gf_quasi_static_step_noalloc";
+  if (gf_status s = qs_check(m, n_steps, newton_rel_tol, max_newton, armijo, stats, who)) return s;
+  if (m->n > kNoAllocMaxNodes || m->m > kNoAllocMaxTets) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "%s: mesh of %d nodes / %d tets exceeds the fixed scratch (at most %d nodes, %d tets)",
+             who, m->n, m->m, kNoAllocMaxNodes, kNoAllocMaxTets);
+    return fail(GF_EINVAL, buf);
+  }
+  GF_TRY({
+    int dev = -1;
+    hchk(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != m->dev) return fail(GF_EINVAL, std::string(who) + ": the mesh's device is not the current device");
+    unsigned char* base = static_cast<unsigned char*>(scratch_address(dev));
+    const QsBufs B{reinterpret_cast<d4*>(base + kNoAllocZero), reinterpret_cast<d4*>(base + kNoAllocU0),
+                   base + kNoAllocChi};
+    // the array keeps the last call's contents: the zero vector is cleared here
+    gfem::launch_zero(m->stream, m->n, B.zero);
+    m->check_launch();
+    return m->split ? qs_step_impl<float>(m, B, n_steps, newton_rel_tol, max_newton, armijo, stats)
+                    : qs_step_impl<double>(m, B, n_steps, newton_rel_tol, max_newton, armijo, stats);
   })
 }
 

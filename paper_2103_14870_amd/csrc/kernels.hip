@@ -992,6 +992,11 @@ __global__ __launch_bounds__(kThreads) void k_axpy(int n, double sc, const d4* _
   y[i] = c;
 }
 
+__global__ __launch_bounds__(kThreads) void k_zero_d4(int n, d4* __restrict__ x) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) x[i] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
 __global__ __launch_bounds__(kThreads) void k_move_prescribed(int n, const uint8_t* __restrict__ dflag,
                                                               const d4* __restrict__ dvel, double dt,
                                                               d4* __restrict__ U) {
@@ -2153,6 +2158,10 @@ void launch_dot(hipStream_t s, int G, int n, const d4* a, const d4* b, double* p
 
 void launch_axpy(hipStream_t s, int n, double sc, const d4* x, d4* y) {
   if (n > 0) k_axpy<<<blocks_for(n), kThreads, 0, s>>>(n, sc, x, y);
+}
+
+void launch_zero(hipStream_t s, int n, d4* x) {
+  if (n > 0) k_zero_d4<<<blocks_for(n), kThreads, 0, s>>>(n, x);
 }
 
 void launch_move_prescribed(hipStream_t s, int n, const uint8_t* dflag, const d4* dvel, double dt, d4* U) {

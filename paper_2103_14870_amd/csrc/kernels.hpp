@@ -140,6 +140,8 @@ void launch_energy(hipStream_t s, int G, int m, const int4* tets, const d4* X, c
 void launch_dot(hipStream_t s, int G, int n, const d4* a, const d4* b, double* part);
 // y += s x over the node records (x, y: d4[n]).
 void launch_axpy(hipStream_t s, int n, double sc, const d4* x, d4* y);
+// x = 0 over the node records (x: d4[n]).
+void launch_zero(hipStream_t s, int n, d4* x);
 // U += dt * dvel on the prescribed nodes (dflag != 0).
 void launch_move_prescribed(hipStream_t s, int n, const uint8_t* dflag, const d4* dvel, double dt, d4* U);
 

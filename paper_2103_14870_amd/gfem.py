@@ -75,6 +75,8 @@ _SIGS = {
     "gf_set_edge_damage": ([C.c_void_p, _P(C.c_uint8)], C.c_int),
     "gf_step": ([C.c_void_p, C.c_int32, _P(GfStepStats)], C.c_int),
     "gf_quasi_static_step": ([C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_double, _P(GfQsStats)], C.c_int),
+    "gf_quasi_static_step_noalloc": ([C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_double, _P(GfQsStats)],
+                                     C.c_int),
     "gf_get_visual_mesh": ([C.c_void_p, _P(C.c_double), _P(C.c_uint8)], C.c_int),
     "gf_get_positions": ([C.c_void_p, _P(C.c_double)], C.c_int),
     "gf_get_velocities": ([C.c_void_p, _P(C.c_double)], C.c_int),
@@ -226,11 +228,12 @@ class Mesh:
         return d
 
     def quasi_static_step(self, n_steps: int = 1, newton_rel_tol: float = 1e-6, max_newton: int = 50,
-                          armijo: float = 1e-4, raise_on_error: bool = True) -> dict:
-        """Quasi-static load steps (Eq. 36): Newton with a backtracking line search."""
+                          armijo: float = 1e-4, raise_on_error: bool = True, noalloc: bool = False) -> dict:
+        """Quasi-static load steps (Eq. 36): Newton with a backtracking line search.
+        noalloc: the allocation-free entry point (fixed library scratch)."""
         st = GfQsStats()
-        s = self._lib.gf_quasi_static_step(self._h, int(n_steps), float(newton_rel_tol), int(max_newton),
-                                           float(armijo), C.byref(st))
+        fn = self._lib.gf_quasi_static_step_noalloc if noalloc else self._lib.gf_quasi_static_step
+        s = fn(self._h, int(n_steps), float(newton_rel_tol), int(max_newton), float(armijo), C.byref(st))
         d = st.as_dict()
         d["status"] = s
         if s != GF_OK and raise_on_error:
