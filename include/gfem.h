@@ -57,6 +57,12 @@ typedef enum { GF_PC_BLOCK_JACOBI = 0, GF_PC_LEARNED = 1 } gf_precond;
  * density of the dynamic runs (Sec. 5.2, Eq. 37, plain Lame constants), both
  * written in the six squared edge lengths (Sec. 3.5, Theorem 3.1). */
 typedef enum { GF_ENERGY_STABLE_NEO_HOOKEAN = 0, GF_ENERGY_STVK = 1 } gf_energy;
+/* Internal node numbering (invisible to the caller, who always uses its own
+ * ids): the caller's order, or reverse Cuthill-McKee on the tet graph (narrow
+ * band, so the gathers of neighbouring rows stay close in memory for any
+ * input order).  The learned factor is block lower triangular in internal
+ * order, so its blocks depend on this choice. */
+typedef enum { GF_REORDER_NONE = 0, GF_REORDER_RCM = 1 } gf_reorder;
 
 /* Material, integrator and solver parameters (copied at create). */
 typedef struct {
@@ -81,6 +87,7 @@ typedef struct {
   int32_t precond;        /* gf_precond */
   int32_t net_every_n_steps; /* learned preconditioner: run the network every n steps (>= 1) */
   int32_t energy;         /* gf_energy */
+  int32_t reorder;        /* gf_reorder */
 } gf_params;
 
 /* Per-call statistics (summed over the steps of one gf_step call, except

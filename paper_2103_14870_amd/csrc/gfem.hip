@@ -977,7 +977,8 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
       !(p.cg_rel_tol > 0) || p.cg_max_iter <= 0 || (p.precision != GF_PREC_FP64 && p.precision != GF_PREC_SPLIT) ||
       (p.precond != GF_PC_BLOCK_JACOBI && p.precond != GF_PC_LEARNED) || !std::isfinite(p.damage_strain) ||
       !(p.damage_radius >= 0.0) || !std::isfinite(p.damage_radius) ||
-      (p.energy != GF_ENERGY_STABLE_NEO_HOOKEAN && p.energy != GF_ENERGY_STVK))
+      (p.energy != GF_ENERGY_STABLE_NEO_HOOKEAN && p.energy != GF_ENERGY_STVK) ||
+      (p.reorder != GF_REORDER_NONE && p.reorder != GF_REORDER_RCM))
     return fail(GF_EINVAL, "gf_mesh_create: invalid parameters");
   if (p.precond == GF_PC_LEARNED && p.precision != GF_PREC_SPLIT)
     return fail(GF_EINVAL, "gf_mesh_create: the learned preconditioner needs the split precision mode");
@@ -987,7 +988,8 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     // reported the same way with or without a device.
     std::unique_ptr<gfem::Topology> topo(new gfem::Topology());
     bool degen = false;
-    std::string err = gfem::build_topology(rest_xyz, n_nodes, tets, n_tets, p.density, topo.get(), &degen);
+    std::string err =
+        gfem::build_topology(rest_xyz, n_nodes, tets, n_tets, p.density, topo.get(), &degen, p.reorder);
     if (!err.empty()) return fail(degen ? GF_EDEGENERATE : GF_EINVAL, "gf_mesh_create: " + err);
     // support of the non-local criterion (Eq. 20), also host-side
     std::vector<int64_t> nl_ptr;

@@ -18,8 +18,95 @@ double det3(const double* a, const double* b, const double* c) {
 
 }  // namespace
 
+// Reverse Cuthill-McKee order of the nodes of the tet graph (caller ids):
+// per connected component a pseudo-peripheral start node (repeated
+// breadth-first sweeps from a node of least degree, each restarting from a
+// least-degree node of the last level, while the depth grows), then a
+// breadth-first sweep visiting neighbours by increasing degree (ties by id);
+// the whole order reversed.  Nodes in no tet come last.  Returns order[k] =
+// the caller id of internal node k (before reversal order is CM).
+std::vector<int32_t> rcm_order(int n, const int32_t* tets, int m) {
+  std::vector<int64_t> pairs;
+  pairs.reserve(12 * (size_t)m);
+  for (int t = 0; t < m; ++t)
+    for (int k = 0; k < 6; ++k) {
+      const int64_t a = tets[4 * (size_t)t + kEdgeA[k]], b = tets[4 * (size_t)t + kEdgeB[k]];
+      pairs.push_back(a * n + b);
+      pairs.push_back(b * n + a);
+    }
+  std::sort(pairs.begin(), pairs.end());
+  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  std::vector<int32_t> ptr(n + 1, 0), adj(pairs.size());
+  for (size_t q = 0; q < pairs.size(); ++q) {
+    ++ptr[pairs[q] / n + 1];
+    adj[q] = (int32_t)(pairs[q] % n);
+  }
+  for (int i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+  auto deg = [&](int i) { return ptr[i + 1] - ptr[i]; };
+  std::vector<int32_t> level(n, -1), order;
+  order.reserve(n);
+  std::vector<int32_t> queue;
+  // breadth-first levels from s over unplaced nodes; returns the last level's nodes
+  auto sweep = [&](int s, std::vector<int32_t>& seen) {
+    queue.assign(1, s);
+    seen.push_back(s);
+    level[s] = 0;
+    int depth = 0;
+    for (size_t h = 0; h < queue.size(); ++h) {
+      const int v = queue[h];
+      depth = level[v];
+      for (int q = ptr[v]; q < ptr[v + 1]; ++q)
+        if (level[adj[q]] < 0) {
+          level[adj[q]] = level[v] + 1;
+          queue.push_back(adj[q]);
+          seen.push_back(adj[q]);
+        }
+    }
+    return depth;
+  };
+  std::vector<char> placed(n, 0);
+  std::vector<int32_t> by_degree(n);
+  std::iota(by_degree.begin(), by_degree.end(), 0);
+  std::stable_sort(by_degree.begin(), by_degree.end(), [&](int a, int b) { return deg(a) < deg(b); });
+  std::vector<int32_t> seen, nb;
+  for (int root : by_degree) {
+    if (placed[root] || deg(root) == 0) continue;
+    int start = root, depth = -1;
+    for (int rep = 0; rep < 8; ++rep) {
+      seen.clear();
+      const int d = sweep(start, seen);
+      int best = -1;
+      for (int v : seen)
+        if (level[v] == d && (best < 0 || deg(v) < deg(best) || (deg(v) == deg(best) && v < best))) best = v;
+      for (int v : seen) level[v] = -1;
+      if (d <= depth) break;
+      depth = d;
+      start = best;
+    }
+    // Cuthill-McKee sweep from start
+    const size_t first = order.size();
+    order.push_back(start);
+    placed[start] = 1;
+    for (size_t h = first; h < order.size(); ++h) {
+      const int v = order[h];
+      nb.clear();
+      for (int q = ptr[v]; q < ptr[v + 1]; ++q)
+        if (!placed[adj[q]]) nb.push_back(adj[q]);
+      std::sort(nb.begin(), nb.end(), [&](int a, int b) { return deg(a) != deg(b) ? deg(a) < deg(b) : a < b; });
+      for (int w : nb) {
+        placed[w] = 1;
+        order.push_back(w);
+      }
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  for (int i = 0; i < n; ++i)
+    if (!placed[i]) order.push_back(i);
+  return order;
+}
+
 std::string build_topology(const double* xyz, int n, const int32_t* tets_in, int m, double density,
-                           Topology* out, bool* degenerate) {
+                           Topology* out, bool* degenerate, int reorder) {
   *degenerate = false;
   Topology& T = *out;
   if (n <= 0 || m <= 0) return "n_nodes and n_tets must be positive";
@@ -27,12 +114,23 @@ std::string build_topology(const double* xyz, int n, const int32_t* tets_in, int
     if (!std::isfinite(xyz[i])) return "non-finite rest coordinate";
   T.n = n;
   T.m = m;
+  for (size_t q = 0; q < 4 * (size_t)m; ++q)
+    if (tets_in[q] < 0 || tets_in[q] >= n) {
+      char buf[128];
+      snprintf(buf, sizeof buf, "tet %d references node %d outside [0,%d)", (int)(q / 4), tets_in[q], n);
+      return buf;
+    }
 
-  // Node numbering (identity: the caller's order is kept internally).
+  // Node numbering: the caller's order, or reverse Cuthill-McKee.
   T.perm_new.resize(n);
   T.perm_old.resize(n);
-  std::iota(T.perm_new.begin(), T.perm_new.end(), 0);
-  std::iota(T.perm_old.begin(), T.perm_old.end(), 0);
+  if (reorder == 1) {
+    T.perm_old = rcm_order(n, tets_in, m);
+    for (int k = 0; k < n; ++k) T.perm_new[T.perm_old[k]] = k;
+  } else {
+    std::iota(T.perm_new.begin(), T.perm_new.end(), 0);
+    std::iota(T.perm_old.begin(), T.perm_old.end(), 0);
+  }
   T.X.resize(3 * (size_t)n);
   for (int i = 0; i < n; ++i)
     for (int d = 0; d < 3; ++d) T.X[3 * (size_t)T.perm_new[i] + d] = xyz[3 * (size_t)i + d];

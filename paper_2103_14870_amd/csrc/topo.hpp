@@ -54,9 +54,16 @@ struct Topology {
 };
 
 // Builds the topology.  Returns "" on success, otherwise an error message;
-// *degenerate is set when the failure is a flat tet.
+// *degenerate is set when the failure is a flat tet.  reorder: 0 keeps the
+// caller's node order internally, 1 renumbers the nodes in reverse
+// Cuthill-McKee order (narrow band: the gathers of neighbouring rows stay
+// close in memory whatever order the caller's ids come in).
 std::string build_topology(const double* xyz, int n, const int32_t* tets, int m, double density,
-                           Topology* out, bool* degenerate);
+                           Topology* out, bool* degenerate, int reorder = 0);
+
+// Reverse Cuthill-McKee order of the nodes of the tet graph: entry k is the
+// caller id of internal node k.
+std::vector<int32_t> rcm_order(int n, const int32_t* tets, int m);
 
 // Support of the non-local fracture criterion (Sec. 3.3, Eq. 20): for each tet
 // t the tets whose rest centroids lie within `radius` of t's (t included),

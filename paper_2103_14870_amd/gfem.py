@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "GF_OK", -1: "GF_EINVAL", -2: "GF_EDEGENERATE", -3: "GF_ENOME
 PREC = {"fp64": 0, "split": 1}
 PRECOND = {"block_jacobi": 0, "learned": 1}
 ENERGY = {"stable_neo_hookean": 0, "stvk": 1}
+REORDER = {"none": 0, "rcm": 1}
 KERNEL_CATEGORIES = ("damage", "element", "assembly", "precond", "spmv", "pcg_vector", "residual", "integrate",
                      "precond_gt")
 
@@ -30,7 +31,8 @@ class GfParams(C.Structure):
                 ("dt", C.c_double),
                 ("rayleigh_alpha", C.c_double), ("rayleigh_beta", C.c_double), ("gravity", C.c_double * 3),
                 ("cg_rel_tol", C.c_double), ("cg_max_iter", C.c_int32), ("precision", C.c_int32),
-                ("precond", C.c_int32), ("net_every_n_steps", C.c_int32), ("energy", C.c_int32)]
+                ("precond", C.c_int32), ("net_every_n_steps", C.c_int32), ("energy", C.c_int32),
+                ("reorder", C.c_int32)]
 
 
 class GfStepStats(C.Structure):
@@ -147,7 +149,7 @@ def make_params(p: dict) -> GfParams:
                     float(p.get("rayleigh_beta", 0.0)), (C.c_double * 3)(*[float(x) for x in g]),
                     float(p["cg_rel_tol"]), int(p.get("cg_max_iter", 5000)), PREC[p.get("precision", "fp64")],
                     PRECOND[p.get("precond", "block_jacobi")], int(p.get("net_every_n_steps", 1)),
-                    ENERGY[p.get("energy", "stable_neo_hookean")])
+                    ENERGY[p.get("energy", "stable_neo_hookean")], REORDER[p.get("reorder", "none")])
 
 
 class Mesh:

@@ -266,6 +266,20 @@ def tiny_cube(n=1, h=1.0, jitter_frac=0.0, seed=0, **param_kw) -> Problem:
     return cube_block(n, n, n, h, jitter_frac=jitter_frac, seed=seed, **param_kw)
 
 
+def permute_nodes(prob: Problem, seed: int) -> Problem:
+    """The same problem with its node ids randomly permuted (seeded): rest
+    positions, tets, prescribed nodes and pre-broken pairs renumbered, so a
+    mesh arrives in no particular order."""
+    n = prob.n_nodes
+    new = np.random.default_rng(seed).permutation(n)  # new id of each old node
+    X = np.empty_like(prob.X)
+    X[new] = prob.X
+    pairs = np.sort(new[prob.broken_pairs], axis=1).astype(np.int32) if prob.broken_pairs.size else prob.broken_pairs
+    return Problem(prob.name + f"-perm{seed}", X, new[prob.tets].astype(np.int32), dict(prob.params),
+                   new[prob.dir_nodes].astype(np.int32), prob.dir_vel.copy(), pairs, prob.n_steps,
+                   dict(prob.meta, node_permutation=new))
+
+
 CONFIGS = {
     1: lambda **kw: cube_block(**kw),
     2: lambda **kw: notched_beam(**kw),

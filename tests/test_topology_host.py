@@ -101,3 +101,30 @@ def test_nonlocal_support_matches_the_oracle(checker, tmp_path):
             assert np.array_equal(np.diff(ptr), np.ones(m))
     bad = subprocess.run([checker, path, "0", str(tmp_path / "x.bin")], capture_output=True, text=True, timeout=60)
     assert bad.returncode == 1 and "radius" in bad.stdout
+
+
+def test_rcm_renumbering_restores_a_narrow_band(checker, tmp_path):
+    """A notched beam whose node ids are randomly permuted has a band of the
+    order of n; reverse Cuthill-McKee renumbering brings it back within
+    twice the band of the generator's own lexicographic order (and keeps the
+    pattern, slot maps and the caller-to-internal mapping consistent)."""
+    prob = meshgen.notched_beam(24, 6, 6, h=0.01, notch_cells=1)
+    X, T = prob.X, prob.tets
+    n = X.shape[0]
+    e = meshgen.unique_edges(T)
+    band0 = int((e[:, 1] - e[:, 0]).max())
+    perm = np.random.default_rng(5).permutation(n)          # new id of each old node
+    Xp = np.empty_like(X)
+    Xp[perm] = X
+    Tp = perm[T].astype(np.int32)
+    ep = meshgen.unique_edges(Tp)
+    band_p = int((ep[:, 1] - ep[:, 0]).max())
+    path = str(tmp_path / "perm.bin")
+    write_mesh(path, Xp, Tp)
+    r = subprocess.run(
+        [checker, path, "--rcm"], capture_output=True, text=True, timeout=120,
+        env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
+    out = r.stdout.split()
+    assert r.returncode == 0 and out[:2] == ["bad", "0"], r.stdout + r.stderr[-2000:]
+    band_rcm = int(out[3])
+    assert band_p > 0.5 * n and band_rcm <= 2 * band0, (band0, band_p, band_rcm)

@@ -6,8 +6,13 @@
 // With two more arguments (radius, output path) it also builds the support of
 // the non-local damage criterion and writes it as int64 m, int64 entries,
 // (m+1) int64 ptr, entries int32 idx, entries f64 weights (tets in input order).
+// "--rcm" as the second argument renumbers the nodes in reverse Cuthill-McKee
+// order, checks the permutation and prints the largest |i - j| over the edges
+// (internal ids) after the count: "bad <count> band <b>".
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
+#include <string>
 #include <fstream>
 #include <vector>
 
@@ -23,9 +28,10 @@ int main(int argc, char** argv) {
   std::vector<int32_t> T(4 * (size_t)m);
   f.read(reinterpret_cast<char*>(X.data()), 8 * X.size());
   f.read(reinterpret_cast<char*>(T.data()), 4 * T.size());
+  const bool rcm = argc >= 3 && std::string(argv[2]) == "--rcm";
   gfem::Topology t;
   bool deg = false;
-  const std::string err = gfem::build_topology(X.data(), n, T.data(), m, 1000.0, &t, &deg);
+  const std::string err = gfem::build_topology(X.data(), n, T.data(), m, 1000.0, &t, &deg, rcm ? 1 : 0);
   if (!err.empty()) {
     printf("err %s\n", err.c_str());
     return 1;
@@ -63,6 +69,30 @@ int main(int argc, char** argv) {
     }
   for (int c : seen)
     if (c != 1) bad++;
+  // the numbering is a permutation and maps the caller's tets
+  {
+    std::vector<int> hit(n, 0);
+    for (int i = 0; i < n; ++i) {
+      if (t.perm_old[i] < 0 || t.perm_old[i] >= n || t.perm_new[t.perm_old[i]] != i) bad++;
+      else hit[t.perm_old[i]]++;
+    }
+    for (int c : hit)
+      if (c != 1) bad++;
+    for (int q = 0; q < m; ++q) {
+      int sa = 0, sb = 0;
+      for (int a = 0; a < 4; ++a) {
+        sa += t.tets[4 * (size_t)q + a];
+        sb += t.perm_new[T[4 * (size_t)q + a]];
+      }
+      if (sa != sb) bad++;
+    }
+  }
+  if (rcm) {
+    int band = 0;
+    for (int e = 0; e < t.ne; ++e) band = std::max(band, t.edges[2 * e + 1] - t.edges[2 * e]);
+    printf("bad %d band %d\n", bad, band);
+    return bad != 0;
+  }
   if (argc >= 4) {
     std::vector<int64_t> ptr;
     std::vector<int32_t> idx;
