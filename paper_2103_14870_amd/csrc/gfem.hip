@@ -88,6 +88,17 @@ struct TimeRec {
 
 int round_up8(int x) { return (x + 7) / 8 * 8; }
 
+// Grid cap of the PCG SpMV and G / G^T passes (their FP64 partials are
+// reduced by every workgroup of the consumer kernel).  Measured on the
+// 619,830-tet ellipsoid (threads per workgroup x cap, learned steps/s):
+// 256 x 1024: 282, 512 x 512: 295, 1024 x 256: 290, 512 x 1024: 260,
+// 512 x 256: 269, 384 x 512: 282, 768 x 256: 284 -- half the partials of
+// 256 x 1024 at the same four waves per SIMD.
+#ifndef GFEM_PCG_MAX_WG
+#define GFEM_PCG_MAX_WG 512
+#endif
+constexpr int kPcgMaxWorkgroups = GFEM_PCG_MAX_WG;
+
 }  // namespace
 
 struct gf_net {
@@ -107,7 +118,7 @@ struct gf_mesh {
   bool plastic = false;
   int dev = 0;
   hipStream_t own = nullptr, stream = nullptr;
-  int n = 0, m = 0, ne = 0, nb = 0, nbp = 0, Gv = 8, Gs = 8, Ga = 8, Gb = 8, Gp = 8;
+  int n = 0, m = 0, ne = 0, nb = 0, nbp = 0, Gv = 8, Gs = 8, Ga = 8, Gb = 8, Gp = 8, Gn = 8;
   double mu = 0, lam = 0, alpha_m1 = 0;
   Alloc al;
   // node data
@@ -623,14 +634,14 @@ void learned_precond(gf_mesh* M) {
   M->timed(3, -1, 0, [&] {
     const bool fresh = !M->net_cached || M->net_age >= every;
     if (fresh) {
-      gfem::net_forward(M->stream, M->net->P, M->netw, in, M->Gb);
+      gfem::net_forward(M->stream, M->net->P, M->netw, in, M->Gn);
       M->net_cached = true;
       M->net_age = 0;
     }
-    gfem::net_build_factor(M->stream, M->net->P, M->netw, in, M->Gb, false);
+    gfem::net_build_factor(M->stream, M->net->P, M->netw, in, M->Gn, false);
     // a row normalisation from an earlier A does not fit the current rows:
     // it is computed for every factor
-    if (M->fact_norm) gfem::net_normalise_factor(M->stream, M->netw, in, M->Gb, M->norm_ptr, M->norm_pairs);
+    if (M->fact_norm) gfem::net_normalise_factor(M->stream, M->netw, in, M->Gn, M->norm_ptr, M->norm_pairs);
   });
   ++M->net_age;
   M->check_launch();
@@ -1024,13 +1035,17 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     M->nbp = (T.nb + 63) / 64 * 64;
     M->Gv = std::min(kMaxPart, std::max(8, round_up8((T.n + gfem::kThreads - 1) / gfem::kThreads)));
     M->Gs = std::min(kMaxPart, std::max(8, round_up8((T.n * gfem::kRowLanes + gfem::kThreads - 1) / gfem::kThreads)));
-    // PCG SpMV grid: one 16-lane group per block row, capped at 1024
-    // workgroups (four resident per CU) so the update kernel reduces few partials.
-    M->Gb = std::min(1024, std::max(8, round_up8((T.n * gfem::kRowLanes + gfem::kSpmvThreads - 1) / gfem::kSpmvThreads)));
+    // PCG SpMV grid: one 16-lane group per block row, capped at
+    // kPcgMaxWorkgroups (two 512-thread workgroups per CU) so the consumer
+    // kernels reduce few partials.
+    M->Gb = std::min(kPcgMaxWorkgroups,
+                     std::max(8, round_up8((T.n * gfem::kRowLanes + gfem::kSpmvThreads - 1) / gfem::kSpmvThreads)));
     M->Ga = std::min(kMaxPart, std::max(8, round_up8((T.n + gfem::kVecThreads - 1) / gfem::kVecThreads)));
     // SpMV of the factorised path: the same cap (its partials are reduced by
     // every workgroup of the G pass, so more of them cost more than they save)
     M->Gp = M->Gb;
+    // network and factor kernels: 256-thread workgroups, one 16-lane group per row, at most 1024
+    M->Gn = std::min(1024, std::max(8, round_up8((T.n * gfem::kRowLanes + 255) / 256)));
     const double E = p.youngs, nu = p.poisson;
     const double mu0 = E / (2 * (1 + nu)), lam0 = E * nu / ((1 + nu) * (1 - 2 * nu));
     if (p.energy == GF_ENERGY_STVK) {
@@ -1710,8 +1725,8 @@ static gf_status net_train_eval(gf_net* net, gf_mesh* m, bool train, double lr, 
     m->solve_iters.clear();
     const gfem::NetInputs in = net_inputs(m, m->zeta[1 - m->zcur]);
     gfem::NetWork& w = m->netw;
-    gfem::net_forward(s, net->P, w, in, m->Gb);
-    gfem::net_build_factor(s, net->P, w, in, m->Gb, true);
+    gfem::net_forward(s, net->P, w, in, m->Gn);
+    gfem::net_build_factor(s, net->P, w, in, m->Gn, true);
     std::vector<d4> hv;
     if (probe) {
       hv.resize(m->n);
@@ -1725,16 +1740,16 @@ static gf_status net_train_eval(gf_net* net, gf_mesh* m, bool train, double lr, 
     // that t / N below is the Rayleigh quotient of X^k v
     const double Nd = 3.0 * m->n;
     for (int k = 0; k < net->power_steps; ++k) {
-      gfem::net_kaporin_u(s, w, in, m->Gb);
+      gfem::net_kaporin_u(s, w, in, m->Gn);
       gfem::launch_resid<float>(s, m->Gs, m->mat(), w.zero, w.u, w.wneg, m->part_a);
-      const int G = gfem::net_power_apply(s, w, in, m->Gb);
+      const int G = gfem::net_power_apply(s, w, in, m->Gn);
       m->check_launch();
       const double yy = read_partials(m, w.dpart, G);
       if (!(yy > 0.0) || !std::isfinite(yy))
         return fail(GF_ESTATE, std::string(who) + ": power step of the probe is not positive and finite");
       gfem::net_scale_probe(s, w, std::sqrt(Nd / yy));
     }
-    gfem::net_kaporin_u(s, w, in, m->Gb);
+    gfem::net_kaporin_u(s, w, in, m->Gn);
     gfem::launch_resid<float>(s, m->Gs, m->mat(), w.zero, w.u, w.wneg, m->part_a);
     const int G = gfem::net_kaporin_dots(s, net->P, w, in);
     m->check_launch();
@@ -1744,7 +1759,7 @@ static gf_status net_train_eval(gf_net* net, gf_mesh* m, bool train, double lr, 
     if (!(t > 0.0) || !std::isfinite(t) || !std::isfinite(ld))
       return fail(GF_ESTATE, std::string(who) + ": probe energy of the factor is not positive and finite");
     const double loss = std::log(t / N) - 2.0 * ld / N;
-    gfem::net_kaporin_backward(s, net->P, w, in, m->Gb, t);
+    gfem::net_kaporin_backward(s, net->P, w, in, m->Gn, t);
     m->check_launch();
     if (train) {
       ++net->adam_t;

@@ -28,7 +28,10 @@ using d4 = v4<double>;
 constexpr int kThreads = 256;     // 4 waves of 64
 constexpr int kMaxPart = 2048;    // max workgroups that leave a reduction partial
 constexpr int kRowLanes = 16;     // lanes cooperating on one block row in the row pass and the FP64 residual
-constexpr int kSpmvThreads = 256; // workgroup size of the PCG SpMV
+#ifndef GFEM_SPMV_THREADS
+#define GFEM_SPMV_THREADS 512
+#endif
+constexpr int kSpmvThreads = GFEM_SPMV_THREADS;  // workgroup size of the PCG SpMV and the G / G^T passes
 constexpr int kSpmvLanes = 8;    // lanes per block row in the two PCG SpMV kernels (two blocks each in flight)
 constexpr int kVecThreads = 256;  // workgroup size of the PCG vector kernels
 

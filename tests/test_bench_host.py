@@ -36,7 +36,7 @@ def test_counter_summary_calibrates_and_round_trips(tmp_path):
     assert bench.measured_traffic(str(out)) == pytest.approx(expect)
     assert "k_pcg_spmv_p<float, 256>" in text
     # a summary taken from other kernel sources is not reported
-    out.write_text(text.replace(text.split("kernels_hip_sha256 ")[1].split()[0], "0" * 64))
+    out.write_text(text.replace(text.split("kernel_sources_sha256 ")[1].split()[0], "0" * 64))
     assert bench.measured_traffic(str(out)) is None
 
 
