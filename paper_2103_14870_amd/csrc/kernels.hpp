@@ -32,7 +32,10 @@ constexpr int kRowLanes = 16;     // lanes cooperating on one block row in the r
 #define GFEM_SPMV_THREADS 512
 #endif
 constexpr int kSpmvThreads = GFEM_SPMV_THREADS;  // workgroup size of the PCG SpMV and the G / G^T passes
-constexpr int kSpmvLanes = 8;    // lanes per block row in the two PCG SpMV kernels (two blocks each in flight)
+#ifndef GFEM_SPMV_LANES
+#define GFEM_SPMV_LANES 8
+#endif
+constexpr int kSpmvLanes = GFEM_SPMV_LANES;  // lanes per block row in the two PCG SpMV kernels (two blocks each in flight)
 constexpr int kVecThreads = 256;  // workgroup size of the PCG vector kernels
 
 struct PcgCtl {
@@ -210,7 +213,10 @@ struct FactView {
   const __bf16* gu8;
   const uint4* gdv;
 };
-constexpr int kFactLanes = 4;  // lanes cooperating on one half row in the G and G^T passes
+#ifndef GFEM_FACT_LANES
+#define GFEM_FACT_LANES 4
+#endif
+constexpr int kFactLanes = GFEM_FACT_LANES;  // lanes cooperating on one half row in the G and G^T passes
 
 // Factorised-preconditioner PCG, three kernels per iteration (G and G^T
 // passes on Gb workgroups of kSpmvThreads, the SpMV on its own grid of Gp,
