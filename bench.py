@@ -189,6 +189,19 @@ def cpu_baseline(prob, n_threads=1):
                        f"(FP64 NumPy/SciPy oracle, block-Jacobi PCG, {iters} iterations, {dt:.1f} s)")
 
 
+def host_cpu_model():
+    """The host CPU's model name (Linux), or the platform's processor string."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
 def timed_steps(m, steps, warmup):
     """The K timed steps are one gf_step(K) call (one host round trip per
     step fewer than K calls of one step); the stats are summed over them."""
@@ -442,6 +455,7 @@ def main():
         log("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(prob)
         out["cpu_baseline"]["host_cpus"] = os.cpu_count()
+        out["cpu_baseline"]["cpu_model"] = host_cpu_model()
     print(json.dumps(out), flush=True)
 
 
