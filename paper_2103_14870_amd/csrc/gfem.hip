@@ -99,6 +99,13 @@ int round_up8(int x) { return (x + 7) / 8 * 8; }
 #endif
 constexpr int kPcgMaxWorkgroups = GFEM_PCG_MAX_WG;
 
+// Each inner (working-precision) PCG solve aims at this fraction of the
+// outer FP64 tolerance relative to its right-hand side.
+#ifndef GFEM_INNER_TOL
+#define GFEM_INNER_TOL 0.5
+#endif
+constexpr double kInnerTol = GFEM_INNER_TOL;
+
 }  // namespace
 
 struct gf_net {
@@ -430,7 +437,8 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
       }
       if (outer >= 30 || res.inner >= budget || !std::isfinite(rr)) break;
     }
-    const double rel_in = outer == 0 ? std::max(0.5 * tol, floor_rel) : std::max(0.5 * tol * std::sqrt(bb / rr), floor_rel);
+    const double rel_in = outer == 0 ? std::max(kInnerTol * tol, floor_rel)
+                                     : std::max(kInnerTol * tol * std::sqrt(bb / rr), floor_rel);
     const int solve_id = (int)M->solve_iters.size();
     // (the control block is reset by the solve's first kernel)
     M->timed(5, -1, 0, [&] {
