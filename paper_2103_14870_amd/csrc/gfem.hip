@@ -311,6 +311,22 @@ void alloc_precision(gf_mesh* M) {
   M->vy = M->al.get<v4<T>>(n);
 }
 
+// Damage pass at the current displacement: counters reset, labels of the
+// current buffer OR-ed with the new breaks into the spare one (Eq. 20-21,
+// local or non-local support), near-threshold edges listed.
+void damage_pass(gf_mesh* M) {
+  hipStream_t s = M->stream;
+  const int zi = M->zcur, zo = 1 - M->zcur;
+  hchk(hipMemsetAsync(M->ctr, 0, sizeof(gfem::Counters), s), "hipMemsetAsync");
+  if (M->nl_ptr)
+    gfem::launch_damage_nonlocal(s, M->m, M->ne, M->tets, M->X, M->U, M->nl_ptr, M->nl_idx, M->nl_w, M->nl_E,
+                                 M->nl_Eavg, M->edges, M->edge_ptr, M->edge_slot, M->zeta[zi], M->zeta[zo],
+                                 M->p.damage_strain, M->ctr, M->near_ids);
+  else
+    gfem::launch_damage(s, M->ne, M->edges, M->X, M->U, M->edge_S, M->zeta[zi], M->zeta[zo], M->p.damage_strain,
+                        M->ctr, M->near_ids);
+}
+
 // What one assembly does (defaults: a timestep's system).
 struct AsmOpt {
   bool damage = true;      // damage pass into the spare label buffer (counters reset first)
@@ -331,18 +347,7 @@ void assemble(gf_mesh* M, const AsmOpt& o) {
   const bool flow = o.flow;
   d4* f_out = o.f_out;
   const int zi = M->zcur, zo = 1 - M->zcur;
-  if (o.damage) {
-  hchk(hipMemsetAsync(M->ctr, 0, sizeof(gfem::Counters), s), "hipMemsetAsync");
-  M->timed(0, -1, 0, [&] {
-    if (M->nl_ptr)
-      gfem::launch_damage_nonlocal(s, M->m, M->ne, M->tets, M->X, M->U, M->nl_ptr, M->nl_idx, M->nl_w, M->nl_E,
-                                   M->nl_Eavg, M->edges, M->edge_ptr, M->edge_slot, M->zeta[zi], M->zeta[zo],
-                                   M->p.damage_strain, M->ctr, M->near_ids);
-    else
-      gfem::launch_damage(s, M->ne, M->edges, M->X, M->U, M->edge_S, M->zeta[zi], M->zeta[zo], M->p.damage_strain,
-                          M->ctr, M->near_ids);
-  });
-  }
+  if (o.damage) M->timed(0, -1, 0, [&] { damage_pass(M); });
   gfem::ElemConst ec{M->mu, M->lam, M->alpha_m1, M->p.energy};
   const T* pl = nullptr;
   if (M->plastic) {
@@ -858,15 +863,7 @@ gf_status qs_step_impl(gf_mesh* M, const QsBufs& B, int n_steps, double rtol, in
   for (int step = 0; step < n_steps; ++step) {
     hchk(hipMemcpyAsync(B.U0, M->U, sizeof(d4) * M->n, hipMemcpyDeviceToDevice, s), "D2D");
     // 1. damage and plastic flow at x_n
-    hchk(hipMemsetAsync(M->ctr, 0, sizeof(gfem::Counters), s), "hipMemsetAsync");
-    const int zi = M->zcur, zo = 1 - M->zcur;
-    if (M->nl_ptr)
-      gfem::launch_damage_nonlocal(s, M->m, M->ne, M->tets, M->X, M->U, M->nl_ptr, M->nl_idx, M->nl_w, M->nl_E,
-                                   M->nl_Eavg, M->edges, M->edge_ptr, M->edge_slot, M->zeta[zi], M->zeta[zo],
-                                   M->p.damage_strain, M->ctr, M->near_ids);
-    else
-      gfem::launch_damage(s, M->ne, M->edges, M->X, M->U, M->edge_S, M->zeta[zi], M->zeta[zo], M->p.damage_strain,
-                          M->ctr, M->near_ids);
+    damage_pass(M);
     const T* pl = nullptr;
     if (M->plastic) {
       gfem::launch_plastic<T>(s, M->m, M->tets, M->X, M->U, static_cast<const T*>(M->pl[M->plcur]),

@@ -96,7 +96,8 @@ def test_flat_and_inverted_tets_match_oracle(prec, seed):
     ean = block_rowrel(bi, bj, blocks, so.A, 1e-3)
     eb, ebn = rel(rhs.ravel(), so.b), rowrel(rhs, so.b.reshape(-1, 3), 1e-3)
     say(f"  small-J tets {int(el.small.sum())}  forces {ef:.2e} / node {efn:.2e}  A {ea:.2e} / block {ean:.2e}  "
-        f"b {eb:.2e} / node {ebn:.2e}  degenerate count {s['degenerate_tets']} (oracle {so.stats['degenerate_tets']})")
+        f"b {eb:.2e} / node {ebn:.2e}  degenerate count {s['degenerate_tets']} (oracle {so.stats['degenerate_tets']}), "
+        f"chi = 0 tets {s['chi_zero_tets']} (oracle {so.stats['chi_zero_tets']})")
     # The library forms nodal forces from per-edge force weights (Eq. 12); on a
     # tet with small J the weights of the volume term grow as 1/J while their
     # sum stays finite, so FP64 rounding of the reconstruction is about
@@ -112,6 +113,7 @@ def test_flat_and_inverted_tets_match_oracle(prec, seed):
     assert ef <= tol_f and eb <= tol_f and ea <= tol
     assert efn <= tol_f_row and ebn <= tol_f_row and ean <= tol_row
     assert s["degenerate_tets"] == so.stats["degenerate_tets"]
+    assert s["chi_zero_tets"] == so.stats["chi_zero_tets"] and so.stats["chi_zero_tets"] > 0
 
 
 @pytest.mark.parametrize("prec,tol,tol_row", [("fp64", 1e-10, 1e-8), ("split", 1e-5, 1e-3)])
