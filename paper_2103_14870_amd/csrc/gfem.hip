@@ -160,6 +160,10 @@ struct gf_mesh {
   double* vis_xyz = nullptr;
   uint8_t* vis_group = nullptr;
   int32_t *edge_ptr = nullptr, *edge_slot = nullptr, *blk_ij = nullptr, *blk_ji = nullptr;
+  // workgroup-staged assembly tables (topo.hpp) and the number of partial records
+  int32_t *part_base = nullptr, *part_cptr = nullptr, *edge_pptr = nullptr, *edge_part = nullptr;
+  uint16_t* part_slot = nullptr;
+  int np = 0;
   void* edge_w = nullptr;
   // block matrix
   int32_t *row_ptr = nullptr, *col = nullptr, *diag_blk = nullptr, *blk_edge = nullptr;
@@ -294,7 +298,7 @@ template <typename T>
 void alloc_precision(gf_mesh* M) {
   const int n = M->n, m = M->m;
   M->val = M->al.get<T>((size_t)9 * M->nbp);
-  M->contrib = M->al.get<gfem::Rec<T>>((size_t)6 * m);
+  M->contrib = M->al.get<gfem::Rec<T>>((size_t)M->np);
   M->edge_w = M->al.get<double>(M->ne);
   M->binv = M->al.get<T>((size_t)6 * n);
   if (M->plastic) {
@@ -362,15 +366,15 @@ void assemble(gf_mesh* M, const AsmOpt& o) {
   }
   M->timed(1, -1, 0, [&] {
     gfem::launch_element<T>(s, M->m, M->tets, M->tet_edge, M->flip, M->X, M->U, M->zeta[o.next_state ? zo : zi], pl,
-                            static_cast<const T*>(o.chi_in), static_cast<T*>(o.chi_out), ec,
-                            static_cast<gfem::Rec<T>*>(M->contrib), M->ctr);
+                            static_cast<const T*>(o.chi_in), static_cast<T*>(o.chi_out), ec, M->part_base,
+                            M->part_cptr, M->part_slot, static_cast<gfem::Rec<T>*>(M->contrib), M->ctr);
   });
   const double dt = M->p.dt;
   const double ra = o.quasi_static ? 0.0 : M->p.rayleigh_alpha;
   const double mass_fac = 1.0 + dt * ra;
   const double stiff_fac = dt * dt + (o.quasi_static ? 0.0 : dt * M->p.rayleigh_beta);
   M->timed(2, -1, 0, [&] {
-    gfem::launch_edge<T>(s, M->ne, M->edge_ptr, M->edge_slot, static_cast<const gfem::Rec<T>*>(M->contrib),
+    gfem::launch_edge<T>(s, M->ne, M->edge_pptr, M->edge_part, static_cast<const gfem::Rec<T>*>(M->contrib),
                          M->edge_mass, mass_fac, stiff_fac, M->blk_ij, M->blk_ji, static_cast<T*>(M->val), M->nbp,
                          static_cast<double*>(M->edge_w));
   });
@@ -666,7 +670,7 @@ void ensure_esc(gf_mesh* M) {
   const size_t n = M->n, m = M->m;
   gf_mesh::PrecBufs& b = M->esc;
   b.val = M->al.get<double>(9 * (size_t)M->nbp);
-  b.contrib = M->al.get<gfem::Rec<double>>(6 * m);
+  b.contrib = M->al.get<gfem::Rec<double>>((size_t)M->np);
   b.edge_w = M->al.get<double>(M->ne);
   b.binv = M->al.get<double>(6 * n);
   b.pl[0] = M->plastic ? M->al.get<double>(6 * m) : nullptr;
@@ -1101,6 +1105,12 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     }
     M->edge_ptr = upload(M, T.edge_ptr);
     M->edge_slot = upload(M, T.edge_slot);
+    M->part_base = upload(M, T.part_base);
+    M->part_cptr = upload(M, T.part_cptr);
+    M->part_slot = upload(M, T.part_slot);
+    M->edge_pptr = upload(M, T.edge_pptr);
+    M->edge_part = upload(M, T.edge_part);
+    M->np = (int)T.edge_part.size();
     M->blk_ij = upload(M, T.blk_ij);
     M->blk_ji = upload(M, T.blk_ji);
     M->row_ptr = upload(M, T.row_ptr);

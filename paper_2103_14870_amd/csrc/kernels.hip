@@ -33,10 +33,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // Per-workgroup event counts: one ballot per wave, one atomic per counter per
-// workgroup, into slot (workgroup % kCtrSlots).  Every thread must call it.
-template <int NC>
+// workgroup, into slot (workgroup % kCtrSlots).  Every thread of an
+// NT-thread workgroup must call it.
+template <int NC, int NT = kThreads>
 __device__ __forceinline__ void block_counts(Counters* ctr, int first_field, const bool (&pred)[NC]) {
-  __shared__ int sc[kThreads / 64][NC];
+  __shared__ int sc[NT / 64][NC];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -47,7 +48,7 @@ __device__ __forceinline__ void block_counts(Counters* ctr, int first_field, con
   if (threadIdx.x < NC) {
     int s = 0;
 #pragma unroll
-    for (int i = 0; i < kThreads / 64; ++i) s += sc[i][threadIdx.x];
+    for (int i = 0; i < NT / 64; ++i) s += sc[i][threadIdx.x];
     if (s) atomicAdd(&ctr->v[(blockIdx.x % kCtrSlots) * kCtrStride + first_field + threadIdx.x], s);
   }
 }
@@ -451,15 +452,18 @@ constexpr double kJMin = 0.05;
 // lam/4 (I_C - 3) c_k + mu/2 tr(E_k A dGe A), edge Hessian
 // lam/4 c c^T + mu/2 tr(E_k A E_l A), PSD without clamping; no J enters).
 template <typename T, int EN>
-__global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restrict__ tets,
+__global__ __launch_bounds__(kElemTets) void k_element(int m, const int4* __restrict__ tets,
                                                       const int32_t* __restrict__ tet_edge,
                                                       const uint8_t* __restrict__ flip,
                                                       const d4* __restrict__ X, const d4* __restrict__ U,
                                                       const uint8_t* __restrict__ zeta, const T* __restrict__ pl,
                                                       const T* __restrict__ chi_in, T* __restrict__ chi_out,
-                                                      ElemConst cst, Rec<T>* __restrict__ contrib,
-                                                      Counters* ctr) {
-  const int t0 = blockIdx.x * kThreads + threadIdx.x;
+                                                      ElemConst cst, const int32_t* __restrict__ part_base,
+                                                      const int32_t* __restrict__ part_cptr,
+                                                      const uint16_t* __restrict__ part_slot,
+                                                      Rec<T>* __restrict__ contrib, Counters* ctr) {
+  __shared__ Rec<T> lrec[kElemTets * 6];
+  const int t0 = blockIdx.x * kElemTets + threadIdx.x;
   const bool act = t0 < m;
   const int t = act ? t0 : m - 1;
   const T mu = (T)cst.mu, lam = (T)cst.lam, am1 = (T)cst.alpha_m1;
@@ -787,107 +791,122 @@ __global__ __launch_bounds__(kThreads) void k_element(int m, const int4* __restr
 
   {
     const bool pr[2] = {act && chi == T(0), act && small};
-    block_counts<2>(ctr, kChiZero, pr);
+    block_counts<2, kElemTets>(ctr, kChiZero, pr);
   }
-  if (!act) return;
-  if (chi_out) chi_out[t] = chi;
+  if (act && chi_out) chi_out[t] = chi;
 
-  if (chi == T(0)) {
+  // This tet's six records, staged in LDS (zero when inactive or chi = 0).
+  Rec<T>* lr = lrec + 6 * threadIdx.x;
+  if (!act || chi == T(0)) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      Rec<T> r;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) r.b[c] = T(0);
-      r.w = 0.0;
-      contrib[(size_t)k * m + t] = r;
+      for (int c = 0; c < 9; ++c) lr[k].b[c] = T(0);
+      lr[k].w = 0.0;
     }
-    return;
-  }
-
-  // Clamped edge Hessian: H = A1 c c^T + A2 v v^T + A3 M, M_kl = tr(G^-1 E_k G^-1 E_l)
-  // = (Gam_ac Gam_bd + Gam_ad Gam_bc)/2; each coefficient clamped at >= 0.
-  // Small |J|: only the I_C term (A1); the volume term adds lam dJ dJ^T.
-  // StVK: A1 = lam/4, A2 = 0, A3 = mu/2 with M_kl = tr(E_k A E_l A) (Gam of A).
-  const T Vc = vol * chi;
-  constexpr bool kSt = EN == kEnergyStVK;
-  const T A1 = kSt ? T(0.25) * lam : T(0.5) * mu / (IC1 * IC1);
-  const T JmA = delta - am1;  // J - alpha
-  const T A2 = (kSt || small) ? T(0) : fmax(T(0.25) * lam * (T(2) * J - T(1) - am1) * J, T(0));
-  const T A3 = kSt ? T(0.5) * mu : (small ? T(0) : fmax(T(-0.5) * lam * JmA * J, T(0)));
-  T H[6][6];
+  } else {
+    // Clamped edge Hessian: H = A1 c c^T + A2 v v^T + A3 M, M_kl = tr(G^-1 E_k G^-1 E_l)
+    // = (Gam_ac Gam_bd + Gam_ad Gam_bc)/2; each coefficient clamped at >= 0.
+    // Small |J|: only the I_C term (A1); the volume term adds lam dJ dJ^T.
+    // StVK: A1 = lam/4, A2 = 0, A3 = mu/2 with M_kl = tr(E_k A E_l A) (Gam of A).
+    const T Vc = vol * chi;
+    constexpr bool kSt = EN == kEnergyStVK;
+    const T A1 = kSt ? T(0.25) * lam : T(0.5) * mu / (IC1 * IC1);
+    const T JmA = delta - am1;  // J - alpha
+    const T A2 = (kSt || small) ? T(0) : fmax(T(0.25) * lam * (T(2) * J - T(1) - am1) * J, T(0));
+    const T A3 = kSt ? T(0.5) * mu : (small ? T(0) : fmax(T(-0.5) * lam * JmA * J, T(0)));
+    T H[6][6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 6; ++k)
 #pragma unroll
-    for (int l = k; l < 6; ++l) {
-      const int a = EA(k), b = EB(k), c = EA(l), d = EB(l);
-      T hkl = A1 * cc[k] * cc[l];
-      if (kSt) {
-        hkl += A3 * T(0.5) * (GamP[a][c] * GamP[b][d] + GamP[a][d] * GamP[b][c]);
-      } else if (!small) {
-        const T Mkl = T(0.5) * (Gam[a][c] * Gam[b][d] + Gam[a][d] * Gam[b][c]);
-        hkl += A2 * vv[k] * vv[l] + A3 * Mkl;
-      }
-      H[k][l] = H[l][k] = hkl;
-    }
-
-  // Stiffness (Eq. 10, 33): K(a,b) = V chi [ sum_{p at a, q at b} H_pq ds_p/dx_a ds_q/dx_b^T
-  //                                          - 2 max(g_ab, 0) I ],  ds_p/dx = +-2 d_p.
-  // Node incidence: (edge, sign) with sign +1 when the node is the edge's head.
-  constexpr int inc_e[4][3] = {{0, 1, 2}, {0, 3, 4}, {1, 3, 5}, {2, 4, 5}};
-  constexpr int inc_s[4][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {1, 1, 1}};
-  const uint8_t fl = flip[t];
-  const double Vcd = (double)vol * (double)chi;
-#pragma unroll
-  for (int b = 1; b < 4; ++b) {
-    T Tb[6][3];
-#pragma unroll
-    for (int p = 0; p < 6; ++p)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        T acc = 0;
-#pragma unroll
-        for (int jq = 0; jq < 3; ++jq) {
-          const int q = inc_e[b][jq];
-          acc += (T)inc_s[b][jq] * H[p][q] * dcur[q][d];
+      for (int l = k; l < 6; ++l) {
+        const int a = EA(k), b = EB(k), c = EA(l), d = EB(l);
+        T hkl = A1 * cc[k] * cc[l];
+        if (kSt) {
+          hkl += A3 * T(0.5) * (GamP[a][c] * GamP[b][d] + GamP[a][d] * GamP[b][c]);
+        } else if (!small) {
+          const T Mkl = T(0.5) * (Gam[a][c] * Gam[b][d] + Gam[a][d] * Gam[b][c]);
+          hkl += A2 * vv[k] * vv[l] + A3 * Mkl;
         }
-        Tb[p][d] = acc;
+        H[k][l] = H[l][k] = hkl;
       }
+
+    // Stiffness (Eq. 10, 33): K(a,b) = V chi [ sum_{p at a, q at b} H_pq ds_p/dx_a ds_q/dx_b^T
+    //                                          - 2 max(g_ab, 0) I ],  ds_p/dx = +-2 d_p.
+    // Node incidence: (edge, sign) with sign +1 when the node is the edge's head.
+    constexpr int inc_e[4][3] = {{0, 1, 2}, {0, 3, 4}, {1, 3, 5}, {2, 4, 5}};
+    constexpr int inc_s[4][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {1, 1, 1}};
+    const uint8_t fl = flip[t];
+    const double Vcd = (double)vol * (double)chi;
 #pragma unroll
-    for (int a = 0; a < b; ++a) {
-      const int k = (a == 0) ? (b - 1) : (a == 1 ? (b == 2 ? 3 : 4) : 5);
-      T Kab[3][3];
+    for (int b = 1; b < 4; ++b) {
+      T Tb[6][3];
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+      for (int p = 0; p < 6; ++p)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int d = 0; d < 3; ++d) {
           T acc = 0;
 #pragma unroll
-          for (int jp = 0; jp < 3; ++jp) {
-            const int p = inc_e[a][jp];
-            acc += (T)inc_s[a][jp] * dcur[p][r] * Tb[p][c];
+          for (int jq = 0; jq < 3; ++jq) {
+            const int q = inc_e[b][jq];
+            acc += (T)inc_s[b][jq] * H[p][q] * dcur[q][d];
           }
-          Kab[r][c] = T(4) * Vc * acc;
+          Tb[p][d] = acc;
         }
-      const T lap = T(2) * Vc * fmax(g[k], T(0));
-      Kab[0][0] -= lap;
-      Kab[1][1] -= lap;
-      Kab[2][2] -= lap;
-      if (cof) {
-        const T kJ = (T)(Vcd * cst.lam);
+#pragma unroll
+      for (int a = 0; a < b; ++a) {
+        const int k = (a == 0) ? (b - 1) : (a == 1 ? (b == 2 ? 3 : 4) : 5);
+        T Kab[3][3];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) Kab[r][c] += kJ * (T)(gJd[a][r] * gJd[b][c]);
+          for (int c = 0; c < 3; ++c) {
+            T acc = 0;
+#pragma unroll
+            for (int jp = 0; jp < 3; ++jp) {
+              const int p = inc_e[a][jp];
+              acc += (T)inc_s[a][jp] * dcur[p][r] * Tb[p][c];
+            }
+            Kab[r][c] = T(4) * Vc * acc;
+          }
+        const T lap = T(2) * Vc * fmax(g[k], T(0));
+        Kab[0][0] -= lap;
+        Kab[1][1] -= lap;
+        Kab[2][2] -= lap;
+        if (cof) {
+          const T kJ = (T)(Vcd * cst.lam);
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Kab[r][c] += kJ * (T)(gJd[a][r] * gJd[b][c]);
+        }
+        const bool tr = (fl >> k) & 1;
+        Rec<T> rec;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) rec.b[3 * r + c] = tr ? Kab[c][r] : Kab[r][c];
+        rec.w = 2.0 * Vcd * ((double)g[k] + wJ[k]);
+        lr[k] = rec;
       }
-      const bool tr = (fl >> k) & 1;
-      Rec<T> rec;
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) rec.b[3 * r + c] = tr ? Kab[c][r] : Kab[r][c];
-      rec.w = 2.0 * Vcd * ((double)g[k] + wJ[k]);
-      contrib[(size_t)k * m + t] = rec;
     }
+  }
+  __syncthreads();
+  // One partial record per edge the workgroup touches: its tets' records
+  // summed in the fixed order of the host-built tables.
+  const int p1 = part_base[blockIdx.x + 1];
+  for (int p = part_base[blockIdx.x] + threadIdx.x; p < p1; p += kElemTets) {
+    Rec<T> acc;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc.b[c] = T(0);
+    acc.w = 0.0;
+    for (int q = part_cptr[p], q1 = part_cptr[p + 1]; q < q1; ++q) {
+      const Rec<T>& r = lrec[part_slot[q]];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc.b[c] += r.b[c];
+      acc.w += r.w;
+    }
+    contrib[p] = acc;
   }
 }
 
@@ -1102,13 +1121,14 @@ __global__ __launch_bounds__(kThreads) void k_visual(int t0, int cnt, int m, con
 
 // ---------------------------------------------------------------- edge pass
 
-// One thread per edge: sum the tets' contributions in slot order (fixed), add
-// the consistent mass, and write A_ij and A_ji = A_ij^T into the block matrix:
+// One thread per edge: sum the edge's partial records (one per element-pass
+// workgroup that touched it) in ascending order (fixed), add the consistent
+// mass, and write A_ij and A_ji = A_ij^T into the block matrix:
 // A_ij = m_ij (1 + dt alpha) I + (dt^2 + dt beta) K_ij; the force weights are
 // summed in FP64.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_edge(int ne, const int32_t* __restrict__ edge_ptr,
-                                                   const int32_t* __restrict__ edge_slot,
+__global__ __launch_bounds__(kThreads) void k_edge(int ne, const int32_t* __restrict__ edge_pptr,
+                                                   const int32_t* __restrict__ edge_part,
                                                    const Rec<T>* __restrict__ contrib,
                                                    const double* __restrict__ edge_mass, double mass_fac,
                                                    double stiff_fac, const int32_t* __restrict__ blk_ij,
@@ -1120,9 +1140,9 @@ __global__ __launch_bounds__(kThreads) void k_edge(int ne, const int32_t* __rest
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = 0;
   double accw = 0.0;
-  const int s0 = edge_ptr[e], s1 = edge_ptr[e + 1];
+  const int s0 = edge_pptr[e], s1 = edge_pptr[e + 1];
   for (int s = s0; s < s1; ++s) {
-    const Rec<T> r = contrib[edge_slot[s]];
+    const Rec<T> r = contrib[edge_part[s]];
 #pragma unroll
     for (int c = 0; c < 9; ++c) acc[c] += r.b[c];
     accw += r.w;
@@ -2014,20 +2034,24 @@ void launch_plastic(hipStream_t s, int m, const int4* tets, const d4* X, const d
 template <typename T>
 void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_edge, const uint8_t* flip,
                     const d4* X, const d4* U, const uint8_t* zeta, const T* pl, const T* chi_in, T* chi_out,
-                    ElemConst c, Rec<T>* contrib, Counters* ctr) {
+                    ElemConst c, const int32_t* part_base, const int32_t* part_cptr, const uint16_t* part_slot,
+                    Rec<T>* contrib, Counters* ctr) {
+  if (m <= 0) return;
+  const int G = (m + kElemTets - 1) / kElemTets;
   if (c.energy == kEnergyStVK)
-    k_element<T, kEnergyStVK><<<blocks_for(m), kThreads, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta, pl, chi_in,
-                                                                  chi_out, c, contrib, ctr);
+    k_element<T, kEnergyStVK><<<G, kElemTets, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta, pl, chi_in, chi_out, c,
+                                                       part_base, part_cptr, part_slot, contrib, ctr);
   else
-    k_element<T, kEnergyStableNeoHookean><<<blocks_for(m), kThreads, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta,
-                                                                             pl, chi_in, chi_out, c, contrib, ctr);
+    k_element<T, kEnergyStableNeoHookean><<<G, kElemTets, 0, s>>>(m, tets, tet_edge, flip, X, U, zeta, pl, chi_in,
+                                                                  chi_out, c, part_base, part_cptr, part_slot,
+                                                                  contrib, ctr);
 }
 
 template <typename T>
-void launch_edge(hipStream_t s, int ne, const int32_t* edge_ptr, const int32_t* edge_slot,
+void launch_edge(hipStream_t s, int ne, const int32_t* edge_pptr, const int32_t* edge_part,
                  const Rec<T>* contrib, const double* edge_mass, double mass_fac, double stiff_fac,
                  const int32_t* blk_ij, const int32_t* blk_ji, T* val, int nbp, double* edge_w) {
-  k_edge<T><<<blocks_for(ne), kThreads, 0, s>>>(ne, edge_ptr, edge_slot, contrib, edge_mass, mass_fac,
+  k_edge<T><<<blocks_for(ne), kThreads, 0, s>>>(ne, edge_pptr, edge_part, contrib, edge_mass, mass_fac,
                                                stiff_fac, blk_ij, blk_ji, val, nbp, edge_w);
 }
 
@@ -2179,8 +2203,8 @@ void launch_visual(hipStream_t s, int t0, int cnt, int m, const int4* tets, cons
   template void launch_energy<T>(hipStream_t, int, int, const int4*, const d4*, const d4*, const d4*, double, \
                                  const T*, const T*, ElemConst, double*);                                    \
   template void launch_element<T>(hipStream_t, int, const int4*, const int32_t*, const uint8_t*, const d4*,  \
-                                  const d4*, const uint8_t*, const T*, const T*, T*, ElemConst, Rec<T>*,     \
-                                  Counters*);                                                                \
+                                  const d4*, const uint8_t*, const T*, const T*, T*, ElemConst,              \
+                                  const int32_t*, const int32_t*, const uint16_t*, Rec<T>*, Counters*);      \
   template void launch_edge<T>(hipStream_t, int, const int32_t*, const int32_t*, const Rec<T>*,              \
                                const double*, double, double, const int32_t*, const int32_t*, T*, int,       \
                                double*);                                                                     \

@@ -5,10 +5,11 @@
 //   tets           : int4 node ids; tet_edge SoA [6][m]; flip bits [m]
 //   block matrix   : BSR 3x3, values SoA [9][nbp] (component-major, so the
 //                    lanes of a wave read consecutive blocks with unit stride)
-//   contributions  : [6][m] records (9 block entries in T + one FP64 force
-//                    weight per tet edge, 48 B in FP32), written tet-major by
-//                    the element pass and read as whole records per edge by
-//                    the edge pass
+//   contributions  : partial records (9 block entries in T + one FP64 force
+//                    weight, 48 B in FP32), one per (element-pass workgroup,
+//                    edge it touches): each workgroup sums its tets'
+//                    contributions per edge in LDS first; the edge pass reads
+//                    whole records, about two per edge
 // No floating-point atomics anywhere: every sum has a fixed order, so a step
 // is bitwise reproducible.
 #pragma once
@@ -16,6 +17,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+
+#include "topo.hpp"
 
 namespace gfem {
 
@@ -118,11 +121,14 @@ void launch_plastic(hipStream_t s, int m, const int4* tets, const d4* X, const d
 
 // pl: plastic rest-shape offsets [6][m], or null.  chi_in (nullable): per-tet
 // energy fractions to use instead of evaluating Eq. 25; chi_out (nullable):
-// receives the fractions used.
+// receives the fractions used.  kElemTets tets per workgroup; each
+// workgroup sums its tets' records per edge in LDS and writes one partial
+// record per edge it touches (part_* tables of the topology) into contrib.
 template <typename T>
 void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_edge,
                     const uint8_t* flip, const d4* X, const d4* U, const uint8_t* zeta,
-                    const T* pl, const T* chi_in, T* chi_out, ElemConst c, Rec<T>* contrib, Counters* ctr);
+                    const T* pl, const T* chi_in, T* chi_out, ElemConst c, const int32_t* part_base,
+                    const int32_t* part_cptr, const uint16_t* part_slot, Rec<T>* contrib, Counters* ctr);
 
 // Split visualisation mesh (Sec. 4.1) of tets t0 .. t0 + cnt - 1: per tet and
 // caller-order corner a the 8 sub-cell vertices (FP64 x, y, z) [corner, edge
@@ -151,8 +157,9 @@ void launch_zero(hipStream_t s, int n, d4* x);
 // U += dt * dvel on the prescribed nodes (dflag != 0).
 void launch_move_prescribed(hipStream_t s, int n, const uint8_t* dflag, const d4* dvel, double dt, d4* U);
 
+// edge_pptr / edge_part: each edge's partial records (ascending).
 template <typename T>
-void launch_edge(hipStream_t s, int ne, const int32_t* edge_ptr, const int32_t* edge_slot,
+void launch_edge(hipStream_t s, int ne, const int32_t* edge_pptr, const int32_t* edge_part,
                  const Rec<T>* contrib, const double* edge_mass, double mass_fac, double stiff_fac,
                  const int32_t* blk_ij, const int32_t* blk_ji, T* val, int nbp, double* edge_w);
 

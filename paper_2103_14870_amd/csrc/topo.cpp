@@ -314,6 +314,40 @@ std::string build_topology(const double* xyz, int n, const int32_t* tets_in, int
   for (int t = 0; t < m; ++t)
     for (int a = 0; a < 4; ++a) T.lumped[T.tets[4 * (size_t)t + a]] += density * T.vol[t] / 4.0;
 
+  // Workgroup-staged assembly tables (see topo.hpp): per workgroup of
+  // kElemTets tets, its (edge, tet, local edge) contributions sorted by edge,
+  // then tet, then local edge; one partial record per distinct edge.
+  {
+    const int nwg = (m + kElemTets - 1) / kElemTets;
+    T.part_base.assign(nwg + 1, 0);
+    T.part_cptr.assign(1, 0);
+    T.part_slot.clear();
+    T.part_slot.reserve(6 * (size_t)m);
+    std::vector<int32_t> part_edge;
+    std::vector<std::pair<int32_t, int32_t>> loc;  // (edge, local slot)
+    for (int w = 0; w < nwg; ++w) {
+      const int t0 = w * kElemTets, t1 = std::min(m, t0 + kElemTets);
+      loc.clear();
+      for (int t = t0; t < t1; ++t)
+        for (int k = 0; k < 6; ++k) loc.push_back({T.tet_edge[(size_t)k * m + t], 6 * (t - t0) + k});
+      std::sort(loc.begin(), loc.end());
+      for (size_t q = 0; q < loc.size(); ++q) {
+        if (q > 0 && loc[q].first != loc[q - 1].first) T.part_cptr.push_back((int32_t)T.part_slot.size());
+        if (q == 0 || loc[q].first != loc[q - 1].first) part_edge.push_back(loc[q].first);
+        T.part_slot.push_back((uint16_t)loc[q].second);
+      }
+      if (!loc.empty()) T.part_cptr.push_back((int32_t)T.part_slot.size());
+      T.part_base[w + 1] = (int32_t)part_edge.size();
+    }
+    const int np = (int)part_edge.size();
+    T.edge_pptr.assign(T.ne + 1, 0);
+    for (int p = 0; p < np; ++p) ++T.edge_pptr[part_edge[p] + 1];
+    for (int e = 0; e < T.ne; ++e) T.edge_pptr[e + 1] += T.edge_pptr[e];
+    T.edge_part.assign(np, 0);
+    std::vector<int32_t> fillp(T.edge_pptr.begin(), T.edge_pptr.end() - 1);
+    for (int p = 0; p < np; ++p) T.edge_part[fillp[part_edge[p]]++] = p;
+  }
+
   // Canonical edge order (caller ids, i < j, lexicographic).
   std::vector<std::pair<std::pair<int32_t, int32_t>, int32_t>> ce(T.ne);
   for (int e = 0; e < T.ne; ++e) {

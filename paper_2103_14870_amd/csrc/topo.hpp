@@ -16,6 +16,10 @@ namespace gfem {
 constexpr int kEdgeA[6] = {0, 0, 0, 1, 1, 2};
 constexpr int kEdgeB[6] = {1, 2, 3, 2, 3, 3};
 
+// Tets per workgroup of the element pass (its contributions are summed per
+// edge in LDS before they go to memory).
+constexpr int kElemTets = 128;
+
 struct Topology {
   int n = 0;   // nodes
   int m = 0;   // tets
@@ -41,6 +45,16 @@ struct Topology {
   // lptr[i] .. lptr[i+1] of lcol, its upper blocks uptr[i] .. uptr[i+1] of ucol.
   std::vector<int32_t> lptr, lcol, uptr, ucol;  // n+1, ne, n+1, ne
   std::vector<int32_t> lpos, upos;  // ne: compact lower / upper index of edge e's blocks (j,i) / (i,j)
+  // Workgroup-staged assembly: the element pass runs kElemTets tets per
+  // workgroup and sums, in LDS, its tets' contributions to each edge the
+  // workgroup touches into one partial record.  Partial records are numbered
+  // workgroup by workgroup, by edge within a workgroup:
+  //   part_base[w] .. part_base[w+1]   partial records of workgroup w (n_wg + 1)
+  //   part_cptr[p] .. part_cptr[p+1]   entries of part_slot summed into record p (P + 1)
+  //   part_slot[q]                     LDS slot 6 * (t - w * kElemTets) + k, in summation order (6m)
+  //   edge_pptr[e] .. edge_pptr[e+1]   entries of edge_part: edge e's partial records, ascending (ne + 1)
+  std::vector<int32_t> part_base, part_cptr, edge_pptr, edge_part;
+  std::vector<uint16_t> part_slot;
   std::vector<double> edge_S;     // ne: rest squared length
   std::vector<double> edge_mass;  // ne: consistent off-diagonal mass, sum rho V / 20
   std::vector<double> lumped;     // n: row sum of the consistent mass, sum rho V / 4

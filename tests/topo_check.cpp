@@ -69,6 +69,38 @@ int main(int argc, char** argv) {
     }
   for (int c : seen)
     if (c != 1) bad++;
+  // workgroup-staged assembly tables: every (tet, local edge) slot of a
+  // workgroup is summed into exactly one partial record; all of a record's
+  // slots belong to one edge; each edge lists exactly its records, ascending
+  {
+    const int nwg = (m + gfem::kElemTets - 1) / gfem::kElemTets;
+    const int np = (int)t.edge_part.size();
+    if ((int)t.part_base.size() != nwg + 1 || t.part_base[nwg] != np || (int)t.part_cptr.size() != np + 1 ||
+        t.part_cptr[np] != 6 * m || (int)t.part_slot.size() != 6 * m)
+      bad++;
+    std::vector<int> pedge(np, -1);
+    std::vector<int> used(6 * (size_t)m, 0);
+    for (int w = 0; w < nwg; ++w)
+      for (int p = t.part_base[w]; p < t.part_base[w + 1]; ++p)
+        for (int q = t.part_cptr[p]; q < t.part_cptr[p + 1]; ++q) {
+          const int tt = w * gfem::kElemTets + t.part_slot[q] / 6, k = t.part_slot[q] % 6;
+          if (tt >= m) {
+            bad++;
+            continue;
+          }
+          used[(size_t)tt * 6 + k]++;
+          const int e = t.tet_edge[(size_t)k * m + tt];
+          if (pedge[p] < 0) pedge[p] = e;
+          else if (pedge[p] != e) bad++;
+        }
+    for (int c : used)
+      if (c != 1) bad++;
+    for (int e = 0; e < t.ne; ++e)
+      for (int q = t.edge_pptr[e]; q < t.edge_pptr[e + 1]; ++q) {
+        if (pedge[t.edge_part[q]] != e) bad++;
+        if (q > t.edge_pptr[e] && t.edge_part[q] <= t.edge_part[q - 1]) bad++;
+      }
+  }
   // the numbering is a permutation and maps the caller's tets
   {
     std::vector<int> hit(n, 0);
