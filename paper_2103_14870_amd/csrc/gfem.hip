@@ -159,12 +159,11 @@ struct gf_mesh {
   uint8_t* tet_swapped = nullptr;
   double* vis_xyz = nullptr;
   uint8_t* vis_group = nullptr;
-  int32_t *edge_ptr = nullptr, *edge_slot = nullptr, *blk_ij = nullptr, *blk_ji = nullptr;
+  int32_t *edge_ptr = nullptr, *edge_slot = nullptr;
   // workgroup-staged assembly tables (topo.hpp) and the number of partial records
   int32_t *part_base = nullptr, *part_cptr = nullptr, *edge_pptr = nullptr, *edge_part = nullptr;
   uint16_t* part_slot = nullptr;
   int np = 0;
-  void* edge_w = nullptr;
   // block matrix
   int32_t *row_ptr = nullptr, *col = nullptr, *diag_blk = nullptr, *blk_edge = nullptr;
   int32_t *lptr = nullptr, *lcol = nullptr, *uptr = nullptr, *ucol = nullptr, *upos = nullptr;
@@ -176,13 +175,13 @@ struct gf_mesh {
   // FP64 copies of the precision-typed buffers of a split-precision mesh, for
   // steps re-run in FP64 (allocated on first use; swapped in for that step)
   struct PrecBufs {
-    void *val, *contrib, *edge_w, *binv, *pl[2], *vr, *vz, *vp[2], *vq, *vx, *vr2, *vy;
+    void *val, *contrib, *binv, *pl[2], *vr, *vz, *vp[2], *vq, *vx, *vr2, *vy;
   };
   bool esc_ready = false;
   PrecBufs esc{};
-  PrecBufs cur() const { return PrecBufs{val, contrib, edge_w, binv, {pl[0], pl[1]}, vr, vz, {vp[0], vp[1]}, vq, vx, vr2, vy}; }
+  PrecBufs cur() const { return PrecBufs{val, contrib, binv, {pl[0], pl[1]}, vr, vz, {vp[0], vp[1]}, vq, vx, vr2, vy}; }
   void use(const PrecBufs& b) {
-    val = b.val; contrib = b.contrib; edge_w = b.edge_w; binv = b.binv; pl[0] = b.pl[0]; pl[1] = b.pl[1];
+    val = b.val; contrib = b.contrib; binv = b.binv; pl[0] = b.pl[0]; pl[1] = b.pl[1];
     vr = b.vr; vz = b.vz; vp[0] = b.vp[0]; vp[1] = b.vp[1]; vq = b.vq; vx = b.vx; vr2 = b.vr2; vy = b.vy;
   }
   double *part_a = nullptr, *part_rz = nullptr, *part_pq = nullptr, *part_r = nullptr;
@@ -299,7 +298,6 @@ void alloc_precision(gf_mesh* M) {
   const int n = M->n, m = M->m;
   M->val = M->al.get<T>((size_t)9 * M->nbp);
   M->contrib = M->al.get<gfem::Rec<T>>((size_t)M->np);
-  M->edge_w = M->al.get<double>(M->ne);
   M->binv = M->al.get<T>((size_t)6 * n);
   if (M->plastic) {
     M->pl[0] = M->al.get<T>((size_t)6 * m);
@@ -344,7 +342,7 @@ struct AsmOpt {
 };
 
 // Damage (into the spare label buffer), element pass (+ plastic flow into the
-// spare plastic buffer), edge pass and row pass: the system of the next step.
+// spare plastic buffer) and row pass (assembly): the system of the next step.
 template <typename T>
 void assemble(gf_mesh* M, const AsmOpt& o) {
   hipStream_t s = M->stream;
@@ -373,18 +371,14 @@ void assemble(gf_mesh* M, const AsmOpt& o) {
   const double ra = o.quasi_static ? 0.0 : M->p.rayleigh_alpha;
   const double mass_fac = 1.0 + dt * ra;
   const double stiff_fac = dt * dt + (o.quasi_static ? 0.0 : dt * M->p.rayleigh_beta);
-  M->timed(2, -1, 0, [&] {
-    gfem::launch_edge<T>(s, M->ne, M->edge_pptr, M->edge_part, static_cast<const gfem::Rec<T>*>(M->contrib),
-                         M->edge_mass, mass_fac, stiff_fac, M->blk_ij, M->blk_ji, static_cast<T*>(M->val), M->nbp,
-                         static_cast<double*>(M->edge_w));
-  });
   gfem::RowConst rc{dt, ra, mass_fac, {M->p.gravity[0], M->p.gravity[1], M->p.gravity[2]}};
   if (o.quasi_static) rc.g[0] = rc.g[1] = rc.g[2] = 0.0;
   const d4* V = o.quasi_static ? o.zero : M->V;
   const d4* dvel = o.quasi_static ? o.zero : M->dvel;
   M->timed(2, -1, 0, [&] {
-    gfem::launch_row<T>(s, M->n, M->Gs, M->mat(), M->diag_blk, M->blk_edge, M->edge_mass,
-                        static_cast<const double*>(M->edge_w), M->lumped, M->X, M->U, V, M->dflag, dvel, rc,
+    gfem::launch_row<T>(s, M->n, M->Gs, M->mat(), M->diag_blk, M->blk_edge, M->edge_mass, M->edge_pptr,
+                        M->edge_part, static_cast<const gfem::Rec<T>*>(M->contrib), stiff_fac, M->lumped, M->X, M->U,
+                        V, M->dflag, dvel, rc,
                         static_cast<T*>(M->val), M->b, M->X64, static_cast<T*>(M->binv), f_out, M->part_a);
   });
   M->check_launch();
@@ -671,7 +665,6 @@ void ensure_esc(gf_mesh* M) {
   gf_mesh::PrecBufs& b = M->esc;
   b.val = M->al.get<double>(9 * (size_t)M->nbp);
   b.contrib = M->al.get<gfem::Rec<double>>((size_t)M->np);
-  b.edge_w = M->al.get<double>(M->ne);
   b.binv = M->al.get<double>(6 * n);
   b.pl[0] = M->plastic ? M->al.get<double>(6 * m) : nullptr;
   b.pl[1] = M->plastic ? M->al.get<double>(6 * m) : nullptr;
@@ -1111,8 +1104,6 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     M->edge_pptr = upload(M, T.edge_pptr);
     M->edge_part = upload(M, T.edge_part);
     M->np = (int)T.edge_part.size();
-    M->blk_ij = upload(M, T.blk_ij);
-    M->blk_ji = upload(M, T.blk_ji);
     M->row_ptr = upload(M, T.row_ptr);
     M->col = upload(M, T.col);
     M->diag_blk = upload(M, T.diag_blk);

@@ -1119,47 +1119,6 @@ __global__ __launch_bounds__(kThreads) void k_visual(int t0, int cnt, int m, con
   }
 }
 
-// ---------------------------------------------------------------- edge pass
-
-// One thread per edge: sum the edge's partial records (one per element-pass
-// workgroup that touched it) in ascending order (fixed), add the consistent
-// mass, and write A_ij and A_ji = A_ij^T into the block matrix:
-// A_ij = m_ij (1 + dt alpha) I + (dt^2 + dt beta) K_ij; the force weights are
-// summed in FP64.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_edge(int ne, const int32_t* __restrict__ edge_pptr,
-                                                   const int32_t* __restrict__ edge_part,
-                                                   const Rec<T>* __restrict__ contrib,
-                                                   const double* __restrict__ edge_mass, double mass_fac,
-                                                   double stiff_fac, const int32_t* __restrict__ blk_ij,
-                                                   const int32_t* __restrict__ blk_ji, T* __restrict__ val,
-                                                   int nbp, double* __restrict__ edge_w) {
-  int e = blockIdx.x * kThreads + threadIdx.x;
-  if (e >= ne) return;
-  T acc[9];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) acc[c] = 0;
-  double accw = 0.0;
-  const int s0 = edge_pptr[e], s1 = edge_pptr[e + 1];
-  for (int s = s0; s < s1; ++s) {
-    const Rec<T> r = contrib[edge_part[s]];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) acc[c] += r.b[c];
-    accw += r.w;
-  }
-  const double md = edge_mass[e] * mass_fac;
-  const int bij = blk_ij[e], bji = blk_ji[e];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const T v = (T)(stiff_fac * (double)acc[3 * r + c] + (r == c ? md : 0.0));
-      val[(size_t)(3 * r + c) * nbp + bij] = v;
-      val[(size_t)(3 * c + r) * nbp + bji] = v;
-    }
-  edge_w[e] = accw;
-}
-
 // ---------------------------------------------------------------- row pass
 
 template <int W>
@@ -1169,8 +1128,14 @@ __device__ __forceinline__ double seg_sum(double v) {
   return v;
 }
 
-// One block row per kRowLanes lanes; each lane takes one off-diagonal block
-// (i, j) of the row and the lanes then sum:
+// Assembly by block rows, one row per kRowPassLanes lanes; each lane takes
+// off-diagonal blocks (i, j) of the row and forms
+//   A_ij = m_ij (1 + dt alpha) I + (dt^2 + dt beta) K_ij
+// from the edge's partial records (one per element-pass workgroup that
+// touched the edge, summed in ascending order; they hold K(min, max), so row
+// i > j takes the transpose: rows i and j sum the same records in the same
+// order and A_ji is exactly A_ij^T), writes it to the row's own blocks
+// (contiguous), and the lanes then sum:
 //   A_ii = (1 + dt alpha) m_i I - sum_j A_ij   (translation invariance of K)
 //   f_i  = sum_j w_ij (x_j - x_i)              (Eq. 12: forces along edges)
 //   b_i  = dt (m_i g + f_i) - dt alpha (M v)_i - sum_j (A_ij - m_ij (1 + dt alpha) I)(v_j - v_i)
@@ -1184,7 +1149,10 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32_t* __restrict__ diag_blk,
                                                   const int32_t* __restrict__ blk_edge,
                                                   const double* __restrict__ edge_mass,
-                                                  const double* __restrict__ edge_w, const double* __restrict__ lumped,
+                                                  const int32_t* __restrict__ edge_pptr,
+                                                  const int32_t* __restrict__ edge_part,
+                                                  const Rec<T>* __restrict__ contrib, double stiff_fac,
+                                                  const double* __restrict__ lumped,
                                                   const d4* __restrict__ X, const d4* __restrict__ U,
                                                   const d4* __restrict__ V, const uint8_t* __restrict__ dflag,
                                                   const d4* __restrict__ dvel, RowConst cst, T* __restrict__ val,
@@ -1213,17 +1181,31 @@ __global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32
       const int j = Am.col[b];
       const int ed = blk_edge[b];
       const double me = edge_mass[ed];
-      const double w = edge_w[ed];
+      T kb[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) kb[c] = T(0);
+      double w = 0.0;
+      for (int q = edge_pptr[ed], q1 = edge_pptr[ed + 1]; q < q1; ++q) {
+        const Rec<T> r = contrib[edge_part[q]];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) kb[c] += r.b[c];
+        w += r.w;
+      }
       const d4 Xj = X[j], Uj = U[j], vj = V[j];
       const double dx[3] = {(Xj.x - Xi.x) + (Uj.x - Ui.x), (Xj.y - Xi.y) + (Uj.y - Ui.y),
                             (Xj.z - Xi.z) + (Uj.z - Ui.z)};
       const double dv[3] = {vj.x - vi.x, vj.y - vi.y, vj.z - vi.z};
+      const double md = me * cst.mass_fac;
       double a[9];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        a[c] = (double)val[(size_t)c * nbp + b];
-        acc[12 + c] += a[c];
-      }
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T kv = i < j ? kb[3 * r + c] : kb[3 * c + r];
+          a[3 * r + c] = (double)(T)(stiff_fac * (double)kv + (r == c ? md : 0.0));
+        }
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[12 + c] += a[c];
       acc[21] += me;
       const double mf = me * cst.mass_fac;
 #pragma unroll
@@ -1244,10 +1226,9 @@ __global__ __launch_bounds__(kThreads) void k_row(int n, MatView Am, const int32
 #pragma unroll
         for (int r = 0; r < 3; ++r) acc[9 + r] += a[3 * r] * dvc[0] + a[3 * r + 1] * dvc[1] + a[3 * r + 2] * dvc[2];
       }
-      if (cj || ci) {
+      const bool zero = cj || ci;
 #pragma unroll
-        for (int c = 0; c < 9; ++c) val[(size_t)c * nbp + b] = T(0);
-      }
+      for (int c = 0; c < 9; ++c) val[(size_t)c * nbp + b] = zero ? T(0) : (T)a[c];
     }
 #pragma unroll
     for (int c = 0; c < 22; ++c) acc[c] = seg_sum<kRowPassLanes>(acc[c]);
@@ -2047,21 +2028,14 @@ void launch_element(hipStream_t s, int m, const int4* tets, const int32_t* tet_e
                                                                   contrib, ctr);
 }
 
-template <typename T>
-void launch_edge(hipStream_t s, int ne, const int32_t* edge_pptr, const int32_t* edge_part,
-                 const Rec<T>* contrib, const double* edge_mass, double mass_fac, double stiff_fac,
-                 const int32_t* blk_ij, const int32_t* blk_ji, T* val, int nbp, double* edge_w) {
-  k_edge<T><<<blocks_for(ne), kThreads, 0, s>>>(ne, edge_pptr, edge_part, contrib, edge_mass, mass_fac,
-                                               stiff_fac, blk_ij, blk_ji, val, nbp, edge_w);
-}
 
 template <typename T>
 void launch_row(hipStream_t s, int n, int G, MatView A, const int32_t* diag_blk, const int32_t* blk_edge,
-                const double* edge_mass, const double* edge_w, const double* lumped, const d4* X, const d4* U,
-                const d4* V, const uint8_t* dflag, const d4* dvel, RowConst c, T* val_mut, d4* b, d4* X64,
-                T* binv, d4* f_out, double* part_bb) {
-  k_row<T><<<G, kThreads, 0, s>>>(n, A, diag_blk, blk_edge, edge_mass, edge_w, lumped, X, U, V, dflag, dvel, c,
-                                  val_mut, b, X64, binv, f_out, part_bb);
+                const double* edge_mass, const int32_t* edge_pptr, const int32_t* edge_part, const Rec<T>* contrib,
+                double stiff_fac, const double* lumped, const d4* X, const d4* U, const d4* V, const uint8_t* dflag,
+                const d4* dvel, RowConst c, T* val_mut, d4* b, d4* X64, T* binv, d4* f_out, double* part_bb) {
+  k_row<T><<<G, kThreads, 0, s>>>(n, A, diag_blk, blk_edge, edge_mass, edge_pptr, edge_part, contrib, stiff_fac,
+                                  lumped, X, U, V, dflag, dvel, c, val_mut, b, X64, binv, f_out, part_bb);
 }
 
 // Launch with dispatch-recorded events when given.
@@ -2205,12 +2179,10 @@ void launch_visual(hipStream_t s, int t0, int cnt, int m, const int4* tets, cons
   template void launch_element<T>(hipStream_t, int, const int4*, const int32_t*, const uint8_t*, const d4*,  \
                                   const d4*, const uint8_t*, const T*, const T*, T*, ElemConst,              \
                                   const int32_t*, const int32_t*, const uint16_t*, Rec<T>*, Counters*);      \
-  template void launch_edge<T>(hipStream_t, int, const int32_t*, const int32_t*, const Rec<T>*,              \
-                               const double*, double, double, const int32_t*, const int32_t*, T*, int,       \
-                               double*);                                                                     \
   template void launch_row<T>(hipStream_t, int, int, MatView, const int32_t*, const int32_t*, const double*, \
-                              const double*, const double*, const d4*, const d4*, const d4*, const uint8_t*, \
-                              const d4*, RowConst, T*, d4*, d4*, T*, d4*, double*);                          \
+                              const int32_t*, const int32_t*, const Rec<T>*, double, const double*,          \
+                              const d4*, const d4*, const d4*, const uint8_t*, const d4*, RowConst, T*, d4*, \
+                              d4*, T*, d4*, double*);                                                        \
   template void launch_pcg_init<T>(hipStream_t, int, int, const d4*, const T*, v4<T>*, v4<T>*, v4<T>*,      \
                                    v4<T>*, double*, PcgCtl*);                                                \
   template void launch_pcg_spmv<T>(hipStream_t, int, int, int, MatView, const v4<T>*, const v4<T>*, v4<T>*, \

@@ -8,8 +8,9 @@
 //   contributions  : partial records (9 block entries in T + one FP64 force
 //                    weight, 48 B in FP32), one per (element-pass workgroup,
 //                    edge it touches): each workgroup sums its tets'
-//                    contributions per edge in LDS first; the edge pass reads
-//                    whole records, about two per edge
+//                    contributions per edge in LDS first; the row pass reads
+//                    whole records, about two per edge, for each of an
+//                    edge's two blocks
 // No floating-point atomics anywhere: every sum has a fixed order, so a step
 // is bitwise reproducible.
 #pragma once
@@ -157,12 +158,6 @@ void launch_zero(hipStream_t s, int n, d4* x);
 // U += dt * dvel on the prescribed nodes (dflag != 0).
 void launch_move_prescribed(hipStream_t s, int n, const uint8_t* dflag, const d4* dvel, double dt, d4* U);
 
-// edge_pptr / edge_part: each edge's partial records (ascending).
-template <typename T>
-void launch_edge(hipStream_t s, int ne, const int32_t* edge_pptr, const int32_t* edge_part,
-                 const Rec<T>* contrib, const double* edge_mass, double mass_fac, double stiff_fac,
-                 const int32_t* blk_ij, const int32_t* blk_ji, T* val, int nbp, double* edge_w);
-
 struct RowConst {
   double dt, ra;      // dt, Rayleigh alpha
   double mass_fac;    // 1 + dt * alpha
@@ -171,7 +166,8 @@ struct RowConst {
 
 template <typename T>
 void launch_row(hipStream_t s, int n, int G, MatView A, const int32_t* diag_blk,
-                const int32_t* blk_edge, const double* edge_mass, const double* edge_w,
+                const int32_t* blk_edge, const double* edge_mass, const int32_t* edge_pptr,
+                const int32_t* edge_part, const Rec<T>* contrib, double stiff_fac,
                 const double* lumped, const d4* X, const d4* U, const d4* V,
                 const uint8_t* dflag, const d4* dvel, RowConst c, T* val_mut, d4* b,
                 d4* X64, T* binv, d4* f_out, double* part_bb);
