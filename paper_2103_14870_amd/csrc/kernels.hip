@@ -1417,7 +1417,11 @@ __global__ __launch_bounds__(NT) void k_pcg_spmv(int k, int Ga, MatView Am, cons
                                                  const double* __restrict__ part_rz,
                                                  double* __restrict__ part_pq, double rel2) {
   __shared__ double sh[3 * (NT / 64)];
-  if (ctl->done) return;
+  // the control words are read together with the first row's loads (all in
+  // bounds); a converged solve returns before anything is written.  At k = 0
+  // the threshold is set here, so it is not read.
+  const int done = ctl->done;
+  const double thr2_prev = k == 0 ? 0.0 : ctl->thr2;
   const int n = Am.n;
   const int G = gridDim.x;
   const int L = xcd_logical(blockIdx.x, G);
@@ -1446,13 +1450,14 @@ __global__ __launch_bounds__(NT) void k_pcg_spmv(int k, int Ga, MatView Am, cons
     rr += cur[kMaxPart + i];
     if (DIR) rzp += prv[i];
   }
+  if (done) return;
   block_sum3n<NT>(rz, rr, rzp, sh);
   double thr2;
   if (k == 0) {
     thr2 = rel2 * rr;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->thr2 = thr2;
   } else {
-    thr2 = ctl->thr2;
+    thr2 = thr2_prev;
   }
   if (!(rr > thr2) || rz == 0.0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->done = 1;
@@ -1505,7 +1510,9 @@ __global__ __launch_bounds__(NT) void k_pcg_update(int k, int n, int Gb, const v
                                                    const double* __restrict__ part_pq,
                                                    double* __restrict__ part_rz) {
   __shared__ double sh[3 * (NT / 64)];
-  if (ctl->done) return;
+  // the control word is read together with the first row's loads (all in
+  // bounds); a converged solve returns before anything is written
+  const int done = ctl->done;
   const int G = gridDim.x;
   const int L = xcd_logical(blockIdx.x, G);
   const int chunk = (n + G - 1) / G;
@@ -1522,6 +1529,7 @@ __global__ __launch_bounds__(NT) void k_pcg_update(int k, int n, int Gb, const v
   double pq = 0, rz = 0, unused = 0;
   for (int t = threadIdx.x; t < Gb; t += NT) pq += part_pq[t];
   for (int t = threadIdx.x; t < G; t += NT) rz += cur[t];
+  if (done) return;
   block_sum3n<NT>(pq, rz, unused, sh);
   if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1646,7 +1654,9 @@ __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, int npq, FactView F, co
   constexpr int MODE = INIT ? 1 : 0;
   __shared__ double sh[3 * (NT / 64)];
   if (INIT && blockIdx.x == 0 && threadIdx.x == 0) *ctl = PcgCtl{0, 0, 0, 0, 0.0};
-  if (!INIT && ctl->done) return;
+  // the control word is read together with the first row's loads (all in
+  // bounds); a converged solve returns before anything is written
+  const int done = INIT ? 0 : ctl->done;
   const int n = F.n;
   const int G = gridDim.x;
   const int L = xcd_logical(blockIdx.x, G);
@@ -1686,6 +1696,7 @@ __global__ __launch_bounds__(NT) void k_pcg_gpass(int k, int npq, FactView F, co
     double pq = 0, rz = 0, unused = 0;
     for (int t = threadIdx.x; t < npq; t += NT) pq += part_pq[t];
     for (int t = threadIdx.x; t < G; t += NT) rz += cur[t];
+    if (done) return;
     block_sum3n<NT>(pq, rz, unused, sh);
     if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1763,7 +1774,10 @@ __global__ __launch_bounds__(NT) void k_pcg_gtpass(int k, FactView F, const v4<T
                                                    const v4<T>* __restrict__ p_old, v4<T>* __restrict__ p_new,
                                                    PcgCtl* ctl, const double* __restrict__ part_rz, double rel2) {
   __shared__ double sh[3 * (NT / 64)];
-  if (!INIT && ctl->done) return;
+  // the control words are read together with the first row's loads (all in
+  // bounds); a converged solve returns before anything is written
+  const int done = INIT ? 0 : ctl->done;
+  const double thr2_prev = INIT ? 0.0 : ctl->thr2;
   const int n = F.n;
   const int G = gridDim.x;
   const int L = xcd_logical(blockIdx.x, G);
@@ -1800,13 +1814,14 @@ __global__ __launch_bounds__(NT) void k_pcg_gtpass(int k, FactView F, const v4<T
     rr += cur[kMaxPart + t];
     if (!INIT) rzp += prv[t];
   }
+  if (done) return;
   block_sum3n<NT>(rz, rr, rzp, sh);
   double thr2;
   if (INIT) {
     thr2 = rel2 * rr;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->thr2 = thr2;
   } else {
-    thr2 = ctl->thr2;
+    thr2 = thr2_prev;
   }
   if (!(rr > thr2) || rz == 0.0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->done = 1;
@@ -1853,7 +1868,9 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_pcg_spmv_p(MatView Am, const v4<T>* __restrict__ p, v4<T>* __restrict__ q,
                                                    PcgCtl* ctl, double* __restrict__ part_pq) {
   __shared__ double sh[3 * (NT / 64)];
-  if (ctl->done) return;
+  // the control word is read together with the first row's loads (all in
+  // bounds); a converged solve returns before anything is written
+  const int done = ctl->done;
   const int n = Am.n;
   const int G = gridDim.x;
   const int L = xcd_logical(blockIdx.x, G);
@@ -1864,11 +1881,25 @@ __global__ __launch_bounds__(NT) void k_pcg_spmv_p(MatView Am, const v4<T>* __re
   const int grp = threadIdx.x / LN;
   constexpr int NG = NT / LN;
   const T* __restrict__ val = static_cast<const T*>(Am.val);
+  int ra = r0 + grp;
+  int sa = 0, cnt = 0;
+  if (ra < r1) {
+    sa = Am.row_ptr[ra];
+    cnt = Am.row_ptr[ra + 1] - sa;
+  }
+  SpmvSlot<T, false> ta = spmv_load<T, false>(Am, val, sa + lane, lane < cnt, nullptr, nullptr, p);
+  SpmvSlot<T, false> tb = spmv_load<T, false>(Am, val, sa + lane + LN, lane + LN < cnt, nullptr, nullptr, p);
+  if (done) return;
   double dot = 0;
-  for (int ra = r0 + grp; ra < r1; ra += NG) {
-    const int sa = Am.row_ptr[ra], cnt = Am.row_ptr[ra + 1] - sa;
-    const SpmvSlot<T, false> ta = spmv_load<T, false>(Am, val, sa + lane, lane < cnt, nullptr, nullptr, p);
-    const SpmvSlot<T, false> tb = spmv_load<T, false>(Am, val, sa + lane + LN, lane + LN < cnt, nullptr, nullptr, p);
+  bool first = true;
+  for (; ra < r1; ra += NG) {
+    if (!first) {
+      sa = Am.row_ptr[ra];
+      cnt = Am.row_ptr[ra + 1] - sa;
+      ta = spmv_load<T, false>(Am, val, sa + lane, lane < cnt, nullptr, nullptr, p);
+      tb = spmv_load<T, false>(Am, val, sa + lane + LN, lane + LN < cnt, nullptr, nullptr, p);
+    }
+    first = false;
     T ax = 0, ay = 0, az = 0;
     if (ta.on) blk_fma(ta.k, ta.p, ax, ay, az);
     if (tb.on) blk_fma(tb.k, tb.p, ax, ay, az);
