@@ -323,7 +323,7 @@ void damage_pass(gf_mesh* M) {
   if (M->nl_ptr)
     gfem::launch_damage_nonlocal(s, M->m, M->ne, M->tets, M->X, M->U, M->nl_ptr, M->nl_idx, M->nl_w, M->nl_E,
                                  M->nl_Eavg, M->edges, M->edge_ptr, M->edge_slot, M->zeta[zi], M->zeta[zo],
-                                 M->p.damage_strain, M->ctr, M->near_ids);
+                                 M->p.damage_strain, M->ctr, M->near_ids, (int64_t)M->nl_entries);
   else
     gfem::launch_damage(s, M->ne, M->edges, M->X, M->U, M->edge_S, M->zeta[zi], M->zeta[zo], M->p.damage_strain,
                         M->ctr, M->near_ids);

@@ -215,25 +215,40 @@ __global__ __launch_bounds__(kThreads) void k_nl_strain(int m, const int4* __res
   E[t] = o;
 }
 
-// Per tet: E*_t = sum_j w_tj E_j over the support (Eq. 20's weighted average).
+// Support-weighted average of the strain tensors (Eq. 20, reading R4): one
+// group of LN lanes per tet; the lanes take the tet's support entries in turn
+// (consecutive entries, so the index and weight loads coalesce), each keeps
+// six partial sums, and a butterfly over the group finishes them in a fixed
+// order, so the result is reproducible.
+template <int LN>
 __global__ __launch_bounds__(kThreads) void k_nl_average(int m, const int64_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ idx,
                                                          const double* __restrict__ w,
                                                          const Sym6* __restrict__ E, Sym6* __restrict__ Eavg) {
-  const int t = blockIdx.x * kThreads + threadIdx.x;
-  if (t >= m) return;
+  const int lane = threadIdx.x & (LN - 1);
+  const int t = (int)(((long)blockIdx.x * kThreads + threadIdx.x) / LN);
+  const bool act = t < m;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  const int64_t j1 = ptr[t + 1];
-  for (int64_t j = ptr[t]; j < j1; ++j) {
-    const Sym6 ej = E[idx[j]];
-    const double wj = w[j];
+  if (act) {
+    const int64_t j1 = ptr[t + 1];
+#pragma unroll 4
+    for (int64_t j = ptr[t] + lane; j < j1; j += LN) {
+      const Sym6 ej = E[idx[j]];
+      const double wj = w[j];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] = fmadd(wj, ej.v[c], acc[c]);
+      for (int c = 0; c < 6; ++c) acc[c] = fmadd(wj, ej.v[c], acc[c]);
+    }
   }
-  Sym6 o;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) o.v[c] = acc[c];
-  Eavg[t] = o;
+  for (int o = LN / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += __shfl_xor(acc[c], o, LN);
+  if (act && lane == 0) {
+    Sym6 o;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) o.v[c] = acc[c];
+    Eavg[t] = o;
+  }
 }
 
 // Per edge: averaged normal strain d^T E* d / d^T d (d the rest edge vector)
@@ -2028,10 +2043,18 @@ void launch_damage(hipStream_t s, int ne, const int2* edges, const d4* X, const 
 void launch_damage_nonlocal(hipStream_t s, int m, int ne, const int4* tets, const d4* X, const d4* U,
                             const int64_t* nl_ptr, const int32_t* nl_idx, const double* nl_w, Sym6* E,
                             Sym6* Eavg, const int2* edges, const int32_t* edge_ptr, const int32_t* edge_slot,
-                            const uint8_t* z_in, uint8_t* z_out, double thr, Counters* ctr, int32_t* near_ids) {
+                            const uint8_t* z_in, uint8_t* z_out, double thr, Counters* ctr, int32_t* near_ids,
+                            int64_t n_entries) {
   if (ne <= 0 || m <= 0) return;
   k_nl_strain<<<blocks_for(m), kThreads, 0, s>>>(m, tets, X, U, E);
-  k_nl_average<<<blocks_for(m), kThreads, 0, s>>>(m, nl_ptr, nl_idx, nl_w, E, Eavg);
+  // lanes per tet from the mean support size
+  const int64_t per = n_entries / m;
+  if (per >= 48)
+    k_nl_average<64><<<blocks_for((long)m * 64), kThreads, 0, s>>>(m, nl_ptr, nl_idx, nl_w, E, Eavg);
+  else if (per >= 12)
+    k_nl_average<16><<<blocks_for((long)m * 16), kThreads, 0, s>>>(m, nl_ptr, nl_idx, nl_w, E, Eavg);
+  else
+    k_nl_average<4><<<blocks_for((long)m * 4), kThreads, 0, s>>>(m, nl_ptr, nl_idx, nl_w, E, Eavg);
   k_nl_damage<<<blocks_for(ne), kThreads, 0, s>>>(ne, m, edges, X, edge_ptr, edge_slot, Eavg, z_in, z_out, thr,
                                                   ctr, near_ids);
 }

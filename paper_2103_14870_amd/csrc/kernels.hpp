@@ -112,7 +112,8 @@ struct alignas(16) Sym6 {
 void launch_damage_nonlocal(hipStream_t s, int m, int ne, const int4* tets, const d4* X, const d4* U,
                             const int64_t* nl_ptr, const int32_t* nl_idx, const double* nl_w, Sym6* E,
                             Sym6* Eavg, const int2* edges, const int32_t* edge_ptr, const int32_t* edge_slot,
-                            const uint8_t* z_in, uint8_t* z_out, double thr, Counters* ctr, int32_t* near_ids);
+                            const uint8_t* z_in, uint8_t* z_out, double thr, Counters* ctr, int32_t* near_ids,
+                            int64_t n_entries);
 
 // Plastic flow of the ductile workload: pl_in -> pl_out, each [6][m] plastic
 // rest-shape offsets Gp - G0 (symmetric 00,11,22,01,02,12).
