@@ -122,7 +122,12 @@ def write_counter_summary(fetch_csv, write_csv, calib_mb, command_f, command_w, 
 STATS = os.path.join(ROOT, "profiles", "pcg_learned_ellipsoid620k_kernel_stats.txt")
 
 
-def write_stats_summary(stats_csv, command, out_path=STATS):
+ELLIPSOID_TITLE = ("# rocprofv3 kernel statistics: bench.py on the 619,830-tet ductile ellipsoid, one MI355X\n"
+                   "# (learned-preconditioner leg, kernel timing leg and block-Jacobi leg, 10 timed steps after "
+                   "5 warm-up each)")
+
+
+def write_stats_summary(stats_csv, command, out_path=STATS, title=ELLIPSOID_TITLE):
     """Per-kernel table from a rocprofv3 --kernel-trace --stats run of
     bench.py (run_kernel_stats.csv), with the command that made it."""
     import csv
@@ -130,8 +135,7 @@ def write_stats_summary(stats_csv, command, out_path=STATS):
     rows = list(csv.DictReader(open(stats_csv)))
     total = sum(float(r["TotalDurationNs"]) for r in rows)
     lines = [
-        "# rocprofv3 kernel statistics: bench.py on the 619,830-tet ductile ellipsoid, one MI355X",
-        "# (learned-preconditioner leg, kernel timing leg and block-Jacobi leg, 10 timed steps after 5 warm-up each)",
+        *title.split("\n"),
         "#",
         "# command (repository root):",
         f"#   {command}",
@@ -187,6 +191,72 @@ def cpu_baseline(prob, n_threads=1):
     return dict(value=2.0 / dt, unit="timesteps/s", cores=n_threads, kind="oracle",
                 sample=f"first 2 steps from rest of the same {prob.n_tets}-tet workload "
                        f"(FP64 NumPy/SciPy oracle, block-Jacobi PCG, {iters} iterations, {dt:.1f} s)")
+
+
+def cpu_baseline_qs(prob, rtol, n_threads=1):
+    """FP64 oracle, the first quasi-static load step of the same block from rest, on host cores."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import gfem_oracle as O
+
+    with threadpool_limits(n_threads):
+        mesh = O.setup(prob.X, prob.tets, prob.params)
+        st = O.initial_state(mesh)
+        O.break_pairs(mesh, st, prob.broken_pairs)
+        t0 = time.perf_counter()
+        st, h = O.quasi_static_step(mesh, st, prob.dir_nodes, prob.dir_vel, newton_rtol=rtol)
+        dt = time.perf_counter() - t0
+    return dict(value=1.0 / dt, unit="load steps/s", cores=n_threads, kind="oracle",
+                sample=f"first load step from rest of the same {prob.n_tets}-tet block (FP64 NumPy/SciPy "
+                       f"oracle, {h['newton_iters']} Newton iterations, {h['inner_iters']} PCG iterations, "
+                       f"{dt:.1f} s)")
+
+
+def quasi_static_leg(m, steps, warmup, rtol, window, log):
+    """Load steps of a quasi-static block (Newton with a line search, Eq. 36),
+    one call per load step: per-window wall time, Newton and PCG iterations,
+    line-search halvings and broken edges."""
+    import torch
+
+    for _ in range(warmup):
+        m.quasi_static_step(1, newton_rel_tol=rtol)
+    torch.cuda.synchronize()
+    from paper_2103_14870_amd import gfem
+
+    rows, cur, tot, failed = [], None, dict(newton=0, inner=0, halvings=0), None
+    t_start = t0 = time.perf_counter()
+    for i in range(steps):
+        if cur is None:
+            cur = dict(first=warmup + i + 1, steps=0, newton=0, inner=0, halvings=0, broken=0)
+        s = m.quasi_static_step(1, newton_rel_tol=rtol, raise_on_error=False)
+        if s["status"] != gfem.GF_OK:
+            failed = dict(load_step=warmup + i + 1, status=gfem.STATUS_NAMES.get(s["status"], s["status"]),
+                          error=(gfem.load().gf_last_error() or b"").decode())
+            log(f"load step {warmup + i + 1} failed: {failed['error']}")
+        else:
+            cur["steps"] += 1
+            cur["newton"] += s["newton_iters"]
+            cur["inner"] += s["inner_iters"]
+            cur["halvings"] += s["line_search_halvings"]
+            cur["broken"] = s["total_broken"]
+        if failed or (i + 1) % window == 0 or i + 1 == steps:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if not cur["steps"]:
+                break
+            cur.update(last=cur["first"] + cur["steps"] - 1, seconds=t1 - t0,
+                       ms_per_load_step=1000.0 * (t1 - t0) / cur["steps"])
+            for k in tot:
+                tot[k] += cur[k]
+            rows.append(cur)
+            log(f"load steps {cur['first']}-{cur['last']}: {cur['ms_per_load_step']:.1f} ms/step, "
+                f"{cur['newton'] / cur['steps']:.1f} Newton, {cur['inner'] / max(cur['newton'], 1):.0f} PCG it/Newton, "
+                f"{cur['halvings']} halvings, broken {cur['broken']}")
+            cur, t0 = None, t1
+        if failed:
+            break
+    elapsed = sum(r["seconds"] for r in rows)
+    return dict(windows=rows, elapsed=elapsed, done=sum(r["steps"] for r in rows), failed=failed, **tot)
 
 
 def host_cpu_model():
@@ -289,9 +359,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="ellipsoid", choices=["ellipsoid", "beam"],
+    ap.add_argument("--workload", default="ellipsoid", choices=["ellipsoid", "beam", "block"],
                     help="ellipsoid: the 619,830-tet ductile ellipsoid (the metric's workload); beam: the "
-                         "122,880-tet notched beam in three-point bending, with --crack-fraction pre-broken edges")
+                         "122,880-tet notched beam in three-point bending, with --crack-fraction pre-broken edges; "
+                         "block: a 168,432-tet block pulled from both ends in quasi-static load steps "
+                         "(--material; --steps load steps, one JSON line of its own)")
+    ap.add_argument("--material", default="stone", choices=["stone", "wood", "cheese"],
+                    help="block workload: stone, wood or cheese (kernel support R_d 0, 0.1, 0.5 m)")
+    ap.add_argument("--newton-rtol", type=float, default=1e-4, help="block workload: Newton force tolerance")
+    ap.add_argument("--cg-max-iter", type=int, default=None, help="block workload: PCG iteration cap per solve")
+    ap.add_argument("--pull", type=float, default=None, help="block workload: m each end moves per load step")
+    ap.add_argument("--energy", default="stable_neo_hookean", choices=["stable_neo_hookean", "stvk"],
+                    help="element energy of the dynamic workloads")
+    ap.add_argument("--visual", action="store_true",
+                    help="after the timed leg, time the split visualisation mesh (gf_get_visual_mesh)")
     ap.add_argument("--crack-fraction", type=float, default=0.0)
     ap.add_argument("--dt", type=float, default=None, help="time step (default: 1e-2 ellipsoid, 1e-4 beam)")
     ap.add_argument("--precond", default="learned", choices=["learned", "block_jacobi"])
@@ -313,6 +394,16 @@ def main():
                     help="write the HBM counter summary from two rocprofv3 --pmc runs and exit (no GPU)")
     args = ap.parse_args()
     if args.stats_summary:
+        if args.workload == "block":
+            write_stats_summary(
+                args.stats_summary,
+                "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/statsQ -o run -- "
+                f"python bench.py --workload block --material {args.material} --steps 10 --warmup 0 --no-cpu-baseline",
+                os.path.join(ROOT, "profiles", f"qs_{args.material}_block168k_kernel_stats.txt"),
+                f"# rocprofv3 kernel statistics: bench.py on the 168,432-tet {args.material} block pulled from both "
+                "ends, one MI355X\n# (10 quasi-static load steps from rest: Newton with a line search, "
+                "block-Jacobi PCG)")
+            return
         write_stats_summary(args.stats_summary,
                             "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/statsL -o run -- "
                             "python bench.py --steps 10 --warmup 5 --no-cpu-baseline")
@@ -349,6 +440,43 @@ def main():
         torch.cuda.synchronize()
         del src, dst, evict
 
+    log = lambda msg: print(f"bench: {msg}", file=sys.stderr, flush=True)
+    if args.workload == "block":
+        kw = {} if args.pull is None else {"pull": args.pull}
+        if args.dt is not None:
+            kw["dt"] = args.dt
+        if args.cg_max_iter is not None:
+            kw["cg_max_iter"] = args.cg_max_iter
+        prob = meshgen.pulled_block(args.material, **kw)
+        nu, thr, radius = meshgen.BLOCK_MATERIALS[args.material]
+        workload = (f"{args.material} block {prob.n_tets} tets / {prob.n_nodes} nodes pulled from both ends, "
+                    f"quasi-static load steps (Newton + line search to {args.newton_rtol:g} of the first force), "
+                    f"R_d={radius:g} m, Green-strain threshold {thr:g}, block-Jacobi PCG to 1e-6")
+        log(f"quasi-static leg ({args.material})")
+        t0 = time.perf_counter()
+        m = gfem.mesh_from_problem(prob)
+        create_s = time.perf_counter() - t0
+        stream = torch.cuda.Stream()
+        m.set_stream(stream.cuda_stream)
+        leg = quasi_static_leg(m, args.steps, args.warmup, args.newton_rtol, max(1, min(args.steps, 5)), log)
+        n_edges = m.n_edges
+        m.close()
+        steps = max(leg["done"], 1)
+        out = {"mode": "quasi_static", "workload": workload, "material": args.material,
+               "tets": prob.n_tets, "nodes": prob.n_nodes, "edges": n_edges, "damage_radius": radius,
+               "load_steps": leg["done"], "warmup": args.warmup, "failed": leg["failed"],
+               "load_steps_per_s": leg["done"] / max(leg["elapsed"], 1e-12),
+               "ms_per_load_step": 1000.0 * leg["elapsed"] / steps,
+               "newton_per_load_step": leg["newton"] / steps,
+               "pcg_iters_per_newton": leg["inner"] / max(leg["newton"], 1),
+               "line_search_halvings": leg["halvings"], "broken": leg["windows"][-1]["broken"] if leg["windows"] else 0,
+               "create_s": create_s, "windows": leg["windows"], "dtype": "f32+f64", "data": "synthetic"}
+        if not args.no_cpu_baseline:
+            log("CPU oracle sample")
+            out["cpu_baseline"] = cpu_baseline_qs(prob, args.newton_rtol)
+            out["cpu_baseline"]["cpu_model"] = host_cpu_model()
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "ellipsoid":
         args.dt = args.dt or 1e-2
         prob = meshgen.make_config(3, dt=args.dt)
@@ -361,6 +489,9 @@ def main():
                     f"{100 * args.crack_fraction:g} % pre-broken edges, dt={args.dt:g}, PCG to 1e-6 FP64 rel. residual")
     prob.params["net_every_n_steps"] = args.net_every
     prob.params["reorder"] = args.reorder
+    prob.params["energy"] = args.energy
+    if args.energy != "stable_neo_hookean":
+        workload += f", {args.energy} energy"
     stream = torch.cuda.Stream()
     net = None
     if args.precond == "learned":
@@ -374,7 +505,6 @@ def main():
             gfem.attach_net(m, net)
         return m
 
-    log = lambda msg: print(f"bench: {msg}", file=sys.stderr, flush=True)
     if args.trajectory > 0:
         out = {"mode": "trajectory", "workload": workload, "steps": args.trajectory, "window": args.window,
                "net_every_n_steps": args.net_every}
@@ -387,6 +517,16 @@ def main():
     log(f"timed leg ({args.precond})")
     m = make_mesh(net is not None)
     main_leg = timed_steps(m, args.steps, args.warmup)
+    visual = None
+    if args.visual:
+        log("visualisation mesh")
+        m.visual_mesh()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            xyz, grp = m.visual_mesh()
+        visual = dict(ms_per_call=1000.0 * (time.perf_counter() - t0) / 5, bytes_out=xyz.nbytes + grp.nbytes,
+                      split_tets=int(np.count_nonzero(grp.max(axis=1) > 0)))
     m.close()
     log("kernel timing leg")
     m = make_mesh(net is not None)
@@ -447,6 +587,8 @@ def main():
         # the same kernel's mean duration in the committed rocprofv3 statistics
         out["roofline"]["profile_avg_launch_us"] = prof_us
         out["roofline"]["profile_frac"] = spmv_bytes / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBS
+    if visual is not None:
+        out["visual_mesh"] = visual
     if jac is not None:
         out["block_jacobi"] = {"value": jac["value"], "pcg_iters_per_step": jac["iters"],
                                "ms_per_step": 1000.0 * jac["elapsed"] / args.steps}

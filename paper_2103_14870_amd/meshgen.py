@@ -280,6 +280,51 @@ def permute_nodes(prob: Problem, seed: int) -> Problem:
                    dict(prob.meta, node_permutation=new))
 
 
+# Quasi-static blocks pulled from both ends (Sec. 5.1): material -> (Poisson
+# ratio, Green-strain threshold, kernel support R_d in m).  R_d is the paper's
+# per-material value; the paper gives no elastic constants or thresholds for
+# these blocks, so brittle-to-soft values are chosen.  In a displacement-driven
+# quasi-static run Young's modulus cancels except against the small mass
+# regulariser, so one modulus serves all three.
+BLOCK_MATERIALS = {
+    "stone": (0.20, 0.004, 0.0),
+    "wood": (0.30, 0.008, 0.1),
+    "cheese": (0.45, 0.02, 0.5),
+}
+
+
+def pulled_block(material="stone", nx=22, ny=22, nz=58, h=0.18, jitter_frac=0.05, seed=3, pull=0.002,
+                 notch_cells=5, dt=1.0, **param_kw) -> Problem:
+    """Rectangular block pulled from both ends, quasi-statically (Sec. 5.1).
+
+    Defaults: 22 x 22 x 58 cubes of 18 cm (168,432 tets, the size of the
+    paper's blocks; 3.96 x 3.96 x 10.44 m, so that the cheese support of
+    R_d = 0.5 m spans 2.8 cells); both end faces prescribed and moved apart
+    by `pull` m each per load step (pseudo-timestep dt, velocity pull / dt);
+    a notch seeds the crack: every edge of every tet in the mid-length cube
+    layer, `notch_cells` cubes deep from the x = 0 face, is pre-broken;
+    E = 1e7 Pa, rho = 1000, split precision, block-Jacobi PCG to 1e-6."""
+    nu, thr, radius = BLOCK_MATERIALS[material]
+    X = grid_nodes(nx, ny, nz, h)
+    tets, cube = freudenthal_tets(nx, ny, nz)
+    if jitter_frac > 0:
+        X = jitter(X, jitter_frac * h, seed)
+    in_notch = (cube[:, 2] == nz // 2) & (cube[:, 0] < notch_cells)
+    broken = tet_pairs(tets[in_notch])
+    k = np.rint((grid_nodes(nx, ny, nz, 1.0))[:, 2]).astype(np.int64)
+    bottom = np.nonzero(k == 0)[0]
+    top = np.nonzero(k == nz)[0]
+    nodes = np.concatenate([bottom, top]).astype(np.int32)
+    vel = np.zeros((nodes.size, 3))
+    vel[:bottom.size, 2] = -pull / dt
+    vel[bottom.size:, 2] = pull / dt
+    params = default_params(youngs=1e7, poisson=nu, density=1000.0, damage_strain=thr, damage_radius=radius,
+                            dt=dt, cg_rel_tol=1e-6, precision="split")
+    params.update(param_kw)
+    return Problem(f"{material}-block{nx}x{ny}x{nz}", X, tets.astype(np.int32), params, nodes, vel,
+                   broken.astype(np.int32), 40, dict(h=h, shape=(nx, ny, nz), material=material))
+
+
 CONFIGS = {
     1: lambda **kw: cube_block(**kw),
     2: lambda **kw: notched_beam(**kw),
