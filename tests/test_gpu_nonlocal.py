@@ -32,12 +32,14 @@ def pulled_block(prec, radius):
     return prob
 
 
-@pytest.mark.parametrize("prec", ["fp64", "split"])
-def test_nonlocal_damage_lockstep(prec):
-    """30 steps of a pulled jittered block with R_d = 2.5 h: labels, near-threshold
-    edge ids and displacements against the oracle."""
-    say(f"case non-local damage prec={prec} R_d=0.25")
-    prob = pulled_block(prec, 0.25)
+@pytest.mark.parametrize("prec,radius", [("fp64", 0.25), ("split", 0.25), ("fp64", 0.12), ("fp64", 0.06)])
+def test_nonlocal_damage_lockstep(prec, radius):
+    """30 steps of a pulled jittered block with R_d = 2.5 h, 1.2 h and 0.6 h
+    (210, 31 and 4 support entries per tet: the averaging kernel's 64-, 16-
+    and 4-lane groups): labels, near-threshold edge ids and displacements
+    against the oracle."""
+    say(f"case non-local damage prec={prec} R_d={radius}")
+    prob = pulled_block(prec, radius)
     m, mesh, st, hist = lockstep(prob, 30, check_every=10)
     broken = int(st.zeta.sum())
     last = hist[-1]
