@@ -771,13 +771,40 @@ __global__ __launch_bounds__(256) void k_kap_grad(NetInputs in, int npad, const 
     epart[(size_t)blockIdx.x * kEdgeGrad + q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
 }
 
-__global__ __launch_bounds__(64) void k_kap_edge_reduce(int nwg, const float* __restrict__ epart,
-                                                        float* __restrict__ grad) {
-  const int q = threadIdx.x;
-  if (q >= kEdgeGrad) return;
+// Sum of nwg per-workgroup partials (record length len, entry src) for 64
+// outputs per 256-thread workgroup: the four waves take every fourth partial
+// (loads coalesced over the 64 outputs, eight in flight per lane) and the four
+// sums are added in order in LDS, so the result does not depend on timing.
+__device__ __forceinline__ float reduce_partials64(int nwg, const float* __restrict__ part, size_t len, int src,
+                                                   bool act, float* sh) {
+  const int o = threadIdx.x & 63, sl = threadIdx.x >> 6;
   float s = 0.f;
-  for (int w = 0; w < nwg; ++w) s += epart[(size_t)w * kEdgeGrad + q];
-  grad[kOffWe + q] = s;
+  if (act) {
+    for (int w0 = sl; w0 < nwg; w0 += 32) {
+      float x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int w = w0 + 4 * u;
+        x[u] = w < nwg ? part[(size_t)w * len + src] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += x[u];
+    }
+  }
+  sh[sl * 64 + o] = s;
+  __syncthreads();
+  return ((sh[o] + sh[64 + o]) + sh[128 + o]) + sh[192 + o];
+}
+
+static_assert(kEdgeGrad <= 64, "one workgroup of 64 outputs reduces the edge-weight gradient");
+
+__global__ __launch_bounds__(256) void k_kap_edge_reduce(int nwg, const float* __restrict__ epart,
+                                                         float* __restrict__ grad) {
+  __shared__ float sh[256];
+  const int q = threadIdx.x & 63;
+  const bool act = q < kEdgeGrad;
+  const float s = reduce_partials64(nwg, epart, kEdgeGrad, act ? q : 0, act, sh);
+  if (act && threadIdx.x < 64) grad[kOffWe + q] = s;
 }
 
 // gh3 = Wh^T go and gz3 = gh3 * (z3 > 0), one thread per padded row.
@@ -856,25 +883,24 @@ __global__ __launch_bounds__(256) void k_net_dw(int npad, const bf16* __restrict
   if (threadIdx.x < kHid) out[kHid * K + threadIdx.x] = dbs;
 }
 
-// Sum the partials in workgroup order into the flat gradient (first Kreal columns).
+// Sum the partials into the flat gradient (first Kreal columns).
 __global__ __launch_bounds__(256) void k_net_dw_reduce(int nwg, int K, int Kreal, const float* __restrict__ part,
                                                        float* __restrict__ grad, int offW, int offb) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
+  __shared__ float sh[256];
+  const int t = blockIdx.x * 64 + (threadIdx.x & 63);
   const int nW = kHid * Kreal;
-  if (t >= nW + kHid) return;
-  int src;
-  int dst;
+  const bool act = t < nW + kHid;
+  int src = 0, dst = 0;
   if (t < nW) {
     const int o = t / Kreal, k = t % Kreal;
     src = o * K + k;
     dst = offW + t;
-  } else {
+  } else if (act) {
     src = kHid * K + (t - nW);
     dst = offb + (t - nW);
   }
-  float s = 0.f;
-  for (int w = 0; w < nwg; ++w) s += part[(size_t)w * (kHid * K + kHid) + src];
-  grad[dst] = s;
+  const float s = reduce_partials64(nwg, part, (size_t)kHid * K + kHid, src, act, sh);
+  if (act && threadIdx.x < 64) grad[dst] = s;
 }
 
 // dWh[k][f] = sum go[k] h3[f], dbh[k] = sum go[k]: per workgroup a node range,
@@ -898,11 +924,11 @@ __global__ __launch_bounds__(512) void k_net_dhead(int npad, const float* __rest
 
 __global__ __launch_bounds__(256) void k_net_dhead_reduce(int nwg, const float* __restrict__ part,
                                                           float* __restrict__ grad) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= kHeadGrad) return;
-  float s = 0.f;
-  for (int w = 0; w < nwg; ++w) s += part[(size_t)w * kHeadGrad + t];
-  grad[kOffWh + t] = s;
+  __shared__ float sh[256];
+  const int t = blockIdx.x * 64 + (threadIdx.x & 63);
+  const bool act = t < kHeadGrad;
+  const float s = reduce_partials64(nwg, part, kHeadGrad, act ? t : 0, act, sh);
+  if (act && threadIdx.x < 64) grad[kOffWh + t] = s;
 }
 
 // ---------------------------------------------------------------- optimiser
@@ -1000,23 +1026,23 @@ void net_kaporin_backward(hipStream_t s, const NetParamsDev& P, NetWork& w, cons
   const double N = 3.0 * in.n;
   k_kap_grad<<<Gb, 256, 0, s>>>(in, np, w.o, P.master, w.probe, w.wneg, w.mv, w.sv, (float)(2.0 / t),
                                 (float)(2.0 / N), w.go, w.epart);
-  k_kap_edge_reduce<<<1, 64, 0, s>>>(Gb, w.epart, w.grad);
+  k_kap_edge_reduce<<<1, 256, 0, s>>>(Gb, w.epart, w.grad);
   k_net_dhead<<<kDwWorkgroups, 512, 0, s>>>(np, w.go, w.h[kNetLayers], w.part);
-  k_net_dhead_reduce<<<nb256(kHeadGrad), 256, 0, s>>>(kDwWorkgroups, w.part, w.grad);
+  k_net_dhead_reduce<<<(kHeadGrad + 63) / 64, 256, 0, s>>>(kDwWorkgroups, w.part, w.grad);
   k_net_head_bwd<<<nb256(np), 256, 0, s>>>(np, P.master, w.go, w.z[kNetLayers], w.gh, w.gz);
   for (int l = kNetLayers - 1; l >= 0; --l) {
     // gz holds dloss/dz_{l+1}
     k_net_dw<kHid, kHid><<<kDwWorkgroups, 256, 0, s>>>(np, w.gz, w.h[l], w.m[l], w.part);
-    k_net_dw_reduce<<<nb256(kHid * 2 * kHid + kHid), 256, 0, s>>>(kDwWorkgroups, 2 * kHid, 2 * kHid, w.part, w.grad,
-                                                                  kOffL0 + l * kLayerSize,
-                                                                  kOffL0 + l * kLayerSize + kHid * 2 * kHid);
+    k_net_dw_reduce<<<(kHid * 2 * kHid + kHid + 63) / 64, 256, 0, s>>>(kDwWorkgroups, 2 * kHid, 2 * kHid, w.part,
+                                                                       w.grad, kOffL0 + l * kLayerSize,
+                                                                       kOffL0 + l * kLayerSize + kHid * 2 * kHid);
     k_net_gemm<kHid, 0, 2 * kHid, 2><<<np / kNetRows, 256, 0, s>>>(w.gz, nullptr, P.WlT[l], nullptr, nullptr,
                                                                    nullptr, nullptr, w.gi);
     k_net_mean_bwd<<<np / 32, 256, 0, s>>>(in, np, w.inv_wdeg, w.gi, w.gh, w.z[l], w.gz);
   }
   k_net_dw<kNetInPad, 0><<<kDwWorkgroups, 256, 0, s>>>(np, w.gz, w.a, nullptr, w.part);
-  k_net_dw_reduce<<<nb256(kHid * kNetIn + kHid), 256, 0, s>>>(kDwWorkgroups, kNetInPad, kNetIn, w.part, w.grad,
-                                                              kOffW0, kOffB0);
+  k_net_dw_reduce<<<(kHid * kNetIn + kHid + 63) / 64, 256, 0, s>>>(kDwWorkgroups, kNetInPad, kNetIn, w.part,
+                                                                   w.grad, kOffW0, kOffB0);
 }
 
 void net_adam(hipStream_t s, NetParamsDev& P, const float* grad, int t, float lr) {
