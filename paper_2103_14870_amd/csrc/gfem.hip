@@ -94,6 +94,16 @@ int round_up8(int x) { return (x + 7) / 8 * 8; }
 // 256 x 1024: 282, 512 x 512: 295, 1024 x 256: 290, 512 x 1024: 260,
 // 512 x 256: 269, 384 x 512: 282, 768 x 256: 284 -- half the partials of
 // 256 x 1024 at the same four waves per SIMD.
+// Launch chunks of a PCG solve: the first covers the previous step's count for
+// the same outer pass plus GFEM_CHUNK_MARGIN iterations, further ones
+// GFEM_CHUNK_NEXT iterations each.
+#ifndef GFEM_CHUNK_MARGIN
+#define GFEM_CHUNK_MARGIN 0
+#endif
+#ifndef GFEM_CHUNK_NEXT
+#define GFEM_CHUNK_NEXT 3
+#endif
+
 #ifndef GFEM_PCG_MAX_WG
 #define GFEM_PCG_MAX_WG 512
 #endif
@@ -469,7 +479,7 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
     // synchronisation, so the prediction carries no margin.
     const int slot = std::min(outer, 3);
     int* hist = M->last_solve_iters[kind];
-    int chunk = hist[slot] > 0 ? hist[slot] : (outer == 0 ? 16 : 8);
+    int chunk = hist[slot] > 0 ? hist[slot] + GFEM_CHUNK_MARGIN : (outer == 0 ? 16 : 8);
     chunk = std::max(1, std::min(chunk, left));
     int iters = 0;
     bool failed = false, converged_flag = false;
@@ -521,7 +531,7 @@ SolveResult solve(gf_mesh* M, const void* precond_blocks, const gfem::FactView* 
       failed = M->h_ctl->fail != 0;
       converged_flag = M->h_ctl->done != 0;
       if (converged_flag || k >= left || bb == 0.0) break;
-      chunk = 3;
+      chunk = GFEM_CHUNK_NEXT;
     }
     M->solve_iters.push_back(iters);
     hist[slot] = iters;
