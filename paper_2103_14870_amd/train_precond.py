@@ -119,10 +119,14 @@ def main():
                     help="fraction of episodes on fine ellipsoids (cells of the 620k-tet workload's size)")
     ap.add_argument("--init-omega", type=float, default=None,
                     help="start from the constant member W = omega I (edge bias only) instead of block-Jacobi")
+    ap.add_argument("--init-weights", default=None,
+                    help="start from these weights (.npy, e.g. the shipped ones) instead of block-Jacobi")
     args = ap.parse_args()
     gfem.load()
     net = gfem.Net(seed=args.seed)
     net.set_power_steps(args.power_steps)
+    if args.init_weights is not None:
+        net.set_weights(np.load(args.init_weights))
     if args.init_omega is not None:
         if not 0.0 <= args.init_omega < 2.0:
             raise SystemExit("--init-omega must lie in [0, 2)")
