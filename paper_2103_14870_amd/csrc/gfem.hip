@@ -108,6 +108,15 @@ int round_up8(int x) { return (x + 7) / 8 * 8; }
 #define GFEM_PCG_MAX_WG 512
 #endif
 constexpr int kPcgMaxWorkgroups = GFEM_PCG_MAX_WG;
+// Below the cap, the grid gives each workgroup about this many block rows: on
+// the 23,409-node notched beam 96 rows (248 workgroups) beat 46 (512, the cap):
+// 233-235 against 214-215 learned steps/s uncracked, 227-236 against 207-210
+// with 30 % pre-broken edges; 183 rows (128 workgroups) lose (186-205).  The
+// 111,912-node ellipsoid stays at the cap either way.
+#ifndef GFEM_PCG_ROWS_PER_WG
+#define GFEM_PCG_ROWS_PER_WG 96
+#endif
+constexpr int kPcgRowsPerWorkgroup = GFEM_PCG_ROWS_PER_WG;
 
 // Each inner (working-precision) PCG solve aims at this fraction of the
 // outer FP64 tolerance relative to its right-hand side.  It must stay below 1
@@ -1064,11 +1073,10 @@ gf_status gf_mesh_create(const double* rest_xyz, int32_t n_nodes, const int32_t*
     M->nbp = (T.nb + 63) / 64 * 64;
     M->Gv = std::min(kMaxPart, std::max(8, round_up8((T.n + gfem::kThreads - 1) / gfem::kThreads)));
     M->Gs = std::min(kMaxPart, std::max(8, round_up8((T.n * gfem::kRowLanes + gfem::kThreads - 1) / gfem::kThreads)));
-    // PCG SpMV grid: one 16-lane group per block row, capped at
-    // kPcgMaxWorkgroups (two 512-thread workgroups per CU) so the consumer
-    // kernels reduce few partials.
-    M->Gb = std::min(kPcgMaxWorkgroups,
-                     std::max(8, round_up8((T.n * gfem::kRowLanes + gfem::kSpmvThreads - 1) / gfem::kSpmvThreads)));
+    // PCG SpMV and G / G^T grid: about kPcgRowsPerWorkgroup block rows per
+    // workgroup, capped at kPcgMaxWorkgroups (two 512-thread workgroups per
+    // CU) so the consumer kernels reduce few partials.
+    M->Gb = std::min(kPcgMaxWorkgroups, std::max(8, round_up8((T.n + kPcgRowsPerWorkgroup - 1) / kPcgRowsPerWorkgroup)));
     M->Ga = std::min(kMaxPart, std::max(8, round_up8((T.n + gfem::kVecThreads - 1) / gfem::kVecThreads)));
     // SpMV of the factorised path: the same cap (its partials are reduced by
     // every workgroup of the G pass, so more of them cost more than they save)
