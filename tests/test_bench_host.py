@@ -44,3 +44,33 @@ def test_kernel_short_name():
     assert bench.kernel_short_name("void gfem::(anonymous namespace)::k_pcg_gpass<float, false, 256>(int, a)") == \
         "k_pcg_gpass<float, false, 256>"
     assert bench.kernel_short_name("void gfem::k_damage(int, int const*)") == "k_damage"
+
+
+def test_pulled_block_inputs():
+    """The quasi-static blocks of the bench: the paper's size, both end faces
+    prescribed and moving apart by the pull per load step, the notch's edges
+    all inside the mid-length cube layer and within the notch depth, and the
+    per-material kernel supports."""
+    import numpy as np
+
+    from paper_2103_14870_amd import meshgen
+
+    for mat, (nu, thr, radius) in meshgen.BLOCK_MATERIALS.items():
+        p = meshgen.pulled_block(mat, pull=0.003, dt=0.5)
+        assert p.n_tets == 168432 and p.params["damage_radius"] == radius
+        assert p.params["poisson"] == nu and p.params["damage_strain"] == thr
+        h, (nx, ny, nz) = p.meta["h"], p.meta["shape"]
+        z = p.X[p.dir_nodes, 2]
+        low = z < 0.5 * nz * h
+        assert low.sum() == (~low).sum() == (nx + 1) * (ny + 1)
+        # displacement per load step = velocity x dt = pull, apart
+        assert np.allclose(p.dir_vel[low, 2] * p.params["dt"], -0.003)
+        assert np.allclose(p.dir_vel[~low, 2] * p.params["dt"], 0.003)
+        assert not p.dir_vel[:, :2].any()
+        # notch: node pairs in the layer nz // 2 .. nz // 2 + 1, x below 5 cells (jitter 5 % h)
+        e = p.broken_pairs
+        assert e.shape[0] > 0 and (e[:, 0] < e[:, 1]).all()
+        zz = p.X[e.ravel(), 2] / h
+        xx = p.X[e.ravel(), 0] / h
+        assert zz.min() > nz // 2 - 0.1 and zz.max() < nz // 2 + 1.1
+        assert xx.max() < 5 + 0.1
