@@ -125,7 +125,11 @@ __global__ __launch_bounds__(256) void k_net_gemm(const bf16* __restrict__ XA, c
 // ---------------------------------------------------------------- neighbour mean
 
 // m_i = (1 / number of unbroken incident edges) sum over unbroken edges of h_j.
-// Eight lanes per node, eight features (one 16-byte load) per lane.
+// Eight lanes per node, eight features (one 16-byte load) per lane.  The
+// row's entries are taken four at a time with every load issued before the
+// sums (an entry that is absent, the diagonal or a broken edge reads a valid
+// stand-in and is skipped), so the gathers overlap; the sums keep the row's
+// order.
 __global__ __launch_bounds__(256) void k_net_mean(NetInputs in, int npad, const float* __restrict__ inv_wdeg,
                                                   const bf16* __restrict__ h, bf16* __restrict__ m) {
   const int node = blockIdx.x * 32 + (threadIdx.x >> 3), f8 = (threadIdx.x & 7) * 8;
@@ -133,12 +137,29 @@ __global__ __launch_bounds__(256) void k_net_mean(NetInputs in, int npad, const 
   float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (node < in.n) {
     const int s = in.A.row_ptr[node], e = in.A.row_ptr[node + 1], db = in.diag_blk[node];
-    for (int b = s; b < e; ++b) {
-      if (b == db) continue;
-      if (in.zeta[in.blk_edge[b]]) continue;
-      const bf16x8 v = *reinterpret_cast<const bf16x8*>(h + (size_t)in.A.col[b] * kHid + f8);
+    for (int b0 = s; b0 < e; b0 += 4) {
+      int col[4], ed[4];
+      bool in_row[4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] += (float)v[q];
+      for (int u = 0; u < 4; ++u) {
+        const int b = b0 + u;
+        in_row[u] = b < e && b != db;
+        const int bb = b < e ? b : s;
+        col[u] = in.A.col[bb];
+        ed[u] = in.blk_edge[bb];  // -1 on the diagonal
+      }
+      bool use[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) use[u] = in_row[u] && in.zeta[ed[u] < 0 ? 0 : ed[u]] == 0;
+      bf16x8 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const bf16x8*>(h + (size_t)col[u] * kHid + f8);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (use[u]) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[q] += (float)v[u][q];
+        }
     }
     const float iw = inv_wdeg[node];
 #pragma unroll
@@ -166,11 +187,30 @@ __global__ __launch_bounds__(256) void k_net_mean_bwd(NetInputs in, int npad, co
     g = *reinterpret_cast<const f32x8*>(gh + (size_t)node * kHid + f8) +
         *reinterpret_cast<const f32x8*>(gi + (size_t)node * 2 * kHid + f8);
     const int s = in.A.row_ptr[node], e = in.A.row_ptr[node + 1], db = in.diag_blk[node];
-    for (int b = s; b < e; ++b) {
-      if (b == db) continue;
-      if (in.zeta[in.blk_edge[b]]) continue;
-      const int j = in.A.col[b];
-      g += inv_wdeg[j] * *reinterpret_cast<const f32x8*>(gi + (size_t)j * 2 * kHid + kHid + f8);
+    // four entries at a time, all loads before the sums (as in k_net_mean)
+    for (int b0 = s; b0 < e; b0 += 4) {
+      int col[4], ed[4];
+      bool in_row[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = b0 + u;
+        in_row[u] = b < e && b != db;
+        const int bb = b < e ? b : s;
+        col[u] = in.A.col[bb];
+        ed[u] = in.blk_edge[bb];  // -1 on the diagonal
+      }
+      bool use[4];
+      float wj[4];
+      f32x8 gj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        use[u] = in_row[u] && in.zeta[ed[u] < 0 ? 0 : ed[u]] == 0;
+        wj[u] = inv_wdeg[col[u]];
+        gj[u] = *reinterpret_cast<const f32x8*>(gi + (size_t)col[u] * 2 * kHid + kHid + f8);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (use[u]) g += wj[u] * gj[u];
     }
   }
   *reinterpret_cast<f32x8*>(gh + (size_t)node * kHid + f8) = g;
