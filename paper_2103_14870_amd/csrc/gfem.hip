@@ -681,7 +681,7 @@ void learned_precond(gf_mesh* M) {
   M->timed(3, -1, 0, [&] {
     const bool fresh = !M->net_cached || M->net_age >= every;
     if (fresh) {
-      gfem::net_forward(M->stream, M->net->P, M->netw, in, M->Gn);
+      gfem::net_forward(M->stream, M->net->P, M->netw, in, M->Gn, false);
       M->net_cached = true;
       M->net_age = 0;
     }

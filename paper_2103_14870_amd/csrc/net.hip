@@ -104,22 +104,45 @@ __global__ __launch_bounds__(256) void k_net_gemm(const bf16* __restrict__ XA, c
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
     }
   }
+  if constexpr (EPI == 2) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = r0 + 4 * (l >> 4) + i, col = t * 16 + (l & 15);
-      const float v = acc[t][i];
-      if (EPI == 2) {
-        Fout[(size_t)row * NOUT + col] = v;
-      } else {
-        const float zz = v + bias[col];
-        Zout[(size_t)row * NOUT + col] = (bf16)zz;
-        float hr = fmaxf(zz, 0.f);
-        if (EPI == 1) hr += (float)Hin[(size_t)row * NOUT + col];
-        Hout[(size_t)row * NOUT + col] = (bf16)hr;
+      for (int i = 0; i < 4; ++i) {
+        const int row = r0 + 4 * (l >> 4) + i, col = t * 16 + (l & 15);
+        Fout[(size_t)row * NOUT + col] = acc[t][i];
       }
+  } else {
+    // The MFMA result layout (lane: 4 rows x NT columns 16 apart) is turned
+    // row-major through this wave's slice of LDS, so that the bias, the
+    // residual input and both outputs move as 16-byte runs of 8 features.
+    static_assert(NOUT == 64, "one 16 x 64 tile per wave");
+    __shared__ float tile[4][16][NOUT + 4];
+    float(*tw)[NOUT + 4] = tile[wv];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tw[4 * (l >> 4) + i][t * 16 + (l & 15)] = acc[t][i];
+    __syncthreads();
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int rl = l >> 2, c8 = (l & 3) * 16 + half * 8;
+      const size_t off = (size_t)(r0 + rl) * NOUT + c8;
+      bf16x8 hin;
+      if (EPI == 1) hin = *reinterpret_cast<const bf16x8*>(Hin + off);
+      bf16x8 zo, ho;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float zz = tw[rl][c8 + q] + bias[c8 + q];
+        zo[q] = (bf16)zz;
+        float hr = fmaxf(zz, 0.f);
+        if (EPI == 1) hr += (float)hin[q];
+        ho[q] = (bf16)hr;
+      }
+      if (Zout) *reinterpret_cast<bf16x8*>(Zout + off) = zo;
+      *reinterpret_cast<bf16x8*>(Hout + off) = ho;
     }
+  }
 }
 
 // ---------------------------------------------------------------- neighbour mean
@@ -1011,16 +1034,16 @@ inline int nb256(int n) { return (n + 255) / 256; }
 
 }  // namespace
 
-void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int) {
+void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int, bool keep_z) {
   const int np = w.npad;
   k_net_inputs<<<nb256(np), 256, 0, s>>>(in, np, w.a, w.inv_wdeg);
   k_net_gemm<kNetInPad, 0, kHid, 0><<<np / kNetRows, 256, 0, s>>>(w.a, nullptr, P.W0, P.master + kOffB0, nullptr,
-                                                                  w.z[0], w.h[0], nullptr);
+                                                                  keep_z ? w.z[0] : nullptr, w.h[0], nullptr);
   for (int l = 0; l < kNetLayers; ++l) {
     k_net_mean<<<np / 32, 256, 0, s>>>(in, np, w.inv_wdeg, w.h[l], w.m[l]);
     k_net_gemm<kHid, kHid, kHid, 1><<<np / kNetRows, 256, 0, s>>>(
-        w.h[l], w.m[l], P.Wl[l], P.master + kOffL0 + l * kLayerSize + kHid * 2 * kHid, w.h[l], w.z[l + 1],
-        w.h[l + 1], nullptr);
+        w.h[l], w.m[l], P.Wl[l], P.master + kOffL0 + l * kLayerSize + kHid * 2 * kHid, w.h[l],
+        keep_z ? w.z[l + 1] : nullptr, w.h[l + 1], nullptr);
   }
   k_net_head_fwd<<<nb256(np), 256, 0, s>>>(np, P.master, w.h[kNetLayers], w.o);
 }

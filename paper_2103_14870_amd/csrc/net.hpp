@@ -109,7 +109,8 @@ struct NetInputs {
 };
 
 // Forward pass: node inputs, embedding, three layers, head -> w.o.
-void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int Gb);
+// keep_z: also store the pre-activations (the backward pass of training needs them).
+void net_forward(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int Gb, bool keep_z = true);
 // Factor values from the head outputs w.o and the current system: packed
 // BF16 (fp32 = false) or FP32 SoA into w.gl32/gu32/gd32.
 void net_build_factor(hipStream_t s, const NetParamsDev& P, NetWork& w, const NetInputs& in, int Gb, bool fp32);
