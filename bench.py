@@ -416,8 +416,8 @@ def main():
                               cmd.format("WRITE_SIZE", "W", args.calib_copy_mb or 512))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding a mesh over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -479,12 +479,12 @@ def main():
         return
     if args.workload == "ellipsoid":
         args.dt = args.dt or 1e-2
-        prob = meshgen.make_config(3, dt=args.dt)
+        prob = meshgen.ellipsoid(dt=args.dt)
         workload = (f"ellipsoid {prob.n_tets} tets / {prob.n_nodes} nodes, ductile (yield 0.05, damage 0.3), "
                     f"end caps pulled 1 cm/step, dt={args.dt:g}, PCG to 1e-6 FP64 rel. residual")
     else:
         args.dt = args.dt or 1e-4
-        prob = meshgen.make_config(5, crack_fraction=args.crack_fraction, dt=args.dt)
+        prob = meshgen.notched_beam(crack_fraction=args.crack_fraction, dt=args.dt)
         workload = (f"notched beam {prob.n_tets} tets / {prob.n_nodes} nodes, three-point bending, "
                     f"{100 * args.crack_fraction:g} % pre-broken edges, dt={args.dt:g}, PCG to 1e-6 FP64 rel. residual")
     prob.params["net_every_n_steps"] = args.net_every

@@ -323,19 +323,3 @@ def pulled_block(material="stone", nx=22, ny=22, nz=58, h=0.18, jitter_frac=0.05
     params.update(param_kw)
     return Problem(f"{material}-block{nx}x{ny}x{nz}", X, tets.astype(np.int32), params, nodes, vel,
                    broken.astype(np.int32), 40, dict(h=h, shape=(nx, ny, nz), material=material))
-
-
-CONFIGS = {
-    1: lambda **kw: cube_block(**kw),
-    2: lambda **kw: notched_beam(**kw),
-    3: lambda **kw: ellipsoid(**kw),
-}
-
-
-def make_config(i: int, **kw) -> Problem:
-    """Config 1: 10^3 FP64 cube; 2: notched beam; 3: 620k-tet ellipsoid;
-    5: beam with extra crack fraction (pass crack_fraction=0.1 or 0.3)."""
-    if i == 5:
-        kw.setdefault("crack_fraction", 0.0)
-        return notched_beam(**kw)
-    return CONFIGS[i](**kw)

@@ -74,3 +74,15 @@ def test_pulled_block_inputs():
         xx = p.X[e.ravel(), 0] / h
         assert zz.min() > nz // 2 - 0.1 and zz.max() < nz // 2 + 1.1
         assert xx.max() < 5 + 0.1
+
+
+def test_more_than_one_gpu_is_refused():
+    """The bench times one GPU; asking for more exits with status 2 and a
+    message, before any device is touched."""
+    import subprocess
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""

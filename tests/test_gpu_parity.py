@@ -92,10 +92,10 @@ def test_system_matches_oracle(prec, tol):
     assert np.array_equal(zg.astype(bool), st.zeta)
 
 
-def test_config1_fp64_full_run():
+def test_cube_block_fp64_full_run():
     """The 10x10x10 FP64 cube, 50 steps, lockstep with the oracle."""
-    say("case config1 fp64 50 steps")
-    prob = meshgen.make_config(1)
+    say("case cube block fp64 50 steps")
+    prob = meshgen.cube_block()
     m, mesh, st, hist = lockstep(prob, 50, check_every=10)
     last = hist[-1]
     say(f"  pos rel {last['pos_rel']:.3e} disp rel {last['disp_rel']:.3e} "
@@ -118,10 +118,10 @@ def test_beam_split_100_steps():
     m.close()
 
 
-def test_config2_full_size_slice():
+def test_notched_beam123k_full_size_slice():
     """Full 122,880-tet notched beam, split precision: a 5-step slice."""
-    say("case config2 full size 5 steps")
-    prob = meshgen.make_config(2)
+    say("case notched beam 122,880 tets, 5 steps")
+    prob = meshgen.notched_beam()
     m, mesh, st, hist = lockstep(prob, 5, check_every=5)
     last = hist[-1]
     say(f"  pos rel {last['pos_rel']:.3e} disp rel {last['disp_rel']:.3e} "
@@ -235,7 +235,7 @@ def test_spmv_bench_hook():
         assert us > 0 and by > 0
 
 
-def test_config3_full_size_jacobi_and_learned():
+def test_ellipsoid620k_full_size_jacobi_and_learned():
     """Full 619,830-tet ductile ellipsoid in the launch configuration the
     benchmark times (split precision; block-Jacobi, and the learned factor with
     the shipped weights and the network every 4 steps): a 2-step slice against
@@ -243,8 +243,8 @@ def test_config3_full_size_jacobi_and_learned():
     labels of the block-Jacobi run equal the oracle's away from the threshold."""
     import os
 
-    say("case config3 full size 2 steps, block-Jacobi and learned")
-    prob = meshgen.make_config(3)
+    say("case ellipsoid 619,830 tets, 2 steps, block-Jacobi and learned")
+    prob = meshgen.ellipsoid()
     prob.params["net_every_n_steps"] = 4
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     net = gfem.Net(seed=0)

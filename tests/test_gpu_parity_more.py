@@ -222,10 +222,10 @@ def test_trained_network_beats_block_jacobi_on_a_held_out_beam():
 
 
 @pytest.mark.timeout(900)
-def test_config2_full_size_10_steps():
+def test_notched_beam123k_full_size_10_steps():
     """Full 122,880-tet notched beam, split precision: a 10-step slice."""
-    say("case config2 full size 10 steps")
-    prob = meshgen.make_config(2)
+    say("case notched beam 122,880 tets, 10 steps")
+    prob = meshgen.notched_beam()
     m, mesh, st, hist = lockstep(prob, 10, check_every=5)
     last = hist[-1]
     say(f"  disp rel {last['disp_rel']:.3e} per node {last['disp_node']:.3e} "
@@ -236,12 +236,12 @@ def test_config2_full_size_10_steps():
 
 
 @pytest.mark.timeout(1100)
-def test_config3_full_size_10_steps_jacobi_and_learned():
+def test_ellipsoid620k_full_size_10_steps_jacobi_and_learned():
     """Full 619,830-tet ductile ellipsoid in the benchmark's launch
     configuration (network every 4 steps): a 10-step slice of both
     preconditioners against the oracle."""
-    say("case config3 full size 10 steps, block-Jacobi and learned")
-    prob = meshgen.make_config(3)
+    say("case ellipsoid 619,830 tets, 10 steps, block-Jacobi and learned")
+    prob = meshgen.ellipsoid()
     prob.params["net_every_n_steps"] = 4
     net = gfem.Net(seed=0)
     net.set_weights(np.load(WEIGHTS))
@@ -274,15 +274,15 @@ def test_config3_full_size_10_steps_jacobi_and_learned():
 
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("frac", [0.0, 0.1, 0.3])
-def test_config5_cracked_beam_full_size(frac):
+def test_cracked_beam123k_full_size(frac):
     """The 122,880-tet beam with 0/10/30 % pre-broken edges (random planar
     cracks, seed 11): 10 steps of block-Jacobi and of the learned factor, each
     against the FP64 oracle.  Two solves that each meet 1e-6 can differ by
     about cond(A) x 1e-6 in the solution; the cracked beams' loose fragments
     make cond(A) large, so the position bar is relative to |x| there and the
     displacement bar is reported."""
-    say(f"case config5 frac={frac}")
-    prob = meshgen.make_config(5, crack_fraction=frac)
+    say(f"case cracked beam 122,880 tets frac={frac}")
+    prob = meshgen.notched_beam(crack_fraction=frac)
     prob.params["net_every_n_steps"] = 4
     net = gfem.Net(seed=0)
     net.set_weights(np.load(WEIGHTS))

@@ -23,8 +23,8 @@ def _lib():
 
 
 def test_permuted_beam_with_rcm_matches_oracle():
-    say("case permuted config2 beam, RCM renumbering, 5 lockstep steps")
-    prob = meshgen.permute_nodes(meshgen.make_config(5, crack_fraction=0.1), seed=3)
+    say("case permuted cracked beam, RCM renumbering, 5 lockstep steps")
+    prob = meshgen.permute_nodes(meshgen.notched_beam(crack_fraction=0.1), seed=3)
     prob.params["reorder"] = "rcm"
     m, mesh, st, hist = lockstep(prob, 5, check_every=5)
     last = hist[-1]
@@ -36,7 +36,7 @@ def test_permuted_beam_with_rcm_matches_oracle():
 
 def test_rcm_spmv_time_matches_the_banded_order():
     say("case SpMV time: banded vs permuted vs permuted + RCM")
-    base = meshgen.make_config(2)
+    base = meshgen.notched_beam()
     perm = meshgen.permute_nodes(base, seed=3)
     res = {}
     for name, prob, reorder in (("banded", base, "none"), ("permuted", perm, "none"),

@@ -51,7 +51,7 @@ def test_visual_mesh_damaged_block():
 
 def test_visual_mesh_full_size_beam_sample():
     say("case visual mesh, 122,880-tet beam with 30 % cracks (sample)")
-    prob = meshgen.make_config(5, crack_fraction=0.3)
+    prob = meshgen.notched_beam(crack_fraction=0.3)
     with gfem.mesh_from_problem(prob) as m:
         m.step(2)
         rng = np.random.default_rng(1)
