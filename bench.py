@@ -289,6 +289,28 @@ def timed_steps(m, steps, warmup):
                 outer=s["outer_iters"] / steps, fallback=s["used_fallback"])
 
 
+def per_call_steps(m, steps, warmup, readback):
+    """The same step window as the timed leg as one gf_step(1) call per step;
+    with readback, each step is followed by gf_get_positions and
+    gf_get_edge_damage into host buffers (the boundary's output path, over
+    PCIe)."""
+    import torch
+
+    if warmup > 0:
+        m.step(warmup)
+    torch.cuda.synchronize()
+    nbytes = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.step(1)
+        if readback:
+            x, z = m.positions(), m.edge_damage()
+            nbytes = x.nbytes + z.nbytes
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return dict(value=steps / elapsed, ms_per_step=1000.0 * elapsed / steps, bytes_per_step=nbytes)
+
+
 def kernel_times(m, steps, warmup):
     """Per-kernel device time over the same step window as the timed leg, on a
     fresh mesh (event timing adds host work, so it is kept out of that leg)."""
@@ -373,6 +395,9 @@ def main():
                     help="element energy of the dynamic workloads")
     ap.add_argument("--visual", action="store_true",
                     help="after the timed leg, time the split visualisation mesh (gf_get_visual_mesh)")
+    ap.add_argument("--readback", action="store_true",
+                    help="after the legs, time the same window as one gf_step(1) call per step, without and with "
+                         "the positions and damage labels read back to the host after every step")
     ap.add_argument("--crack-fraction", type=float, default=0.0)
     ap.add_argument("--dt", type=float, default=None, help="time step (default: 1e-2 ellipsoid, 1e-4 beam)")
     ap.add_argument("--precond", default="learned", choices=["learned", "block_jacobi"])
@@ -549,6 +574,14 @@ def main():
         mj = make_mesh(False)
         jac = timed_steps(mj, args.steps, args.warmup)
         mj.close()
+    readback = None
+    if args.readback:
+        readback = {}
+        for key, rb in (("per_step_calls", False), ("with_readback", True)):
+            log(f"per-call leg ({key})")
+            mr = make_mesh(net is not None)
+            readback[key] = per_call_steps(mr, args.steps, args.warmup, rb)
+            mr.close()
 
     out = {
         "metric": "timesteps/s @620k tets: learned-PCG vs Jacobi-PCG at 1e-6 rel. residual",
@@ -589,6 +622,8 @@ def main():
         out["roofline"]["profile_frac"] = spmv_bytes / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBS
     if visual is not None:
         out["visual_mesh"] = visual
+    if readback is not None:
+        out["readback"] = readback
     if jac is not None:
         out["block_jacobi"] = {"value": jac["value"], "pcg_iters_per_step": jac["iters"],
                                "ms_per_step": 1000.0 * jac["elapsed"] / args.steps}
