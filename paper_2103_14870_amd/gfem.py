@@ -65,6 +65,7 @@ class GfemError(RuntimeError):
 
 
 _lib = None
+_lib_path = None
 
 _P = C.POINTER
 _SIGS = {
@@ -108,11 +109,16 @@ _SIGS = {
 }
 
 
-def load(path: str = LIB_PATH):
-    """Load libgfem.so (raises if it is not built)."""
-    global _lib
+def load(path: str | None = None):
+    """Load libgfem.so, or the library at `path` (raises if it is not
+    built).  A process holds one library: with no path the loaded one is
+    returned, and naming another file once one is loaded raises."""
+    global _lib, _lib_path
     if _lib is not None:
+        if path is not None and os.path.realpath(path) != _lib_path:
+            raise RuntimeError(f"{_lib_path} is already loaded; cannot also load {path}")
         return _lib
+    path = LIB_PATH if path is None else path
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} is not built; run __graft_entry__.build() first")
     lib = C.CDLL(path)
@@ -120,7 +126,7 @@ def load(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
-    _lib = lib
+    _lib, _lib_path = lib, os.path.realpath(path)
     return lib
 
 

@@ -64,3 +64,24 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "FileNotFoundError" in r.stderr and "is not built" in r.stderr
+
+
+def test_binding_holds_one_library(tmp_path):
+    """Once a library is loaded, calls without a path reuse it and naming
+    another file raises instead of mixing two builds in one process."""
+    import subprocess
+    import sys
+
+    code = (
+        "from paper_2103_14870_amd import gfem\n"
+        "a = gfem.load()\n"
+        "assert gfem.load() is a and gfem.load(gfem.LIB_PATH) is a\n"
+        "try:\n"
+        f"    gfem.load({str(tmp_path / 'other.so')!r})\n"
+        "except RuntimeError as e:\n"
+        "    assert 'already loaded' in str(e)\n"
+        "    print('refused')\n"
+    )
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "refused"
